@@ -1,0 +1,155 @@
+"""Seeded synthetic inputs for the ternary LB workloads.
+
+This module only builds initial concentration fields, wetting-parameter
+arrays and parameter sets.  It holds none of the lattice Boltzmann
+arithmetic, so both the GPU library's callers and the CPU oracle's tests can
+draw the same inputs from it.
+
+Layouts: node index ``n = x + nx*(y + ny*z)``; concentrations ``[3][N]``;
+wetting parameters ``[wall (y-, y+)][component][x + nx*z]``.
+
+Workloads (the paper's benchmark geometries restated as synthetic inputs):
+
+* ``nested_drop``: a C1 drop inside a C2 shell in C3 bulk, the double
+  emulsion of Sec. V.A (Fig. 1), with interface profiles of eq. (tanh);
+* ``spinodal``: a homogeneous mixture with uniform random fluctuations of
+  amplitude ``delta`` on C1 and C2 (C3 = 1 - C1 - C2), the initial condition
+  of the phase-separation runs of Sec. V.C;
+* ``sessile_drop`` / ``lens``: the wall geometries of Sec. V.A/V.B.
+
+Random numbers come from ``numpy.random.default_rng(seed)`` (PCG64) and are
+generated on the host; no generator runs on the device.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def mobility_to_gamma(M: float, tau_g: float, tau_k: float):
+    """Gamma_phi, Gamma_psi for a symmetric per-component mobility M.
+
+    The appendix gives M_phi = 2 M and M_psi = 2 M / 3 for equal mobilities of
+    C1, C2, C3; Sec. IV relates M_phi = Gamma_phi (tau_phi - 1/2) and
+    M_psi = Gamma_psi (tau_psi - 1/2).
+    """
+    return 2.0 * M / (tau_g - 0.5), 2.0 * M / (3.0 * (tau_k - 0.5))
+
+
+def _coords(nx, ny, nz=1):
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    return x.astype(np.float64).ravel(), y.astype(np.float64).ravel(), z.astype(np.float64).ravel()
+
+
+def tanh_profile(d, R, alpha):
+    """1 inside radius R, 0 outside, with the profile of eq. (tanh) (width alpha)."""
+    return 0.5 * (1.0 + np.tanh((R - d) / (2.0 * alpha)))
+
+
+def nested_drop(nx, ny, R_in=12.0, R_out=20.0, alpha=1.0, centre=None):
+    """C1 drop of radius R_in inside a C2 shell of outer radius R_out, in C3."""
+    x, y, _ = _coords(nx, ny)
+    cx, cy = (nx / 2.0, ny / 2.0) if centre is None else centre
+    d = np.hypot(x - cx, y - cy)
+    c1 = tanh_profile(d, R_in, alpha)
+    c12 = tanh_profile(d, R_out, alpha)
+    C = np.stack([c1, c12 - c1, 1.0 - c12])
+    return C
+
+
+def spinodal(nx, ny, nz=1, mean=(1.0 / 3.0, 1.0 / 3.0), delta=0.01, seed=0):
+    """Uniform noise U(-delta, delta) on C1 and C2 around ``mean``; C3 = 1 - C1 - C2."""
+    rng = np.random.default_rng(seed)
+    N = nx * ny * nz
+    noise = rng.uniform(-delta, delta, size=(2, N))
+    c1 = mean[0] + noise[0]
+    c2 = mean[1] + noise[1]
+    return np.stack([c1, c2, 1.0 - c1 - c2])
+
+
+def sessile_drop(nx, ny, R, x0=None, alpha=1.0, top_layer=None):
+    """C1 drop of radius R centred on the lower wall (centre (x0, -1/2)) in C2.
+
+    With ``top_layer`` set, nodes with y > top_layer are C3 (tanh profile).
+    """
+    x, y, _ = _coords(nx, ny)
+    x0 = nx / 2.0 if x0 is None else x0
+    d = np.hypot(x - x0, y + 0.5)
+    c1 = tanh_profile(d, R, alpha)
+    if top_layer is None:
+        c3 = np.zeros_like(c1)
+    else:
+        c3 = 0.5 * (1.0 + np.tanh((y - top_layer) / (2.0 * alpha)))
+        c3 = np.minimum(c3, 1.0 - c1)
+    c2 = 1.0 - c1 - c3
+    return np.stack([c1, c2, c3])
+
+
+def lens(nx, ny, R, alpha=1.0, y_interface=None):
+    """C1 disc of radius R at the interface between C2 (below) and C3 (above)."""
+    x, y, _ = _coords(nx, ny)
+    yi = ny / 2.0 if y_interface is None else y_interface
+    d = np.hypot(x - nx / 2.0, y - yi)
+    c1 = tanh_profile(d, R, alpha)
+    upper = 0.5 * (1.0 + np.tanh((y - yi) / (2.0 * alpha)))
+    c3 = (1.0 - c1) * upper
+    c2 = 1.0 - c1 - c3
+    return np.stack([c1, c2, c3])
+
+
+def uniform_h(nx, h, nz=1, walls=2):
+    """Wetting parameters [2][3][nx*nz] with the same (h1, h2, h3) everywhere."""
+    arr = np.zeros((2, 3, nx * nz))
+    for w in range(walls):
+        for m in range(3):
+            arr[w, m, :] = h[m]
+    return arr
+
+
+def random_h(nx, lo=-0.01, hi=0.01, nz=1, seed=0, bottom_only=True):
+    """Seeded per-node wetting parameters U(lo, hi); the top wall is neutral if bottom_only."""
+    rng = np.random.default_rng(seed)
+    arr = np.zeros((2, 3, nx * nz))
+    arr[0] = rng.uniform(lo, hi, size=(3, nx * nz))
+    if not bottom_only:
+        arr[1] = rng.uniform(lo, hi, size=(3, nx * nz))
+    return arr
+
+
+# --------------------------------------------------------------------------
+# The named workloads.  Each returns a dict of plain values:
+#   lattice (0 D2Q9 / 1 D3Q19), nx, ny, nz, walls_y, kappa, alpha, tau_f,
+#   tau_g, tau_k, gamma_phi, gamma_psi, steps, C (callable -> [3][N]), h.
+# --------------------------------------------------------------------------
+
+def _params(lattice, nx, ny, nz, walls_y, kappa, alpha, tau, M, steps):
+    gp, gk = mobility_to_gamma(M, tau, tau)
+    return dict(lattice=lattice, nx=nx, ny=ny, nz=nz, walls_y=walls_y, kappa=tuple(kappa),
+                alpha=alpha, tau_f=tau, tau_g=tau, tau_k=tau, gamma_phi=gp, gamma_psi=gk,
+                steps=steps)
+
+
+def double_emulsion_64():
+    """D2Q9 64x64 periodic, nested drop R=12 in shell R=20; kappa=0.01, tau=1, M=0.1; 1000 steps."""
+    w = _params(0, 64, 64, 1, 0, (0.01, 0.01, 0.01), 1.0, 1.0, 0.1, 1000)
+    w["name"] = "d2q9_64x64_double_emulsion"
+    w["C"] = lambda: nested_drop(64, 64, 12.0, 20.0, 1.0)
+    w["h"] = None
+    return w
+
+
+def spinodal_2d(n=1024, steps=10000, seed=2):
+    """D2Q9 n x n periodic spinodal; kappa=(0.01,0.015,0.02), tau=1, M=0.1."""
+    w = _params(0, n, n, 1, 0, (0.01, 0.015, 0.02), 1.0, 1.0, 0.1, steps)
+    w["name"] = f"d2q9_{n}x{n}_spinodal"
+    w["C"] = lambda: spinodal(n, n, 1, seed=seed)
+    w["h"] = None
+    return w
+
+
+def spinodal_3d(n=256, steps=2000, seed=3):
+    """D3Q19 n^3 periodic spinodal; kappa=0.01, tau=0.8, M=0.05."""
+    w = _params(1, n, n, n, 0, (0.01, 0.01, 0.01), 1.0, 0.8, 0.05, steps)
+    w["name"] = f"d3q19_{n}^3_spinodal"
+    w["C"] = lambda: spinodal(n, n, n, seed=seed)
+    w["h"] = None
+    return w
