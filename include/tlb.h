@@ -1,0 +1,226 @@
+/*
+ * tlb.h - C ABI of libtlb, an MI355X (gfx950) implementation of the ternary
+ * free-energy lattice Boltzmann method of Semprebon, Krueger & Kusumaatmaja
+ * (arXiv:1511.02155).
+ *
+ * What one time step computes (Sec. IV of the paper):
+ *   - moments rho = sum f, rho v = sum f e, phi = sum g, psi = sum k (eq. lbconstraint);
+ *   - concentrations C1 = (rho+phi-psi)/2, C2 = (rho-phi-psi)/2, C3 = psi (Sec. II.C);
+ *   - gradients and Laplacians of C_m with isotropic lattice stencils, using
+ *     ghost rows at walls that impose alpha^2 kappa_m grad_perp C_m = -h_m
+ *     (Sec. II.B, eq. cahn_gradient);
+ *   - chemical potentials mu_phi, mu_psi and the pressure-tensor terms (Sec. III);
+ *   - equilibria f^eq, g^eq, k^eq (eq. eqdistfbinary), BGK collision with
+ *     tau_f, tau_g (= tau_phi), tau_k (= tau_psi) (eq. latboltCollision);
+ *   - propagation (eq. latboltPropagation) with half-way bounce-back at walls.
+ *
+ * Lattices and layouts
+ *   D2Q9 velocities, index order: 0 (0,0); 1 (1,0); 2 (-1,0); 3 (0,1); 4 (0,-1);
+ *     5 (1,1); 6 (1,-1); 7 (-1,1); 8 (-1,-1).
+ *   D3Q19 velocities, index order (the order of the weight index sets printed in
+ *     Sec. IV): 0 rest; 1,2 = +-x; 3,4 = +-y; 5,6 = +-z; 7..10 = (1,1,0),
+ *     (1,-1,0), (-1,1,0), (-1,-1,0); 11..14 = (0,1,1), (0,1,-1), (0,-1,1),
+ *     (0,-1,-1); 15..18 = (1,0,1), (1,0,-1), (-1,0,1), (-1,0,-1).
+ *   Node index n = x + nx*(y + ny*z), N = nx*ny*nz.  x and z are periodic; y is
+ *   periodic or bounded by two half-way walls (below y = 0 and above y = ny-1).
+ *   Concentrations / fields: [component][N].  Velocities: [D][N].
+ *   Populations of one species: [Q][N].  Species 0 = f, 1 = g, 2 = k.
+ *   Wetting parameters of one wall: [component m = 0..2][x + nx*z].
+ *
+ * Ownership and threading
+ *   A tlb_sim owns all of its device memory.  Host arrays passed in are
+ *   borrowed for the duration of the call.  Host-I/O calls (plain names) are
+ *   ordered on the simulation's stream and return after the data has been
+ *   copied.  *_dev calls take device pointers in the simulation's own precision
+ *   (float for TLB_F32, double for TLB_F64), are enqueued on the simulation's
+ *   stream and do not synchronise.  A tlb_sim must not be used from two host
+ *   threads at once.
+ *
+ * Errors
+ *   Every call returns a tlb_status: TLB_OK (0) or a negative code.
+ *   TLB_EINVAL  invalid argument (parameters outside the ranges below, NULL
+ *               pointer, index out of range);
+ *   TLB_ENOMEM  device allocation failed;
+ *   TLB_EHIP    a HIP runtime call failed (tlb_last_hip_error() gives the code);
+ *   TLB_ENAN    a non-finite population was detected;
+ *   TLB_ESTATE  call out of order (e.g. tlb_step before any initialisation).
+ */
+#ifndef TLB_H
+#define TLB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    TLB_OK = 0,
+    TLB_EINVAL = -1,
+    TLB_ENOMEM = -2,
+    TLB_EHIP = -3,
+    TLB_ENAN = -4,
+    TLB_ESTATE = -5
+} tlb_status;
+
+enum { TLB_D2Q9 = 0, TLB_D3Q19 = 1 };
+enum { TLB_F32 = 0, TLB_F64 = 1 };
+
+/* Field selectors of tlb_get_field. */
+enum {
+    TLB_FIELD_C1 = 0,
+    TLB_FIELD_C2 = 1,
+    TLB_FIELD_C3 = 2,
+    TLB_FIELD_RHO = 3,
+    TLB_FIELD_PHI = 4,
+    TLB_FIELD_PSI = 5,
+    TLB_FIELD_UX = 6,
+    TLB_FIELD_UY = 7,
+    TLB_FIELD_UZ = 8,
+    TLB_FIELD_MU_PHI = 9,
+    TLB_FIELD_MU_PSI = 10,
+    TLB_NFIELDS = 11
+};
+
+/*
+ * Simulation parameters.
+ *   lattice   TLB_D2Q9 (requires nz == 1) or TLB_D3Q19 (requires nz >= 3).
+ *   prec      TLB_F32 or TLB_F64: storage and arithmetic precision.
+ *   nx, ny    lattice size, each >= 3; nz >= 1.
+ *   walls_y   0: periodic in y; 1: half-way walls below y = 0 and above y = ny-1.
+ *   kappa[m]  bulk coefficients kappa_1..3 > 0 (Sec. II.A); kappa'_m = alpha^2 kappa_m.
+ *   alpha     interface width parameter > 0 (Sec. II.A).
+ *   tau_f, tau_g, tau_k   relaxation times of f, g, k, each > 1/2 (Sec. IV).
+ *   gamma_phi, gamma_psi  the tunable Gamma_phi, Gamma_psi of the g and k
+ *             equilibria; mobilities are M = Gamma (tau - 1/2) (Sec. IV).
+ */
+typedef struct {
+    int32_t lattice;
+    int32_t prec;
+    int32_t nx, ny, nz;
+    int32_t walls_y;
+    double kappa[3];
+    double alpha;
+    double tau_f, tau_g, tau_k;
+    double gamma_phi, gamma_psi;
+} tlb_params;
+
+/* Conservation and stability check of the current state s_t (all sums in FP64). */
+typedef struct {
+    double mass[3];     /* sum rho, sum phi, sum psi over fluid nodes */
+    double momentum[3]; /* sum rho v */
+    double max_speed;   /* max |v| */
+    int64_t nonfinite;  /* number of nodes with a non-finite moment */
+    int64_t step;       /* time steps taken since initialisation */
+} tlb_diag;
+
+typedef struct tlb_sim tlb_sim;
+
+/* Text of a status code (static storage). */
+const char* tlb_status_str(int status);
+/* HIP error code of the last TLB_EHIP returned on this thread (0 if none). */
+int tlb_last_hip_error(void);
+/* ABI version (major * 100 + minor). */
+int tlb_version(void);
+
+/*
+ * Create a simulation on the current HIP device.  stream: a hipStream_t to
+ * enqueue all work on, or NULL to let the simulation create (and own) one.
+ * The state is undefined until tlb_init_equilibrium or tlb_set_populations.
+ * Wetting parameters start at zero (neutral walls).
+ */
+tlb_status tlb_create(const tlb_params* params, void* stream, tlb_sim** out);
+tlb_status tlb_destroy(tlb_sim* sim);
+tlb_status tlb_get_params(const tlb_sim* sim, tlb_params* out);
+
+/*
+ * Wetting parameters h_m of one wall (Sec. II.B, eq. Cahn): wall 0 = below
+ * y = 0, wall 1 = above y = ny-1; h: host array [3][nx*nz], finite values.
+ * Requires walls_y == 1.  Takes effect from the next step (or initialisation).
+ */
+tlb_status tlb_set_wetting(tlb_sim* sim, int wall, const double* h);
+
+/*
+ * Initialise s_0 to the equilibria of the concentration fields C (host,
+ * [3][N], rho = C1 + C2 + C3, phi = C1 - C2, psi = C3, Sec. II.C) and the
+ * velocity u (host, [D][N]; NULL = at rest), with the gradient terms of the
+ * equilibria evaluated from C.  Resets the step counter.
+ */
+tlb_status tlb_init_equilibrium(tlb_sim* sim, const double* C, const double* u);
+
+/* Advance the state by nsteps >= 0 time steps (asynchronous on the stream). */
+tlb_status tlb_step(tlb_sim* sim, int64_t nsteps);
+
+/*
+ * Check for non-finite populations every `every` steps inside tlb_step
+ * (0 = never, the default).  A check synchronises the stream; tlb_step then
+ * returns TLB_ENAN when one is found.
+ */
+tlb_status tlb_set_check_every(tlb_sim* sim, int64_t every);
+
+/* Macroscopic field `which` (TLB_FIELD_*) of the state s_t into host out[N]. */
+tlb_status tlb_get_field(tlb_sim* sim, int which, double* out);
+
+/* Post-propagation populations s_t of one species into host out[Q][N]. */
+tlb_status tlb_get_populations(tlb_sim* sim, int species, double* out);
+
+/* Overwrite the populations s_t of one species from host in[Q][N]. */
+tlb_status tlb_set_populations(tlb_sim* sim, int species, const double* in);
+
+/* Mass, momentum, max |v| and a non-finite count of s_t.  Returns TLB_ENAN
+ * (with *out filled) when non-finite values are present. */
+tlb_status tlb_diagnostics(tlb_sim* sim, tlb_diag* out);
+
+/* Time steps taken since initialisation. */
+tlb_status tlb_get_step(const tlb_sim* sim, int64_t* step);
+
+/* Wait for all work enqueued by this simulation. */
+tlb_status tlb_synchronize(tlb_sim* sim);
+
+/* The hipStream_t this simulation enqueues on. */
+void* tlb_get_stream(const tlb_sim* sim);
+
+/*
+ * Checkpoint and resume.  The raw state is the stored population buffer of
+ * the current step in the simulation's own representation (tlb_state_bytes()
+ * bytes); saving and loading it resumes a run bit for bit.  tlb_save_state /
+ * tlb_load_state copy to / from host memory and synchronise;  the _dev forms
+ * copy to / from device memory asynchronously.  Loading keeps the step count
+ * given by `step`.
+ */
+int64_t tlb_state_bytes(const tlb_sim* sim);
+tlb_status tlb_save_state(tlb_sim* sim, void* host_dst, int64_t* step);
+tlb_status tlb_load_state(tlb_sim* sim, const void* host_src, int64_t step);
+tlb_status tlb_save_state_dev(tlb_sim* sim, void* dev_dst);
+tlb_status tlb_load_state_dev(tlb_sim* sim, const void* dev_src, int64_t step);
+
+/* Device-pointer variants (native precision, asynchronous). */
+tlb_status tlb_init_equilibrium_dev(tlb_sim* sim, const void* C_dev, const void* u_dev);
+tlb_status tlb_get_field_dev(tlb_sim* sim, int which, void* out_dev);
+tlb_status tlb_get_populations_dev(tlb_sim* sim, int species, void* out_dev);
+tlb_status tlb_set_populations_dev(tlb_sim* sim, int species, const void* in_dev);
+tlb_status tlb_set_wetting_dev(tlb_sim* sim, int wall, const void* h_dev);
+
+/*
+ * Launch shape of the fused step kernel.  D2Q9: each workgroup sweeps a strip
+ * of `width` columns (64, 128 or 256) over `chunk` rows.  D3Q19: each workgroup
+ * sweeps a tile of width x height columns (32x8, 64x4, and for TLB_F32 with
+ * hold = 0 also 32x16, 64x8) over `chunk` planes.  chunk >= 1; 0 picks a default.  hold = 1
+ * keeps the populations of the next row/plane in registers between its two
+ * uses; hold = 0 reads them a second time from cache.  Results are identical
+ * for every shape.
+ */
+typedef struct {
+    int32_t width, height, chunk, hold;
+} tlb_launch;
+tlb_status tlb_set_launch(tlb_sim* sim, const tlb_launch* launch);
+tlb_status tlb_get_launch(const tlb_sim* sim, tlb_launch* out);
+
+/* Algorithmic HBM bytes one fused step moves per fluid node (read + write). */
+double tlb_bytes_per_node(const tlb_sim* sim);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TLB_H */

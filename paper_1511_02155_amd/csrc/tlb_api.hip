@@ -1,0 +1,601 @@
+// C ABI of libtlb (declared in include/tlb.h): simulation objects, host and
+// device I/O, the step loop and the conservation check.
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <new>
+
+#include "../../include/tlb.h"
+#include "tlb_internal.hpp"
+
+using namespace tlb;
+
+struct tlb_sim {
+    tlb_params p;
+    int Q, D;
+    int64_t N;
+    int dev;
+    hipStream_t stream;
+    bool own_stream;
+    size_t esize;       // bytes per stored value
+    void* state[2];     // [3][Q][N] each
+    int cur;            // index of the buffer holding u_t
+    void* wet;          // [2][3][nx*nz] or nullptr
+    void* fields;       // [11][N] (lazy)
+    double* staging;    // device doubles for host I/O (lazy)
+    size_t staging_elems;
+    double* diag_partial;
+    double* diag_out;
+    int64_t step;
+    bool ready;
+    int64_t check_every;
+    tlb_launch launch;
+};
+
+static thread_local int g_last_hip = 0;
+
+static tlb_status hip_fail(hipError_t e)
+{
+    g_last_hip = (int)e;
+    return e == hipErrorOutOfMemory ? TLB_ENOMEM : TLB_EHIP;
+}
+
+#define HIPCHK(...)                                \
+    do {                                           \
+        hipError_t e_ = (__VA_ARGS__);             \
+        if (e_ != hipSuccess) return hip_fail(e_); \
+    } while (0)
+
+extern "C" const char* tlb_status_str(int s)
+{
+    switch (s) {
+        case TLB_OK: return "ok";
+        case TLB_EINVAL: return "invalid argument";
+        case TLB_ENOMEM: return "out of device memory";
+        case TLB_EHIP: return "HIP runtime error";
+        case TLB_ENAN: return "non-finite value in the state";
+        case TLB_ESTATE: return "call out of order";
+        default: return "unknown status";
+    }
+}
+
+extern "C" int tlb_last_hip_error(void) { return g_last_hip; }
+extern "C" int tlb_version(void) { return 100; }
+
+static bool params_valid(const tlb_params* p)
+{
+    if (!p) return false;
+    if (p->lattice != TLB_D2Q9 && p->lattice != TLB_D3Q19) return false;
+    if (p->prec != TLB_F32 && p->prec != TLB_F64) return false;
+    if (p->nx < 3 || p->ny < 3 || p->nz < 1) return false;
+    if (p->lattice == TLB_D2Q9 && p->nz != 1) return false;
+    if (p->lattice == TLB_D3Q19 && p->nz < 3) return false;
+    if (p->walls_y != 0 && p->walls_y != 1) return false;
+    for (int m = 0; m < 3; ++m)
+        if (!(p->kappa[m] > 0.0) || !isfinite(p->kappa[m])) return false;
+    if (!(p->alpha > 0.0) || !isfinite(p->alpha)) return false;
+    if (!(p->tau_f > 0.5 && p->tau_g > 0.5 && p->tau_k > 0.5)) return false;
+    if (!isfinite(p->tau_f) || !isfinite(p->tau_g) || !isfinite(p->tau_k)) return false;
+    if (!isfinite(p->gamma_phi) || !isfinite(p->gamma_psi)) return false;
+    const int64_t N = (int64_t)p->nx * p->ny * p->nz;
+    const int Q = p->lattice == TLB_D2Q9 ? 9 : 19;
+    if ((int64_t)Q * N >= ((int64_t)1 << 32)) return false;  // 32-bit offsets within a species
+    return true;
+}
+
+template <typename T>
+static Phys<T> make_phys(const tlb_params& p)
+{
+    Phys<T> P;
+    const double a2 = p.alpha * p.alpha;
+    for (int m = 0; m < 3; ++m) {
+        P.kappa[m] = T(p.kappa[m]);
+        P.a2kappa[m] = T(a2 * p.kappa[m]);
+    }
+    P.omega[0] = T(1.0 / p.tau_f);
+    P.omega[1] = T(1.0 / p.tau_g);
+    P.omega[2] = T(1.0 / p.tau_k);
+    P.gphi3 = T(3.0 * p.gamma_phi);
+    P.gpsi3 = T(3.0 * p.gamma_psi);
+    return P;
+}
+
+static AuxGeom geom(const tlb_sim* s)
+{
+    AuxGeom g;
+    g.lattice = s->p.lattice;
+    g.nx = s->p.nx;
+    g.ny = s->p.ny;
+    g.nz = s->p.nz;
+    g.walls = s->p.walls_y;
+    g.N = s->N;
+    return g;
+}
+
+static void default_launch(tlb_sim* s)
+{
+    const tlb_params& p = s->p;
+    if (p.lattice == TLB_D2Q9) {
+        int w = p.nx >= 256 ? 256 : (p.nx >= 128 ? 128 : 64);
+        const int ntx = (p.nx + w - 1) / w;
+        // aim for about 2048 wavefronts in flight (8 per CU)
+        const int64_t waves_per_item = w / 64;
+        int64_t want_items = 2048 / waves_per_item;
+        int64_t nch = (want_items + ntx - 1) / ntx;
+        int chunk = (int)((p.ny + nch - 1) / nch);
+        if (chunk < 4) chunk = 4;
+        s->launch.width = w;
+        s->launch.height = 1;
+        s->launch.chunk = chunk;
+    } else {
+        int bx = 32, by = (p.prec == TLB_F32) ? 16 : 8;
+        const int ntx = (p.nx + bx - 1) / bx, nty = (p.ny + by - 1) / by;
+        const int64_t waves_per_item = (bx * by) / 64;
+        int64_t want_items = 2048 / waves_per_item;
+        int64_t nch = (want_items + (int64_t)ntx * nty - 1) / ((int64_t)ntx * nty);
+        if (nch < 1) nch = 1;
+        int chunk = (int)((p.nz + nch - 1) / nch);
+        if (chunk < 4) chunk = 4;
+        s->launch.width = bx;
+        s->launch.height = by;
+        s->launch.chunk = chunk;
+    }
+}
+
+static bool launch_valid(const tlb_sim* s, const tlb_launch* l)
+{
+    if (l->chunk < 1 || (l->hold != 0 && l->hold != 1)) return false;
+    if (s->p.lattice == TLB_D2Q9) return l->width == 64 || l->width == 128 || l->width == 256;
+    const int w = l->width, h = l->height;
+    if (w == 32 && h == 8) return true;
+    if (w == 64 && h == 4) return true;
+    if (!l->hold && s->p.prec == TLB_F32 && ((w == 32 && h == 16) || (w == 64 && h == 8))) return true;
+    return false;
+}
+
+extern "C" tlb_status tlb_create(const tlb_params* params, void* stream, tlb_sim** out)
+{
+    if (!out || !params_valid(params)) return TLB_EINVAL;
+    *out = nullptr;
+    tlb_sim* s = new (std::nothrow) tlb_sim();
+    if (!s) return TLB_ENOMEM;
+    memset(s, 0, sizeof(*s));
+    s->p = *params;
+    s->Q = params->lattice == TLB_D2Q9 ? 9 : 19;
+    s->D = params->lattice == TLB_D2Q9 ? 2 : 3;
+    s->N = (int64_t)params->nx * params->ny * params->nz;
+    s->esize = params->prec == TLB_F32 ? 4 : 8;
+    hipError_t e = hipGetDevice(&s->dev);
+    if (e != hipSuccess) {
+        delete s;
+        return hip_fail(e);
+    }
+    if (stream) {
+        s->stream = (hipStream_t)stream;
+        s->own_stream = false;
+    } else {
+        e = hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            delete s;
+            return hip_fail(e);
+        }
+        s->own_stream = true;
+    }
+    const size_t bytes = (size_t)3 * s->Q * s->N * s->esize;
+    for (int b = 0; b < 2; ++b) {
+        e = hipMalloc(&s->state[b], bytes);
+        if (e != hipSuccess) {
+            tlb_destroy(s);
+            return hip_fail(e);
+        }
+    }
+    if (params->walls_y) {
+        const size_t wb = (size_t)2 * 3 * params->nx * params->nz * s->esize;
+        e = hipMalloc(&s->wet, wb);
+        if (e == hipSuccess) e = hipMemsetAsync(s->wet, 0, wb, s->stream);
+        if (e != hipSuccess) {
+            tlb_destroy(s);
+            return hip_fail(e);
+        }
+    }
+    e = hipMalloc((void**)&s->diag_partial, sizeof(double) * kDiagBlocks * kDiagSlots);
+    if (e == hipSuccess) e = hipMalloc((void**)&s->diag_out, sizeof(double) * kDiagSlots);
+    if (e != hipSuccess) {
+        tlb_destroy(s);
+        return hip_fail(e);
+    }
+    default_launch(s);
+    *out = s;
+    return TLB_OK;
+}
+
+extern "C" tlb_status tlb_destroy(tlb_sim* s)
+{
+    if (!s) return TLB_EINVAL;
+    if (s->stream) (void)hipStreamSynchronize(s->stream);
+    for (int b = 0; b < 2; ++b)
+        if (s->state[b]) (void)hipFree(s->state[b]);
+    if (s->wet) (void)hipFree(s->wet);
+    if (s->fields) (void)hipFree(s->fields);
+    if (s->staging) (void)hipFree(s->staging);
+    if (s->diag_partial) (void)hipFree(s->diag_partial);
+    if (s->diag_out) (void)hipFree(s->diag_out);
+    if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
+    delete s;
+    return TLB_OK;
+}
+
+extern "C" tlb_status tlb_get_params(const tlb_sim* s, tlb_params* out)
+{
+    if (!s || !out) return TLB_EINVAL;
+    *out = s->p;
+    return TLB_OK;
+}
+
+extern "C" void* tlb_get_stream(const tlb_sim* s) { return s ? (void*)s->stream : nullptr; }
+
+extern "C" tlb_status tlb_get_step(const tlb_sim* s, int64_t* step)
+{
+    if (!s || !step) return TLB_EINVAL;
+    *step = s->step;
+    return TLB_OK;
+}
+
+extern "C" tlb_status tlb_synchronize(tlb_sim* s)
+{
+    if (!s) return TLB_EINVAL;
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return TLB_OK;
+}
+
+static tlb_status ensure_staging(tlb_sim* s, size_t elems)
+{
+    if (s->staging_elems >= elems) return TLB_OK;
+    if (s->staging) {
+        HIPCHK(hipStreamSynchronize(s->stream));
+        HIPCHK(hipFree(s->staging));
+        s->staging = nullptr;
+        s->staging_elems = 0;
+    }
+    HIPCHK(hipMalloc((void**)&s->staging, elems * sizeof(double)));
+    s->staging_elems = elems;
+    return TLB_OK;
+}
+
+static tlb_status ensure_fields(tlb_sim* s)
+{
+    if (s->fields) return TLB_OK;
+    HIPCHK(hipMalloc(&s->fields, (size_t)TLB_NFIELDS * s->N * s->esize));
+    return TLB_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Wetting parameters
+// ---------------------------------------------------------------------------
+template <typename TIn>
+static tlb_status set_wet_impl(tlb_sim* s, int wall, const TIn* h_dev)
+{
+    const int n = s->p.nx * s->p.nz;
+    const double a2 = s->p.alpha * s->p.alpha;
+    const double i0 = 1.0 / (a2 * s->p.kappa[0]), i1 = 1.0 / (a2 * s->p.kappa[1]), i2 = 1.0 / (a2 * s->p.kappa[2]);
+    hipError_t e;
+    if (s->p.prec == TLB_F32)
+        e = launch_wet<float, TIn>(n, h_dev, i0, i1, i2, (float*)s->wet + (size_t)wall * 3 * n, s->stream);
+    else
+        e = launch_wet<double, TIn>(n, h_dev, i0, i1, i2, (double*)s->wet + (size_t)wall * 3 * n, s->stream);
+    HIPCHK(e);
+    return TLB_OK;
+}
+
+extern "C" tlb_status tlb_set_wetting(tlb_sim* s, int wall, const double* h)
+{
+    if (!s || !h || (wall != 0 && wall != 1) || !s->p.walls_y) return TLB_EINVAL;
+    const size_t n = (size_t)3 * s->p.nx * s->p.nz;
+    for (size_t j = 0; j < n; ++j)
+        if (!isfinite(h[j])) return TLB_EINVAL;
+    tlb_status st = ensure_staging(s, n);
+    if (st) return st;
+    HIPCHK(hipMemcpyAsync(s->staging, h, n * sizeof(double), hipMemcpyHostToDevice, s->stream));
+    st = set_wet_impl<double>(s, wall, s->staging);
+    if (st) return st;
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return TLB_OK;
+}
+
+extern "C" tlb_status tlb_set_wetting_dev(tlb_sim* s, int wall, const void* h_dev)
+{
+    if (!s || !h_dev || (wall != 0 && wall != 1) || !s->p.walls_y) return TLB_EINVAL;
+    if (s->p.prec == TLB_F32) return set_wet_impl<float>(s, wall, (const float*)h_dev);
+    return set_wet_impl<double>(s, wall, (const double*)h_dev);
+}
+
+// ---------------------------------------------------------------------------
+// Initialisation
+// ---------------------------------------------------------------------------
+template <typename T, typename TIn>
+static tlb_status init_impl(tlb_sim* s, const TIn* C, const TIn* u)
+{
+    s->cur = 0;
+    HIPCHK(launch_init<T, TIn>(geom(s), make_phys<T>(s->p), C, u, (const T*)s->wet, (T*)s->state[0], s->stream));
+    s->step = 0;
+    s->ready = true;
+    return TLB_OK;
+}
+
+extern "C" tlb_status tlb_init_equilibrium(tlb_sim* s, const double* C, const double* u)
+{
+    if (!s || !C) return TLB_EINVAL;
+    const size_t nc = (size_t)3 * s->N, nu = u ? (size_t)s->D * s->N : 0;
+    tlb_status st = ensure_staging(s, nc + nu);
+    if (st) return st;
+    HIPCHK(hipMemcpyAsync(s->staging, C, nc * sizeof(double), hipMemcpyHostToDevice, s->stream));
+    if (u) HIPCHK(hipMemcpyAsync(s->staging + nc, u, nu * sizeof(double), hipMemcpyHostToDevice, s->stream));
+    const double* ud = u ? s->staging + nc : nullptr;
+    st = (s->p.prec == TLB_F32) ? init_impl<float, double>(s, s->staging, ud) : init_impl<double, double>(s, s->staging, ud);
+    if (st) return st;
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return TLB_OK;
+}
+
+extern "C" tlb_status tlb_init_equilibrium_dev(tlb_sim* s, const void* C, const void* u)
+{
+    if (!s || !C) return TLB_EINVAL;
+    if (s->p.prec == TLB_F32) return init_impl<float, float>(s, (const float*)C, (const float*)u);
+    return init_impl<double, double>(s, (const double*)C, (const double*)u);
+}
+
+// ---------------------------------------------------------------------------
+// Stepping
+// ---------------------------------------------------------------------------
+template <typename T>
+static tlb_status step_impl(tlb_sim* s, int64_t nsteps)
+{
+    StepArgs<T> a;
+    memset(&a, 0, sizeof(a));
+    const tlb_params& p = s->p;
+    a.wet = (const T*)s->wet;
+    a.nx = p.nx;
+    a.ny = p.ny;
+    a.nz = p.nz;
+    a.walls = p.walls_y;
+    a.N = s->N;
+    a.P = make_phys<T>(p);
+    a.chunk = s->launch.chunk;
+    if (p.lattice == TLB_D2Q9) {
+        a.ntx = (p.nx + s->launch.width - 1) / s->launch.width;
+        a.nty = 1;
+        a.nchunks = (p.ny + a.chunk - 1) / a.chunk;
+    } else {
+        a.ntx = (p.nx + s->launch.width - 1) / s->launch.width;
+        a.nty = (p.ny + s->launch.height - 1) / s->launch.height;
+        a.nchunks = (p.nz + a.chunk - 1) / a.chunk;
+    }
+    a.nitems = a.ntx * a.nty * a.nchunks;
+    for (int64_t t = 0; t < nsteps; ++t) {
+        a.src = (const T*)s->state[s->cur];
+        a.dst = (T*)s->state[s->cur ^ 1];
+        hipError_t e = (p.lattice == TLB_D2Q9)
+                           ? launch_step2d<T>(a, s->launch.width, s->launch.hold, s->stream)
+                           : launch_step3d<T>(a, s->launch.width, s->launch.height, s->launch.hold, s->stream);
+        HIPCHK(e);
+        s->cur ^= 1;
+        s->step += 1;
+        if (s->check_every > 0 && s->step % s->check_every == 0) {
+            tlb_diag d;
+            tlb_status st = tlb_diagnostics(s, &d);
+            if (st) return st;
+        }
+    }
+    return TLB_OK;
+}
+
+extern "C" tlb_status tlb_step(tlb_sim* s, int64_t nsteps)
+{
+    if (!s || nsteps < 0) return TLB_EINVAL;
+    if (!s->ready) return TLB_ESTATE;
+    return s->p.prec == TLB_F32 ? step_impl<float>(s, nsteps) : step_impl<double>(s, nsteps);
+}
+
+extern "C" tlb_status tlb_set_check_every(tlb_sim* s, int64_t every)
+{
+    if (!s || every < 0) return TLB_EINVAL;
+    s->check_every = every;
+    return TLB_OK;
+}
+
+extern "C" tlb_status tlb_set_launch(tlb_sim* s, const tlb_launch* l)
+{
+    if (!s || !l) return TLB_EINVAL;
+    tlb_launch v = *l;
+    if (s->p.lattice == TLB_D2Q9) v.height = 1;
+    if (v.chunk == 0) {
+        tlb_launch d = s->launch;
+        default_launch(s);
+        v.chunk = s->launch.chunk;
+        s->launch = d;
+    }
+    if (!launch_valid(s, &v)) return TLB_EINVAL;
+    s->launch = v;
+    return TLB_OK;
+}
+
+extern "C" tlb_status tlb_get_launch(const tlb_sim* s, tlb_launch* out)
+{
+    if (!s || !out) return TLB_EINVAL;
+    *out = s->launch;
+    return TLB_OK;
+}
+
+extern "C" double tlb_bytes_per_node(const tlb_sim* s)
+{
+    if (!s) return 0.0;
+    return 2.0 * 3.0 * s->Q * (double)s->esize;
+}
+
+// ---------------------------------------------------------------------------
+// Readout
+// ---------------------------------------------------------------------------
+template <typename T, typename TOut>
+static tlb_status field_impl(tlb_sim* s, int which, TOut* out)
+{
+    tlb_status st = ensure_fields(s);
+    if (st) return st;
+    const AuxGeom g = geom(s);
+    HIPCHK(launch_fields<T>(g, make_phys<T>(s->p), (const T*)s->state[s->cur], (const T*)s->wet, (T*)s->fields,
+                            s->stream));
+    HIPCHK(launch_export_field<T, TOut>(g, (const T*)s->fields, which, out, s->stream));
+    return TLB_OK;
+}
+
+extern "C" tlb_status tlb_get_field(tlb_sim* s, int which, double* out)
+{
+    if (!s || !out || which < 0 || which >= TLB_NFIELDS) return TLB_EINVAL;
+    if (!s->ready) return TLB_ESTATE;
+    tlb_status st = ensure_staging(s, (size_t)s->N);
+    if (st) return st;
+    st = (s->p.prec == TLB_F32) ? field_impl<float, double>(s, which, s->staging)
+                                : field_impl<double, double>(s, which, s->staging);
+    if (st) return st;
+    HIPCHK(hipMemcpyAsync(out, s->staging, (size_t)s->N * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return TLB_OK;
+}
+
+extern "C" tlb_status tlb_get_field_dev(tlb_sim* s, int which, void* out)
+{
+    if (!s || !out || which < 0 || which >= TLB_NFIELDS) return TLB_EINVAL;
+    if (!s->ready) return TLB_ESTATE;
+    if (s->p.prec == TLB_F32) return field_impl<float, float>(s, which, (float*)out);
+    return field_impl<double, double>(s, which, (double*)out);
+}
+
+extern "C" tlb_status tlb_get_populations(tlb_sim* s, int species, double* out)
+{
+    if (!s || !out || species < 0 || species > 2) return TLB_EINVAL;
+    if (!s->ready) return TLB_ESTATE;
+    const size_t n = (size_t)s->Q * s->N;
+    tlb_status st = ensure_staging(s, n);
+    if (st) return st;
+    const AuxGeom g = geom(s);
+    hipError_t e = (s->p.prec == TLB_F32)
+                       ? launch_get_pops<float, double>(g, (const float*)s->state[s->cur], species, s->staging, s->stream)
+                       : launch_get_pops<double, double>(g, (const double*)s->state[s->cur], species, s->staging,
+                                                         s->stream);
+    HIPCHK(e);
+    HIPCHK(hipMemcpyAsync(out, s->staging, n * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return TLB_OK;
+}
+
+extern "C" tlb_status tlb_get_populations_dev(tlb_sim* s, int species, void* out)
+{
+    if (!s || !out || species < 0 || species > 2) return TLB_EINVAL;
+    if (!s->ready) return TLB_ESTATE;
+    const AuxGeom g = geom(s);
+    hipError_t e = (s->p.prec == TLB_F32)
+                       ? launch_get_pops<float, float>(g, (const float*)s->state[s->cur], species, (float*)out, s->stream)
+                       : launch_get_pops<double, double>(g, (const double*)s->state[s->cur], species, (double*)out,
+                                                         s->stream);
+    HIPCHK(e);
+    return TLB_OK;
+}
+
+extern "C" tlb_status tlb_set_populations(tlb_sim* s, int species, const double* in)
+{
+    if (!s || !in || species < 0 || species > 2) return TLB_EINVAL;
+    const size_t n = (size_t)s->Q * s->N;
+    tlb_status st = ensure_staging(s, n);
+    if (st) return st;
+    HIPCHK(hipMemcpyAsync(s->staging, in, n * sizeof(double), hipMemcpyHostToDevice, s->stream));
+    const AuxGeom g = geom(s);
+    hipError_t e = (s->p.prec == TLB_F32)
+                       ? launch_set_pops<float, double>(g, s->staging, species, (float*)s->state[s->cur], s->stream)
+                       : launch_set_pops<double, double>(g, s->staging, species, (double*)s->state[s->cur], s->stream);
+    HIPCHK(e);
+    HIPCHK(hipStreamSynchronize(s->stream));
+    s->ready = true;
+    return TLB_OK;
+}
+
+extern "C" tlb_status tlb_set_populations_dev(tlb_sim* s, int species, const void* in)
+{
+    if (!s || !in || species < 0 || species > 2) return TLB_EINVAL;
+    const AuxGeom g = geom(s);
+    hipError_t e = (s->p.prec == TLB_F32)
+                       ? launch_set_pops<float, float>(g, (const float*)in, species, (float*)s->state[s->cur], s->stream)
+                       : launch_set_pops<double, double>(g, (const double*)in, species, (double*)s->state[s->cur],
+                                                         s->stream);
+    HIPCHK(e);
+    s->ready = true;
+    return TLB_OK;
+}
+
+extern "C" tlb_status tlb_diagnostics(tlb_sim* s, tlb_diag* out)
+{
+    if (!s || !out) return TLB_EINVAL;
+    if (!s->ready) return TLB_ESTATE;
+    const AuxGeom g = geom(s);
+    hipError_t e = (s->p.prec == TLB_F32)
+                       ? launch_diag<float>(g, (const float*)s->state[s->cur], s->diag_partial, kDiagBlocks,
+                                            s->diag_out, s->stream)
+                       : launch_diag<double>(g, (const double*)s->state[s->cur], s->diag_partial, kDiagBlocks,
+                                             s->diag_out, s->stream);
+    HIPCHK(e);
+    double h[kDiagSlots];
+    HIPCHK(hipMemcpyAsync(h, s->diag_out, sizeof(h), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    for (int m = 0; m < 3; ++m) {
+        out->mass[m] = h[m];
+        out->momentum[m] = h[3 + m];
+    }
+    out->max_speed = h[6];
+    out->nonfinite = (int64_t)h[7];
+    out->step = s->step;
+    return out->nonfinite ? TLB_ENAN : TLB_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Raw checkpoints
+// ---------------------------------------------------------------------------
+extern "C" int64_t tlb_state_bytes(const tlb_sim* s)
+{
+    return s ? (int64_t)3 * s->Q * s->N * (int64_t)s->esize : 0;
+}
+
+extern "C" tlb_status tlb_save_state(tlb_sim* s, void* dst, int64_t* step)
+{
+    if (!s || !dst) return TLB_EINVAL;
+    if (!s->ready) return TLB_ESTATE;
+    HIPCHK(hipMemcpyAsync(dst, s->state[s->cur], (size_t)tlb_state_bytes(s), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    if (step) *step = s->step;
+    return TLB_OK;
+}
+
+extern "C" tlb_status tlb_load_state(tlb_sim* s, const void* src, int64_t step)
+{
+    if (!s || !src || step < 0) return TLB_EINVAL;
+    HIPCHK(hipMemcpyAsync(s->state[s->cur], src, (size_t)tlb_state_bytes(s), hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    s->step = step;
+    s->ready = true;
+    return TLB_OK;
+}
+
+extern "C" tlb_status tlb_save_state_dev(tlb_sim* s, void* dst)
+{
+    if (!s || !dst) return TLB_EINVAL;
+    if (!s->ready) return TLB_ESTATE;
+    HIPCHK(hipMemcpyAsync(dst, s->state[s->cur], (size_t)tlb_state_bytes(s), hipMemcpyDeviceToDevice, s->stream));
+    return TLB_OK;
+}
+
+extern "C" tlb_status tlb_load_state_dev(tlb_sim* s, const void* src, int64_t step)
+{
+    if (!s || !src || step < 0) return TLB_EINVAL;
+    HIPCHK(hipMemcpyAsync(s->state[s->cur], src, (size_t)tlb_state_bytes(s), hipMemcpyDeviceToDevice, s->stream));
+    s->step = step;
+    s->ready = true;
+    return TLB_OK;
+}

@@ -1,0 +1,253 @@
+// Device-side building blocks of the ternary free-energy LB step for gfx950:
+// lattice tables, the storage shift, and the per-node thermodynamics,
+// equilibria and BGK collision (Sec. III and IV of arXiv:1511.02155).
+//
+// Storage shift.  Populations are kept in HBM as deviations from a constant,
+// direction-symmetric reference r_{s,i}: f: w_i (the rest equilibrium at
+// rho = 1, v = 0); g: 0; k: psi_ref at i = 0, 0 otherwise (psi_ref = 1/3).
+// Propagation and half-way bounce-back map a uniform, direction-symmetric
+// field onto itself, and collision is affine, so the deviations obey the same
+// update; keeping O(1) constants out of the stored values keeps FP32 rounding
+// at the scale of the deviations.  Every moment and equilibrium below is
+// written directly in terms of the deviations.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tlb {
+
+constexpr double kPsiRef = 1.0 / 3.0;
+
+// ---------------------------------------------------------------------------
+// Lattices (velocity order documented in include/tlb.h).
+// ---------------------------------------------------------------------------
+struct D2Q9 {
+    static constexpr int Q = 9;
+    static constexpr int D = 2;
+    static constexpr int ex[9] = {0, 1, -1, 0, 0, 1, 1, -1, -1};
+    static constexpr int ey[9] = {0, 0, 0, 1, -1, 1, -1, 1, -1};
+    static constexpr int ez[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    static constexpr int opp[9] = {0, 2, 1, 4, 3, 8, 7, 6, 5};
+};
+
+struct D3Q19 {
+    static constexpr int Q = 19;
+    static constexpr int D = 3;
+    static constexpr int ex[19] = {0, 1, -1, 0, 0, 0, 0, 1, 1, -1, -1, 0, 0, 0, 0, 1, 1, -1, -1};
+    static constexpr int ey[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, 1, -1, 1, 1, -1, -1, 0, 0, 0, 0};
+    static constexpr int ez[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1};
+    static constexpr int opp[19] = {0, 2, 1, 4, 3, 6, 5, 10, 9, 8, 7, 14, 13, 12, 11, 18, 17, 16, 15};
+};
+
+template <class L>
+__host__ __device__ constexpr int e2(int i)
+{
+    return L::ex[i] * L::ex[i] + L::ey[i] * L::ey[i] + L::ez[i] * L::ez[i];
+}
+
+// Lattice weights: D2Q9 4/9, 1/9, 1/36; D3Q19 1/3, 1/18, 1/36 (Sec. IV).
+template <class L>
+__host__ __device__ constexpr double weight(int i)
+{
+    return L::D == 2 ? (e2<L>(i) == 0 ? 4.0 / 9.0 : e2<L>(i) == 1 ? 1.0 / 9.0 : 1.0 / 36.0)
+                     : (e2<L>(i) == 0 ? 1.0 / 3.0 : e2<L>(i) == 1 ? 1.0 / 18.0 : 1.0 / 36.0);
+}
+
+template <class L>
+__host__ __device__ constexpr int ecomp(int i, int a)
+{
+    return a == 0 ? L::ex[i] : a == 1 ? L::ey[i] : L::ez[i];
+}
+
+// Gradient weights w_i^{aa} (assigned by velocity class: D3Q19 values of
+// Sec. IV; D2Q9 values 1/9, -1/18, -1/72 satisfying the same second-moment
+// conditions) and w_i^{ab} = e_a e_b / 12 on diagonals.
+template <class L>
+__host__ __device__ constexpr double wdiag(int i, int a)
+{
+    return e2<L>(i) == 0 ? 0.0
+           : e2<L>(i) == 1
+               ? (ecomp<L>(i, a) != 0 ? (L::D == 2 ? 1.0 / 9.0 : 5.0 / 36.0)
+                                      : (L::D == 2 ? -1.0 / 18.0 : -1.0 / 9.0))
+               : (ecomp<L>(i, a) != 0 ? -1.0 / 72.0 : 1.0 / 36.0);
+}
+
+template <class L>
+__host__ __device__ constexpr double woff(int i, int a, int b)
+{
+    return e2<L>(i) == 2 ? ecomp<L>(i, a) * ecomp<L>(i, b) / 12.0 : 0.0;
+}
+
+// Storage reference r_{s,i} (see the header comment).
+template <class L>
+__host__ __device__ constexpr double ref(int s, int i)
+{
+    return s == 0 ? weight<L>(i) : (s == 2 && i == 0 ? kPsiRef : 0.0);
+}
+
+// ---------------------------------------------------------------------------
+// Parameters in the form the kernels use.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Phys {
+    T kappa[3];
+    T a2kappa[3];  // alpha^2 kappa_m
+    T omega[3];    // 1/tau for f, g, k
+    T gphi3, gpsi3;  // Gamma_phi / c_s^2, Gamma_psi / c_s^2
+};
+
+// Moments of one node from its (shifted) populations.
+template <typename T>
+struct Moments {
+    T drho;   // rho - 1
+    T jx, jy, jz;
+    T phi;
+    T dpsi;   // psi - psi_ref
+};
+
+template <class L, typename T>
+__device__ __forceinline__ Moments<T> moments(const T* f, const T* g, const T* k)
+{
+    Moments<T> m;
+    T r = 0, jx = 0, jy = 0, jz = 0, ph = 0, ps = 0;
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) {
+        r += f[i];
+        if (L::ex[i] == 1) jx += f[i];
+        if (L::ex[i] == -1) jx -= f[i];
+        if (L::ey[i] == 1) jy += f[i];
+        if (L::ey[i] == -1) jy -= f[i];
+        if (L::ez[i] == 1) jz += f[i];
+        if (L::ez[i] == -1) jz -= f[i];
+        ph += g[i];
+        ps += k[i];
+    }
+    m.drho = r;
+    m.jx = jx;
+    m.jy = jy;
+    m.jz = jz;
+    m.phi = ph;
+    m.dpsi = ps;
+    return m;
+}
+
+// Concentration deviations dC_m = C_m - 1/3 from the moments:
+// C1 = (rho + phi - psi)/2, C2 = (rho - phi - psi)/2, C3 = psi (Sec. II.C),
+// with rho = 1 + drho and psi = 1/3 + dpsi.
+template <typename T>
+__device__ __forceinline__ void conc_dev(const Moments<T>& m, T dc[3])
+{
+    dc[0] = T(0.5) * (m.drho + m.phi - m.dpsi);
+    dc[1] = T(0.5) * (m.drho - m.phi - m.dpsi);
+    dc[2] = m.dpsi;
+}
+
+// Chemical potentials mu_phi, mu_psi of Sec. III from dC_m and lap C_m.
+template <typename T>
+__device__ __forceinline__ void chem_potentials(const Phys<T>& P, const T dc[3], const T lC[3], T& mu_phi,
+                                                T& mu_psi)
+{
+    T mu[3];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        const T c = T(1.0 / 3.0) + dc[m];
+        mu[m] = P.kappa[m] * c * (T(1) - c) * (T(1) - T(2) * c) - P.a2kappa[m] * lC[m];
+    }
+    mu_phi = T(0.5) * (mu[0] - mu[1]);
+    mu_psi = mu[2] - T(0.5) * (mu[0] + mu[1]);
+}
+
+// Per-node collision.  Inputs: the node's shifted populations f, g, k (in
+// place -> post-collision), its moments, the concentration deviations dC,
+// their gradients gC[m][a] and Laplacians lC[m].
+//   mu_m   = kappa_m C_m (1 - C_m)(1 - 2 C_m) - alpha^2 kappa_m lap C_m
+//   mu_phi = (mu_1 - mu_2)/2,  mu_psi = mu_3 - (mu_1 + mu_2)/2          (Sec. III)
+//   p_b    = rho/3 + sum_m kappa_m/2 C_m^2 (1 - C_m)(1 - 3 C_m)        (Sec. III)
+//   Lambda = alpha^2 sum_m kappa_m C_m lap C_m
+//   T_ab   = alpha^2 sum_m kappa_m d_a C_m d_b C_m
+//   f_i^eq = w_i [ (p_b - Lambda)/c_s^2 + rho U_i ] + (1/c_s^2) sum_ab w_i^{ab} T_ab
+//   g_i^eq = w_i [ Gamma_phi mu_phi / c_s^2 + phi U_i ],  k_i^eq likewise (eq. eqdistfbinary)
+//   U_i    = e_i.v / c_s^2 + (e_i.v)^2 / (2 c_s^4) - v^2 / (2 c_s^2)
+//   rest populations from the mass constraints; BGK with 1/tau per species.
+template <class L, typename T>
+__device__ __forceinline__ void collide(const Phys<T>& P, const Moments<T>& mo, const T dc[3],
+                                        const T gC[3][3], const T lC[3], T* f, T* g, T* k)
+{
+    const T third = T(1.0 / 3.0);
+    T mu[3];
+    T pbx = mo.drho * third;  // p_b - 1/3 (the 1/3 is the reference pressure of the shifted f)
+    T lam = 0;
+    T Txx = 0, Tyy = 0, Tzz = 0, Txy = 0, Tyz = 0, Tzx = 0;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+        const T c = third + dc[m];
+        const T omc = T(1) - c;
+        mu[m] = P.kappa[m] * c * omc * (T(1) - T(2) * c) - P.a2kappa[m] * lC[m];
+        pbx += T(0.5) * P.kappa[m] * c * c * omc * (T(1) - T(3) * c);
+        lam += P.a2kappa[m] * c * lC[m];
+        const T gx = gC[m][0], gy = gC[m][1], gz = gC[m][2];
+        Txx += P.a2kappa[m] * gx * gx;
+        Tyy += P.a2kappa[m] * gy * gy;
+        Txy += P.a2kappa[m] * gx * gy;
+        if (L::D == 3) {
+            Tzz += P.a2kappa[m] * gz * gz;
+            Tyz += P.a2kappa[m] * gy * gz;
+            Tzx += P.a2kappa[m] * gz * gx;
+        }
+    }
+    const T mu_phi = T(0.5) * (mu[0] - mu[1]);
+    const T mu_psi = mu[2] - T(0.5) * (mu[0] + mu[1]);
+
+    const T rho = T(1) + mo.drho;
+    const T irho = T(1) / rho;
+    const T vx = mo.jx * irho, vy = mo.jy * irho, vz = (L::D == 3) ? mo.jz * irho : T(0);
+    const T psi = T(kPsiRef) + mo.dpsi;
+    const T vv = vx * vx + vy * vy + vz * vz;
+
+    const T A = T(3) * (pbx - lam);
+    const T Bp = P.gphi3 * mu_phi;
+    const T Bk = P.gpsi3 * mu_psi;
+    const T wf = P.omega[0], wg = P.omega[1], wk = P.omega[2];
+
+    // i > 0: equilibrium and relaxation in place; the rest population last,
+    // from the mass constraints.
+    T sf = 0, sg = 0, sk = 0;
+#pragma unroll
+    for (int i = 1; i < L::Q; ++i) {
+        const T w = T(weight<L>(i));
+        const T ev = T(L::ex[i]) * vx + T(L::ey[i]) * vy + T(L::ez[i]) * vz;
+        const T U = T(3) * ev + T(4.5) * ev * ev - T(1.5) * vv;
+        T G = T(3 * wdiag<L>(i, 0)) * Txx + T(3 * wdiag<L>(i, 1)) * Tyy +
+              T(3 * woff<L>(i, 0, 1)) * Txy;
+        if (L::D == 3)
+            G += T(3 * wdiag<L>(i, 2)) * Tzz + T(3 * woff<L>(i, 1, 2)) * Tyz +
+                 T(3 * woff<L>(i, 2, 0)) * Tzx;
+        const T feq = w * (A + rho * U) + G;
+        const T geq = w * (Bp + mo.phi * U);
+        const T keq = w * (Bk + psi * U);
+        sf += feq;
+        sg += geq;
+        sk += keq;
+        f[i] += wf * (feq - f[i]);
+        g[i] += wg * (geq - g[i]);
+        k[i] += wk * (keq - k[i]);
+    }
+    f[0] += wf * ((mo.drho - sf) - f[0]);
+    g[0] += wg * ((mo.phi - sg) - g[0]);
+    k[0] += wk * ((mo.dpsi - sk) - k[0]);
+}
+
+// Equilibrium populations (shifted) of given fields; used by initialisation.
+template <class L, typename T>
+__device__ __forceinline__ void equilibrium(const Phys<T>& P, const Moments<T>& mo, const T dc[3],
+                                            const T gC[3][3], const T lC[3], T* f, T* g, T* k)
+{
+    Phys<T> Q = P;
+    Q.omega[0] = Q.omega[1] = Q.omega[2] = T(1);
+#pragma unroll
+    for (int i = 0; i < L::Q; ++i) f[i] = g[i] = k[i] = T(0);
+    collide<L, T>(Q, mo, dc, gC, lC, f, g, k);
+}
+
+}  // namespace tlb

@@ -1,0 +1,71 @@
+// Internal interface between the C ABI layer and the kernel translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "tlb_device.hpp"
+
+namespace tlb {
+
+// Arguments of the fused step kernels (passed by value).
+template <typename T>
+struct StepArgs {
+    const T* __restrict__ src;  // state u_t = post-collision populations of step t-1 [3][Q][N]
+    T* __restrict__ dst;        // u_{t+1}
+    const T* __restrict__ wet;  // [2][3][nx*nz] h_m / (alpha^2 kappa_m), or nullptr
+    int nx, ny, nz;
+    int walls;
+    int64_t N;
+    int chunk;    // rows (D2Q9) / planes (D3Q19) swept per workgroup
+    int nchunks;  // chunks along the sweep axis
+    int ntx, nty; // strips (D2Q9: ntx) / tiles (D3Q19: ntx * nty) across the sweep
+    int nitems;   // ntx * nty * nchunks
+    Phys<T> P;
+};
+
+// Map a hardware workgroup id onto a logical work item so that each XCD
+// (workgroups are dispatched round-robin over the 8 XCDs) receives a
+// contiguous range of items, which share halo rows through that XCD's L2.
+__device__ __forceinline__ int xcd_item(int b, int G)
+{
+    const int q = G >> 3, r = G & 7;
+    const int k = b & 7, j = b >> 3;
+    return k * q + (k < r ? k : r) + j;
+}
+
+template <typename T>
+hipError_t launch_step2d(const StepArgs<T>& a, int width, int hold, hipStream_t s);
+template <typename T>
+hipError_t launch_step3d(const StepArgs<T>& a, int width, int height, int hold, hipStream_t s);
+
+// Auxiliary kernels (tlb_aux.hip).
+struct AuxGeom {
+    int lattice;  // 0 D2Q9, 1 D3Q19
+    int nx, ny, nz, walls;
+    int64_t N;
+};
+
+template <typename T, typename TIn>
+hipError_t launch_init(const AuxGeom& g, const Phys<T>& P, const TIn* C, const TIn* u, const T* wet,
+                       T* state, hipStream_t s);
+template <typename T>
+hipError_t launch_fields(const AuxGeom& g, const Phys<T>& P, const T* state, const T* wet,
+                         T* fields /*[11][N] deviations*/, hipStream_t s);
+template <typename T, typename TOut>
+hipError_t launch_export_field(const AuxGeom& g, const T* fields, int which, TOut* out, hipStream_t s);
+template <typename T, typename TOut>
+hipError_t launch_get_pops(const AuxGeom& g, const T* state, int species, TOut* out, hipStream_t s);
+template <typename T, typename TIn>
+hipError_t launch_set_pops(const AuxGeom& g, const TIn* in, int species, T* state, hipStream_t s);
+template <typename T>
+hipError_t launch_diag(const AuxGeom& g, const T* state, double* partial, int nblocks, double* out,
+                       hipStream_t s);
+template <typename T, typename TIn>
+hipError_t launch_wet(int n, const TIn* h, double inv_a2k0, double inv_a2k1, double inv_a2k2, T* wet,
+                      hipStream_t s);
+
+constexpr int kDiagBlocks = 1024;
+constexpr int kDiagSlots = 8;  // mass[3], momentum[3], max|v|, nonfinite
+
+}  // namespace tlb

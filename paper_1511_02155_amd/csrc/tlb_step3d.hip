@@ -1,0 +1,260 @@
+// Fused D3Q19 ternary LB step for gfx950 (same stages as the D2Q9 kernel).
+//
+// Work decomposition.  A workgroup of BX x BY lanes owns a BX x BY tile of
+// (x, y) columns and sweeps `chunk` z-planes.  Each lane keeps its own
+// column's dC_m for planes z-1, z, z+1 in registers; in-plane neighbours come
+// from a double-buffered LDS plane of (BX+2) x (BY+2) entries whose one-node
+// ring is filled by the first 2(BX+BY)+4 lanes in an extra pull.  Ghost
+// entries beyond a y wall are the adjacent fluid node plus h_m/(alpha^2
+// kappa_m).  Per plane and component a lane derives from LDS
+//   A  = sum of the 4 in-plane axis neighbours,  Dx, Dy = axis differences,
+//   E  = sum of the 4 in-plane diagonals,
+//   Fx = sum over y+-1 of [C(x+1) - C(x-1)],  Fy = sum over x+-1 of [C(y+1) - C(y-1)],
+// and the D3Q19 isotropic stencils become
+//   d_x C = Dx_z/6 + (Fx_z + Dx_{z-1} + Dx_{z+1})/12      (d_y likewise)
+//   d_z C = (C_{z+1} - C_{z-1})/6 + (A_{z+1} - A_{z-1})/12
+//   lap C = (A_z + C_{z-1} + C_{z+1})/3 + (E_z + A_{z-1} + A_{z+1})/6 - 4 C_z.
+// HBM traffic per node and step: 57 values read + 57 written; the ring and
+// the chunk-end planes are re-read from L2.
+#include "tlb_internal.hpp"
+
+namespace tlb {
+
+using L19 = D3Q19;
+
+template <typename T>
+__device__ __forceinline__ void pull3d(const StepArgs<T>& A, int x, int y, int z, T* f, T* g, T* k)
+{
+    const int nx = A.nx, ny = A.ny, nz = A.nz;
+    const int xm = (x == 0) ? nx - 1 : x - 1;
+    const int xp = (x == nx - 1) ? 0 : x + 1;
+    const int ym = (y == 0) ? ny - 1 : y - 1;
+    const int yp = (y == ny - 1) ? 0 : y + 1;
+    const int zm = (z == 0) ? nz - 1 : z - 1;
+    const int zp = (z == nz - 1) ? 0 : z + 1;
+    const bool blo = A.walls && y == 0;
+    const bool bhi = A.walls && y == ny - 1;
+    const uint32_t N = (uint32_t)A.N;
+    const uint32_t n0 = (uint32_t)x + (uint32_t)nx * ((uint32_t)y + (uint32_t)ny * z);
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+        const T* __restrict__ b = A.src + (int64_t)s * 19 * A.N;
+        T* out = (s == 0) ? f : (s == 1) ? g : k;
+#pragma unroll
+        for (int i = 0; i < 19; ++i) {
+            const int ex = L19::ex[i], ey = L19::ey[i], ez = L19::ez[i];
+            const bool bb = (ey == 1) ? blo : (ey == -1) ? bhi : false;
+            const int xs = ex == 0 ? x : (ex == 1 ? xm : xp);
+            const int ys = ey == 0 ? y : (ey == 1 ? ym : yp);
+            const int zs = ez == 0 ? z : (ez == 1 ? zm : zp);
+            const uint32_t off = bb ? (uint32_t)L19::opp[i] * N + n0
+                                    : (uint32_t)i * N + (uint32_t)xs + (uint32_t)nx * ((uint32_t)ys + (uint32_t)ny * zs);
+            out[i] = b[off];
+        }
+    }
+}
+
+template <typename T>
+struct PlaneLite {
+    T c[3], A[3], Dx[3], Dy[3];
+};
+template <typename T>
+struct PlaneFull {
+    T c[3], A[3], Dx[3], Dy[3], E[3], Fx[3], Fy[3];
+};
+
+// HOLD selects between keeping the pulled populations of plane z+1 in
+// registers and pulling plane z again (from cache) when it is collided.
+template <typename T, int BX, int BY, bool HOLD>
+__global__ __launch_bounds__(BX* BY) void k_step3d(StepArgs<T> A)
+{
+    __shared__ T lds[2][3][BY + 2][BX + 2];
+
+    const int item = xcd_item(blockIdx.x, A.nitems);
+    const int tile = item / A.nchunks;
+    const int chunk = item - tile * A.nchunks;
+    const int tyi = tile / A.ntx;
+    const int txi = tile - tyi * A.ntx;
+    const int x0 = txi * BX, y0 = tyi * BY;
+    const int ax = min(BX, A.nx - x0), ay = min(BY, A.ny - y0);
+    const int t = threadIdx.x;
+    const int tx = t % BX, ty = t / BX;
+    const bool active = tx < ax && ty < ay;
+    const int x = x0 + min(tx, ax - 1);
+    const int y = y0 + min(ty, ay - 1);
+    const int z0 = chunk * A.chunk;
+    const int z1 = min(z0 + A.chunk, A.nz);
+
+    // Ring node handled by this lane (if any), in tile coordinates.
+    const int nh = 2 * (ax + 2) + 2 * ay;
+    const bool ring = t < nh;
+    int hx, hy;
+    if (t < ax + 2) {
+        hy = -1;
+        hx = t - 1;
+    } else if (t < 2 * (ax + 2)) {
+        hy = ay;
+        hx = t - (ax + 2) - 1;
+    } else {
+        const int j = t - 2 * (ax + 2);
+        hx = (j & 1) ? ax : -1;
+        hy = j >> 1;
+    }
+    int gx = x0 + hx;
+    gx = gx < 0 ? gx + A.nx : (gx >= A.nx ? gx - A.nx : gx);
+    int gy = y0 + hy;
+    int gwall = -1;  // ghost of wall 0 / 1, or -1 for a fluid node
+    if (A.walls) {
+        if (gy < 0) {
+            gwall = 0;
+            gy = 0;
+        } else if (gy >= A.ny) {
+            gwall = 1;
+            gy = A.ny - 1;
+        }
+    } else {
+        gy = gy < 0 ? gy + A.ny : (gy >= A.ny ? gy - A.ny : gy);
+    }
+    const uint32_t nxz = (uint32_t)A.nx * A.nz;
+
+    T fb[19], gb[19], kb[19];  // HOLD: populations of plane z
+    T fc[19], gc[19], kc[19];  // pull buffer (plane z + 1)
+    PlaneLite<T> pa;
+    PlaneFull<T> pb, pc;
+    int buf = 0;
+
+    auto plane = [&](int z, PlaneFull<T>& p) {
+        pull3d<T>(A, x, y, z, fc, gc, kc);
+        const Moments<T> mo = moments<L19, T>(fc, gc, kc);
+        conc_dev<T>(mo, p.c);
+        if (active) {
+#pragma unroll
+            for (int m = 0; m < 3; ++m) lds[buf][m][ty + 1][tx + 1] = p.c[m];
+        }
+        if (ring) {
+            T hf[19], hg[19], hk[19];
+            pull3d<T>(A, gx, gy, z, hf, hg, hk);
+            Moments<T> hm = moments<L19, T>(hf, hg, hk);
+            T hc[3];
+            conc_dev<T>(hm, hc);
+            if (gwall >= 0) {
+                const T* __restrict__ wt = A.wet + (size_t)gwall * 3 * nxz + gx + (uint32_t)A.nx * z;
+#pragma unroll
+                for (int m = 0; m < 3; ++m) hc[m] += wt[m * nxz];
+            }
+#pragma unroll
+            for (int m = 0; m < 3; ++m) lds[buf][m][hy + 1][hx + 1] = hc[m];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            const T l = lds[buf][m][ty + 1][tx];
+            const T r = lds[buf][m][ty + 1][tx + 2];
+            const T d = lds[buf][m][ty][tx + 1];
+            const T u = lds[buf][m][ty + 2][tx + 1];
+            const T ld = lds[buf][m][ty][tx];
+            const T rd = lds[buf][m][ty][tx + 2];
+            const T lu = lds[buf][m][ty + 2][tx];
+            const T ru = lds[buf][m][ty + 2][tx + 2];
+            p.A[m] = (l + r) + (d + u);
+            p.Dx[m] = r - l;
+            p.Dy[m] = u - d;
+            p.E[m] = (ld + rd) + (lu + ru);
+            p.Fx[m] = (rd + ru) - (ld + lu);
+            p.Fy[m] = (lu + ru) - (ld + rd);
+        }
+        buf ^= 1;
+    };
+
+    auto hold = [&]() {
+        if constexpr (HOLD) {
+#pragma unroll
+            for (int i = 0; i < 19; ++i) {
+                fb[i] = fc[i];
+                gb[i] = gc[i];
+                kb[i] = kc[i];
+            }
+        }
+    };
+
+    // Prologue: planes z0 - 1 and z0.
+    {
+        const int za = (z0 == 0) ? A.nz - 1 : z0 - 1;
+        plane(za, pc);
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            pa.c[m] = pc.c[m];
+            pa.A[m] = pc.A[m];
+            pa.Dx[m] = pc.Dx[m];
+            pa.Dy[m] = pc.Dy[m];
+        }
+        plane(z0, pb);
+        hold();
+    }
+
+    const uint32_t N = (uint32_t)A.N;
+    for (int z = z0; z < z1; ++z) {
+        const int zn = (z + 1 == A.nz) ? 0 : z + 1;
+        plane(zn, pc);
+
+        T gC[3][3], lC[3];
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            gC[m][0] = pb.Dx[m] * T(1.0 / 6.0) + (pb.Fx[m] + pa.Dx[m] + pc.Dx[m]) * T(1.0 / 12.0);
+            gC[m][1] = pb.Dy[m] * T(1.0 / 6.0) + (pb.Fy[m] + pa.Dy[m] + pc.Dy[m]) * T(1.0 / 12.0);
+            gC[m][2] = (pc.c[m] - pa.c[m]) * T(1.0 / 6.0) + (pc.A[m] - pa.A[m]) * T(1.0 / 12.0);
+            lC[m] = (pb.A[m] + pa.c[m] + pc.c[m]) * T(1.0 / 3.0) + (pb.E[m] + pa.A[m] + pc.A[m]) * T(1.0 / 6.0) -
+                    pb.c[m] * T(4);
+        }
+        if constexpr (!HOLD) pull3d<T>(A, x, y, z, fb, gb, kb);
+        const Moments<T> mb = moments<L19, T>(fb, gb, kb);
+        collide<L19, T>(A.P, mb, pb.c, gC, lC, fb, gb, kb);
+
+        if (active) {
+            T* __restrict__ dst = A.dst;
+            const uint32_t n0 = (uint32_t)x + (uint32_t)A.nx * ((uint32_t)y + (uint32_t)A.ny * z);
+#pragma unroll
+            for (int i = 0; i < 19; ++i) {
+                dst[(uint32_t)i * N + n0] = fb[i];
+                dst[(int64_t)19 * A.N + (uint32_t)i * N + n0] = gb[i];
+                dst[(int64_t)38 * A.N + (uint32_t)i * N + n0] = kb[i];
+            }
+        }
+
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            pa.c[m] = pb.c[m];
+            pa.A[m] = pb.A[m];
+            pa.Dx[m] = pb.Dx[m];
+            pa.Dy[m] = pb.Dy[m];
+        }
+        pb = pc;
+        hold();
+    }
+}
+
+template <typename T>
+hipError_t launch_step3d(const StepArgs<T>& a, int width, int height, int hold, hipStream_t s)
+{
+    dim3 grid(a.nitems);
+#define TLB_L3(BX, BY, H)                                                              \
+    if (width == BX && height == BY && (hold != 0) == H) {                             \
+        hipLaunchKernelGGL((k_step3d<T, BX, BY, H>), grid, dim3(BX * BY), 0, s, a);    \
+        return hipGetLastError();                                                      \
+    }
+    TLB_L3(32, 8, false)
+    TLB_L3(64, 4, false)
+    TLB_L3(32, 8, true)
+    TLB_L3(64, 4, true)
+    if constexpr (sizeof(T) == 4) {
+        TLB_L3(32, 16, false)
+        TLB_L3(64, 8, false)
+    }
+#undef TLB_L3
+    return hipErrorInvalidValue;
+}
+
+template hipError_t launch_step3d<float>(const StepArgs<float>&, int, int, int, hipStream_t);
+template hipError_t launch_step3d<double>(const StepArgs<double>&, int, int, int, hipStream_t);
+
+}  // namespace tlb

@@ -1,0 +1,250 @@
+"""ctypes binding of libtlb (the C ABI in include/tlb.h).
+
+The functions below carry the C names and only marshal arguments: every
+step of the lattice Boltzmann update runs in the HIP kernels of libtlb.so.
+Importing this module loads the library and raises ``ImportError`` when it
+has not been built (``python -m paper_1511_02155_amd.build``); there is no
+fallback implementation.
+
+``Sim`` wraps one ``tlb_sim*`` for convenience; torch tensors on the GPU can
+be passed to the ``*_dev`` calls through ``tensor.data_ptr()``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtlb.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1511_02155_amd.build`")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+TLB_OK, TLB_EINVAL, TLB_ENOMEM, TLB_EHIP, TLB_ENAN, TLB_ESTATE = 0, -1, -2, -3, -4, -5
+TLB_D2Q9, TLB_D3Q19 = 0, 1
+TLB_F32, TLB_F64 = 0, 1
+FIELDS = ("C1", "C2", "C3", "rho", "phi", "psi", "ux", "uy", "uz", "mu_phi", "mu_psi")
+FIELD_INDEX = {name: i for i, name in enumerate(FIELDS)}
+
+# Every symbol declared in include/tlb.h.
+EXPORTS = (
+    "tlb_status_str", "tlb_last_hip_error", "tlb_version", "tlb_create", "tlb_destroy",
+    "tlb_get_params", "tlb_set_wetting", "tlb_init_equilibrium", "tlb_step", "tlb_set_check_every",
+    "tlb_get_field", "tlb_get_populations", "tlb_set_populations", "tlb_diagnostics", "tlb_get_step",
+    "tlb_synchronize", "tlb_get_stream", "tlb_init_equilibrium_dev", "tlb_get_field_dev",
+    "tlb_get_populations_dev", "tlb_set_populations_dev", "tlb_set_wetting_dev", "tlb_set_launch",
+    "tlb_get_launch", "tlb_bytes_per_node", "tlb_state_bytes", "tlb_save_state", "tlb_load_state",
+    "tlb_save_state_dev", "tlb_load_state_dev",
+)
+
+
+class tlb_params(ctypes.Structure):
+    _fields_ = [
+        ("lattice", ctypes.c_int32), ("prec", ctypes.c_int32),
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("walls_y", ctypes.c_int32),
+        ("kappa", ctypes.c_double * 3), ("alpha", ctypes.c_double),
+        ("tau_f", ctypes.c_double), ("tau_g", ctypes.c_double), ("tau_k", ctypes.c_double),
+        ("gamma_phi", ctypes.c_double), ("gamma_psi", ctypes.c_double),
+    ]
+
+
+class tlb_diag(ctypes.Structure):
+    _fields_ = [
+        ("mass", ctypes.c_double * 3), ("momentum", ctypes.c_double * 3),
+        ("max_speed", ctypes.c_double), ("nonfinite", ctypes.c_int64), ("step", ctypes.c_int64),
+    ]
+
+
+class tlb_launch(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32), ("chunk", ctypes.c_int32),
+                ("hold", ctypes.c_int32)]
+
+
+_vp = ctypes.c_void_p
+_dp = ctypes.POINTER(ctypes.c_double)
+_P = ctypes.POINTER(tlb_params)
+
+
+def _sig(name, res, args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = args
+    return f
+
+
+tlb_status_str = _sig("tlb_status_str", ctypes.c_char_p, [ctypes.c_int])
+tlb_last_hip_error = _sig("tlb_last_hip_error", ctypes.c_int, [])
+tlb_version = _sig("tlb_version", ctypes.c_int, [])
+tlb_create = _sig("tlb_create", ctypes.c_int, [_P, _vp, ctypes.POINTER(_vp)])
+tlb_destroy = _sig("tlb_destroy", ctypes.c_int, [_vp])
+tlb_get_params = _sig("tlb_get_params", ctypes.c_int, [_vp, _P])
+tlb_set_wetting = _sig("tlb_set_wetting", ctypes.c_int, [_vp, ctypes.c_int, _dp])
+tlb_init_equilibrium = _sig("tlb_init_equilibrium", ctypes.c_int, [_vp, _dp, _dp])
+tlb_step = _sig("tlb_step", ctypes.c_int, [_vp, ctypes.c_int64])
+tlb_set_check_every = _sig("tlb_set_check_every", ctypes.c_int, [_vp, ctypes.c_int64])
+tlb_get_field = _sig("tlb_get_field", ctypes.c_int, [_vp, ctypes.c_int, _dp])
+tlb_get_populations = _sig("tlb_get_populations", ctypes.c_int, [_vp, ctypes.c_int, _dp])
+tlb_set_populations = _sig("tlb_set_populations", ctypes.c_int, [_vp, ctypes.c_int, _dp])
+tlb_diagnostics = _sig("tlb_diagnostics", ctypes.c_int, [_vp, ctypes.POINTER(tlb_diag)])
+tlb_get_step = _sig("tlb_get_step", ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int64)])
+tlb_synchronize = _sig("tlb_synchronize", ctypes.c_int, [_vp])
+tlb_get_stream = _sig("tlb_get_stream", _vp, [_vp])
+tlb_init_equilibrium_dev = _sig("tlb_init_equilibrium_dev", ctypes.c_int, [_vp, _vp, _vp])
+tlb_get_field_dev = _sig("tlb_get_field_dev", ctypes.c_int, [_vp, ctypes.c_int, _vp])
+tlb_get_populations_dev = _sig("tlb_get_populations_dev", ctypes.c_int, [_vp, ctypes.c_int, _vp])
+tlb_set_populations_dev = _sig("tlb_set_populations_dev", ctypes.c_int, [_vp, ctypes.c_int, _vp])
+tlb_set_wetting_dev = _sig("tlb_set_wetting_dev", ctypes.c_int, [_vp, ctypes.c_int, _vp])
+tlb_set_launch = _sig("tlb_set_launch", ctypes.c_int, [_vp, ctypes.POINTER(tlb_launch)])
+tlb_get_launch = _sig("tlb_get_launch", ctypes.c_int, [_vp, ctypes.POINTER(tlb_launch)])
+tlb_bytes_per_node = _sig("tlb_bytes_per_node", ctypes.c_double, [_vp])
+tlb_state_bytes = _sig("tlb_state_bytes", ctypes.c_int64, [_vp])
+tlb_save_state = _sig("tlb_save_state", ctypes.c_int, [_vp, _vp, ctypes.POINTER(ctypes.c_int64)])
+tlb_load_state = _sig("tlb_load_state", ctypes.c_int, [_vp, _vp, ctypes.c_int64])
+tlb_save_state_dev = _sig("tlb_save_state_dev", ctypes.c_int, [_vp, _vp])
+tlb_load_state_dev = _sig("tlb_load_state_dev", ctypes.c_int, [_vp, _vp, ctypes.c_int64])
+
+
+class TLBError(RuntimeError):
+    def __init__(self, code, what):
+        msg = tlb_status_str(code).decode()
+        if code == TLB_EHIP:
+            msg += f" (hip error {tlb_last_hip_error()})"
+        super().__init__(f"{what}: {msg} [{code}]")
+        self.code = code
+
+
+def check(code, what="tlb"):
+    if code != TLB_OK:
+        raise TLBError(code, what)
+    return code
+
+
+def _arr(a, n=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if n is not None and a.size != n:
+        raise ValueError(f"expected {n} values, got {a.size}")
+    return a
+
+
+def make_params(lattice, nx, ny, nz=1, prec=TLB_F64, walls_y=0, kappa=(0.01, 0.01, 0.01), alpha=1.0,
+                tau_f=1.0, tau_g=1.0, tau_k=1.0, gamma_phi=1.0, gamma_psi=1.0, **_ignored):
+    p = tlb_params()
+    p.lattice, p.prec, p.nx, p.ny, p.nz, p.walls_y = lattice, prec, nx, ny, nz, walls_y
+    for m in range(3):
+        p.kappa[m] = kappa[m]
+    p.alpha, p.tau_f, p.tau_g, p.tau_k = alpha, tau_f, tau_g, tau_k
+    p.gamma_phi, p.gamma_psi = gamma_phi, gamma_psi
+    return p
+
+
+class Sim:
+    """One simulation (owns a tlb_sim*)."""
+
+    def __init__(self, params: tlb_params, stream=None):
+        self._h = _vp()
+        check(tlb_create(ctypes.byref(params), stream, ctypes.byref(self._h)), "tlb_create")
+        self.params = params
+        self.Q = 9 if params.lattice == TLB_D2Q9 else 19
+        self.D = 2 if params.lattice == TLB_D2Q9 else 3
+        self.N = params.nx * params.ny * params.nz
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            tlb_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_wetting(self, wall, h):
+        h = _arr(h, 3 * self.params.nx * self.params.nz)
+        check(tlb_set_wetting(self._h, wall, h.ctypes.data_as(_dp)), "tlb_set_wetting")
+
+    def set_wetting_both(self, h):
+        """h: [2][3][nx*nz] (wall 0 = below y=0, wall 1 = above y=ny-1)."""
+        h = _arr(h).reshape(2, -1)
+        self.set_wetting(0, h[0])
+        self.set_wetting(1, h[1])
+
+    def init_equilibrium(self, C, u=None):
+        C = _arr(C, 3 * self.N)
+        up = None
+        if u is not None:
+            u = _arr(u, self.D * self.N)
+            up = u.ctypes.data_as(_dp)
+        check(tlb_init_equilibrium(self._h, C.ctypes.data_as(_dp), up), "tlb_init_equilibrium")
+
+    def step(self, n):
+        check(tlb_step(self._h, int(n)), "tlb_step")
+
+    def synchronize(self):
+        check(tlb_synchronize(self._h), "tlb_synchronize")
+
+    def field(self, which):
+        idx = FIELD_INDEX[which] if isinstance(which, str) else int(which)
+        out = np.empty(self.N)
+        check(tlb_get_field(self._h, idx, out.ctypes.data_as(_dp)), "tlb_get_field")
+        return out
+
+    def fields(self):
+        return {name: self.field(i) for i, name in enumerate(FIELDS)}
+
+    def populations(self, species):
+        out = np.empty((self.Q, self.N))
+        check(tlb_get_populations(self._h, species, out.ctypes.data_as(_dp)), "tlb_get_populations")
+        return out
+
+    def all_populations(self):
+        return np.stack([self.populations(s) for s in range(3)])
+
+    def set_populations(self, species, pop):
+        pop = _arr(pop, self.Q * self.N)
+        check(tlb_set_populations(self._h, species, pop.ctypes.data_as(_dp)), "tlb_set_populations")
+
+    def diagnostics(self, allow_nan=False):
+        d = tlb_diag()
+        rc = tlb_diagnostics(self._h, ctypes.byref(d))
+        if rc != TLB_OK and not (allow_nan and rc == TLB_ENAN):
+            check(rc, "tlb_diagnostics")
+        return dict(mass=list(d.mass), momentum=list(d.momentum), max_speed=d.max_speed,
+                    nonfinite=d.nonfinite, step=d.step)
+
+    def set_launch(self, width, height=1, chunk=0, hold=0):
+        l = tlb_launch(width, height, chunk, hold)
+        check(tlb_set_launch(self._h, ctypes.byref(l)), "tlb_set_launch")
+
+    def launch(self):
+        l = tlb_launch()
+        check(tlb_get_launch(self._h, ctypes.byref(l)), "tlb_get_launch")
+        return dict(width=l.width, height=l.height, chunk=l.chunk, hold=l.hold)
+
+    def save_state(self):
+        """Raw state bytes and step count (bitwise resume with load_state)."""
+        buf = np.empty(tlb_state_bytes(self._h), dtype=np.uint8)
+        st = ctypes.c_int64()
+        check(tlb_save_state(self._h, buf.ctypes.data_as(_vp), ctypes.byref(st)), "tlb_save_state")
+        return buf, st.value
+
+    def load_state(self, buf, step):
+        buf = np.ascontiguousarray(buf, dtype=np.uint8)
+        if buf.size != tlb_state_bytes(self._h):
+            raise ValueError("state size mismatch")
+        check(tlb_load_state(self._h, buf.ctypes.data_as(_vp), int(step)), "tlb_load_state")
+
+    def bytes_per_node(self):
+        return tlb_bytes_per_node(self._h)
+
+    def stream(self):
+        return tlb_get_stream(self._h)

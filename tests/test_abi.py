@@ -1,0 +1,92 @@
+"""The C ABI library loads and exports every symbol include/tlb.h declares.
+
+No test here launches a kernel: argument validation happens before any HIP
+call, so the invalid-argument paths run without a GPU.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tlb.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(tlb_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_header_declares_expected_entry_points():
+    names = _declared()
+    for must in ("tlb_create", "tlb_destroy", "tlb_step", "tlb_init_equilibrium", "tlb_get_field",
+                 "tlb_set_wetting", "tlb_diagnostics", "tlb_get_populations", "tlb_set_populations"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1511_02155_amd import tlb
+
+    lib = ctypes.CDLL(tlb.LIB_PATH)
+    declared = _declared()
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert sorted(tlb.EXPORTS) == declared
+    out = subprocess.run(["nm", "-D", "--defined-only", tlb.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\b(tlb_[a-z0-9_]+)\b", out))
+    assert set(declared) <= exported
+
+
+def test_library_is_built_for_gfx950():
+    from paper_1511_02155_amd import tlb
+
+    blob = open(tlb.LIB_PATH, "rb").read()
+    assert b"amdgcn-amd-amdhsa--gfx950" in blob
+
+
+def test_status_strings():
+    from paper_1511_02155_amd import tlb
+
+    assert tlb.tlb_status_str(0) == b"ok"
+    assert tlb.tlb_status_str(-1) == b"invalid argument"
+    assert tlb.tlb_version() >= 100
+
+
+@pytest.mark.parametrize("bad", [
+    dict(tau_f=0.5), dict(tau_g=0.4), dict(tau_k=-1.0), dict(kappa=(0.01, 0.0, 0.01)),
+    dict(kappa=(0.01, 0.01, -0.1)), dict(alpha=0.0), dict(nx=2), dict(ny=2), dict(nz=2),
+    dict(prec=7), dict(lattice=5), dict(walls_y=2), dict(alpha=float("nan")),
+])
+def test_create_rejects_invalid_parameters(bad):
+    from paper_1511_02155_amd import tlb
+
+    kw = dict(lattice=tlb.TLB_D2Q9, nx=8, ny=8, nz=1)
+    kw.update(bad)
+    if "nz" in bad:
+        kw["lattice"] = tlb.TLB_D3Q19
+    p = tlb.make_params(**kw)
+    h = ctypes.c_void_p()
+    assert tlb.tlb_create(ctypes.byref(p), None, ctypes.byref(h)) == tlb.TLB_EINVAL
+    assert not h.value
+
+
+def test_create_rejects_lattices_beyond_32bit_offsets():
+    from paper_1511_02155_amd import tlb
+
+    p = tlb.make_params(tlb.TLB_D3Q19, 1024, 1024, 256, prec=tlb.TLB_F32)  # 19 * 2^28 > 2^32
+    h = ctypes.c_void_p()
+    assert tlb.tlb_create(ctypes.byref(p), None, ctypes.byref(h)) == tlb.TLB_EINVAL
+
+
+def test_null_handles_are_rejected():
+    from paper_1511_02155_amd import tlb
+
+    assert tlb.tlb_step(None, 1) == tlb.TLB_EINVAL
+    assert tlb.tlb_destroy(None) == tlb.TLB_EINVAL
+    assert tlb.tlb_get_field(None, 0, None) == tlb.TLB_EINVAL
+    assert tlb.tlb_bytes_per_node(None) == 0.0

@@ -1,0 +1,313 @@
+"""GPU (HIP, through the C ABI) against the FP64 CPU oracle on the same seeded inputs.
+
+Tolerances: FP64 max |gpu - oracle| <= 1e-12 * max |oracle| per population
+species and per concentration field; FP32 max |C_gpu - C_oracle| <= 1e-5
+absolute on the concentrations after the stated step count.
+"""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1511_02155_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+F64_REL = 1e-12
+F32_ABS = 1e-5
+
+
+def _note(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def tlb():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.init()
+    from paper_1511_02155_amd import tlb as t
+
+    return t
+
+
+def _oparams(orc, w):
+    keys = ("lattice", "nx", "ny", "nz", "walls_y", "kappa", "alpha", "tau_f", "tau_g", "tau_k",
+            "gamma_phi", "gamma_psi")
+    return orc.Params(**{k: w[k] for k in keys})
+
+
+def _gsim(tlb, w, prec, launch=None):
+    p = tlb.make_params(prec=prec, **{k: v for k, v in w.items() if k in (
+        "lattice", "nx", "ny", "nz", "walls_y", "kappa", "alpha", "tau_f", "tau_g", "tau_k", "gamma_phi",
+        "gamma_psi")})
+    s = tlb.Sim(p)
+    if launch:
+        s.set_launch(**launch)
+    return s
+
+
+def _run_both(tlb, orc, w, C, h, steps, prec, launch=None):
+    _note(f"{w.get('name', 'case')} prec={prec} steps={steps} launch={launch}")
+    p = _oparams(orc, w)
+    pop = orc.init_equilibrium(p, C, None, h)
+    orc.step(p, pop, steps, h)
+    s = _gsim(tlb, w, prec, launch)
+    if h is not None:
+        s.set_wetting_both(h)
+    s.init_equilibrium(C)
+    s.step(steps)
+    s.synchronize()
+    return p, pop, s
+
+
+def _compare_f64(orc, p, pop, h, s):
+    for sp in range(3):
+        g = s.populations(sp)
+        o = pop[sp]
+        err = np.abs(g - o).max()
+        assert err <= F64_REL * np.abs(o).max(), (sp, err)
+    Fo = orc.fields(p, pop, h)
+    for name in ("C1", "C2", "C3", "rho", "phi", "psi"):
+        err = np.abs(s.field(name) - Fo[name]).max()
+        assert err <= F64_REL * max(np.abs(Fo[name]).max(), 1e-300), (name, err)
+    vscale = np.abs(pop[0]).max()
+    for name in ("ux", "uy", "uz"):
+        assert np.abs(s.field(name) - Fo[name]).max() <= F64_REL * vscale, name
+    for name in ("mu_phi", "mu_psi"):
+        err = np.abs(s.field(name) - Fo[name]).max()
+        assert err <= 1e-11 * max(np.abs(Fo[name]).max(), 1e-6), (name, err)
+
+
+def _compare_f32(orc, p, pop, h, s, tol=F32_ABS):
+    Fo = orc.fields(p, pop, h)
+    for name in ("C1", "C2", "C3"):
+        err = np.abs(s.field(name) - Fo[name]).max()
+        assert err <= tol, (name, err)
+
+
+def _wet_case(nx, ny, nz=1, lattice=0, seed=1, walls=1, kappa=(0.012, 0.02, 0.016), tau=(1.0, 0.9, 0.8)):
+    M = 0.1
+    gp, gk = inputs.mobility_to_gamma(M, tau[1], tau[2])
+    w = dict(lattice=lattice, nx=nx, ny=ny, nz=nz, walls_y=walls, kappa=kappa, alpha=1.0, tau_f=tau[0],
+             tau_g=tau[1], tau_k=tau[2], gamma_phi=gp, gamma_psi=gk, name=f"wet_{lattice}_{nx}x{ny}x{nz}")
+    if lattice == 0:
+        C = inputs.sessile_drop(nx, ny, 0.35 * min(nx, ny), top_layer=0.75 * ny)
+    else:
+        C = inputs.spinodal(nx, ny, nz, delta=0.25, seed=seed)
+    h = inputs.random_h(nx, -0.004, 0.004, nz=nz, seed=seed + 100, bottom_only=False) if walls else None
+    return w, C, h
+
+
+# --------------------------------------------------------------------------
+# FP64 parity: 1e-12 relative
+# --------------------------------------------------------------------------
+
+def test_double_emulsion_64_fp64_1000_steps(tlb, orc):
+    """64x64 periodic double emulsion, FP64, 1000 steps (the small correctness workload)."""
+    w = inputs.double_emulsion_64()
+    C = w["C"]()
+    p, pop, s = _run_both(tlb, orc, w, C, None, w["steps"], tlb.TLB_F64)
+    _compare_f64(orc, p, pop, None, s)
+
+
+@pytest.mark.parametrize("nx,ny,width,chunk", [(70, 37, 64, 8), (131, 20, 128, 7), (300, 9, 256, 3),
+                                               (3, 3, 64, 1), (5, 64, 64, 64)])
+def test_d2q9_walls_wetting_ragged_fp64(tlb, orc, nx, ny, width, chunk):
+    """Walls with per-node wetting, ragged strips and chunks, minimum sizes."""
+    w, C, h = _wet_case(nx, ny)
+    for hold in (0, 1):
+        p, pop, s = _run_both(tlb, orc, w, C, h, 150, tlb.TLB_F64, dict(width=width, chunk=chunk, hold=hold))
+        _compare_f64(orc, p, pop, h, s)
+
+
+@pytest.mark.parametrize("walls", [0, 1])
+@pytest.mark.parametrize("dims,tile", [((37, 21, 13), (32, 8)), ((9, 70, 5), (64, 4)), ((3, 3, 3), (32, 8))])
+def test_d3q19_ragged_fp64(tlb, orc, dims, tile, walls):
+    nx, ny, nz = dims
+    w, C, h = _wet_case(nx, ny, nz, lattice=1, walls=walls)
+    for hold in (0, 1):
+        p, pop, s = _run_both(tlb, orc, w, C, h, 30, tlb.TLB_F64,
+                              dict(width=tile[0], height=tile[1], chunk=4, hold=hold))
+        _compare_f64(orc, p, pop, h, s)
+
+
+# --------------------------------------------------------------------------
+# FP32 parity: 1e-5 absolute on C_m
+# --------------------------------------------------------------------------
+
+def test_double_emulsion_64_fp32_1000_steps(tlb, orc):
+    w = inputs.double_emulsion_64()
+    C = w["C"]()
+    p, pop, s = _run_both(tlb, orc, w, C, None, w["steps"], tlb.TLB_F32)
+    _compare_f32(orc, p, pop, None, s)
+
+
+@pytest.mark.parametrize("width,hold", [(64, 0), (128, 1), (256, 0)])
+def test_d2q9_walls_fp32(tlb, orc, width, hold):
+    w, C, h = _wet_case(150, 61)
+    p, pop, s = _run_both(tlb, orc, w, C, h, 400, tlb.TLB_F32, dict(width=width, chunk=9, hold=hold))
+    _compare_f32(orc, p, pop, h, s)
+
+
+@pytest.mark.parametrize("tile", [(32, 16), (64, 8), (32, 8), (64, 4)])
+def test_d3q19_fp32(tlb, orc, tile):
+    w, C, h = _wet_case(40, 34, 12, lattice=1, walls=1)
+    p, pop, s = _run_both(tlb, orc, w, C, h, 60, tlb.TLB_F32, dict(width=tile[0], height=tile[1], chunk=5))
+    _compare_f32(orc, p, pop, h, s)
+
+
+# --------------------------------------------------------------------------
+# Launch shapes give bitwise identical results; determinism
+# --------------------------------------------------------------------------
+
+def test_launch_shapes_bitwise_identical(tlb):
+    w, C, h = _wet_case(200, 50)
+    ref = None
+    for width in (64, 128, 256):
+        for chunk in (1, 5, 50):
+            for hold in (0, 1):
+                _note(f"shape width={width} chunk={chunk} hold={hold}")
+                s = _gsim(tlb, w, tlb.TLB_F64, dict(width=width, chunk=chunk, hold=hold))
+                s.set_wetting_both(h)
+                s.init_equilibrium(C)
+                s.step(40)
+                got = np.stack([s.populations(k) for k in range(3)])
+                if ref is None:
+                    ref = got
+                else:
+                    assert np.array_equal(got, ref)
+
+
+def test_run_twice_is_deterministic_and_restart_continues(tlb):
+    w, C, h = _wet_case(96, 40)
+    runs = []
+    for _ in range(2):
+        s = _gsim(tlb, w, tlb.TLB_F32)
+        s.set_wetting_both(h)
+        s.init_equilibrium(C)
+        s.step(100)
+        runs.append(s.all_populations())
+    assert np.array_equal(runs[0], runs[1])
+    # checkpoint / restart: 50 steps, save, load into a new sim, 50 more == 100 steps, bit for bit
+    a = _gsim(tlb, w, tlb.TLB_F64)
+    a.set_wetting_both(h)
+    a.init_equilibrium(C)
+    a.step(50)
+    raw, step = a.save_state()
+    pops50 = a.all_populations()
+    a.step(50)
+    b = _gsim(tlb, w, tlb.TLB_F64)
+    b.set_wetting_both(h)
+    b.load_state(raw, step)
+    b.step(50)
+    assert np.array_equal(a.all_populations(), b.all_populations())
+    assert b.diagnostics()["step"] == 100
+    # restart from exported populations (s_t in absolute terms): equal to rounding
+    c = _gsim(tlb, w, tlb.TLB_F64)
+    c.set_wetting_both(h)
+    for sp in range(3):
+        c.set_populations(sp, pops50[sp])
+    c.step(50)
+    assert np.abs(c.all_populations() - a.all_populations()).max() < 1e-14
+
+
+# --------------------------------------------------------------------------
+# Invariants on the GPU
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("lattice", [0, 1])
+def test_gpu_conservation_and_fixed_point(tlb, lattice):
+    if lattice == 0:
+        w, C, h = _wet_case(120, 50)
+    else:
+        w, C, h = _wet_case(24, 20, 16, lattice=1)
+    s = _gsim(tlb, w, tlb.TLB_F64)
+    s.set_wetting_both(h)
+    s.init_equilibrium(C)
+    d0 = s.diagnostics()
+    s.step(200)
+    d1 = s.diagnostics()
+    for m in range(3):
+        assert abs(d1["mass"][m] - d0["mass"][m]) <= 1e-12 * max(1.0, abs(d0["mass"][m]))
+    assert d1["nonfinite"] == 0 and d1["step"] == 200
+    # uniform state at rest between neutral walls: fixed point
+    U = np.zeros_like(C)
+    U[0], U[1], U[2] = 0.25, 0.45, 0.30
+    s2 = _gsim(tlb, w, tlb.TLB_F64)
+    s2.init_equilibrium(U)
+    a = s2.all_populations()
+    s2.step(20)
+    assert np.abs(s2.all_populations() - a).max() < 1e-14
+
+
+def test_nan_is_detected(tlb):
+    w, C, _ = _wet_case(64, 32, walls=0)
+    s = _gsim(tlb, w, tlb.TLB_F64)
+    s.init_equilibrium(C)
+    pop = s.populations(1)
+    pop[3, 100] = np.nan
+    s.set_populations(1, pop)
+    d = s.diagnostics(allow_nan=True)
+    assert d["nonfinite"] >= 1
+    rc = tlb.tlb_set_check_every(s.handle, 1)
+    assert rc == 0
+    assert tlb.tlb_step(s.handle, 1) == tlb.TLB_ENAN
+
+
+# --------------------------------------------------------------------------
+# Full-size workloads in the benchmark's launch configuration
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_spinodal_1024_full_size_few_steps(tlb, orc, prec):
+    """1024x1024 spinodal at full size, default launch shape: every node after 3 steps."""
+    w = inputs.spinodal_2d(1024, 3)
+    C = w["C"]()
+    P = tlb.TLB_F64 if prec == "f64" else tlb.TLB_F32
+    p, pop, s = _run_both(tlb, orc, w, C, None, 3, P)
+    if prec == "f64":
+        _compare_f64(orc, p, pop, None, s)
+    else:
+        _compare_f32(orc, p, pop, None, s, tol=1e-6)
+
+
+def _window(C, dims, centre, W):
+    nx, ny, nz = dims
+    xs = (np.arange(W) + centre[0] - W // 2) % nx
+    ys = (np.arange(W) + centre[1] - W // 2) % ny
+    zs = (np.arange(W) + centre[2] - W // 2) % nz
+    Cg = C.reshape(3, nz, ny, nx)
+    sub = Cg[:, zs][:, :, ys][:, :, :, xs]
+    return sub.reshape(3, -1)
+
+
+def test_spinodal_256cube_full_size_sampled(tlb, orc):
+    """256^3 D3Q19 FP32 at full size: sampled nodes after 2 steps, each recomputed by the oracle on a
+    periodic 16^3 window around it (the update reaches 2 nodes per step plus 1 for the initial stencil,
+    so the window's own wrap-around cannot reach the centre)."""
+    steps = 2
+    w = inputs.spinodal_3d(256, steps)
+    C = w["C"]()
+    _note("256^3 fp32 full size")
+    s = _gsim(tlb, w, tlb.TLB_F32)
+    s.init_equilibrium(C)
+    s.step(steps)
+    gpu_pops = [s.populations(k) for k in range(3)]
+    rng = np.random.default_rng(77)
+    W = 16
+    pw = _oparams(orc, w).replace(nx=W, ny=W, nz=W)
+    for _ in range(6):
+        c = rng.integers(0, 256, 3)
+        sub = _window(C, (256, 256, 256), c, W)
+        pop = orc.init_equilibrium(pw, sub)
+        orc.step(pw, pop, steps)
+        ic = W // 2 + W * (W // 2 + W * (W // 2))
+        n = c[0] + 256 * (c[1] + 256 * c[2])
+        for sp in range(3):
+            assert np.abs(gpu_pops[sp][:, n] - pop[sp][:, ic]).max() < 2e-7, (c, sp)
