@@ -202,22 +202,34 @@ tlb_status tlb_set_populations_dev(tlb_sim* sim, int species, const void* in_dev
 tlb_status tlb_set_wetting_dev(tlb_sim* sim, int wall, const void* h_dev);
 
 /*
- * Launch shape of the fused step kernel.  D2Q9: each workgroup sweeps a strip
- * of `width` columns (64, 128 or 256) over `chunk` rows.  D3Q19: each workgroup
- * sweeps a tile of width x height columns (32x8, 64x4, and for TLB_F32 with
- * hold = 0 also 32x16, 64x8) over `chunk` planes.  chunk >= 1; 0 picks a default.  hold = 1
- * keeps the populations of the next row/plane in registers between its two
- * uses; hold = 0 reads them a second time from cache.  Results are identical
- * for every shape.
+ * Launch shape of the fused step kernel.
+ *   D2Q9: each workgroup sweeps a strip of `width` columns (64, 128 or 256)
+ *     over `chunk` rows; variant 1 prefetches the next row's populations while
+ *     the current row is collided, variant 0 does not.
+ *   D3Q19: each workgroup sweeps a tile of width x height columns (32x8 or
+ *     64x4; for TLB_F32 with variant 0 also 32x16 and 64x8) over `chunk`
+ *     planes; variant 1 keeps the next plane's populations in registers
+ *     between their two uses, variant 0 reads them a second time from cache.
+ *   chunk >= 1; chunk = 0 picks a default.  Results are bitwise identical for
+ *   every shape and variant.
  */
 typedef struct {
-    int32_t width, height, chunk, hold;
+    int32_t width, height, chunk, variant;
 } tlb_launch;
 tlb_status tlb_set_launch(tlb_sim* sim, const tlb_launch* launch);
 tlb_status tlb_get_launch(const tlb_sim* sim, tlb_launch* out);
 
 /* Algorithmic HBM bytes one fused step moves per fluid node (read + write). */
 double tlb_bytes_per_node(const tlb_sim* sim);
+
+/*
+ * Plain device-to-device copy kernel (16-byte vector loads and stores) of
+ * `bytes` bytes (a multiple of 16; both pointers 16-byte aligned), enqueued
+ * on `stream` (NULL: the null stream).  It is the bandwidth reference the
+ * step kernels are measured against: its runtime gives the attainable copy
+ * bandwidth and its hardware byte counters calibrate the step kernels'.
+ */
+tlb_status tlb_device_copy(void* dst, const void* src, int64_t bytes, void* stream);
 
 #ifdef __cplusplus
 }

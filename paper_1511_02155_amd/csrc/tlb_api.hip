@@ -117,22 +117,27 @@ static void default_launch(tlb_sim* s)
 {
     const tlb_params& p = s->p;
     if (p.lattice == TLB_D2Q9) {
+        // Measured on MI355X (1024^2): 256-wide strips holding the next row in
+        // registers; about 16 (FP64) / 8 (FP32) rows per workgroup, i.e. ~1000
+        // (FP64) / ~2000 (FP32) wavefronts in flight.
         int w = p.nx >= 256 ? 256 : (p.nx >= 128 ? 128 : 64);
         const int ntx = (p.nx + w - 1) / w;
-        // aim for about 2048 wavefronts in flight (8 per CU)
         const int64_t waves_per_item = w / 64;
-        int64_t want_items = 2048 / waves_per_item;
+        int64_t want_items = (p.prec == TLB_F64 ? 1024 : 2048) / waves_per_item;
         int64_t nch = (want_items + ntx - 1) / ntx;
         int chunk = (int)((p.ny + nch - 1) / nch);
         if (chunk < 4) chunk = 4;
         s->launch.width = w;
         s->launch.height = 1;
         s->launch.chunk = chunk;
+        s->launch.variant = 1;
     } else {
-        int bx = 32, by = (p.prec == TLB_F32) ? 16 : 8;
+        // Measured on MI355X (256^3 FP32): 64x4 tiles holding the next plane,
+        // ~1000 wavefronts in flight.
+        int bx = p.nx >= 64 ? 64 : 32, by = bx == 64 ? 4 : 8;
         const int ntx = (p.nx + bx - 1) / bx, nty = (p.ny + by - 1) / by;
         const int64_t waves_per_item = (bx * by) / 64;
-        int64_t want_items = 2048 / waves_per_item;
+        int64_t want_items = 1024 / waves_per_item;
         int64_t nch = (want_items + (int64_t)ntx * nty - 1) / ((int64_t)ntx * nty);
         if (nch < 1) nch = 1;
         int chunk = (int)((p.nz + nch - 1) / nch);
@@ -140,17 +145,18 @@ static void default_launch(tlb_sim* s)
         s->launch.width = bx;
         s->launch.height = by;
         s->launch.chunk = chunk;
+        s->launch.variant = 1;
     }
 }
 
 static bool launch_valid(const tlb_sim* s, const tlb_launch* l)
 {
-    if (l->chunk < 1 || (l->hold != 0 && l->hold != 1)) return false;
+    if (l->chunk < 1 || (l->variant != 0 && l->variant != 1)) return false;
     if (s->p.lattice == TLB_D2Q9) return l->width == 64 || l->width == 128 || l->width == 256;
     const int w = l->width, h = l->height;
     if (w == 32 && h == 8) return true;
     if (w == 64 && h == 4) return true;
-    if (!l->hold && s->p.prec == TLB_F32 && ((w == 32 && h == 16) || (w == 64 && h == 8))) return true;
+    if (!l->variant && s->p.prec == TLB_F32 && ((w == 32 && h == 16) || (w == 64 && h == 8))) return true;
     return false;
 }
 
@@ -376,8 +382,8 @@ static tlb_status step_impl(tlb_sim* s, int64_t nsteps)
         a.src = (const T*)s->state[s->cur];
         a.dst = (T*)s->state[s->cur ^ 1];
         hipError_t e = (p.lattice == TLB_D2Q9)
-                           ? launch_step2d<T>(a, s->launch.width, s->launch.hold, s->stream)
-                           : launch_step3d<T>(a, s->launch.width, s->launch.height, s->launch.hold, s->stream);
+                           ? launch_step2d<T>(a, s->launch.width, s->launch.variant, s->stream)
+                           : launch_step3d<T>(a, s->launch.width, s->launch.height, s->launch.variant, s->stream);
         HIPCHK(e);
         s->cur ^= 1;
         s->step += 1;
@@ -424,6 +430,14 @@ extern "C" tlb_status tlb_get_launch(const tlb_sim* s, tlb_launch* out)
 {
     if (!s || !out) return TLB_EINVAL;
     *out = s->launch;
+    return TLB_OK;
+}
+
+extern "C" tlb_status tlb_device_copy(void* dst, const void* src, int64_t bytes, void* stream)
+{
+    if (!dst || !src || bytes < 0 || (bytes & 15) || ((uintptr_t)dst & 15) || ((uintptr_t)src & 15)) return TLB_EINVAL;
+    if (bytes == 0) return TLB_OK;
+    HIPCHK(launch_copy16(src, dst, bytes / 16, (hipStream_t)stream));
     return TLB_OK;
 }
 

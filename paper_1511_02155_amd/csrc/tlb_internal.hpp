@@ -65,6 +65,8 @@ template <typename T, typename TIn>
 hipError_t launch_wet(int n, const TIn* h, double inv_a2k0, double inv_a2k1, double inv_a2k2, T* wet,
                       hipStream_t s);
 
+hipError_t launch_copy16(const void* src, void* dst, int64_t n16, hipStream_t s);
+
 constexpr int kDiagBlocks = 1024;
 constexpr int kDiagSlots = 8;  // mass[3], momentum[3], max|v|, nonfinite
 

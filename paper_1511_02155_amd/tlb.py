@@ -38,7 +38,7 @@ EXPORTS = (
     "tlb_synchronize", "tlb_get_stream", "tlb_init_equilibrium_dev", "tlb_get_field_dev",
     "tlb_get_populations_dev", "tlb_set_populations_dev", "tlb_set_wetting_dev", "tlb_set_launch",
     "tlb_get_launch", "tlb_bytes_per_node", "tlb_state_bytes", "tlb_save_state", "tlb_load_state",
-    "tlb_save_state_dev", "tlb_load_state_dev",
+    "tlb_save_state_dev", "tlb_load_state_dev", "tlb_device_copy",
 )
 
 
@@ -62,7 +62,7 @@ class tlb_diag(ctypes.Structure):
 
 class tlb_launch(ctypes.Structure):
     _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32), ("chunk", ctypes.c_int32),
-                ("hold", ctypes.c_int32)]
+                ("variant", ctypes.c_int32)]
 
 
 _vp = ctypes.c_void_p
@@ -107,6 +107,7 @@ tlb_save_state = _sig("tlb_save_state", ctypes.c_int, [_vp, _vp, ctypes.POINTER(
 tlb_load_state = _sig("tlb_load_state", ctypes.c_int, [_vp, _vp, ctypes.c_int64])
 tlb_save_state_dev = _sig("tlb_save_state_dev", ctypes.c_int, [_vp, _vp])
 tlb_load_state_dev = _sig("tlb_load_state_dev", ctypes.c_int, [_vp, _vp, ctypes.c_int64])
+tlb_device_copy = _sig("tlb_device_copy", ctypes.c_int, [_vp, _vp, ctypes.c_int64, _vp])
 
 
 class TLBError(RuntimeError):
@@ -221,14 +222,14 @@ class Sim:
         return dict(mass=list(d.mass), momentum=list(d.momentum), max_speed=d.max_speed,
                     nonfinite=d.nonfinite, step=d.step)
 
-    def set_launch(self, width, height=1, chunk=0, hold=0):
-        l = tlb_launch(width, height, chunk, hold)
+    def set_launch(self, width, height=1, chunk=0, variant=1):
+        l = tlb_launch(width, height, chunk, variant)
         check(tlb_set_launch(self._h, ctypes.byref(l)), "tlb_set_launch")
 
     def launch(self):
         l = tlb_launch()
         check(tlb_get_launch(self._h, ctypes.byref(l)), "tlb_get_launch")
-        return dict(width=l.width, height=l.height, chunk=l.chunk, hold=l.hold)
+        return dict(width=l.width, height=l.height, chunk=l.chunk, variant=l.variant)
 
     def save_state(self):
         """Raw state bytes and step count (bitwise resume with load_state)."""

@@ -122,7 +122,7 @@ def test_d2q9_walls_wetting_ragged_fp64(tlb, orc, nx, ny, width, chunk):
     """Walls with per-node wetting, ragged strips and chunks, minimum sizes."""
     w, C, h = _wet_case(nx, ny)
     for hold in (0, 1):
-        p, pop, s = _run_both(tlb, orc, w, C, h, 150, tlb.TLB_F64, dict(width=width, chunk=chunk, hold=hold))
+        p, pop, s = _run_both(tlb, orc, w, C, h, 150, tlb.TLB_F64, dict(width=width, chunk=chunk, variant=hold))
         _compare_f64(orc, p, pop, h, s)
 
 
@@ -133,7 +133,7 @@ def test_d3q19_ragged_fp64(tlb, orc, dims, tile, walls):
     w, C, h = _wet_case(nx, ny, nz, lattice=1, walls=walls)
     for hold in (0, 1):
         p, pop, s = _run_both(tlb, orc, w, C, h, 30, tlb.TLB_F64,
-                              dict(width=tile[0], height=tile[1], chunk=4, hold=hold))
+                              dict(width=tile[0], height=tile[1], chunk=4, variant=hold))
         _compare_f64(orc, p, pop, h, s)
 
 
@@ -148,17 +148,18 @@ def test_double_emulsion_64_fp32_1000_steps(tlb, orc):
     _compare_f32(orc, p, pop, None, s)
 
 
-@pytest.mark.parametrize("width,hold", [(64, 0), (128, 1), (256, 0)])
+@pytest.mark.parametrize("width,hold", [(64, 0), (128, 1), (256, 1)])
 def test_d2q9_walls_fp32(tlb, orc, width, hold):
     w, C, h = _wet_case(150, 61)
-    p, pop, s = _run_both(tlb, orc, w, C, h, 400, tlb.TLB_F32, dict(width=width, chunk=9, hold=hold))
+    p, pop, s = _run_both(tlb, orc, w, C, h, 400, tlb.TLB_F32, dict(width=width, chunk=9, variant=hold))
     _compare_f32(orc, p, pop, h, s)
 
 
 @pytest.mark.parametrize("tile", [(32, 16), (64, 8), (32, 8), (64, 4)])
 def test_d3q19_fp32(tlb, orc, tile):
     w, C, h = _wet_case(40, 34, 12, lattice=1, walls=1)
-    p, pop, s = _run_both(tlb, orc, w, C, h, 60, tlb.TLB_F32, dict(width=tile[0], height=tile[1], chunk=5))
+    p, pop, s = _run_both(tlb, orc, w, C, h, 60, tlb.TLB_F32,
+                          dict(width=tile[0], height=tile[1], chunk=5, variant=0 if tile[0] * tile[1] > 256 else 1))
     _compare_f32(orc, p, pop, h, s)
 
 
@@ -172,8 +173,8 @@ def test_launch_shapes_bitwise_identical(tlb):
     for width in (64, 128, 256):
         for chunk in (1, 5, 50):
             for hold in (0, 1):
-                _note(f"shape width={width} chunk={chunk} hold={hold}")
-                s = _gsim(tlb, w, tlb.TLB_F64, dict(width=width, chunk=chunk, hold=hold))
+                _note(f"shape width={width} chunk={chunk} variant={hold}")
+                s = _gsim(tlb, w, tlb.TLB_F64, dict(width=width, chunk=chunk, variant=hold))
                 s.set_wetting_both(h)
                 s.init_equilibrium(C)
                 s.step(40)
