@@ -80,7 +80,11 @@ static bool params_valid(const tlb_params* p)
     if (!isfinite(p->gamma_phi) || !isfinite(p->gamma_psi)) return false;
     const int64_t N = (int64_t)p->nx * p->ny * p->nz;
     const int Q = p->lattice == TLB_D2Q9 ? 9 : 19;
-    if ((int64_t)Q * N >= ((int64_t)1 << 32)) return false;  // 32-bit offsets within a species
+    // one species array must stay addressable by 32-bit byte offsets
+    const int64_t esize = p->prec == TLB_F32 ? 4 : 8;
+    if ((int64_t)Q * N * esize > (int64_t)0xFFFFFF00) return false;
+    // the D2Q9 kernels address the three species of a state through one descriptor
+    if (p->lattice == TLB_D2Q9 && (int64_t)3 * Q * N * esize > (int64_t)0xFFFFFF00) return false;
     return true;
 }
 
@@ -117,20 +121,20 @@ static void default_launch(tlb_sim* s)
 {
     const tlb_params& p = s->p;
     if (p.lattice == TLB_D2Q9) {
-        // Measured on MI355X (1024^2): 256-wide strips holding the next row in
-        // registers; about 16 (FP64) / 8 (FP32) rows per workgroup, i.e. ~1000
-        // (FP64) / ~2000 (FP32) wavefronts in flight.
+        // Measured on MI355X (1024^2): 256-wide strips, 8 rows per workgroup
+        // (about 2000 wavefronts in flight); FP32 prefetches the next row,
+        // FP64 does not (its prefetch buffer would cost occupancy).
         int w = p.nx >= 256 ? 256 : (p.nx >= 128 ? 128 : 64);
         const int ntx = (p.nx + w - 1) / w;
         const int64_t waves_per_item = w / 64;
-        int64_t want_items = (p.prec == TLB_F64 ? 1024 : 2048) / waves_per_item;
+        int64_t want_items = 2048 / waves_per_item;
         int64_t nch = (want_items + ntx - 1) / ntx;
         int chunk = (int)((p.ny + nch - 1) / nch);
         if (chunk < 4) chunk = 4;
         s->launch.width = w;
         s->launch.height = 1;
         s->launch.chunk = chunk;
-        s->launch.variant = 1;
+        s->launch.variant = p.prec == TLB_F32 ? 1 : 0;
     } else {
         // Measured on MI355X (256^3 FP32): 64x4 tiles holding the next plane,
         // ~1000 wavefronts in flight.

@@ -87,6 +87,48 @@ __host__ __device__ constexpr double ref(int s, int i)
 }
 
 // ---------------------------------------------------------------------------
+// Raw buffer access.  A buffer resource covers one species array; loads and
+// stores take a per-lane 32-bit byte offset (voffset) and a wavefront-uniform
+// byte offset (soffset), so the address arithmetic of the lattice pull runs
+// on the scalar unit.  The third resource word is the raw (untyped) access
+// configuration of gfx9-family targets.
+// ---------------------------------------------------------------------------
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+constexpr int kRsrcWord3 = 0x00020000;
+
+__device__ __forceinline__ Rsrc make_rsrc(const void* base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, kRsrcWord3);
+}
+
+template <typename T>
+__device__ __forceinline__ T bload(Rsrc r, uint32_t voff, uint32_t soff);
+template <>
+__device__ __forceinline__ float bload<float>(Rsrc r, uint32_t voff, uint32_t soff)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+template <>
+__device__ __forceinline__ double bload<double>(Rsrc r, uint32_t voff, uint32_t soff)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+}
+
+template <typename T>
+__device__ __forceinline__ void bstore(T v, Rsrc r, uint32_t voff, uint32_t soff);
+template <>
+__device__ __forceinline__ void bstore<float>(float v, Rsrc r, uint32_t voff, uint32_t soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)voff, (int)soff, 0);
+}
+template <>
+__device__ __forceinline__ void bstore<double>(double v, Rsrc r, uint32_t voff, uint32_t soff)
+{
+    typedef uint32_t u2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, (int)voff, (int)soff, 0);
+}
+
+// ---------------------------------------------------------------------------
 // Parameters in the form the kernels use.
 // ---------------------------------------------------------------------------
 template <typename T>

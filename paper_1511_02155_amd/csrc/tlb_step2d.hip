@@ -10,10 +10,10 @@
 // strip of W columns and sweeps a chunk of rows, upwards for even chunks and
 // downwards for odd ones, so that two neighbouring chunks reach their shared
 // boundary rows at the same time and the second read of those rows hits L2.
-// Lane t keeps its own column's concentration deviations dC_m for three
-// consecutive rows in registers; the x-neighbours come from a double-buffered
-// LDS row.  Per row the lane needs from LDS only S = C(x-1) + C(x+1) and
-// D = C(x+1) - C(x-1), which fold the 9-point stencils into
+// The concentration deviations dC_m of the last four rows of the sweep sit in
+// LDS (W+2 entries per row: the strip and one halo column on each side).  Per
+// row the lane needs S = C(x-1) + C(x+1) and D = C(x+1) - C(x-1), which fold
+// the 9-point stencils into
 //   d_x C = D_y/3 + (D_{y-1} + D_{y+1})/12
 //   d_y C = (C_{y+1} - C_{y-1})/3 + (S_{y+1} - S_{y-1})/12
 //   lap C = 2/3 (S_y + (C_{y-1} + C_{y+1})) + (S_{y-1} + S_{y+1})/6 - 10/3 C_y
@@ -36,33 +36,28 @@ namespace tlb {
 
 using L9 = D2Q9;
 
-// Pull the post-propagation populations of node (x, y): f_i(r) = u_i(r - e_i),
-// or u_opp(i)(r) when r - e_i lies beyond a wall (half-way bounce-back).
+// Pull of the post-propagation populations of row y at the lane's column:
+// f_i(r) = u_i(r - e_i), or u_opp(i)(r) when r - e_i lies beyond a wall
+// (half-way bounce-back).  vo[0..2]: byte offsets of columns x, x-1, x+1;
+// every row-dependent part of the address is wavefront-uniform.
 template <typename T>
-__device__ __forceinline__ void pull2d(const StepArgs<T>& A, int x, int y, T* f, T* g, T* k)
+__device__ __forceinline__ void pull2d(const StepArgs<T>& A, Rsrc src, const uint32_t* vo, int y, T* p)
 {
-    const int nx = A.nx, ny = A.ny;
-    const int xm = (x == 0) ? nx - 1 : x - 1;
-    const int xp = (x == nx - 1) ? 0 : x + 1;
-    const int ym = (y == 0) ? ny - 1 : y - 1;
-    const int yp = (y == ny - 1) ? 0 : y + 1;
+    const int ny = A.ny;
+    const uint32_t nx = (uint32_t)A.nx, N = (uint32_t)A.N;
+    const uint32_t ym = (y == 0) ? ny - 1 : y - 1;
+    const uint32_t yp = (y == ny - 1) ? 0 : y + 1;
     const bool blo = A.walls && y == 0;
     const bool bhi = A.walls && y == ny - 1;
-    const uint32_t N = (uint32_t)A.N;
-    const uint32_t n0 = (uint32_t)y * nx + x;
 #pragma unroll
-    for (int s = 0; s < 3; ++s) {
-        const T* __restrict__ b = A.src + (int64_t)s * 9 * A.N;
-        T* out = (s == 0) ? f : (s == 1) ? g : k;
+    for (int i = 0; i < 9; ++i) {
+        const int ex = L9::ex[i], ey = L9::ey[i];
+        const bool bb = (ey == 1) ? blo : (ey == -1) ? bhi : false;
+        const uint32_t ys = ey == 0 ? (uint32_t)y : (ey == 1 ? ym : yp);
+        const uint32_t so = (bb ? (uint32_t)L9::opp[i] * N + (uint32_t)y * nx : (uint32_t)i * N + ys * nx) * sizeof(T);
+        const uint32_t v = bb ? vo[0] : vo[ex == 0 ? 0 : (ex == 1 ? 1 : 2)];
 #pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            const int ex = L9::ex[i], ey = L9::ey[i];
-            const bool bb = (ey == 1) ? blo : (ey == -1) ? bhi : false;
-            const int xs = ex == 0 ? x : (ex == 1 ? xm : xp);
-            const int ys = ey == 0 ? y : (ey == 1 ? ym : yp);
-            const uint32_t off = bb ? (uint32_t)L9::opp[i] * N + n0 : (uint32_t)i * N + (uint32_t)ys * nx + xs;
-            out[i] = b[off];
-        }
+        for (int s = 0; s < 3; ++s) p[9 * s + i] = bload<T>(src, v, so + (uint32_t)(9 * s) * N * sizeof(T));
     }
 }
 
@@ -93,17 +88,17 @@ __device__ __forceinline__ T pull2d_one(const StepArgs<T>& A, int j, int x, int 
     return A.src[(int64_t)s * 9 * A.N + off];
 }
 
-template <typename T>
-struct Row2 {
-    T c[3];  // own dC_m
-    T S[3];  // dC(x-1) + dC(x+1)
-    T D[3];  // dC(x+1) - dC(x-1)
-};
+// Occupancy target (wavefronts per SIMD) the register allocation is held to.
+template <typename T, int DEPTH>
+constexpr int step2d_waves() { return sizeof(T) == 8 ? (DEPTH ? 1 : 2) : (DEPTH ? 3 : 4); }
 
 template <typename T, int W, int DEPTH>
-__global__ __launch_bounds__(W) void k_step2d(StepArgs<T> A)
+__global__ __launch_bounds__(W) __attribute__((amdgpu_waves_per_eu(step2d_waves<T, DEPTH>())))
+void k_step2d(StepArgs<T> A)
 {
-    __shared__ T lds[2][3][W];
+    // Rows of dC_m in sweep order, four rotating buffers; slot 0 and slot
+    // nact+1 hold the halo columns, slot t+1 lane t's own column.
+    __shared__ T lds[4][3][W + 2];
     __shared__ T hsc[2][2][27];  // halo populations [buf][left/right][j]
 
     const int item = xcd_item(blockIdx.x, A.nitems);
@@ -133,151 +128,163 @@ __global__ __launch_bounds__(W) void k_step2d(StepArgs<T> A)
     const uint32_t nxz = (uint32_t)A.nx;  // nz == 1
     const uint32_t N = (uint32_t)A.N;
 
-    // Row r_j of the sweep (j = -1 .. L); kind: -1 fluid, 0/1 ghost of that wall.
+    // Row r_j of the sweep (j = -1 .. L) lives in LDS buffer (j + 1) & 3.
     auto row_of = [&](int j) { return yfirst + j * dir; };
     auto ghost_of = [&](int y) { return (A.walls && y < 0) ? 0 : ((A.walls && y >= A.ny) ? 1 : -1); };
     auto wrap_y = [&](int y) { return y < 0 ? y + A.ny : (y >= A.ny ? y - A.ny : y); };
 
-    T pB[27], pC[27], pN[27];  // populations: row being collided, next row, prefetched row
+    // buffer resources of the source and destination states (27 N values each)
+    const uint32_t sbytes = (uint32_t)(27 * A.N * (int64_t)sizeof(T));
+    const Rsrc rs = make_rsrc(A.src, sbytes);
+    const Rsrc rd = make_rsrc(A.dst, sbytes);
+    const uint32_t vo[3] = {(uint32_t)x * (uint32_t)sizeof(T),
+                            (uint32_t)(x == 0 ? A.nx - 1 : x - 1) * (uint32_t)sizeof(T),
+                            (uint32_t)(x == A.nx - 1 ? 0 : x + 1) * (uint32_t)sizeof(T)};
+
+    // Three population buffers that take turns as: the row being collided,
+    // the next row, and (DEPTH = 1) the row being prefetched.  The sweep loop
+    // is unrolled so that the roles rotate without register copies.
+    T P0[27], P1[27], P2[27];
 #pragma unroll
-    for (int i = 0; i < 27; ++i) pB[i] = pC[i] = pN[i] = T(0);
-    T hvC = T(0), hvN = T(0);  // halo population held by a loader lane (next / prefetched row)
-    Row2<T> ra, rb, rc;
-    T hcl[3], hcr[3];  // halo dC of the most recent fluid row (lanes 0 / nact-1)
-    int buf = 0;
+    for (int i = 0; i < 27; ++i) P0[i] = P1[i] = P2[i] = T(0);
+    Moments<T> M0, M1, M2;
+    T H0 = T(0), H1 = T(0), H2 = T(0);  // halo population held by a loader lane per buffer
+    int hb = 0;
 
     auto load_row = [&](int y, T* p, T& hv) {
-        if (active) pull2d<T>(A, x, y, p, p + 9, p + 18);
+        if (active) pull2d<T>(A, rs, vo, y, p);
         if (ldl || ldr) hv = pull2d_one<T>(A, hj, hx, y);
     };
 
-    // Publish a row: own dC and (for a fluid row) the halo populations to
-    // LDS; after the barrier read the neighbour sums.  The lanes next to the
-    // halo build the halo dC from the gathered populations.
-    auto publish = [&](Row2<T>& r, bool fluid, int gw) {
+    // Fluid row into buffer q: own dC and the halo populations to LDS, a
+    // barrier, then the lanes next to the halo sum the gathered populations
+    // (in the same order as every node) into the halo slots.
+    auto finish_fluid = [&](const T* p, T hv, int q, Moments<T>& mo) {
+        mo = moments<L9, T>(p, p + 9, p + 18);
+        T c[3];
+        conc_dev<T>(mo, c);
         if (active) {
 #pragma unroll
-            for (int m = 0; m < 3; ++m) lds[buf][m][t] = r.c[m];
+            for (int m = 0; m < 3; ++m) lds[q][m][t + 1] = c[m];
         }
-        if (fluid && (ldl || ldr)) hsc[buf][hside][hj] = hvC;
+        if (ldl || ldr) hsc[hb][hside][hj] = hv;
         __syncthreads();
-        if (fluid && (hl || hr)) {
 #pragma unroll
-            for (int side = 0; side < 2; ++side) {
-                if ((side == 0 && hl) || (side == 1 && hr)) {
-                    T q[27];
+        for (int side = 0; side < 2; ++side) {
+            if ((side == 0 && hl) || (side == 1 && hr)) {
+                T v[27];
 #pragma unroll
-                    for (int j = 0; j < 27; ++j) q[j] = hsc[buf][side][j];
-                    const Moments<T> hm = moments<L9, T>(q, q + 9, q + 18);
-                    conc_dev<T>(hm, side == 0 ? hcl : hcr);
-                }
+                for (int j = 0; j < 27; ++j) v[j] = hsc[hb][side][j];
+                const Moments<T> hm = moments<L9, T>(v, v + 9, v + 18);
+                T hc[3];
+                conc_dev<T>(hm, hc);
+                const int slot = side == 0 ? 0 : nact + 1;
+#pragma unroll
+                for (int m = 0; m < 3; ++m) lds[q][m][slot] = hc[m];
             }
         }
-        if (!fluid) {
-            const T* __restrict__ wt = A.wet + (size_t)gw * 3 * nxz;
+        hb ^= 1;
+    };
+    // Ghost row beyond wall w into buffer q from the adjacent fluid row in
+    // buffer qa (reading R8): C_m(ghost) = C_m(adjacent) + h_m / (alpha^2 kappa_m).
+    auto finish_ghost = [&](int w, int qa, int q) {
+        const T* __restrict__ wt = A.wet + (size_t)w * 3 * nxz;
+        if (active) {
 #pragma unroll
-            for (int m = 0; m < 3; ++m) {
-                if (hl) hcl[m] += wt[m * nxz + xl];
-                if (hr) hcr[m] += wt[m * nxz + xr];
-            }
+            for (int m = 0; m < 3; ++m) lds[q][m][t + 1] = lds[qa][m][t + 1] + wt[m * nxz + x];
         }
 #pragma unroll
         for (int m = 0; m < 3; ++m) {
-            const T l = hl ? hcl[m] : lds[buf][m][t > 0 ? t - 1 : 0];
-            const T rr = hr ? hcr[m] : lds[buf][m][t + 1 < W ? t + 1 : W - 1];
-            r.S[m] = l + rr;
-            r.D[m] = rr - l;
+            if (hl) lds[q][m][0] = lds[qa][m][0] + wt[m * nxz + xl];
+            if (hr) lds[q][m][nact + 1] = lds[qa][m][nact + 1] + wt[m * nxz + xr];
         }
-        buf ^= 1;
+        __syncthreads();
     };
 
-    // Finish row y whose populations are in p (moments -> dC -> publish).
-    auto finish_fluid = [&](const T* p, Row2<T>& r) {
-        const Moments<T> mo = moments<L9, T>(p, p + 9, p + 18);
-        conc_dev<T>(mo, r.c);
-        publish(r, true, 0);
-    };
-    // Ghost row beyond wall w from the adjacent fluid row (reading R8):
-    // C_m(ghost) = C_m(adjacent) + h_m / (alpha^2 kappa_m).
-    auto finish_ghost = [&](int w, const Row2<T>& adj, Row2<T>& r) {
-        const T* __restrict__ wt = A.wet + (size_t)w * 3 * nxz;
+    // One row of the sweep: Pc/Mc hold row r_j, Pn row r_{j+1} (in flight),
+    // Pp receives row r_{j+2} (DEPTH = 1).
+    auto row_step = [&](int j, T* Pc, Moments<T>& Mc, T* Pn, Moments<T>& Mn, T& Hn, T* Pp, T& Hp) {
+        const int y = row_of(j);
+        const int qa = j & 3, qb = (j + 1) & 3, qc = (j + 2) & 3;
+        const int yc = row_of(j + 1);
+        const int gc = ghost_of(yc);
+        if constexpr (DEPTH == 0) {
+            if (gc < 0 && j > 0) load_row(wrap_y(yc), Pn, Hn);
+        }
+        if (gc < 0)
+            finish_fluid(Pn, Hn, qc, Mn);
+        else
+            finish_ghost(gc, qb, qc);
+        if constexpr (DEPTH == 1) {
+            const int yn = row_of(j + 2);
+            if (j + 2 <= L && ghost_of(yn) < 0) load_row(wrap_y(yn), Pp, Hp);
+        }
+        if (active) {
+            // Stencils of row y from the three rows in LDS (qa: previous row in
+            // sweep order, qc: next one).
+            T gC[3][3], lC[3];
 #pragma unroll
-        for (int m = 0; m < 3; ++m) r.c[m] = adj.c[m] + wt[m * nxz + x];
-        publish(r, false, w);
+            for (int m = 0; m < 3; ++m) {
+                const T ac = lds[qa][m][t + 1], aS = lds[qa][m][t] + lds[qa][m][t + 2],
+                        aD = lds[qa][m][t + 2] - lds[qa][m][t];
+                const T bc = lds[qb][m][t + 1], bS = lds[qb][m][t] + lds[qb][m][t + 2],
+                        bD = lds[qb][m][t + 2] - lds[qb][m][t];
+                const T cc = lds[qc][m][t + 1], cS = lds[qc][m][t] + lds[qc][m][t + 2],
+                        cD = lds[qc][m][t + 2] - lds[qc][m][t];
+                const T up = dir > 0 ? cc : ac, dn = dir > 0 ? ac : cc;
+                const T Sup = dir > 0 ? cS : aS, Sdn = dir > 0 ? aS : cS;
+                gC[m][0] = bD * T(1.0 / 3.0) + (aD + cD) * T(1.0 / 12.0);
+                gC[m][1] = (up - dn) * T(1.0 / 3.0) + (Sup - Sdn) * T(1.0 / 12.0);
+                gC[m][2] = T(0);
+                lC[m] = (bS + (ac + cc)) * T(2.0 / 3.0) + (aS + cS) * T(1.0 / 6.0) - bc * T(10.0 / 3.0);
+            }
+            T dc[3] = {lds[qb][0][t + 1], lds[qb][1][t + 1], lds[qb][2][t + 1]};
+            collide<L9, T>(A.P, Mc, dc, gC, lC, Pc, Pc + 9, Pc + 18);
+            const uint32_t rowo = (uint32_t)y * (uint32_t)A.nx;
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                const uint32_t so = ((uint32_t)i * N + rowo) * (uint32_t)sizeof(T);
+#pragma unroll
+                for (int s = 0; s < 3; ++s) bstore<T>(Pc[9 * s + i], rd, vo[0], so + (uint32_t)(9 * s) * N * sizeof(T));
+            }
+        }
     };
 
-    // Prologue: rows r_{-1} (ra) and r_0 (rb, populations in pB); prefetch r_1.
+    // Prologue: rows r_{-1} (LDS buffer 0) and r_0 (buffer 1, populations in
+    // P0); the pull of r_1 into P1.
     {
         const int ya = row_of(-1);
         const int ga = ghost_of(ya);
         if (ga < 0) {
-            load_row(wrap_y(ya), pC, hvC);
-            finish_fluid(pC, ra);
-            load_row(yfirst, pB, hvC);
-            finish_fluid(pB, rb);
+            load_row(wrap_y(ya), P1, H1);
+            finish_fluid(P1, H1, 0, M1);
+            load_row(yfirst, P0, H0);
+            finish_fluid(P0, H0, 1, M0);
         } else {
-            load_row(yfirst, pB, hvC);
-            finish_fluid(pB, rb);
-            finish_ghost(ga, rb, ra);
+            load_row(yfirst, P0, H0);
+            finish_fluid(P0, H0, 1, M0);
+            finish_ghost(ga, 1, 0);
         }
         const int yc = row_of(1);
-        if (ghost_of(yc) < 0) load_row(wrap_y(yc), pC, hvC);
+        if (ghost_of(yc) < 0) load_row(wrap_y(yc), P1, H1);
     }
 
-    for (int j = 0; j < L; ++j) {
-        const int y = row_of(j);
-        // Row r_{j+1}: finish the fluid row already in flight, or build the ghost row.
-        const int yc = row_of(j + 1);
-        const int gc = ghost_of(yc);
-        if constexpr (DEPTH == 0) {
-            if (gc < 0 && j > 0) load_row(wrap_y(yc), pC, hvC);
+    if constexpr (DEPTH == 0) {
+        int j = 0;
+        for (; j + 1 < L; j += 2) {
+            row_step(j, P0, M0, P1, M1, H1, P2, H2);
+            row_step(j + 1, P1, M1, P0, M0, H0, P2, H2);
         }
-        if (gc < 0)
-            finish_fluid(pC, rc);
-        else
-            finish_ghost(gc, rb, rc);
-        // Prefetch row r_{j+2} (needed while j + 2 <= L).
-        if constexpr (DEPTH == 1) {
-            const int yn = row_of(j + 2);
-            if (j + 2 <= L && ghost_of(yn) < 0) load_row(wrap_y(yn), pN, hvN);
+        if (j < L) row_step(j, P0, M0, P1, M1, H1, P2, H2);
+    } else {
+        int j = 0;
+        for (; j + 2 < L; j += 3) {
+            row_step(j, P0, M0, P1, M1, H1, P2, H2);
+            row_step(j + 1, P1, M1, P2, M2, H2, P0, H0);
+            row_step(j + 2, P2, M2, P0, M0, H0, P1, H1);
         }
-
-        // Stencils of row y (ra: previous row in sweep order, rc: next one).
-        T gC[3][3], lC[3];
-#pragma unroll
-        for (int m = 0; m < 3; ++m) {
-            const T up = dir > 0 ? rc.c[m] : ra.c[m];
-            const T dn = dir > 0 ? ra.c[m] : rc.c[m];
-            const T Sup = dir > 0 ? rc.S[m] : ra.S[m];
-            const T Sdn = dir > 0 ? ra.S[m] : rc.S[m];
-            gC[m][0] = rb.D[m] * T(1.0 / 3.0) + (ra.D[m] + rc.D[m]) * T(1.0 / 12.0);
-            gC[m][1] = (up - dn) * T(1.0 / 3.0) + (Sup - Sdn) * T(1.0 / 12.0);
-            gC[m][2] = T(0);
-            lC[m] = (rb.S[m] + (ra.c[m] + rc.c[m])) * T(2.0 / 3.0) + (ra.S[m] + rc.S[m]) * T(1.0 / 6.0) -
-                    rb.c[m] * T(10.0 / 3.0);
-        }
-        if (active) {
-            const Moments<T> mb = moments<L9, T>(pB, pB + 9, pB + 18);
-            collide<L9, T>(A.P, mb, rb.c, gC, lC, pB, pB + 9, pB + 18);
-            T* __restrict__ dst = A.dst;
-            const uint32_t n0 = (uint32_t)y * A.nx + x;
-#pragma unroll
-            for (int i = 0; i < 9; ++i) {
-                dst[(uint32_t)i * N + n0] = pB[i];
-                dst[(int64_t)9 * A.N + (uint32_t)i * N + n0] = pB[9 + i];
-                dst[(int64_t)18 * A.N + (uint32_t)i * N + n0] = pB[18 + i];
-            }
-        }
-
-        ra = rb;
-        rb = rc;
-#pragma unroll
-        for (int i = 0; i < 27; ++i) pB[i] = pC[i];
-        if constexpr (DEPTH == 1) {
-#pragma unroll
-            for (int i = 0; i < 27; ++i) pC[i] = pN[i];
-            hvC = hvN;
-        }
+        if (j < L) row_step(j, P0, M0, P1, M1, H1, P2, H2);
+        if (j + 1 < L) row_step(j + 1, P1, M1, P2, M2, H2, P0, H0);
     }
 }
 
