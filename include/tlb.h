@@ -231,6 +231,53 @@ double tlb_bytes_per_node(const tlb_sim* sim);
  */
 tlb_status tlb_device_copy(void* dst, const void* src, int64_t bytes, void* stream);
 
+/* ------------------------------------------------------------------------ */
+/* Batched D2Q9 lattices                                                    */
+/* ------------------------------------------------------------------------ */
+/*
+ * A batch advances ndom independent D2Q9 lattices (the benchmark geometries
+ * of Sec. V, e.g. sweeps over kappa_m and h_m) together.  Each domain has its
+ * own tlb_params (lattice TLB_D2Q9, nx, ny <= 65535, its own walls_y, kappa,
+ * alpha, tau and Gamma); every domain must use the same prec.  One time step
+ * of the batch is one persistent kernel launch whose workgroups take
+ * (domain, strip, row-chunk) work items from per-XCD queues; with
+ * tlb_batch_set_graph the steps are replayed from a captured hipGraph.
+ * A domain evolves exactly (bit for bit) as a tlb_sim with the same
+ * parameters.  Domain indices run 0..ndom-1; host arrays follow the layouts
+ * of the single-lattice calls for that domain's nx, ny.
+ */
+typedef struct tlb_batch tlb_batch;
+tlb_status tlb_batch_create(const tlb_params* per_dom, int32_t ndom, void* stream, tlb_batch** out);
+tlb_status tlb_batch_destroy(tlb_batch* batch);
+int32_t tlb_batch_size(const tlb_batch* batch);
+/* Total number of fluid nodes over all domains. */
+int64_t tlb_batch_nodes(const tlb_batch* batch);
+void* tlb_batch_get_stream(const tlb_batch* batch);
+tlb_status tlb_batch_synchronize(tlb_batch* batch);
+tlb_status tlb_batch_set_wetting(tlb_batch* batch, int32_t dom, int wall, const double* h);
+tlb_status tlb_batch_init_equilibrium(tlb_batch* batch, int32_t dom, const double* C, const double* u);
+tlb_status tlb_batch_step(tlb_batch* batch, int64_t nsteps);
+tlb_status tlb_batch_get_field(tlb_batch* batch, int32_t dom, int which, double* out);
+tlb_status tlb_batch_get_populations(tlb_batch* batch, int32_t dom, int species, double* out);
+tlb_status tlb_batch_diagnostics(tlb_batch* batch, int32_t dom, tlb_diag* out);
+/*
+ * Launch shape of the batched step: width = strip width (64, 128, 256),
+ * chunk = rows per work item (1..65535), variant as for a D2Q9 tlb_sim;
+ * height is ignored.  Results do not depend on it.
+ */
+tlb_status tlb_batch_set_launch(tlb_batch* batch, const tlb_launch* launch);
+tlb_status tlb_batch_get_launch(const tlb_batch* batch, tlb_launch* out);
+/*
+ * Time every launch shape for trial_steps steps from the current state
+ * (which is restored) and keep the fastest; writes it to *chosen if not NULL.
+ * If the environment variable TLB_TUNE_CACHE names a file, a previous result
+ * for the same domain sizes is taken from it, and new results are appended.
+ */
+tlb_status tlb_batch_autotune(tlb_batch* batch, int32_t trial_steps, tlb_launch* chosen);
+/* Capture steps_per_graph (even, > 0) steps once in a hipGraph and replay it
+ * inside tlb_batch_step; 0 launches every step directly (the default). */
+tlb_status tlb_batch_set_graph(tlb_batch* batch, int32_t steps_per_graph);
+
 #ifdef __cplusplus
 }
 #endif

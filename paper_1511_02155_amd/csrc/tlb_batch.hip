@@ -1,0 +1,690 @@
+// Batched D2Q9 ternary LB: many independent lattices of uneven size and
+// parameters advanced together.
+//
+// One time step of the whole batch is one persistent launch: a grid sized to
+// the number of workgroups the GPU holds at once, whose workgroups take
+// (domain, strip, chunk) work items from eight queues (one per XCD, filled
+// largest domain first and balanced by load) and steal from the other queues
+// once their own is empty.  The kernel boundary is the per-step barrier; the
+// queue counters of the next step are cleared inside the kernel, so a chain
+// of steps can be captured once in a hipGraph and replayed.  Each work item
+// runs the same strip sweep as the single-lattice kernel, so a domain's result
+// is bit-for-bit the one a single tlb_sim of that domain produces.
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/tlb.h"
+#include "tlb_sweep2d.hpp"
+
+namespace tlb {
+
+template <typename T>
+struct DomDesc {
+    int64_t off;      // element offset of the domain's state in a state buffer
+    int64_t wet_off;  // element offset of its wetting array, or -1 (no walls)
+    int32_t nx, ny, walls, chunk, ntx, nchunks;
+    Phys<T> P;
+};
+
+template <typename T>
+struct BatchArgs {
+    const T* src;
+    T* dst;
+    const T* wet;
+    const DomDesc<T>* doms;
+    const int2* items;  // {domain, strip << 16 | chunk}
+    const int* qstart;  // [9]: queue k holds items [qstart[k], qstart[k+1])
+    int* counters;      // [2][8]
+    int parity;
+};
+
+constexpr int kQueues = 8;
+
+template <typename T, int W, int DEPTH>
+__global__ __launch_bounds__(W) __attribute__((amdgpu_waves_per_eu(step2d_waves<T, DEPTH>())))
+void k_batch2d(BatchArgs<T> B)
+{
+    __shared__ Sweep2Lds<T, W> S;
+    __shared__ int s_item;
+    if (blockIdx.x == 0 && threadIdx.x < kQueues) B.counters[(B.parity ^ 1) * kQueues + threadIdx.x] = 0;
+    // Workgroups are dispatched round-robin over the XCDs: start on the
+    // queue of this workgroup's XCD, then move on to the others.
+    int q = blockIdx.x & (kQueues - 1);
+    int empty = 0;
+    while (empty < kQueues) {
+        if (threadIdx.x == 0) {
+            const int k = atomicAdd(&B.counters[B.parity * kQueues + q], 1);
+            const int idx = B.qstart[q] + k;
+            s_item = (idx < B.qstart[q + 1]) ? idx : -1;
+        }
+        __syncthreads();
+        const int it = s_item;
+        __syncthreads();
+        if (it < 0) {
+            q = (q + 1) & (kQueues - 1);
+            ++empty;
+            continue;
+        }
+        const int2 w = B.items[it];
+        const DomDesc<T>& D = B.doms[w.x];
+        StepArgs<T> A;
+        A.src = B.src + D.off;
+        A.dst = B.dst + D.off;
+        A.wet = D.wet_off >= 0 ? B.wet + D.wet_off : nullptr;
+        A.nx = D.nx;
+        A.ny = D.ny;
+        A.nz = 1;
+        A.walls = D.walls;
+        A.N = (int64_t)D.nx * D.ny;
+        A.chunk = D.chunk;
+        A.nchunks = D.nchunks;
+        A.ntx = D.ntx;
+        A.nty = 1;
+        A.nitems = D.ntx * D.nchunks;
+        A.P = D.P;
+        sweep2d<T, W, DEPTH>(A, w.y >> 16, w.y & 0xffff, S);
+        __syncthreads();
+    }
+}
+
+template <typename T>
+static hipError_t launch_batch2d(const BatchArgs<T>& a, int width, int depth, int grid, hipStream_t s)
+{
+#define TLB_LB(WW, DD)                                                                         \
+    if (width == WW && depth == DD) {                                                          \
+        hipLaunchKernelGGL((k_batch2d<T, WW, DD>), dim3(grid), dim3(WW), 0, s, a);             \
+        return hipGetLastError();                                                              \
+    }
+    TLB_LB(64, 0)
+    TLB_LB(128, 0)
+    TLB_LB(256, 0)
+    TLB_LB(64, 1)
+    TLB_LB(128, 1)
+    TLB_LB(256, 1)
+#undef TLB_LB
+    return hipErrorInvalidValue;
+}
+
+template <typename T>
+static hipError_t occupancy_batch2d(int width, int depth, int* blocks_per_cu)
+{
+#define TLB_OB(WW, DD)                                                                                 \
+    if (width == WW && depth == DD)                                                                    \
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batch2d<T, WW, DD>, WW, 0);
+    TLB_OB(64, 0)
+    TLB_OB(128, 0)
+    TLB_OB(256, 0)
+    TLB_OB(64, 1)
+    TLB_OB(128, 1)
+    TLB_OB(256, 1)
+#undef TLB_OB
+    return hipErrorInvalidValue;
+}
+
+}  // namespace tlb
+
+using namespace tlb;
+
+struct tlb_batch {
+    int ndom;
+    int prec;
+    size_t esize;
+    std::vector<tlb_params> p;
+    std::vector<int64_t> off;      // state offsets (elements)
+    std::vector<int64_t> wet_off;  // wetting offsets (elements) or -1
+    int64_t state_elems, wet_elems, total_nodes, max_nodes;
+    hipStream_t stream;
+    bool own_stream;
+    void* state[2];
+    int cur;  // buffer holding u_t; also the queue-counter parity of the next step
+    void* wet;
+    void* doms;  // DomDesc<T>[ndom]
+    int2* items;
+    int* qstart;
+    int* counters;
+    int nitems;
+    void* fields;
+    double* staging;
+    double* diag_partial;
+    double* diag_out;
+    int64_t step;
+    bool ready;
+    tlb_launch launch;  // width, height (unused), chunk = rows per work item, variant
+    int grid;
+    int graph_steps;
+    hipGraphExec_t graph_exec;
+    hipGraph_t graph;
+};
+
+static thread_local int g_batch_last_hip = 0;
+
+#define BHIP(...)                                                 \
+    do {                                                          \
+        hipError_t e_ = (__VA_ARGS__);                            \
+        if (e_ != hipSuccess) {                                   \
+            g_batch_last_hip = (int)e_;                           \
+            return e_ == hipErrorOutOfMemory ? TLB_ENOMEM : TLB_EHIP; \
+        }                                                         \
+    } while (0)
+
+template <typename T>
+static Phys<T> phys_of(const tlb_params& p)
+{
+    Phys<T> P;
+    const double a2 = p.alpha * p.alpha;
+    for (int m = 0; m < 3; ++m) {
+        P.kappa[m] = T(p.kappa[m]);
+        P.a2kappa[m] = T(a2 * p.kappa[m]);
+    }
+    P.omega[0] = T(1.0 / p.tau_f);
+    P.omega[1] = T(1.0 / p.tau_g);
+    P.omega[2] = T(1.0 / p.tau_k);
+    P.gphi3 = T(3.0 * p.gamma_phi);
+    P.gpsi3 = T(3.0 * p.gamma_psi);
+    return P;
+}
+
+static AuxGeom dom_geom(const tlb_batch* b, int d)
+{
+    AuxGeom g;
+    g.lattice = 0;
+    g.nx = b->p[d].nx;
+    g.ny = b->p[d].ny;
+    g.nz = 1;
+    g.walls = b->p[d].walls_y;
+    g.N = (int64_t)g.nx * g.ny;
+    return g;
+}
+
+static void drop_graph(tlb_batch* b)
+{
+    if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->graph_exec = nullptr;
+    b->graph = nullptr;
+}
+
+// Work items and queues for the current launch shape: domains go to the
+// least-loaded queue in decreasing size; within a queue, larger domains come
+// first and the strips of one chunk are adjacent.
+template <typename T>
+static tlb_status build_items(tlb_batch* b)
+{
+    const int W = b->launch.width, rows = b->launch.chunk;
+    std::vector<int> order(b->ndom);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
+        return (int64_t)b->p[a].nx * b->p[a].ny > (int64_t)b->p[c].nx * b->p[c].ny;
+    });
+    std::vector<std::vector<int2>> q(kQueues);
+    std::vector<int64_t> load(kQueues, 0);
+    std::vector<DomDesc<T>> dd(b->ndom);
+    for (int d : order) {
+        const tlb_params& p = b->p[d];
+        DomDesc<T>& D = dd[d];
+        D.off = b->off[d];
+        D.wet_off = b->wet_off[d];
+        D.nx = p.nx;
+        D.ny = p.ny;
+        D.walls = p.walls_y;
+        D.chunk = std::min(rows, p.ny);
+        D.ntx = (p.nx + W - 1) / W;
+        D.nchunks = (p.ny + D.chunk - 1) / D.chunk;
+        D.P = phys_of<T>(p);
+        const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        load[k] += (int64_t)D.ntx * W * p.ny;
+        for (int c = 0; c < D.nchunks; ++c)
+            for (int s = 0; s < D.ntx; ++s) q[k].push_back(make_int2(d, (s << 16) | c));
+    }
+    std::vector<int2> items;
+    std::vector<int> qs(kQueues + 1, 0);
+    for (int k = 0; k < kQueues; ++k) {
+        qs[k] = (int)items.size();
+        items.insert(items.end(), q[k].begin(), q[k].end());
+    }
+    qs[kQueues] = (int)items.size();
+    if (b->items) BHIP(hipFree(b->items));
+    b->items = nullptr;
+    BHIP(hipMalloc((void**)&b->items, sizeof(int2) * items.size()));
+    BHIP(hipMemcpyAsync(b->items, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice, b->stream));
+    BHIP(hipMemcpyAsync(b->qstart, qs.data(), sizeof(int) * qs.size(), hipMemcpyHostToDevice, b->stream));
+    BHIP(hipMemcpyAsync(b->doms, dd.data(), sizeof(DomDesc<T>) * dd.size(), hipMemcpyHostToDevice, b->stream));
+    BHIP(hipMemsetAsync(b->counters, 0, sizeof(int) * 2 * kQueues, b->stream));
+    BHIP(hipStreamSynchronize(b->stream));
+    b->nitems = (int)items.size();
+    int dev = 0, ncu = 0, per_cu = 0;
+    BHIP(hipGetDevice(&dev));
+    BHIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+    BHIP(occupancy_batch2d<T>(W, b->launch.variant, &per_cu));
+    if (per_cu < 1) per_cu = 1;
+    b->grid = std::max(1, std::min(ncu * per_cu, b->nitems));
+    drop_graph(b);
+    return TLB_OK;
+}
+
+static tlb_status rebuild(tlb_batch* b)
+{
+    return b->prec == TLB_F32 ? build_items<float>(b) : build_items<double>(b);
+}
+
+extern "C" tlb_status tlb_batch_create(const tlb_params* per_dom, int32_t ndom, void* stream, tlb_batch** out)
+{
+    if (!per_dom || !out || ndom < 1) return TLB_EINVAL;
+    *out = nullptr;
+    const int prec = per_dom[0].prec;
+    for (int d = 0; d < ndom; ++d) {
+        const tlb_params& p = per_dom[d];
+        if (p.lattice != TLB_D2Q9 || p.prec != prec || p.nz != 1) return TLB_EINVAL;
+        if (p.nx < 3 || p.ny < 3 || p.nx > 65535 || p.ny > 65535 || (p.walls_y != 0 && p.walls_y != 1)) return TLB_EINVAL;
+        for (int m = 0; m < 3; ++m)
+            if (!(p.kappa[m] > 0.0) || !isfinite(p.kappa[m])) return TLB_EINVAL;
+        if (!(p.alpha > 0.0) || !isfinite(p.alpha)) return TLB_EINVAL;
+        if (!(p.tau_f > 0.5 && p.tau_g > 0.5 && p.tau_k > 0.5)) return TLB_EINVAL;
+        if (!isfinite(p.tau_f) || !isfinite(p.tau_g) || !isfinite(p.tau_k)) return TLB_EINVAL;
+        if (!isfinite(p.gamma_phi) || !isfinite(p.gamma_psi)) return TLB_EINVAL;
+        if (prec != TLB_F32 && prec != TLB_F64) return TLB_EINVAL;
+        const int64_t bytes = (int64_t)27 * p.nx * p.ny * (prec == TLB_F32 ? 4 : 8);
+        if (bytes > (int64_t)0xFFFFFF00) return TLB_EINVAL;
+    }
+    tlb_batch* b = new (std::nothrow) tlb_batch();
+    if (!b) return TLB_ENOMEM;
+    b->ndom = ndom;
+    b->prec = prec;
+    b->esize = prec == TLB_F32 ? 4 : 8;
+    b->p.assign(per_dom, per_dom + ndom);
+    b->off.resize(ndom);
+    b->wet_off.resize(ndom);
+    b->state_elems = b->wet_elems = b->total_nodes = b->max_nodes = 0;
+    for (int d = 0; d < ndom; ++d) {
+        const int64_t N = (int64_t)per_dom[d].nx * per_dom[d].ny;
+        b->off[d] = b->state_elems;
+        b->state_elems += ((27 * N + 63) / 64) * 64;  // 512-byte aligned domain blocks (FP64)
+        b->wet_off[d] = per_dom[d].walls_y ? b->wet_elems : -1;
+        if (per_dom[d].walls_y) b->wet_elems += 6 * (int64_t)per_dom[d].nx;
+        b->total_nodes += N;
+        b->max_nodes = std::max(b->max_nodes, N);
+    }
+    b->launch.width = 64;
+    b->launch.height = 1;
+    b->launch.chunk = 16;
+    b->launch.variant = prec == TLB_F32 ? 1 : 0;
+    hipError_t e = hipSuccess;
+    if (stream) {
+        b->stream = (hipStream_t)stream;
+    } else {
+        e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
+        b->own_stream = true;
+    }
+    const size_t dsz = prec == TLB_F32 ? sizeof(DomDesc<float>) : sizeof(DomDesc<double>);
+    if (e == hipSuccess) e = hipMalloc(&b->state[0], b->state_elems * b->esize);
+    if (e == hipSuccess) e = hipMalloc(&b->state[1], b->state_elems * b->esize);
+    if (e == hipSuccess) e = hipMalloc(&b->wet, std::max<int64_t>(b->wet_elems, 1) * b->esize);
+    if (e == hipSuccess) e = hipMemsetAsync(b->wet, 0, std::max<int64_t>(b->wet_elems, 1) * b->esize, b->stream);
+    if (e == hipSuccess) e = hipMalloc(&b->doms, dsz * ndom);
+    if (e == hipSuccess) e = hipMalloc((void**)&b->qstart, sizeof(int) * (kQueues + 1));
+    if (e == hipSuccess) e = hipMalloc((void**)&b->counters, sizeof(int) * 2 * kQueues);
+    if (e == hipSuccess) e = hipMalloc((void**)&b->diag_partial, sizeof(double) * kDiagBlocks * kDiagSlots);
+    if (e == hipSuccess) e = hipMalloc((void**)&b->diag_out, sizeof(double) * kDiagSlots);
+    if (e != hipSuccess) {
+        g_batch_last_hip = (int)e;
+        tlb_batch_destroy(b);
+        return e == hipErrorOutOfMemory ? TLB_ENOMEM : TLB_EHIP;
+    }
+    tlb_status st = rebuild(b);
+    if (st) {
+        tlb_batch_destroy(b);
+        return st;
+    }
+    *out = b;
+    return TLB_OK;
+}
+
+extern "C" tlb_status tlb_batch_destroy(tlb_batch* b)
+{
+    if (!b) return TLB_EINVAL;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    drop_graph(b);
+    for (void* ptr : {b->state[0], b->state[1], b->wet, b->doms, (void*)b->items, (void*)b->qstart, (void*)b->counters,
+                      b->fields, (void*)b->staging, (void*)b->diag_partial, (void*)b->diag_out})
+        if (ptr) (void)hipFree(ptr);
+    if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+    return TLB_OK;
+}
+
+extern "C" int32_t tlb_batch_size(const tlb_batch* b) { return b ? b->ndom : 0; }
+extern "C" int64_t tlb_batch_nodes(const tlb_batch* b) { return b ? b->total_nodes : 0; }
+extern "C" void* tlb_batch_get_stream(const tlb_batch* b) { return b ? (void*)b->stream : nullptr; }
+
+extern "C" tlb_status tlb_batch_synchronize(tlb_batch* b)
+{
+    if (!b) return TLB_EINVAL;
+    BHIP(hipStreamSynchronize(b->stream));
+    return TLB_OK;
+}
+
+static tlb_status staging(tlb_batch* b)
+{
+    if (b->staging) return TLB_OK;
+    BHIP(hipMalloc((void**)&b->staging, sizeof(double) * 27 * b->max_nodes));
+    return TLB_OK;
+}
+
+extern "C" tlb_status tlb_batch_set_wetting(tlb_batch* b, int32_t dom, int wall, const double* h)
+{
+    if (!b || !h || dom < 0 || dom >= b->ndom || (wall != 0 && wall != 1) || !b->p[dom].walls_y) return TLB_EINVAL;
+    const tlb_params& p = b->p[dom];
+    for (int j = 0; j < 3 * p.nx; ++j)
+        if (!isfinite(h[j])) return TLB_EINVAL;
+    tlb_status st = staging(b);
+    if (st) return st;
+    BHIP(hipMemcpyAsync(b->staging, h, sizeof(double) * 3 * p.nx, hipMemcpyHostToDevice, b->stream));
+    const double a2 = p.alpha * p.alpha;
+    const int64_t o = b->wet_off[dom] + (int64_t)wall * 3 * p.nx;
+    if (b->prec == TLB_F32)
+        BHIP(launch_wet<float, double>(p.nx, b->staging, 1.0 / (a2 * p.kappa[0]), 1.0 / (a2 * p.kappa[1]),
+                                       1.0 / (a2 * p.kappa[2]), (float*)b->wet + o, b->stream));
+    else
+        BHIP(launch_wet<double, double>(p.nx, b->staging, 1.0 / (a2 * p.kappa[0]), 1.0 / (a2 * p.kappa[1]),
+                                        1.0 / (a2 * p.kappa[2]), (double*)b->wet + o, b->stream));
+    BHIP(hipStreamSynchronize(b->stream));
+    return TLB_OK;
+}
+
+extern "C" tlb_status tlb_batch_init_equilibrium(tlb_batch* b, int32_t dom, const double* C, const double* u)
+{
+    if (!b || !C || dom < 0 || dom >= b->ndom) return TLB_EINVAL;
+    const AuxGeom g = dom_geom(b, dom);
+    tlb_status st = staging(b);
+    if (st) return st;
+    BHIP(hipMemcpyAsync(b->staging, C, sizeof(double) * 3 * g.N, hipMemcpyHostToDevice, b->stream));
+    const double* ud = nullptr;
+    if (u) {
+        BHIP(hipMemcpyAsync(b->staging + 3 * g.N, u, sizeof(double) * 2 * g.N, hipMemcpyHostToDevice, b->stream));
+        ud = b->staging + 3 * g.N;
+    }
+    if (b->prec == TLB_F32)
+        BHIP(launch_init<float, double>(g, phys_of<float>(b->p[dom]), b->staging, ud,
+                                        b->wet_off[dom] >= 0 ? (const float*)b->wet + b->wet_off[dom] : nullptr,
+                                        (float*)b->state[b->cur] + b->off[dom], b->stream));
+    else
+        BHIP(launch_init<double, double>(g, phys_of<double>(b->p[dom]), b->staging, ud,
+                                         b->wet_off[dom] >= 0 ? (const double*)b->wet + b->wet_off[dom] : nullptr,
+                                         (double*)b->state[b->cur] + b->off[dom], b->stream));
+    BHIP(hipStreamSynchronize(b->stream));
+    b->ready = true;
+    b->step = 0;
+    return TLB_OK;
+}
+
+template <typename T>
+static tlb_status batch_launch_one(tlb_batch* b)
+{
+    BatchArgs<T> a;
+    a.src = (const T*)b->state[b->cur];
+    a.dst = (T*)b->state[b->cur ^ 1];
+    a.wet = (const T*)b->wet;
+    a.doms = (const DomDesc<T>*)b->doms;
+    a.items = b->items;
+    a.qstart = b->qstart;
+    a.counters = b->counters;
+    a.parity = b->cur;
+    BHIP(launch_batch2d<T>(a, b->launch.width, b->launch.variant, b->grid, b->stream));
+    b->cur ^= 1;
+    return TLB_OK;
+}
+
+static tlb_status batch_direct(tlb_batch* b, int64_t n)
+{
+    for (int64_t t = 0; t < n; ++t) {
+        tlb_status st = b->prec == TLB_F32 ? batch_launch_one<float>(b) : batch_launch_one<double>(b);
+        if (st) return st;
+    }
+    return TLB_OK;
+}
+
+extern "C" tlb_status tlb_batch_step(tlb_batch* b, int64_t nsteps)
+{
+    if (!b || nsteps < 0) return TLB_EINVAL;
+    if (!b->ready) return TLB_ESTATE;
+    int64_t left = nsteps;
+    if (b->graph_steps > 0 && left >= b->graph_steps) {
+        if (b->cur != 0) {  // the captured chain starts from buffer 0
+            tlb_status st = batch_direct(b, 1);
+            if (st) return st;
+            --left;
+        }
+        if (!b->graph_exec) {
+            BHIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+            tlb_status st = batch_direct(b, b->graph_steps);
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamEndCapture(b->stream, &g);
+            if (st) return st;
+            BHIP(e);
+            b->graph = g;
+            BHIP(hipGraphInstantiate(&b->graph_exec, g, nullptr, nullptr, 0));
+            b->cur = 0;  // capture recorded the launches without running them
+        }
+        while (left >= b->graph_steps) {
+            BHIP(hipGraphLaunch(b->graph_exec, b->stream));
+            left -= b->graph_steps;
+        }
+    }
+    tlb_status st = batch_direct(b, left);
+    if (st) return st;
+    b->step += nsteps;
+    return TLB_OK;
+}
+
+extern "C" tlb_status tlb_batch_set_graph(tlb_batch* b, int32_t steps_per_graph)
+{
+    if (!b || steps_per_graph < 0 || (steps_per_graph & 1)) return TLB_EINVAL;
+    BHIP(hipStreamSynchronize(b->stream));
+    drop_graph(b);
+    b->graph_steps = steps_per_graph;
+    return TLB_OK;
+}
+
+extern "C" tlb_status tlb_batch_set_launch(tlb_batch* b, const tlb_launch* l)
+{
+    if (!b || !l) return TLB_EINVAL;
+    if ((l->width != 64 && l->width != 128 && l->width != 256) || l->chunk < 1 || l->chunk > 65535 ||
+        (l->variant != 0 && l->variant != 1))
+        return TLB_EINVAL;
+    BHIP(hipStreamSynchronize(b->stream));
+    b->launch = *l;
+    b->launch.height = 1;
+    return rebuild(b);
+}
+
+extern "C" tlb_status tlb_batch_get_launch(const tlb_batch* b, tlb_launch* out)
+{
+    if (!b || !out) return TLB_EINVAL;
+    *out = b->launch;
+    return TLB_OK;
+}
+
+extern "C" tlb_status tlb_batch_get_field(tlb_batch* b, int32_t dom, int which, double* out)
+{
+    if (!b || !out || dom < 0 || dom >= b->ndom || which < 0 || which >= TLB_NFIELDS) return TLB_EINVAL;
+    if (!b->ready) return TLB_ESTATE;
+    const AuxGeom g = dom_geom(b, dom);
+    tlb_status st = staging(b);
+    if (st) return st;
+    if (!b->fields) BHIP(hipMalloc(&b->fields, (size_t)TLB_NFIELDS * b->max_nodes * b->esize));
+    if (b->prec == TLB_F32) {
+        const float* wet = b->wet_off[dom] >= 0 ? (const float*)b->wet + b->wet_off[dom] : nullptr;
+        BHIP(launch_fields<float>(g, phys_of<float>(b->p[dom]), (const float*)b->state[b->cur] + b->off[dom], wet,
+                                  (float*)b->fields, b->stream));
+        BHIP(launch_export_field<float, double>(g, (const float*)b->fields, which, b->staging, b->stream));
+    } else {
+        const double* wet = b->wet_off[dom] >= 0 ? (const double*)b->wet + b->wet_off[dom] : nullptr;
+        BHIP(launch_fields<double>(g, phys_of<double>(b->p[dom]), (const double*)b->state[b->cur] + b->off[dom], wet,
+                                   (double*)b->fields, b->stream));
+        BHIP(launch_export_field<double, double>(g, (const double*)b->fields, which, b->staging, b->stream));
+    }
+    BHIP(hipMemcpyAsync(out, b->staging, sizeof(double) * g.N, hipMemcpyDeviceToHost, b->stream));
+    BHIP(hipStreamSynchronize(b->stream));
+    return TLB_OK;
+}
+
+extern "C" tlb_status tlb_batch_get_populations(tlb_batch* b, int32_t dom, int species, double* out)
+{
+    if (!b || !out || dom < 0 || dom >= b->ndom || species < 0 || species > 2) return TLB_EINVAL;
+    if (!b->ready) return TLB_ESTATE;
+    const AuxGeom g = dom_geom(b, dom);
+    tlb_status st = staging(b);
+    if (st) return st;
+    if (b->prec == TLB_F32)
+        BHIP(launch_get_pops<float, double>(g, (const float*)b->state[b->cur] + b->off[dom], species, b->staging,
+                                            b->stream));
+    else
+        BHIP(launch_get_pops<double, double>(g, (const double*)b->state[b->cur] + b->off[dom], species, b->staging,
+                                             b->stream));
+    BHIP(hipMemcpyAsync(out, b->staging, sizeof(double) * 9 * g.N, hipMemcpyDeviceToHost, b->stream));
+    BHIP(hipStreamSynchronize(b->stream));
+    return TLB_OK;
+}
+
+extern "C" tlb_status tlb_batch_diagnostics(tlb_batch* b, int32_t dom, tlb_diag* out)
+{
+    if (!b || !out || dom < 0 || dom >= b->ndom) return TLB_EINVAL;
+    if (!b->ready) return TLB_ESTATE;
+    const AuxGeom g = dom_geom(b, dom);
+    if (b->prec == TLB_F32)
+        BHIP(launch_diag<float>(g, (const float*)b->state[b->cur] + b->off[dom], b->diag_partial, kDiagBlocks,
+                                b->diag_out, b->stream));
+    else
+        BHIP(launch_diag<double>(g, (const double*)b->state[b->cur] + b->off[dom], b->diag_partial, kDiagBlocks,
+                                 b->diag_out, b->stream));
+    double h[kDiagSlots];
+    BHIP(hipMemcpyAsync(h, b->diag_out, sizeof(h), hipMemcpyDeviceToHost, b->stream));
+    BHIP(hipStreamSynchronize(b->stream));
+    for (int m = 0; m < 3; ++m) {
+        out->mass[m] = h[m];
+        out->momentum[m] = h[3 + m];
+    }
+    out->max_speed = h[6];
+    out->nonfinite = (int64_t)h[7];
+    out->step = b->step;
+    return out->nonfinite ? TLB_ENAN : TLB_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner: times every launch shape for a few steps from the current state
+// (restored afterwards) and keeps the fastest.  With the environment variable
+// TLB_TUNE_CACHE naming a file, results are looked up there first and new
+// ones appended, keyed by the batch's shape signature.
+// ---------------------------------------------------------------------------
+static std::string batch_signature(const tlb_batch* b)
+{
+    uint64_t h = 1469598103934665603ull;  // FNV-1a over the domain sizes and walls
+    for (const tlb_params& p : b->p) {
+        const uint64_t v[3] = {(uint64_t)p.nx, (uint64_t)p.ny, (uint64_t)p.walls_y};
+        for (uint64_t x : v)
+            for (int k = 0; k < 8; ++k) {
+                h ^= (x >> (8 * k)) & 0xff;
+                h *= 1099511628211ull;
+            }
+    }
+    char buf[128];
+    snprintf(buf, sizeof(buf), "batch-d2q9-%s-%d-%llx", b->prec == TLB_F32 ? "f32" : "f64", b->ndom,
+             (unsigned long long)h);
+    return buf;
+}
+
+static bool cache_lookup(const char* path, const std::string& key, tlb_launch* l)
+{
+    FILE* f = fopen(path, "r");
+    if (!f) return false;
+    char k[128];
+    int w, c, v;
+    bool found = false;
+    while (fscanf(f, "%127s %d %d %d", k, &w, &c, &v) == 4)
+        if (key == k) {
+            l->width = w;
+            l->height = 1;
+            l->chunk = c;
+            l->variant = v;
+            found = true;
+        }
+    fclose(f);
+    return found;
+}
+
+extern "C" tlb_status tlb_batch_autotune(tlb_batch* b, int32_t trial_steps, tlb_launch* chosen)
+{
+    if (!b || trial_steps < 1) return TLB_EINVAL;
+    if (!b->ready) return TLB_ESTATE;
+    const char* cache = getenv("TLB_TUNE_CACHE");
+    const std::string key = batch_signature(b);
+    tlb_launch best;
+    if (cache && cache_lookup(cache, key, &best)) {
+        tlb_status st = tlb_batch_set_launch(b, &best);
+        if (st) return st;
+        if (chosen) *chosen = best;
+        return TLB_OK;
+    }
+    BHIP(hipStreamSynchronize(b->stream));
+    const size_t bytes = (size_t)b->state_elems * b->esize;
+    void* save = nullptr;
+    BHIP(hipMalloc(&save, bytes));
+    const int cur0 = b->cur;
+    const int gsave = b->graph_steps;
+    b->graph_steps = 0;
+    hipEvent_t e0, e1;
+    BHIP(hipEventCreate(&e0));
+    BHIP(hipEventCreate(&e1));
+    BHIP(hipMemcpyAsync(save, b->state[cur0], bytes, hipMemcpyDeviceToDevice, b->stream));
+    float best_ms = 1e30f;
+    best = b->launch;
+    const int widths[3] = {64, 128, 256};
+    const int chunks[4] = {8, 16, 32, 64};
+    tlb_status st = TLB_OK;
+    for (int wi = 0; wi < 3 && !st; ++wi)
+        for (int ci = 0; ci < 4 && !st; ++ci)
+            for (int v = 0; v < 2 && !st; ++v) {
+                tlb_launch l = {widths[wi], 1, chunks[ci], v};
+                st = tlb_batch_set_launch(b, &l);
+                if (st) break;
+                st = batch_direct(b, 1);  // warm-up
+                if (st) break;
+                (void)hipEventRecord(e0, b->stream);
+                st = batch_direct(b, trial_steps);
+                (void)hipEventRecord(e1, b->stream);
+                (void)hipEventSynchronize(e1);
+                float ms = 0;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+                if (!st && ms < best_ms) {
+                    best_ms = ms;
+                    best = l;
+                }
+            }
+    (void)hipMemcpyAsync(b->state[cur0], save, bytes, hipMemcpyDeviceToDevice, b->stream);
+    (void)hipStreamSynchronize(b->stream);
+    (void)hipFree(save);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    b->cur = cur0;
+    b->graph_steps = gsave;
+    if (st) return st;
+    st = tlb_batch_set_launch(b, &best);
+    if (st) return st;
+    if (cache) {
+        FILE* f = fopen(cache, "a");
+        if (f) {
+            fprintf(f, "%s %d %d %d\n", key.c_str(), best.width, best.chunk, best.variant);
+            fclose(f);
+        }
+    }
+    if (chosen) *chosen = best;
+    return TLB_OK;
+}

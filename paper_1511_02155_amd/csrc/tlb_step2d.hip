@@ -1,291 +1,18 @@
-// Fused D2Q9 ternary LB step for gfx950: pull propagation + half-way
-// bounce-back, moments, wetting ghost rows, lattice stencils, local
-// thermodynamics, equilibria and BGK collision in one pass over HBM.
-//
-// State: u_t = post-collision populations of the previous step, SoA
-// [species][q][n] (shifted storage, see tlb_device.hpp).  One launch maps
-// u_t -> u_{t+1}; the post-propagation state s_t is the pull of u_t.
-//
-// Work decomposition.  A workgroup of W lanes (W = 64, 128 or 256) owns a
-// strip of W columns and sweeps a chunk of rows, upwards for even chunks and
-// downwards for odd ones, so that two neighbouring chunks reach their shared
-// boundary rows at the same time and the second read of those rows hits L2.
-// The concentration deviations dC_m of the last four rows of the sweep sit in
-// LDS (W+2 entries per row: the strip and one halo column on each side).  Per
-// row the lane needs S = C(x-1) + C(x+1) and D = C(x+1) - C(x-1), which fold
-// the 9-point stencils into
-//   d_x C = D_y/3 + (D_{y-1} + D_{y+1})/12
-//   d_y C = (C_{y+1} - C_{y-1})/3 + (S_{y+1} - S_{y-1})/12
-//   lap C = 2/3 (S_y + (C_{y-1} + C_{y+1})) + (S_{y-1} + S_{y+1})/6 - 10/3 C_y
-// (the isotropic stencils d_a X = 3 sum w_i e_ia X(r+e_i),
-//  lap X = 6 sum w_i [X(r+e_i) - X(r)] written out for D2Q9), grouped so that
-// both sweep directions round identically.
-//
-// The columns x0-1 and x0+W of the neighbouring strips are gathered
-// cooperatively: lanes 0..26 of the first wavefront load the 27 populations
-// of the left halo node (one each) and lanes 32..58 of the last wavefront
-// those of the right one; the values pass through LDS to the lane next to
-// the halo, which sums them in the same order as every other node.
-//
-// DEPTH = 1 software-pipelines the sweep: the pull of row r+2 is issued
-// before row r is collided, so the HBM reads overlap the arithmetic.
-// HBM traffic per node and step: 27 values read (pull) + 27 written.
-#include "tlb_internal.hpp"
+// Plain D2Q9 step: one workgroup per (strip, chunk) item of one lattice.
+// The sweep itself (tlb_sweep2d.hpp) is shared with the batched kernel.
+#include "tlb_sweep2d.hpp"
 
 namespace tlb {
-
-using L9 = D2Q9;
-
-// Pull of the post-propagation populations of row y at the lane's column:
-// f_i(r) = u_i(r - e_i), or u_opp(i)(r) when r - e_i lies beyond a wall
-// (half-way bounce-back).  vo[0..2]: byte offsets of columns x, x-1, x+1;
-// every row-dependent part of the address is wavefront-uniform.
-template <typename T>
-__device__ __forceinline__ void pull2d(const StepArgs<T>& A, Rsrc src, const uint32_t* vo, int y, T* p)
-{
-    const int ny = A.ny;
-    const uint32_t nx = (uint32_t)A.nx, N = (uint32_t)A.N;
-    const uint32_t ym = (y == 0) ? ny - 1 : y - 1;
-    const uint32_t yp = (y == ny - 1) ? 0 : y + 1;
-    const bool blo = A.walls && y == 0;
-    const bool bhi = A.walls && y == ny - 1;
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        const int ex = L9::ex[i], ey = L9::ey[i];
-        const bool bb = (ey == 1) ? blo : (ey == -1) ? bhi : false;
-        const uint32_t ys = ey == 0 ? (uint32_t)y : (ey == 1 ? ym : yp);
-        const uint32_t so = (bb ? (uint32_t)L9::opp[i] * N + (uint32_t)y * nx : (uint32_t)i * N + ys * nx) * sizeof(T);
-        const uint32_t v = bb ? vo[0] : vo[ex == 0 ? 0 : (ex == 1 ? 1 : 2)];
-#pragma unroll
-        for (int s = 0; s < 3; ++s) p[9 * s + i] = bload<T>(src, v, so + (uint32_t)(9 * s) * N * sizeof(T));
-    }
-}
-
-// One population (species s = j / 9, direction i = j % 9) of the pull of node (x, y).
-template <typename T>
-__device__ __forceinline__ T pull2d_one(const StepArgs<T>& A, int j, int x, int y)
-{
-    // e_x + 1, e_y + 1 and opp(i) of the D2Q9 order, packed 2 / 2 / 4 bits per direction
-    constexpr uint32_t EXP = 1u | 2u << 2 | 0u << 4 | 1u << 6 | 1u << 8 | 2u << 10 | 2u << 12 | 0u << 14 | 0u << 16;
-    constexpr uint32_t EYP = 1u | 1u << 2 | 1u << 4 | 2u << 6 | 0u << 8 | 2u << 10 | 0u << 12 | 2u << 14 | 0u << 16;
-    constexpr uint64_t OPP = 0ull | 2ull << 4 | 1ull << 8 | 4ull << 12 | 3ull << 16 | 8ull << 20 | 7ull << 24 |
-                             6ull << 28 | 5ull << 32;
-    const int s = j / 9, i = j - 9 * s;
-    const int ex = (int)((EXP >> (2 * i)) & 3u) - 1;
-    const int ey = (int)((EYP >> (2 * i)) & 3u) - 1;
-    const int op = (int)((OPP >> (4 * i)) & 15u);
-    const int nx = A.nx, ny = A.ny;
-    int xs = x - ex;
-    xs = xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs);
-    int ys = y - ey;
-    int64_t off;
-    if (A.walls && (ys < 0 || ys >= ny)) {
-        off = (int64_t)op * A.N + (int64_t)y * nx + x;
-    } else {
-        ys = ys < 0 ? ys + ny : (ys >= ny ? ys - ny : ys);
-        off = (int64_t)i * A.N + (int64_t)ys * nx + xs;
-    }
-    return A.src[(int64_t)s * 9 * A.N + off];
-}
-
-// Occupancy target (wavefronts per SIMD) the register allocation is held to.
-template <typename T, int DEPTH>
-constexpr int step2d_waves() { return sizeof(T) == 8 ? (DEPTH ? 1 : 2) : (DEPTH ? 3 : 4); }
 
 template <typename T, int W, int DEPTH>
 __global__ __launch_bounds__(W) __attribute__((amdgpu_waves_per_eu(step2d_waves<T, DEPTH>())))
 void k_step2d(StepArgs<T> A)
 {
-    // Rows of dC_m in sweep order, four rotating buffers; slot 0 and slot
-    // nact+1 hold the halo columns, slot t+1 lane t's own column.
-    __shared__ T lds[4][3][W + 2];
-    __shared__ T hsc[2][2][27];  // halo populations [buf][left/right][j]
-
+    __shared__ Sweep2Lds<T, W> S;
     const int item = xcd_item(blockIdx.x, A.nitems);
     const int chunk = item / A.ntx;  // chunk-major: an XCD's range covers whole bands
     const int strip = item - chunk * A.ntx;
-    const int t = threadIdx.x;
-    const int x0 = strip * W;
-    const int nact = min(W, A.nx - x0);
-    const bool active = t < nact;
-    const int x = x0 + (active ? t : nact - 1);
-    const int y0 = chunk * A.chunk;
-    const int y1 = min(y0 + A.chunk, A.ny);
-    const int L = y1 - y0;
-    const int dir = (chunk & 1) ? -1 : 1;
-    const int yfirst = dir > 0 ? y0 : y1 - 1;
-    const bool hl = (t == 0);
-    const bool hr = (t == nact - 1);
-    const int xl = (x0 == 0) ? A.nx - 1 : x0 - 1;
-    const int xr = (x0 + nact == A.nx) ? 0 : x0 + nact;
-    // cooperative halo loaders
-    const int lane = t & 63;
-    const bool ldl = (t < 64) && lane < 27;
-    const bool ldr = (t >= W - 64) && lane >= 32 && lane < 59;
-    const int hj = ldl ? lane : lane - 32;
-    const int hx = ldl ? xl : xr;
-    const int hside = ldl ? 0 : 1;
-    const uint32_t nxz = (uint32_t)A.nx;  // nz == 1
-    const uint32_t N = (uint32_t)A.N;
-
-    // Row r_j of the sweep (j = -1 .. L) lives in LDS buffer (j + 1) & 3.
-    auto row_of = [&](int j) { return yfirst + j * dir; };
-    auto ghost_of = [&](int y) { return (A.walls && y < 0) ? 0 : ((A.walls && y >= A.ny) ? 1 : -1); };
-    auto wrap_y = [&](int y) { return y < 0 ? y + A.ny : (y >= A.ny ? y - A.ny : y); };
-
-    // buffer resources of the source and destination states (27 N values each)
-    const uint32_t sbytes = (uint32_t)(27 * A.N * (int64_t)sizeof(T));
-    const Rsrc rs = make_rsrc(A.src, sbytes);
-    const Rsrc rd = make_rsrc(A.dst, sbytes);
-    const uint32_t vo[3] = {(uint32_t)x * (uint32_t)sizeof(T),
-                            (uint32_t)(x == 0 ? A.nx - 1 : x - 1) * (uint32_t)sizeof(T),
-                            (uint32_t)(x == A.nx - 1 ? 0 : x + 1) * (uint32_t)sizeof(T)};
-
-    // Three population buffers that take turns as: the row being collided,
-    // the next row, and (DEPTH = 1) the row being prefetched.  The sweep loop
-    // is unrolled so that the roles rotate without register copies.
-    T P0[27], P1[27], P2[27];
-#pragma unroll
-    for (int i = 0; i < 27; ++i) P0[i] = P1[i] = P2[i] = T(0);
-    Moments<T> M0, M1, M2;
-    T H0 = T(0), H1 = T(0), H2 = T(0);  // halo population held by a loader lane per buffer
-    int hb = 0;
-
-    auto load_row = [&](int y, T* p, T& hv) {
-        if (active) pull2d<T>(A, rs, vo, y, p);
-        if (ldl || ldr) hv = pull2d_one<T>(A, hj, hx, y);
-    };
-
-    // Fluid row into buffer q: own dC and the halo populations to LDS, a
-    // barrier, then the lanes next to the halo sum the gathered populations
-    // (in the same order as every node) into the halo slots.
-    auto finish_fluid = [&](const T* p, T hv, int q, Moments<T>& mo) {
-        mo = moments<L9, T>(p, p + 9, p + 18);
-        T c[3];
-        conc_dev<T>(mo, c);
-        if (active) {
-#pragma unroll
-            for (int m = 0; m < 3; ++m) lds[q][m][t + 1] = c[m];
-        }
-        if (ldl || ldr) hsc[hb][hside][hj] = hv;
-        __syncthreads();
-#pragma unroll
-        for (int side = 0; side < 2; ++side) {
-            if ((side == 0 && hl) || (side == 1 && hr)) {
-                T v[27];
-#pragma unroll
-                for (int j = 0; j < 27; ++j) v[j] = hsc[hb][side][j];
-                const Moments<T> hm = moments<L9, T>(v, v + 9, v + 18);
-                T hc[3];
-                conc_dev<T>(hm, hc);
-                const int slot = side == 0 ? 0 : nact + 1;
-#pragma unroll
-                for (int m = 0; m < 3; ++m) lds[q][m][slot] = hc[m];
-            }
-        }
-        hb ^= 1;
-    };
-    // Ghost row beyond wall w into buffer q from the adjacent fluid row in
-    // buffer qa (reading R8): C_m(ghost) = C_m(adjacent) + h_m / (alpha^2 kappa_m).
-    auto finish_ghost = [&](int w, int qa, int q) {
-        const T* __restrict__ wt = A.wet + (size_t)w * 3 * nxz;
-        if (active) {
-#pragma unroll
-            for (int m = 0; m < 3; ++m) lds[q][m][t + 1] = lds[qa][m][t + 1] + wt[m * nxz + x];
-        }
-#pragma unroll
-        for (int m = 0; m < 3; ++m) {
-            if (hl) lds[q][m][0] = lds[qa][m][0] + wt[m * nxz + xl];
-            if (hr) lds[q][m][nact + 1] = lds[qa][m][nact + 1] + wt[m * nxz + xr];
-        }
-        __syncthreads();
-    };
-
-    // One row of the sweep: Pc/Mc hold row r_j, Pn row r_{j+1} (in flight),
-    // Pp receives row r_{j+2} (DEPTH = 1).
-    auto row_step = [&](int j, T* Pc, Moments<T>& Mc, T* Pn, Moments<T>& Mn, T& Hn, T* Pp, T& Hp) {
-        const int y = row_of(j);
-        const int qa = j & 3, qb = (j + 1) & 3, qc = (j + 2) & 3;
-        const int yc = row_of(j + 1);
-        const int gc = ghost_of(yc);
-        if constexpr (DEPTH == 0) {
-            if (gc < 0 && j > 0) load_row(wrap_y(yc), Pn, Hn);
-        }
-        if (gc < 0)
-            finish_fluid(Pn, Hn, qc, Mn);
-        else
-            finish_ghost(gc, qb, qc);
-        if constexpr (DEPTH == 1) {
-            const int yn = row_of(j + 2);
-            if (j + 2 <= L && ghost_of(yn) < 0) load_row(wrap_y(yn), Pp, Hp);
-        }
-        if (active) {
-            // Stencils of row y from the three rows in LDS (qa: previous row in
-            // sweep order, qc: next one).
-            T gC[3][3], lC[3];
-#pragma unroll
-            for (int m = 0; m < 3; ++m) {
-                const T ac = lds[qa][m][t + 1], aS = lds[qa][m][t] + lds[qa][m][t + 2],
-                        aD = lds[qa][m][t + 2] - lds[qa][m][t];
-                const T bc = lds[qb][m][t + 1], bS = lds[qb][m][t] + lds[qb][m][t + 2],
-                        bD = lds[qb][m][t + 2] - lds[qb][m][t];
-                const T cc = lds[qc][m][t + 1], cS = lds[qc][m][t] + lds[qc][m][t + 2],
-                        cD = lds[qc][m][t + 2] - lds[qc][m][t];
-                const T up = dir > 0 ? cc : ac, dn = dir > 0 ? ac : cc;
-                const T Sup = dir > 0 ? cS : aS, Sdn = dir > 0 ? aS : cS;
-                gC[m][0] = bD * T(1.0 / 3.0) + (aD + cD) * T(1.0 / 12.0);
-                gC[m][1] = (up - dn) * T(1.0 / 3.0) + (Sup - Sdn) * T(1.0 / 12.0);
-                gC[m][2] = T(0);
-                lC[m] = (bS + (ac + cc)) * T(2.0 / 3.0) + (aS + cS) * T(1.0 / 6.0) - bc * T(10.0 / 3.0);
-            }
-            T dc[3] = {lds[qb][0][t + 1], lds[qb][1][t + 1], lds[qb][2][t + 1]};
-            collide<L9, T>(A.P, Mc, dc, gC, lC, Pc, Pc + 9, Pc + 18);
-            const uint32_t rowo = (uint32_t)y * (uint32_t)A.nx;
-#pragma unroll
-            for (int i = 0; i < 9; ++i) {
-                const uint32_t so = ((uint32_t)i * N + rowo) * (uint32_t)sizeof(T);
-#pragma unroll
-                for (int s = 0; s < 3; ++s) bstore<T>(Pc[9 * s + i], rd, vo[0], so + (uint32_t)(9 * s) * N * sizeof(T));
-            }
-        }
-    };
-
-    // Prologue: rows r_{-1} (LDS buffer 0) and r_0 (buffer 1, populations in
-    // P0); the pull of r_1 into P1.
-    {
-        const int ya = row_of(-1);
-        const int ga = ghost_of(ya);
-        if (ga < 0) {
-            load_row(wrap_y(ya), P1, H1);
-            finish_fluid(P1, H1, 0, M1);
-            load_row(yfirst, P0, H0);
-            finish_fluid(P0, H0, 1, M0);
-        } else {
-            load_row(yfirst, P0, H0);
-            finish_fluid(P0, H0, 1, M0);
-            finish_ghost(ga, 1, 0);
-        }
-        const int yc = row_of(1);
-        if (ghost_of(yc) < 0) load_row(wrap_y(yc), P1, H1);
-    }
-
-    if constexpr (DEPTH == 0) {
-        int j = 0;
-        for (; j + 1 < L; j += 2) {
-            row_step(j, P0, M0, P1, M1, H1, P2, H2);
-            row_step(j + 1, P1, M1, P0, M0, H0, P2, H2);
-        }
-        if (j < L) row_step(j, P0, M0, P1, M1, H1, P2, H2);
-    } else {
-        int j = 0;
-        for (; j + 2 < L; j += 3) {
-            row_step(j, P0, M0, P1, M1, H1, P2, H2);
-            row_step(j + 1, P1, M1, P2, M2, H2, P0, H0);
-            row_step(j + 2, P2, M2, P0, M0, H0, P1, H1);
-        }
-        if (j < L) row_step(j, P0, M0, P1, M1, H1, P2, H2);
-        if (j + 1 < L) row_step(j + 1, P1, M1, P2, M2, H2, P0, H0);
-    }
+    sweep2d<T, W, DEPTH>(A, strip, chunk, S);
 }
 
 template <typename T>

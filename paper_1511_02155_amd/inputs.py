@@ -153,3 +153,30 @@ def spinodal_3d(n=256, steps=2000, seed=3):
     w["C"] = lambda: spinodal(n, n, n, seed=seed)
     w["h"] = None
     return w
+
+
+def batched_walls(ndom=512, lo=32, hi=256, steps=5000, seed=4, prec_kappa=(0.005, 0.03), h_range=(-0.01, 0.01)):
+    """Many walled D2Q9 domains of uneven size: Lx, Ly ~ U{lo..hi}; even domains hold a
+    sessile C1 drop (R = 0.3 min(Lx, Ly), centre (Lx/2, -1/2)) in C2 under a C3 layer above
+    0.8 Ly, odd domains a C1 lens (R = 0.2 min) at the C2 (below) / C3 (above) interface.
+    kappa_m ~ U[0.005, 0.03] and h_m ~ U[-0.01, 0.01] per domain (the same on both walls),
+    with |h_m| clipped to alpha kappa_m / 4 so that the wall values of Sec. II.B exist;
+    tau = 1, M = 0.1, alpha = 1.  Returns a list of dicts (parameters, C, h)."""
+    rng = np.random.default_rng(seed)
+    L = rng.integers(lo, hi + 1, size=(ndom, 2))
+    kap = rng.uniform(prec_kappa[0], prec_kappa[1], size=(ndom, 3))
+    hh = rng.uniform(h_range[0], h_range[1], size=(ndom, 3))
+    gp, gk = mobility_to_gamma(0.1, 1.0, 1.0)
+    doms = []
+    for d in range(ndom):
+        nx, ny = int(L[d, 0]), int(L[d, 1])
+        kappa = tuple(float(k) for k in kap[d])
+        h = np.clip(hh[d], -np.asarray(kappa) / 4.0, np.asarray(kappa) / 4.0)
+        if d % 2 == 0:
+            C = sessile_drop(nx, ny, 0.3 * min(nx, ny), top_layer=0.8 * ny)
+        else:
+            C = lens(nx, ny, 0.2 * min(nx, ny))
+        doms.append(dict(lattice=0, nx=nx, ny=ny, nz=1, walls_y=1, kappa=kappa, alpha=1.0, tau_f=1.0, tau_g=1.0,
+                         tau_k=1.0, gamma_phi=gp, gamma_psi=gk, steps=steps, C=C,
+                         h=uniform_h(nx, tuple(float(v) for v in h))))
+    return doms

@@ -39,6 +39,10 @@ EXPORTS = (
     "tlb_get_populations_dev", "tlb_set_populations_dev", "tlb_set_wetting_dev", "tlb_set_launch",
     "tlb_get_launch", "tlb_bytes_per_node", "tlb_state_bytes", "tlb_save_state", "tlb_load_state",
     "tlb_save_state_dev", "tlb_load_state_dev", "tlb_device_copy",
+    "tlb_batch_create", "tlb_batch_destroy", "tlb_batch_size", "tlb_batch_nodes", "tlb_batch_get_stream",
+    "tlb_batch_synchronize", "tlb_batch_set_wetting", "tlb_batch_init_equilibrium", "tlb_batch_step",
+    "tlb_batch_get_field", "tlb_batch_get_populations", "tlb_batch_diagnostics", "tlb_batch_set_launch",
+    "tlb_batch_get_launch", "tlb_batch_autotune", "tlb_batch_set_graph",
 )
 
 
@@ -108,6 +112,22 @@ tlb_load_state = _sig("tlb_load_state", ctypes.c_int, [_vp, _vp, ctypes.c_int64]
 tlb_save_state_dev = _sig("tlb_save_state_dev", ctypes.c_int, [_vp, _vp])
 tlb_load_state_dev = _sig("tlb_load_state_dev", ctypes.c_int, [_vp, _vp, ctypes.c_int64])
 tlb_device_copy = _sig("tlb_device_copy", ctypes.c_int, [_vp, _vp, ctypes.c_int64, _vp])
+tlb_batch_create = _sig("tlb_batch_create", ctypes.c_int, [_P, ctypes.c_int32, _vp, ctypes.POINTER(_vp)])
+tlb_batch_destroy = _sig("tlb_batch_destroy", ctypes.c_int, [_vp])
+tlb_batch_size = _sig("tlb_batch_size", ctypes.c_int32, [_vp])
+tlb_batch_nodes = _sig("tlb_batch_nodes", ctypes.c_int64, [_vp])
+tlb_batch_get_stream = _sig("tlb_batch_get_stream", _vp, [_vp])
+tlb_batch_synchronize = _sig("tlb_batch_synchronize", ctypes.c_int, [_vp])
+tlb_batch_set_wetting = _sig("tlb_batch_set_wetting", ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int, _dp])
+tlb_batch_init_equilibrium = _sig("tlb_batch_init_equilibrium", ctypes.c_int, [_vp, ctypes.c_int32, _dp, _dp])
+tlb_batch_step = _sig("tlb_batch_step", ctypes.c_int, [_vp, ctypes.c_int64])
+tlb_batch_get_field = _sig("tlb_batch_get_field", ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int, _dp])
+tlb_batch_get_populations = _sig("tlb_batch_get_populations", ctypes.c_int, [_vp, ctypes.c_int32, ctypes.c_int, _dp])
+tlb_batch_diagnostics = _sig("tlb_batch_diagnostics", ctypes.c_int, [_vp, ctypes.c_int32, ctypes.POINTER(tlb_diag)])
+tlb_batch_set_launch = _sig("tlb_batch_set_launch", ctypes.c_int, [_vp, ctypes.POINTER(tlb_launch)])
+tlb_batch_get_launch = _sig("tlb_batch_get_launch", ctypes.c_int, [_vp, ctypes.POINTER(tlb_launch)])
+tlb_batch_autotune = _sig("tlb_batch_autotune", ctypes.c_int, [_vp, ctypes.c_int32, ctypes.POINTER(tlb_launch)])
+tlb_batch_set_graph = _sig("tlb_batch_set_graph", ctypes.c_int, [_vp, ctypes.c_int32])
 
 
 class TLBError(RuntimeError):
@@ -249,3 +269,93 @@ class Sim:
 
     def stream(self):
         return tlb_get_stream(self._h)
+
+
+class Batch:
+    """Many independent D2Q9 lattices advanced together (owns a tlb_batch*)."""
+
+    def __init__(self, params_list, stream=None):
+        arr = (tlb_params * len(params_list))(*params_list)
+        self._h = _vp()
+        check(tlb_batch_create(arr, len(params_list), stream, ctypes.byref(self._h)), "tlb_batch_create")
+        self.params = list(params_list)
+        self.ndom = len(params_list)
+
+    def close(self):
+        if self._h:
+            tlb_batch_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def nodes(self):
+        return tlb_batch_nodes(self._h)
+
+    def _N(self, d):
+        return self.params[d].nx * self.params[d].ny
+
+    def set_wetting(self, d, wall, h):
+        h = _arr(h, 3 * self.params[d].nx)
+        check(tlb_batch_set_wetting(self._h, d, wall, h.ctypes.data_as(_dp)), "tlb_batch_set_wetting")
+
+    def init_equilibrium(self, d, C, u=None):
+        C = _arr(C, 3 * self._N(d))
+        up = None
+        if u is not None:
+            u = _arr(u, 2 * self._N(d))
+            up = u.ctypes.data_as(_dp)
+        check(tlb_batch_init_equilibrium(self._h, d, C.ctypes.data_as(_dp), up), "tlb_batch_init_equilibrium")
+
+    def step(self, n):
+        check(tlb_batch_step(self._h, int(n)), "tlb_batch_step")
+
+    def synchronize(self):
+        check(tlb_batch_synchronize(self._h), "tlb_batch_synchronize")
+
+    def field(self, d, which):
+        idx = FIELD_INDEX[which] if isinstance(which, str) else int(which)
+        out = np.empty(self._N(d))
+        check(tlb_batch_get_field(self._h, d, idx, out.ctypes.data_as(_dp)), "tlb_batch_get_field")
+        return out
+
+    def populations(self, d, species):
+        out = np.empty((9, self._N(d)))
+        check(tlb_batch_get_populations(self._h, d, species, out.ctypes.data_as(_dp)), "tlb_batch_get_populations")
+        return out
+
+    def all_populations(self, d):
+        return np.stack([self.populations(d, s) for s in range(3)])
+
+    def diagnostics(self, d):
+        dg = tlb_diag()
+        check(tlb_batch_diagnostics(self._h, d, ctypes.byref(dg)), "tlb_batch_diagnostics")
+        return dict(mass=list(dg.mass), momentum=list(dg.momentum), max_speed=dg.max_speed,
+                    nonfinite=dg.nonfinite, step=dg.step)
+
+    def set_launch(self, width, chunk, variant=1):
+        l = tlb_launch(width, 1, chunk, variant)
+        check(tlb_batch_set_launch(self._h, ctypes.byref(l)), "tlb_batch_set_launch")
+
+    def launch(self):
+        l = tlb_launch()
+        check(tlb_batch_get_launch(self._h, ctypes.byref(l)), "tlb_batch_get_launch")
+        return dict(width=l.width, chunk=l.chunk, variant=l.variant)
+
+    def autotune(self, trial_steps=10):
+        l = tlb_launch()
+        check(tlb_batch_autotune(self._h, int(trial_steps), ctypes.byref(l)), "tlb_batch_autotune")
+        return dict(width=l.width, chunk=l.chunk, variant=l.variant)
+
+    def set_graph(self, steps_per_graph):
+        check(tlb_batch_set_graph(self._h, int(steps_per_graph)), "tlb_batch_set_graph")
+
+    def stream(self):
+        return tlb_batch_get_stream(self._h)

@@ -1,0 +1,151 @@
+"""Batched D2Q9 path (one persistent launch per step over many uneven domains).
+
+Every domain of a batch must evolve bit for bit as a single tlb_sim of the
+same domain (same kernels, same arithmetic); small batches are also checked
+against the FP64 oracle, and the full 512-domain workload on sampled domains.
+"""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1511_02155_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("lattice", "nx", "ny", "nz", "walls_y", "kappa", "alpha", "tau_f", "tau_g", "tau_k", "gamma_phi", "gamma_psi")
+
+
+def _note(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def tlb():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.init()
+    from paper_1511_02155_amd import tlb as t
+
+    return t
+
+
+def _small_batch(ndom=10, seed=21):
+    doms = inputs.batched_walls(ndom=ndom, lo=20, hi=140, seed=seed)
+    # make a few domains periodic in y to cover both boundary kinds
+    for d in range(0, ndom, 3):
+        doms[d]["walls_y"] = 0
+        doms[d]["h"] = None
+    return doms
+
+
+def _make_batch(tlb, doms, prec, launch=None, graph=0):
+    b = tlb.Batch([tlb.make_params(prec=prec, **{k: d[k] for k in KEYS}) for d in doms])
+    if launch:
+        b.set_launch(**launch)
+    if graph:
+        b.set_graph(graph)
+    for i, d in enumerate(doms):
+        if d["h"] is not None:
+            b.set_wetting(i, 0, d["h"][0])
+            b.set_wetting(i, 1, d["h"][1])
+        b.init_equilibrium(i, d["C"])
+    return b
+
+
+def _single(tlb, d, prec, steps):
+    s = tlb.Sim(tlb.make_params(prec=prec, **{k: d[k] for k in KEYS}))
+    if d["h"] is not None:
+        s.set_wetting_both(d["h"])
+    s.init_equilibrium(d["C"])
+    s.step(steps)
+    return s.all_populations()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("launch", [dict(width=64, chunk=8, variant=0), dict(width=128, chunk=16, variant=1),
+                                    dict(width=256, chunk=5, variant=1)])
+def test_batch_equals_single_lattices_bitwise(tlb, prec, launch):
+    P = tlb.TLB_F64 if prec == "f64" else tlb.TLB_F32
+    doms = _small_batch()
+    _note(f"batch {len(doms)} domains {prec} {launch}")
+    b = _make_batch(tlb, doms, P, launch)
+    b.step(60)
+    for i, d in enumerate(doms):
+        ref = _single(tlb, d, P, 60)
+        assert np.array_equal(b.all_populations(i), ref), i
+
+
+def test_batch_graph_replays_match_direct(tlb):
+    doms = _small_batch(seed=22)
+    ref = _make_batch(tlb, doms, tlb.TLB_F32)
+    gb = _make_batch(tlb, doms, tlb.TLB_F32, graph=10)
+    total = 0
+    for chunk in (25, 10, 31, 20):  # graph replays plus direct remainders, eager reads in between
+        _note(f"graph replay chunk {chunk}")
+        ref.step(chunk)
+        gb.step(chunk)
+        total += chunk
+        for i in (0, 3, len(doms) - 1):
+            assert np.array_equal(gb.all_populations(i), ref.all_populations(i)), (total, i)
+    assert gb.diagnostics(0)["step"] == total
+
+
+def test_batch_autotune_keeps_state(tlb, tmp_path, monkeypatch):
+    doms = _small_batch(seed=23)
+    monkeypatch.setenv("TLB_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    a = _make_batch(tlb, doms, tlb.TLB_F32)
+    a.step(7)
+    chosen = a.autotune(3)
+    assert chosen["width"] in (64, 128, 256)
+    a.step(13)
+    b = _make_batch(tlb, doms, tlb.TLB_F32)
+    b.step(20)
+    for i in range(len(doms)):
+        assert np.array_equal(a.all_populations(i), b.all_populations(i)), i
+    # the cached choice is found again without timing
+    c = _make_batch(tlb, doms, tlb.TLB_F32)
+    assert c.autotune(3) == chosen
+    assert (tmp_path / "tune.txt").read_text().count("batch-d2q9") == 1
+
+
+def test_batch_small_domains_vs_oracle(tlb, orc):
+    doms = _small_batch(ndom=5, seed=24)
+    b = _make_batch(tlb, doms, tlb.TLB_F64)
+    b.step(150)
+    for i, d in enumerate(doms):
+        p = orc.Params(**{k: d[k] for k in KEYS})
+        pop = orc.init_equilibrium(p, d["C"], None, d["h"])
+        orc.step(p, pop, 150, d["h"])
+        got = b.all_populations(i)
+        for s in range(3):
+            assert np.abs(got[s] - pop[s]).max() <= 1e-12 * np.abs(pop[s]).max(), (i, s)
+
+
+def test_batch_512_domains_sampled(tlb, orc):
+    """The full 512-domain workload (FP32), 4 steps through a captured graph; sampled domains
+    (smallest, largest, two seeded picks) against the FP64 oracle, and conservation in all."""
+    doms = inputs.batched_walls()
+    b = _make_batch(tlb, doms, tlb.TLB_F32, graph=2)
+    m0 = [b.diagnostics(i)["mass"] for i in range(len(doms))]
+    b.step(4)
+    sizes = [d["nx"] * d["ny"] for d in doms]
+    pick = {int(np.argmin(sizes)), int(np.argmax(sizes))} | set(np.random.default_rng(5).integers(0, 512, 2).tolist())
+    for i in sorted(pick):
+        d = doms[i]
+        _note(f"domain {i} {d['nx']}x{d['ny']}")
+        p = orc.Params(**{k: d[k] for k in KEYS})
+        pop = orc.init_equilibrium(p, d["C"], None, d["h"])
+        orc.step(p, pop, 4, d["h"])
+        F = orc.fields(p, pop, d["h"])
+        for name in ("C1", "C2", "C3"):
+            assert np.abs(b.field(i, name) - F[name]).max() < 1e-5, (i, name)
+    for i in range(len(doms)):
+        m1 = b.diagnostics(i)["mass"]
+        for k in range(3):
+            assert abs(m1[k] - m0[i][k]) <= 1e-4 * max(1.0, abs(m0[i][k])), (i, k)
