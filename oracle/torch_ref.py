@@ -1,0 +1,131 @@
+"""FP64 PyTorch-CPU re-expression of the D2Q9 ternary LB step (test infrastructure).
+
+A second, independent CPU implementation of the step of Sec. IV of
+arXiv:1511.02155 (D2Q9, periodic x, periodic y or half-way walls with the
+wetting ghost rows), written with whole-array torch operations so that
+autograd can differentiate a run of steps with respect to the wetting
+parameters h_m and the bulk coefficients kappa_m.  It serves as the
+reference for the GPU adjoint; it is pinned to the C oracle (same forward
+map to rounding) and to central finite differences of the C oracle.
+
+Only the test suite may import it.  It shares no code with the C oracle or
+with the GPU library.  Readings of the paper are those of tlb_oracle.c
+(R1-R9); the state is the post-propagation populations [species][q][ny][nx].
+"""
+from __future__ import annotations
+
+import torch
+
+# D2Q9 velocities (order of include/tlb.h), weights and gradient weights
+E = [(0, 0), (1, 0), (-1, 0), (0, 1), (0, -1), (1, 1), (1, -1), (-1, 1), (-1, -1)]
+OPP = [0, 2, 1, 4, 3, 8, 7, 6, 5]
+W = [4.0 / 9.0] + [1.0 / 9.0] * 4 + [1.0 / 36.0] * 4
+
+
+def _wab(i):
+    """(w^xx, w^yy, w^xy) of direction i (reading R6)."""
+    ex, ey = E[i]
+    if ex == 0 and ey == 0:
+        return 0.0, 0.0, 0.0
+    if ex * ex + ey * ey == 1:
+        return (1.0 / 9.0 if ex else -1.0 / 18.0), (1.0 / 9.0 if ey else -1.0 / 18.0), 0.0
+    return -1.0 / 72.0, -1.0 / 72.0, ex * ey / 12.0
+
+
+def _shift(a, dx, dy):
+    """b[..., y, x] = a[..., y + dy, x + dx] with periodic wrap in both directions."""
+    return torch.roll(a, shifts=(-dy, -dx), dims=(-2, -1))
+
+
+def step(pop, h, kappa, alpha, tau, gamma, walls):
+    """One step s_t -> s_{t+1}.  pop: [3][9][ny][nx]; h: [2][3][nx] (walls) or None;
+    kappa: [3] tensor; tau = (tau_f, tau_g, tau_k); gamma = (Gamma_phi, Gamma_psi)."""
+    f, g, k = pop[0], pop[1], pop[2]
+    ny = pop.shape[-2]
+    ex = torch.tensor([e[0] for e in E], dtype=pop.dtype).view(9, 1, 1)
+    ey = torch.tensor([e[1] for e in E], dtype=pop.dtype).view(9, 1, 1)
+    rho = f.sum(0)
+    vx = (f * ex).sum(0) / rho
+    vy = (f * ey).sum(0) / rho
+    phi = g.sum(0)
+    psi = k.sum(0)
+    C = torch.stack([0.5 * (rho + phi - psi), 0.5 * (rho - phi - psi), psi])  # [3][ny][nx]
+    a2 = alpha * alpha
+    a2k = (a2 * kappa).view(3, 1)
+    # neighbour values C_m(r + e_i), with ghost rows beyond the walls (reading R8)
+    if walls:
+        below = C[:, :1, :] + (h[0] / a2k).unsqueeze(1)
+        above = C[:, -1:, :] + (h[1] / a2k).unsqueeze(1)
+        Cg = torch.cat([below, C, above], dim=1)  # rows -1 .. ny
+
+        def nb(dx, dy):
+            return torch.roll(Cg[:, 1 + dy: 1 + dy + ny, :], shifts=-dx, dims=-1)
+    else:
+        def nb(dx, dy):
+            return _shift(C, dx, dy)
+    gx = torch.zeros_like(C)
+    gy = torch.zeros_like(C)
+    lap = torch.zeros_like(C)
+    for i in range(1, 9):
+        c = nb(*E[i])
+        gx = gx + 3.0 * W[i] * E[i][0] * c
+        gy = gy + 3.0 * W[i] * E[i][1] * c
+        lap = lap + 6.0 * W[i] * (c - C)
+    km = kappa.view(3, 1, 1)
+    mu = km * C * (1 - C) * (1 - 2 * C) - a2 * km * lap
+    mu_phi = 0.5 * (mu[0] - mu[1])
+    mu_psi = mu[2] - 0.5 * (mu[0] + mu[1])
+    pb = rho / 3.0 + (0.5 * km * C * C * (1 - C) * (1 - 3 * C)).sum(0)
+    lam = (a2 * km * C * lap).sum(0)
+    Txx = (a2 * km * gx * gx).sum(0)
+    Tyy = (a2 * km * gy * gy).sum(0)
+    Txy = (a2 * km * gx * gy).sum(0)
+    vv = vx * vx + vy * vy
+    feq, geq, keq = [], [], []
+    for i in range(1, 9):
+        ev = E[i][0] * vx + E[i][1] * vy
+        U = 3.0 * ev + 4.5 * ev * ev - 1.5 * vv
+        wxx, wyy, wxy = _wab(i)
+        feq.append(W[i] * (3.0 * (pb - lam) + rho * U) + 3.0 * (wxx * Txx + wyy * Tyy + wxy * Txy))
+        geq.append(W[i] * (3.0 * gamma[0] * mu_phi + phi * U))
+        keq.append(W[i] * (3.0 * gamma[1] * mu_psi + psi * U))
+    feq = torch.stack([rho - sum(feq)] + feq)
+    geq = torch.stack([phi - sum(geq)] + geq)
+    keq = torch.stack([psi - sum(keq)] + keq)
+    eq = torch.stack([feq, geq, keq])
+    itau = torch.tensor([1.0 / t for t in tau], dtype=pop.dtype).view(3, 1, 1, 1)
+    post = pop - itau * (pop - eq)
+    # pull propagation with half-way bounce-back at the y walls
+    out = []
+    for i in range(9):
+        dx, dy = E[i]
+        pulled = _shift(post[:, i], -dx, -dy)
+        if walls and dy != 0:
+            row = 0 if dy == 1 else ny - 1
+            rows = torch.arange(ny).view(1, ny, 1)
+            pulled = torch.where(rows == row, post[:, OPP[i]], pulled)
+        out.append(pulled)
+    return torch.stack(out, dim=1)
+
+
+def concentrations(pop):
+    rho, phi, psi = pop[0].sum(0), pop[1].sum(0), pop[2].sum(0)
+    return torch.stack([0.5 * (rho + phi - psi), 0.5 * (rho - phi - psi), psi])
+
+
+def run(pop0, h, kappa, alpha, tau, gamma, walls, nsteps):
+    pop = pop0
+    for _ in range(nsteps):
+        pop = step(pop, h, kappa, alpha, tau, gamma, walls)
+    return pop
+
+
+def loss_and_grads(pop0, h, kappa, alpha, tau, gamma, walls, nsteps, target):
+    """L = sum (C1 - C1*)^2 after nsteps from the fixed state pop0; returns (L, dL/dh, dL/dkappa)."""
+    h = h.clone().detach().requires_grad_(True)
+    kappa = kappa.clone().detach().requires_grad_(True)
+    pop = run(pop0, h, kappa, alpha, tau, gamma, walls, nsteps)
+    C1 = concentrations(pop)[0]
+    L = ((C1 - target) ** 2).sum()
+    L.backward()
+    return L.item(), h.grad.detach(), kappa.grad.detach()
