@@ -194,6 +194,45 @@ tlb_status tlb_load_state(tlb_sim* sim, const void* host_src, int64_t step);
 tlb_status tlb_save_state_dev(tlb_sim* sim, void* dev_dst);
 tlb_status tlb_load_state_dev(tlb_sim* sim, const void* dev_src, int64_t step);
 
+/*
+ * Change kappa_1..3 (each > 0) between runs; the wetting ghost values
+ * h_m / (alpha^2 kappa_m) are recomputed from the h_m last set.
+ */
+tlb_status tlb_set_kappa(tlb_sim* sim, const double* kappa);
+
+/* ------------------------------------------------------------------------ */
+/* Reverse mode (D2Q9; TLB_EINVAL for D3Q19)                                 */
+/* ------------------------------------------------------------------------ */
+/*
+ * Adjoint variables lambda live in the layout of the raw state
+ * (tlb_state_bytes() bytes, native precision): lambda_t = dL/du_t where u_t
+ * is the stored state of step t.  One reverse step maps lambda_{t+1} to
+ *   lambda_t = (d u_{t+1} / d u_t)^T lambda_{t+1}
+ * and adds (d u_{t+1} / d theta)^T lambda_{t+1} to the gradients of
+ * theta = (h_m of both walls, kappa_m) (the initial state is held fixed).
+ *
+ * tlb_adjoint_seed_dev: lambda_T from dL/dC of the final state s_T;
+ *   dLdC_dev: [3][N] native precision (dL/dC1, dL/dC2, dL/dC3) or NULL (zero).
+ * tlb_adjoint_step_dev: one reverse step; state_dev is the raw state u_t
+ *   (from tlb_save_state_dev or a checkpoint); lambda_in_dev != lambda_out_dev;
+ *   dh_dev [2][3][nx] FP64 and dkappa_dev [3] FP64 are accumulated into
+ *   (either may be NULL).
+ * tlb_forward_checkpointed: advance nsteps from the current state, storing the
+ *   raw state before steps 0, every, 2*every, ... into ckpt_dev, which holds
+ *   tlb_checkpoint_slots(nsteps, every) states (every ~ sqrt(nsteps)).
+ * tlb_adjoint_backward: with those checkpoints, run the whole reverse pass
+ *   for dL/dC of the state after nsteps: each segment is recomputed from its
+ *   checkpoint into internal scratch (every states) and traversed backwards.
+ *   The simulation's own state is not changed.
+ */
+tlb_status tlb_adjoint_seed_dev(tlb_sim* sim, const void* dLdC_dev, void* lambda_dev);
+tlb_status tlb_adjoint_step_dev(tlb_sim* sim, const void* state_dev, const void* lambda_in_dev,
+                                void* lambda_out_dev, double* dh_dev, double* dkappa_dev);
+int64_t tlb_checkpoint_slots(int64_t nsteps, int64_t every);
+tlb_status tlb_forward_checkpointed(tlb_sim* sim, int64_t nsteps, int64_t every, void* ckpt_dev);
+tlb_status tlb_adjoint_backward(tlb_sim* sim, int64_t nsteps, int64_t every, const void* ckpt_dev,
+                                const void* dLdC_dev, double* dh_dev, double* dkappa_dev);
+
 /* Device-pointer variants (native precision, asynchronous). */
 tlb_status tlb_init_equilibrium_dev(tlb_sim* sim, const void* C_dev, const void* u_dev);
 tlb_status tlb_get_field_dev(tlb_sim* sim, int which, void* out_dev);

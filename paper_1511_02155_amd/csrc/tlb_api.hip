@@ -21,7 +21,16 @@ struct tlb_sim {
     size_t esize;       // bytes per stored value
     void* state[2];     // [3][Q][N] each
     int cur;            // index of the buffer holding u_t
-    void* wet;          // [2][3][nx*nz] or nullptr
+    void* wet;          // [2][3][nx*nz] h_m / (alpha^2 kappa_m), or nullptr
+    double* hbuf;       // [2][3][nx*nz] h_m as set (to rescale when kappa changes)
+    // adjoint scratch (lazy)
+    void* lam[2];
+    void* adjF;
+    void* adjA;
+    double* kfield;
+    double* dhs;        // [2][3][nx*nz] sink for dL/dh when the caller passes none
+    void* seg;
+    int64_t seg_cap;
     void* fields;       // [11][N] (lazy)
     double* staging;    // device doubles for host I/O (lazy)
     size_t staging_elems;
@@ -204,6 +213,9 @@ extern "C" tlb_status tlb_create(const tlb_params* params, void* stream, tlb_sim
         const size_t wb = (size_t)2 * 3 * params->nx * params->nz * s->esize;
         e = hipMalloc(&s->wet, wb);
         if (e == hipSuccess) e = hipMemsetAsync(s->wet, 0, wb, s->stream);
+        if (e == hipSuccess) e = hipMalloc((void**)&s->hbuf, (size_t)2 * 3 * params->nx * params->nz * sizeof(double));
+        if (e == hipSuccess)
+            e = hipMemsetAsync(s->hbuf, 0, (size_t)2 * 3 * params->nx * params->nz * sizeof(double), s->stream);
         if (e != hipSuccess) {
             tlb_destroy(s);
             return hip_fail(e);
@@ -227,6 +239,8 @@ extern "C" tlb_status tlb_destroy(tlb_sim* s)
     for (int b = 0; b < 2; ++b)
         if (s->state[b]) (void)hipFree(s->state[b]);
     if (s->wet) (void)hipFree(s->wet);
+    for (void* q : {(void*)s->hbuf, s->lam[0], s->lam[1], s->adjF, s->adjA, (void*)s->kfield, (void*)s->dhs, s->seg})
+        if (q) (void)hipFree(q);
     if (s->fields) (void)hipFree(s->fields);
     if (s->staging) (void)hipFree(s->staging);
     if (s->diag_partial) (void)hipFree(s->diag_partial);
@@ -283,19 +297,27 @@ static tlb_status ensure_fields(tlb_sim* s)
 // ---------------------------------------------------------------------------
 // Wetting parameters
 // ---------------------------------------------------------------------------
-template <typename TIn>
-static tlb_status set_wet_impl(tlb_sim* s, int wall, const TIn* h_dev)
+static tlb_status rescale_wet(tlb_sim* s, int wall)
 {
     const int n = s->p.nx * s->p.nz;
     const double a2 = s->p.alpha * s->p.alpha;
     const double i0 = 1.0 / (a2 * s->p.kappa[0]), i1 = 1.0 / (a2 * s->p.kappa[1]), i2 = 1.0 / (a2 * s->p.kappa[2]);
+    const double* h = s->hbuf + (size_t)wall * 3 * n;
     hipError_t e;
     if (s->p.prec == TLB_F32)
-        e = launch_wet<float, TIn>(n, h_dev, i0, i1, i2, (float*)s->wet + (size_t)wall * 3 * n, s->stream);
+        e = launch_wet<float, double>(n, h, i0, i1, i2, (float*)s->wet + (size_t)wall * 3 * n, s->stream);
     else
-        e = launch_wet<double, TIn>(n, h_dev, i0, i1, i2, (double*)s->wet + (size_t)wall * 3 * n, s->stream);
+        e = launch_wet<double, double>(n, h, i0, i1, i2, (double*)s->wet + (size_t)wall * 3 * n, s->stream);
     HIPCHK(e);
     return TLB_OK;
+}
+
+template <typename TIn>
+static tlb_status set_wet_impl(tlb_sim* s, int wall, const TIn* h_dev)
+{
+    const int n = s->p.nx * s->p.nz;
+    HIPCHK(launch_convert<TIn, double>(h_dev, s->hbuf + (size_t)wall * 3 * n, 3 * (int64_t)n, s->stream));
+    return rescale_wet(s, wall);
 }
 
 extern "C" tlb_status tlb_set_wetting(tlb_sim* s, int wall, const double* h)
@@ -359,7 +381,7 @@ extern "C" tlb_status tlb_init_equilibrium_dev(tlb_sim* s, const void* C, const 
 // Stepping
 // ---------------------------------------------------------------------------
 template <typename T>
-static tlb_status step_impl(tlb_sim* s, int64_t nsteps)
+static StepArgs<T> step_args(const tlb_sim* s)
 {
     StepArgs<T> a;
     memset(&a, 0, sizeof(a));
@@ -382,13 +404,25 @@ static tlb_status step_impl(tlb_sim* s, int64_t nsteps)
         a.nchunks = (p.nz + a.chunk - 1) / a.chunk;
     }
     a.nitems = a.ntx * a.nty * a.nchunks;
+    return a;
+}
+
+template <typename T>
+static hipError_t launch_one(const tlb_sim* s, const StepArgs<T>& a)
+{
+    return (s->p.lattice == TLB_D2Q9)
+               ? launch_step2d<T>(a, s->launch.width, s->launch.variant, s->stream)
+               : launch_step3d<T>(a, s->launch.width, s->launch.height, s->launch.variant, s->stream);
+}
+
+template <typename T>
+static tlb_status step_impl(tlb_sim* s, int64_t nsteps)
+{
+    StepArgs<T> a = step_args<T>(s);
     for (int64_t t = 0; t < nsteps; ++t) {
         a.src = (const T*)s->state[s->cur];
         a.dst = (T*)s->state[s->cur ^ 1];
-        hipError_t e = (p.lattice == TLB_D2Q9)
-                           ? launch_step2d<T>(a, s->launch.width, s->launch.variant, s->stream)
-                           : launch_step3d<T>(a, s->launch.width, s->launch.height, s->launch.variant, s->stream);
-        HIPCHK(e);
+        HIPCHK(launch_one<T>(s, a));
         s->cur ^= 1;
         s->step += 1;
         if (s->check_every > 0 && s->step % s->check_every == 0) {
@@ -615,5 +649,152 @@ extern "C" tlb_status tlb_load_state_dev(tlb_sim* s, const void* src, int64_t st
     HIPCHK(hipMemcpyAsync(s->state[s->cur], src, (size_t)tlb_state_bytes(s), hipMemcpyDeviceToDevice, s->stream));
     s->step = step;
     s->ready = true;
+    return TLB_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Parameters that may change between runs, and the adjoint
+// ---------------------------------------------------------------------------
+extern "C" tlb_status tlb_set_kappa(tlb_sim* s, const double* kappa)
+{
+    if (!s || !kappa) return TLB_EINVAL;
+    for (int m = 0; m < 3; ++m)
+        if (!(kappa[m] > 0.0) || !isfinite(kappa[m])) return TLB_EINVAL;
+    for (int m = 0; m < 3; ++m) s->p.kappa[m] = kappa[m];
+    if (s->p.walls_y) {
+        tlb_status st = rescale_wet(s, 0);
+        if (!st) st = rescale_wet(s, 1);
+        if (st) return st;
+    }
+    return TLB_OK;
+}
+
+static tlb_status adj_alloc(tlb_sim* s, int64_t seg_states)
+{
+    const size_t sb = (size_t)tlb_state_bytes(s);
+    for (int b = 0; b < 2; ++b)
+        if (!s->lam[b]) HIPCHK(hipMalloc(&s->lam[b], sb));
+    if (!s->adjF) HIPCHK(hipMalloc(&s->adjF, (size_t)8 * s->N * s->esize));
+    if (!s->adjA) HIPCHK(hipMalloc(&s->adjA, (size_t)17 * s->N * s->esize));
+    if (!s->kfield) HIPCHK(hipMalloc((void**)&s->kfield, (size_t)3 * s->N * sizeof(double)));
+    if (!s->dhs) HIPCHK(hipMalloc((void**)&s->dhs, (size_t)6 * s->p.nx * s->p.nz * sizeof(double)));
+    if (seg_states > s->seg_cap) {
+        if (s->seg) {
+            HIPCHK(hipStreamSynchronize(s->stream));
+            HIPCHK(hipFree(s->seg));
+            s->seg = nullptr;
+            s->seg_cap = 0;
+        }
+        HIPCHK(hipMalloc(&s->seg, sb * (size_t)seg_states));
+        s->seg_cap = seg_states;
+    }
+    return TLB_OK;
+}
+
+template <typename T>
+static tlb_status adj_step(tlb_sim* s, const void* u, const void* lam1, void* lam0, double* dh, double* kfield)
+{
+    HIPCHK(launch_adjoint_step<T>(geom(s), make_phys<T>(s->p), (const T*)u, (const T*)s->wet, (const T*)lam1,
+                                  (T*)lam0, (T*)s->adjF, (T*)s->adjA, dh, kfield, s->stream));
+    return TLB_OK;
+}
+
+static tlb_status adj_step_any(tlb_sim* s, const void* u, const void* lam1, void* lam0, double* dh, double* kfield)
+{
+    return s->p.prec == TLB_F32 ? adj_step<float>(s, u, lam1, lam0, dh, kfield)
+                                : adj_step<double>(s, u, lam1, lam0, dh, kfield);
+}
+
+// dh accumulation target [2][3][nx]: the caller's array, or a scratch sink.
+static double* dh_target(tlb_sim* s, double* dh) { return dh ? dh : s->dhs; }
+
+extern "C" tlb_status tlb_adjoint_seed_dev(tlb_sim* s, const void* dLdC, void* lam)
+{
+    if (!s || !lam) return TLB_EINVAL;
+    if (s->p.lattice != TLB_D2Q9) return TLB_EINVAL;
+    const AuxGeom g = geom(s);
+    hipError_t e = (s->p.prec == TLB_F32) ? launch_adjoint_seed<float>(g, (const float*)dLdC, (float*)lam, s->stream)
+                                          : launch_adjoint_seed<double>(g, (const double*)dLdC, (double*)lam, s->stream);
+    HIPCHK(e);
+    return TLB_OK;
+}
+
+extern "C" tlb_status tlb_adjoint_step_dev(tlb_sim* s, const void* state, const void* lam_in, void* lam_out,
+                                           double* dh, double* dkappa)
+{
+    if (!s || !state || !lam_in || !lam_out || lam_in == lam_out) return TLB_EINVAL;
+    if (s->p.lattice != TLB_D2Q9) return TLB_EINVAL;
+    tlb_status st = adj_alloc(s, 0);
+    if (st) return st;
+    HIPCHK(launch_fill0(s->kfield, 3 * s->N, s->stream));
+    st = adj_step_any(s, state, lam_in, lam_out, dh_target(s, dh), s->kfield);
+    if (st) return st;
+    if (dkappa) HIPCHK(launch_reduce3(s->kfield, s->N, dkappa, s->stream));
+    return TLB_OK;
+}
+
+extern "C" int64_t tlb_checkpoint_slots(int64_t nsteps, int64_t every)
+{
+    if (nsteps < 1 || every < 1) return 0;
+    return (nsteps + every - 1) / every;
+}
+
+extern "C" tlb_status tlb_forward_checkpointed(tlb_sim* s, int64_t nsteps, int64_t every, void* ckpt)
+{
+    if (!s || !ckpt || nsteps < 1 || every < 1) return TLB_EINVAL;
+    if (!s->ready) return TLB_ESTATE;
+    const size_t sb = (size_t)tlb_state_bytes(s);
+    for (int64_t t = 0; t < nsteps; t += every) {
+        HIPCHK(hipMemcpyAsync((char*)ckpt + sb * (size_t)(t / every), s->state[s->cur], sb, hipMemcpyDeviceToDevice,
+                              s->stream));
+        const int64_t n = (t + every <= nsteps) ? every : nsteps - t;
+        tlb_status st = tlb_step(s, n);
+        if (st) return st;
+    }
+    return TLB_OK;
+}
+
+template <typename T>
+static tlb_status recompute(tlb_sim* s, const void* from, int64_t count)
+{
+    // seg[0] = from; seg[k] = step(seg[k-1]) for k < count
+    const size_t sb = (size_t)tlb_state_bytes(s);
+    HIPCHK(hipMemcpyAsync(s->seg, from, sb, hipMemcpyDeviceToDevice, s->stream));
+    StepArgs<T> a = step_args<T>(s);
+    for (int64_t k = 1; k < count; ++k) {
+        a.src = (const T*)((const char*)s->seg + sb * (size_t)(k - 1));
+        a.dst = (T*)((char*)s->seg + sb * (size_t)k);
+        HIPCHK(launch_one<T>(s, a));
+    }
+    return TLB_OK;
+}
+
+extern "C" tlb_status tlb_adjoint_backward(tlb_sim* s, int64_t nsteps, int64_t every, const void* ckpt,
+                                           const void* dLdC, double* dh, double* dkappa)
+{
+    if (!s || !ckpt || nsteps < 1 || every < 1) return TLB_EINVAL;
+    if (s->p.lattice != TLB_D2Q9) return TLB_EINVAL;
+    tlb_status st = adj_alloc(s, every);
+    if (st) return st;
+    const size_t sb = (size_t)tlb_state_bytes(s);
+    HIPCHK(launch_fill0(s->kfield, 3 * s->N, s->stream));
+    st = tlb_adjoint_seed_dev(s, dLdC, s->lam[0]);
+    if (st) return st;
+    int cur = 0;
+    const int64_t nseg = tlb_checkpoint_slots(nsteps, every);
+    for (int64_t seg = nseg - 1; seg >= 0; --seg) {
+        const int64_t t0 = seg * every;
+        const int64_t t1 = (t0 + every <= nsteps) ? t0 + every : nsteps;
+        const void* from = (const char*)ckpt + sb * (size_t)seg;
+        st = (s->p.prec == TLB_F32) ? recompute<float>(s, from, t1 - t0) : recompute<double>(s, from, t1 - t0);
+        if (st) return st;
+        for (int64_t t = t1 - 1; t >= t0; --t) {
+            const void* u = (const char*)s->seg + sb * (size_t)(t - t0);
+            st = adj_step_any(s, u, s->lam[cur], s->lam[cur ^ 1], dh_target(s, dh), s->kfield);
+            if (st) return st;
+            cur ^= 1;
+        }
+    }
+    if (dkappa) HIPCHK(launch_reduce3(s->kfield, s->N, dkappa, s->stream));
     return TLB_OK;
 }

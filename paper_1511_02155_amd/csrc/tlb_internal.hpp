@@ -67,6 +67,17 @@ hipError_t launch_wet(int n, const TIn* h, double inv_a2k0, double inv_a2k1, dou
 
 hipError_t launch_copy16(const void* src, void* dst, int64_t n16, hipStream_t s);
 
+// Adjoint kernels (tlb_adjoint.hip), D2Q9.  F: [8][N], Ab: [17][N] scratch.
+template <typename T>
+hipError_t launch_adjoint_step(const AuxGeom& g, const Phys<T>& P, const T* u, const T* wet, const T* lam1, T* lam0,
+                               T* F, T* Ab, double* dh, double* kbar, hipStream_t s);
+template <typename T>
+hipError_t launch_adjoint_seed(const AuxGeom& g, const T* dC, T* lam, hipStream_t s);
+hipError_t launch_fill0(double* p, int64_t n, hipStream_t s);
+hipError_t launch_reduce3(const double* f, int64_t N, double* out, hipStream_t s);
+template <typename TIn, typename TOut>
+hipError_t launch_convert(const TIn* in, TOut* out, int64_t n, hipStream_t s);
+
 constexpr int kDiagBlocks = 1024;
 constexpr int kDiagSlots = 8;  // mass[3], momentum[3], max|v|, nonfinite
 

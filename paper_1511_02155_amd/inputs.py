@@ -180,3 +180,21 @@ def batched_walls(ndom=512, lo=32, hi=256, steps=5000, seed=4, prec_kappa=(0.005
                          tau_k=1.0, gamma_phi=gp, gamma_psi=gk, steps=steps, C=C,
                          h=uniform_h(nx, tuple(float(v) for v in h))))
     return doms
+
+
+def adjoint_drop_512(n=512, steps=2000, seed_h=5, seed_target=6):
+    """D2Q9 n x n with walls below y = 0 and above y = n-1: per-node h_m on the lower wall
+    ~ U[-0.01, 0.01] (3 x n values, seeded), neutral upper wall; a C1 drop of radius 60
+    centred on the lower wall at x = n/2 in C2; the loss target is the same profile with
+    centre x ~ U[n/2 - 32, n/2 + 32] and radius ~ U[50, 70] (seeded).  kappa = 0.01,
+    alpha = 1, tau = 1, M = 0.1."""
+    gp, gk = mobility_to_gamma(0.1, 1.0, 1.0)
+    w = dict(lattice=0, nx=n, ny=n, nz=1, walls_y=1, kappa=(0.01, 0.01, 0.01), alpha=1.0, tau_f=1.0, tau_g=1.0,
+             tau_k=1.0, gamma_phi=gp, gamma_psi=gk, steps=steps, name=f"d2q9_{n}x{n}_wall_drop_adjoint")
+    w["h"] = random_h(n, -0.01, 0.01, seed=seed_h, bottom_only=True)
+    w["C"] = sessile_drop(n, n, 60.0, x0=n / 2.0)
+    rng = np.random.default_rng(seed_target)
+    xc = rng.uniform(n / 2.0 - 32.0, n / 2.0 + 32.0)
+    R = rng.uniform(50.0, 70.0)
+    w["target"] = sessile_drop(n, n, R, x0=xc)[0]
+    return w

@@ -43,6 +43,8 @@ EXPORTS = (
     "tlb_batch_synchronize", "tlb_batch_set_wetting", "tlb_batch_init_equilibrium", "tlb_batch_step",
     "tlb_batch_get_field", "tlb_batch_get_populations", "tlb_batch_diagnostics", "tlb_batch_set_launch",
     "tlb_batch_get_launch", "tlb_batch_autotune", "tlb_batch_set_graph",
+    "tlb_set_kappa", "tlb_adjoint_seed_dev", "tlb_adjoint_step_dev", "tlb_checkpoint_slots",
+    "tlb_forward_checkpointed", "tlb_adjoint_backward",
 )
 
 
@@ -128,6 +130,13 @@ tlb_batch_set_launch = _sig("tlb_batch_set_launch", ctypes.c_int, [_vp, ctypes.P
 tlb_batch_get_launch = _sig("tlb_batch_get_launch", ctypes.c_int, [_vp, ctypes.POINTER(tlb_launch)])
 tlb_batch_autotune = _sig("tlb_batch_autotune", ctypes.c_int, [_vp, ctypes.c_int32, ctypes.POINTER(tlb_launch)])
 tlb_batch_set_graph = _sig("tlb_batch_set_graph", ctypes.c_int, [_vp, ctypes.c_int32])
+tlb_set_kappa = _sig("tlb_set_kappa", ctypes.c_int, [_vp, _dp])
+tlb_adjoint_seed_dev = _sig("tlb_adjoint_seed_dev", ctypes.c_int, [_vp, _vp, _vp])
+tlb_adjoint_step_dev = _sig("tlb_adjoint_step_dev", ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp])
+tlb_checkpoint_slots = _sig("tlb_checkpoint_slots", ctypes.c_int64, [ctypes.c_int64, ctypes.c_int64])
+tlb_forward_checkpointed = _sig("tlb_forward_checkpointed", ctypes.c_int, [_vp, ctypes.c_int64, ctypes.c_int64, _vp])
+tlb_adjoint_backward = _sig("tlb_adjoint_backward", ctypes.c_int,
+                            [_vp, ctypes.c_int64, ctypes.c_int64, _vp, _vp, _vp, _vp])
 
 
 class TLBError(RuntimeError):
@@ -266,6 +275,15 @@ class Sim:
 
     def bytes_per_node(self):
         return tlb_bytes_per_node(self._h)
+
+    def state_bytes(self):
+        return tlb_state_bytes(self._h)
+
+    def set_kappa(self, kappa):
+        k = _arr(kappa, 3)
+        check(tlb_set_kappa(self._h, k.ctypes.data_as(_dp)), "tlb_set_kappa")
+        for m in range(3):
+            self.params.kappa[m] = float(k[m])
 
     def stream(self):
         return tlb_get_stream(self._h)

@@ -1,0 +1,213 @@
+"""Reverse mode of the D2Q9 step on the GPU.
+
+Checks: the transpose identity <lambda, J v> = <J^T lambda, v> of one step
+(J v from central differences of the GPU forward step, state and wetting
+parameters), gradients of a C1 loss against the PyTorch-CPU autodiff
+reference, independence of the checkpoint interval, the autograd Function,
+and central finite differences at the full 512x512 size.
+"""
+from __future__ import annotations
+
+import ctypes
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1511_02155_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("lattice", "nx", "ny", "nz", "walls_y", "kappa", "alpha", "tau_f", "tau_g", "tau_k", "gamma_phi", "gamma_psi")
+
+
+def _note(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.init()
+    from paper_1511_02155_amd import tlb
+
+    return torch, tlb
+
+
+def _wall_case(nx=24, ny=16, R=7.0, kappa=(0.012, 0.02, 0.016), seed=5):
+    gp, gk = inputs.mobility_to_gamma(0.1, 0.9, 0.8)
+    w = dict(lattice=0, nx=nx, ny=ny, nz=1, walls_y=1, kappa=kappa, alpha=1.1, tau_f=1.0, tau_g=0.9, tau_k=0.8,
+             gamma_phi=gp, gamma_psi=gk)
+    C = inputs.sessile_drop(nx, ny, R, top_layer=0.7 * ny)
+    h = inputs.random_h(nx, -0.003, 0.003, seed=seed, bottom_only=False)
+    target = inputs.sessile_drop(nx, ny, R + 1.5, x0=nx / 2 + 1.0)[0]
+    return w, C, h, target
+
+
+def _sim(torch, tlb, w, C, h, prec, stream):
+    """A tlb_sim on ``stream``; the caller runs its torch work on the same stream."""
+    s = tlb.Sim(tlb.make_params(prec=prec, **{k: w[k] for k in KEYS}), stream=stream.cuda_stream)
+    s.set_wetting_both(h)
+    s.init_equilibrium(C)
+    return s
+
+
+def _dev(torch, s):
+    return torch.empty(s.state_bytes() // 8, dtype=torch.float64, device="cuda")
+
+
+def test_one_step_transpose_identity(env):
+    """<lambda, J v> == <J^T lambda, v> for the state and for h (FP64, walls with wetting)."""
+    torch, tlb = env
+    w, C, h, _ = _wall_case()
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        _transpose_identity(torch, tlb, w, C, h, st)
+
+
+def _transpose_identity(torch, tlb, w, C, h, st):
+    s = _sim(torch, tlb, w, C, h, tlb.TLB_F64, st)
+    s.step(5)
+    u = _dev(torch, s)
+    tlb.check(tlb.tlb_save_state_dev(s.handle, u.data_ptr()), "save")
+    gen = torch.Generator(device="cuda").manual_seed(0)
+    lam = torch.randn(u.shape, dtype=torch.float64, device="cuda", generator=gen)
+    v = torch.randn(u.shape, dtype=torch.float64, device="cuda", generator=gen)
+    dh = torch.zeros((2, 3, w["nx"]), dtype=torch.float64, device="cuda")
+    dk = torch.zeros(3, dtype=torch.float64, device="cuda")
+    lam_out = torch.empty_like(u)
+    tlb.check(tlb.tlb_adjoint_step_dev(s.handle, u.data_ptr(), lam.data_ptr(), lam_out.data_ptr(), dh.data_ptr(),
+                                       dk.data_ptr()), "adjoint step")
+    torch.cuda.synchronize()
+
+    def S(state, hh=None, kap=None):
+        if hh is not None:
+            s.set_wetting_both(hh)
+        if kap is not None:
+            s.set_kappa(kap)
+        tlb.check(tlb.tlb_load_state_dev(s.handle, state.data_ptr(), 0), "load")
+        s.step(1)
+        out = torch.empty_like(state)
+        tlb.check(tlb.tlb_save_state_dev(s.handle, out.data_ptr()), "save")
+        torch.cuda.synchronize()
+        return out
+
+    eps = 1e-6
+    Jv = (S(u + eps * v) - S(u - eps * v)) / (2 * eps)
+    lhs = torch.dot(lam, Jv).item()
+    rhs = torch.dot(lam_out, v).item()
+    assert lhs == pytest.approx(rhs, rel=1e-7)
+    # wetting parameters: directional derivative along a random dh direction
+    dhv = np.random.default_rng(1).normal(size=h.shape)
+    Jh = (S(u, h + eps * dhv) - S(u, h - eps * dhv)) / (2 * eps)
+    s.set_wetting_both(h)
+    assert torch.dot(lam, Jh).item() == pytest.approx((dh.cpu().numpy() * dhv).sum(), rel=1e-7)
+    # kappa
+    for m in range(3):
+        kp, km = list(w["kappa"]), list(w["kappa"])
+        kp[m] += eps
+        km[m] -= eps
+        Jk = (S(u, kap=kp) - S(u, kap=km)) / (2 * eps)
+        assert torch.dot(lam, Jk).item() == pytest.approx(dk[m].item(), rel=1e-6, abs=1e-12)
+        s.set_kappa(w["kappa"])
+
+
+def _gpu_grad(torch, tlb, w, C, h, target, steps, every, prec):
+    from paper_1511_02155_amd.autograd import Runner, TernaryLB
+
+    p = tlb.make_params(prec=prec, **{k: w[k] for k in KEYS})
+    r = Runner(p, C, steps, every=every, h=h)
+    dt = torch.float64 if prec == tlb.TLB_F64 else torch.float32
+    hb = torch.tensor(h[0], dtype=dt, device="cuda", requires_grad=True)
+    kap = torch.tensor(w["kappa"], dtype=torch.float64, device="cuda", requires_grad=True)
+    Cf = TernaryLB.apply(hb, kap, r)
+    tgt = torch.tensor(target.reshape(w["ny"], w["nx"]), dtype=dt, device="cuda")
+    L = ((Cf[0] - tgt) ** 2).sum()
+    L.backward()
+    return L.item(), hb.grad.double().cpu().numpy(), kap.grad.cpu().numpy()
+
+
+def test_gradients_match_autodiff_reference(env, orc):
+    """dL/dh (wall below y=0) and dL/dkappa of L = sum (C1 - C1*)^2 after 30 steps against autograd through
+    the PyTorch-CPU FP64 reference started from the same initial state."""
+    torch, tlb = env
+    from oracle import torch_ref
+
+    w, C, h, target = _wall_case()
+    steps = 30
+    L, dh, dk = _gpu_grad(torch, tlb, w, C, h, target, steps, 6, tlb.TLB_F64)
+    p = orc.Params(**{k: w[k] for k in KEYS})
+    pop0 = orc.init_equilibrium(p, C, None, h)
+    t0 = torch.tensor(pop0.reshape(3, 9, w["ny"], w["nx"]))
+    hh = torch.tensor(h.reshape(2, 3, w["nx"]))
+    Lr, dhr, dkr = torch_ref.loss_and_grads(t0, hh, torch.tensor(w["kappa"], dtype=torch.float64), w["alpha"],
+                                            (w["tau_f"], w["tau_g"], w["tau_k"]), (w["gamma_phi"], w["gamma_psi"]),
+                                            True, steps, torch.tensor(target.reshape(w["ny"], w["nx"])))
+    assert L == pytest.approx(Lr, rel=1e-11)
+    scale = np.abs(dhr[0].numpy()).max()
+    assert np.abs(dh - dhr[0].numpy()).max() <= 1e-9 * scale
+    assert np.allclose(dk, dkr.numpy(), rtol=1e-9, atol=1e-12 * np.abs(dkr.numpy()).max())
+
+
+def test_checkpoint_interval_does_not_change_gradients(env):
+    torch, tlb = env
+    w, C, h, target = _wall_case(nx=30, ny=18)
+    res = [_gpu_grad(torch, tlb, w, C, h, target, 37, every, tlb.TLB_F64) for every in (1, 6, 37)]
+    for r in res[1:]:
+        assert r[0] == res[0][0]
+        assert np.array_equal(r[1], res[0][1]) and np.array_equal(r[2], res[0][2])
+
+
+def test_fp32_gradients_close_to_fp64(env):
+    torch, tlb = env
+    w, C, h, target = _wall_case(nx=40, ny=24, R=10.0)
+    _, dh64, dk64 = _gpu_grad(torch, tlb, w, C, h, target, 60, 8, tlb.TLB_F64)
+    _, dh32, dk32 = _gpu_grad(torch, tlb, w, C, h, target, 60, 8, tlb.TLB_F32)
+    assert np.abs(dh32 - dh64).max() <= 2e-3 * np.abs(dh64).max()
+    assert np.allclose(dk32, dk64, rtol=2e-3)
+
+
+def test_adjoint_512_full_size_vs_finite_differences(env):
+    """512x512, wall below y=0 with seeded per-node h_m in [-0.01, 0.01], a C1 drop
+    of radius 60 on the wall (h not clipped); L = sum (C1 - C1*)^2 against a seeded target drop; 2000 steps, FP64, checkpoints
+    every 45 steps.  Gradient entries against central differences of the full forward run."""
+    torch, tlb = env
+    w = inputs.adjoint_drop_512()
+    _note("adjoint 512^2 fp64 2000 steps")
+    L, dh, dk = _gpu_grad(torch, tlb, w, w["C"], w["h"], w["target"], w["steps"], 45, tlb.TLB_F64)
+    p = tlb.make_params(prec=tlb.TLB_F64, **{k: w[k] for k in KEYS})
+    s = tlb.Sim(p)
+    s.set_wetting_both(w["h"])
+    s.init_equilibrium(w["C"])
+    raw, _ = s.save_state()
+
+    def loss(hb=None, kap=None):
+        hh = w["h"].copy()
+        if hb is not None:
+            hh[0] = hb
+        s.set_kappa(kap if kap is not None else w["kappa"])
+        s.set_wetting_both(hh)
+        s.load_state(raw, 0)
+        s.step(w["steps"])
+        return float(((s.field("C1") - w["target"]) ** 2).sum())
+
+    assert loss() == pytest.approx(L, rel=1e-12)
+    eps = 1e-6
+    big = np.argsort(-np.abs(dh).ravel())[:2]
+    for flat in big:
+        m, x = divmod(int(flat), w["nx"])
+        hp, hm = w["h"][0].copy(), w["h"][0].copy()
+        hp[m, x] += eps
+        hm[m, x] -= eps
+        fd = (loss(hb=hp) - loss(hb=hm)) / (2 * eps)
+        assert dh[m, x] == pytest.approx(fd, rel=1e-6), (m, x)
+    for m in range(3):
+        kp, km = list(w["kappa"]), list(w["kappa"])
+        kp[m] *= 1 + eps
+        km[m] *= 1 - eps
+        fd = (loss(kap=kp) - loss(kap=km)) / (2 * eps * w["kappa"][m])
+        assert dk[m] == pytest.approx(fd, rel=1e-6), m
