@@ -23,6 +23,40 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+_CSRC = "paper_1511_02155_amd/csrc/"
+_COMMON = [_CSRC + "tlb_device.hpp", _CSRC + "tlb_internal.hpp", "paper_1511_02155_amd/build.py"]
+# sources that decide each measured kernel's code; its counter readings are used only while they are unchanged
+KERNEL_SOURCES = {
+    "step2d": _COMMON + [_CSRC + "tlb_sweep2d.hpp", _CSRC + "tlb_step2d.hip"],
+    "step3d": _COMMON + [_CSRC + "tlb_step3d.hip"],
+    "batch2d": _COMMON + [_CSRC + "tlb_sweep2d.hpp", _CSRC + "tlb_batch.hip"],
+    "adjoint": _COMMON + [_CSRC + "tlb_adjoint.hip"],
+}
+
+
+def kernel_sha(kind):
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[kind]:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload):
+    """HBM bytes per launch (read + write) of a workload's dominant kernel from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE scaled by the copy-kernel calibration), or None when there is no
+    reading or the kernel's sources changed since it was taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)[workload]
+    except (OSError, KeyError, ValueError):
+        return None
+    if rec.get("source_sha") != kernel_sha(rec["kind"]):
+        return None
+    return rec["read_bytes_per_launch"] + rec["write_bytes_per_launch"]
 
 
 def _events_time(torch, stream, fn):
@@ -62,6 +96,8 @@ def run_plain(tlb, torch, w, prec, steps, warmup, launch=None):
         bytes_per_launch=bytes_per_launch,
         nodes=N,
         launch=sim.launch(),
+        steps=steps,
+        kernel="k_step2d" if w["lattice"] == 0 else "k_step3d",
         mass=d["mass"],
         max_speed=d["max_speed"],
         nonfinite=d["nonfinite"],
@@ -92,9 +128,77 @@ def run_batched(tlb, torch, steps, warmup=10, graph_steps=50):
     bytes_per_step = 216.0 * nodes
     out = dict(mlups=nodes * steps / (ms * 1e-3) / 1e6, ms_per_step=ms / steps,
                achieved_GBps=bytes_per_step / (ms / steps * 1e-3) / 1e9, domains=len(doms), nodes=nodes,
-               steps=steps, launch=chosen, graph_steps=graph_steps)
-    out["frac_of_hbm"] = out["achieved_GBps"] / HBM_PEAK_GBS
+               steps=steps, launch=chosen, graph_steps=graph_steps, bytes_per_launch=bytes_per_step,
+               kernel="k_batch2d")
     b.close()
+    return out
+
+
+def run_adjoint(tlb, torch, prec, steps, grad_runs=1):
+    """The 512x512 walled drop workload of the gradient problem (per-node h on the wall below y = 0).
+
+    (1) The reverse step alone: `steps` calls of tlb_adjoint_step_dev on a fixed state with the adjoint
+    populations ping-ponged, timed with events on the library's stream; algorithmic bytes per node are
+    81 values (read s_t and lambda_{t+1}, write lambda_t).  (2) A whole gradient: forward with a
+    checkpoint every 45 steps plus the checkpointed backward (which recomputes each segment) over the
+    workload's 2000 steps through the torch.autograd Function."""
+    from paper_1511_02155_amd.autograd import Runner, TernaryLB
+
+    w = inputs_mod().adjoint_drop_512()
+    keys = ("lattice", "nx", "ny", "nz", "walls_y", "kappa", "alpha", "tau_f", "tau_g", "tau_k", "gamma_phi",
+            "gamma_psi")
+    p = tlb.make_params(prec=prec, **{k: w[k] for k in keys})
+    dt = torch.float64 if prec == tlb.TLB_F64 else torch.float32
+    esize = 8 if prec == tlb.TLB_F64 else 4
+    N = w["nx"] * w["ny"]
+    stream = torch.cuda.Stream()
+    sim = tlb.Sim(p, stream=stream.cuda_stream)
+    sim.set_wetting_both(w["h"])
+    sim.init_equilibrium(w["C"])
+    sim.step(50)
+    with torch.cuda.stream(stream):
+        u = torch.empty(sim.state_bytes() // esize, dtype=dt, device="cuda")
+        lam = [torch.zeros_like(u), torch.zeros_like(u)]
+        dh = torch.zeros((2, 3, w["nx"]), dtype=torch.float64, device="cuda")
+        dk = torch.zeros(3, dtype=torch.float64, device="cuda")
+        tlb.check(tlb.tlb_save_state_dev(sim.handle, u.data_ptr()), "tlb_save_state_dev")
+        lam[0].normal_()
+    sim.synchronize()
+
+    def go(n):
+        for t in range(n):
+            tlb.check(tlb.tlb_adjoint_step_dev(sim.handle, u.data_ptr(), lam[t & 1].data_ptr(),
+                                               lam[(t + 1) & 1].data_ptr(), dh.data_ptr(), dk.data_ptr()),
+                      "tlb_adjoint_step_dev")
+
+    go(10)
+    sim.synchronize()
+    ms = _events_time(torch, stream, lambda: go(steps))
+    alg = 81.0 * esize
+    out = dict(mlups=N * steps / (ms * 1e-3) / 1e6, ms_per_step=ms / steps, steps=steps, bytes_per_node=alg,
+               bytes_per_launch=alg * N, achieved_GBps=alg * N / (ms / steps * 1e-3) / 1e9,
+               kernel="reverse step (tlb_adjoint_step_dev)")
+    sim.close()
+    del u, lam
+    # a whole gradient through the autograd Function
+    r = Runner(p, w["C"], w["steps"], every=45, h=w["h"])
+    tgt = torch.tensor(w["target"].reshape(w["ny"], w["nx"]), dtype=dt, device="cuda")
+
+    def grad():
+        hb = torch.tensor(w["h"][0], dtype=dt, device="cuda", requires_grad=True)
+        kap = torch.tensor(w["kappa"], dtype=torch.float64, device="cuda", requires_grad=True)
+        C = TernaryLB.apply(hb, kap, r)
+        L = ((C[0] - tgt) ** 2).sum()
+        L.backward()
+        return hb, kap
+
+    grad()
+    cur = torch.cuda.current_stream()
+    ms_g = _events_time(torch, cur, lambda: [grad() for _ in range(grad_runs)]) / grad_runs
+    out.update(gradient_ms=ms_g, gradient_steps=w["steps"], checkpoint_every=45,
+               gradient_mlups=N * w["steps"] / (ms_g * 1e-3) / 1e6,
+               note="gradient_mlups counts each of the 2000 time steps once (forward, recompute and "
+                    "reverse step all included)")
     return out
 
 
@@ -145,9 +249,9 @@ def main():
     ap.add_argument("--steps", type=int, default=10000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle timing")
-    ap.add_argument("--cpu-steps", type=int, default=40)
+    ap.add_argument("--cpu-steps", type=int, default=300)
     ap.add_argument("--quick", action="store_true", help="headline only (no extra workloads)")
-    ap.add_argument("--only", default=None, help="run a single workload: f64, f32, d3q19, batched")
+    ap.add_argument("--only", default=None, help="run a single workload: f64, f32, d3q19, batched, adjoint64, adjoint32")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -162,68 +266,86 @@ def main():
     from paper_1511_02155_amd import inputs, tlb
 
     w2 = inputs.spinodal_2d(1024, args.steps)
-    extra = {}
-    if args.only in (None, "f64"):
+    sel = args.only
+    every = sel is None and not args.quick
+    res = {}  # workload name -> measurements, the headline first
+
+    def add(name, r):
+        r["frac_of_hbm"] = r["achieved_GBps"] / HBM_PEAK_GBS
+        t = measured_traffic(name)
+        r["traffic"] = t
+        if t is not None:
+            r["traffic_over_algorithmic"] = t / r["bytes_per_launch"]
+        res[name] = r
+
+    if sel in (None, "f64"):
         print(f"[bench] d2q9 1024^2 f64: {args.warmup} warm-up + {args.steps} timed steps", file=sys.stderr,
               flush=True)
-        head = run_plain(tlb, torch, w2, tlb.TLB_F64, args.steps, args.warmup)
-    if args.only == "f32":
-        head = run_plain(tlb, torch, w2, tlb.TLB_F32, args.steps, args.warmup)
-    if args.only == "d3q19":
-        w3 = inputs.spinodal_3d(256, args.steps)
-        head = run_plain(tlb, torch, w3, tlb.TLB_F32, args.steps, args.warmup)
-    if args.only == "batched":
-        r = run_batched(tlb, torch, args.steps)
-        head = dict(mlups=r["mlups"], ms_per_step=r["ms_per_step"], achieved_GBps=r["achieved_GBps"],
-                    bytes_per_launch=216.0 * r["nodes"], launch=r["launch"], nonfinite=0, mass=None)
-    if args.only is None and not args.quick:
-        print("[bench] d2q9 1024^2 f32", file=sys.stderr, flush=True)
+        add("d2q9_1024x1024_spinodal_f64", run_plain(tlb, torch, w2, tlb.TLB_F64, args.steps, args.warmup))
+    if sel == "f32" or every:
+        print(f"[bench] d2q9 1024^2 f32: {args.steps} steps", file=sys.stderr, flush=True)
         r = run_plain(tlb, torch, w2, tlb.TLB_F32, args.steps, args.warmup)
-        extra["d2q9_1024x1024_spinodal_f32"] = dict(
-            mlups=r["mlups"], ms_per_step=r["ms_per_step"], achieved_GBps=r["achieved_GBps"],
-            frac_of_hbm=r["achieved_GBps"] / HBM_PEAK_GBS, steps=args.steps, launch=r["launch"],
-            note="working set 226 MB fits the 256 MB Infinity Cache (cache-assisted)")
-        s3 = max(50, min(2000, args.steps // 20))
-        print(f"[bench] d3q19 256^3 f32, {s3} steps", file=sys.stderr, flush=True)
-        w3 = inputs.spinodal_3d(256, s3)
-        r = run_plain(tlb, torch, w3, tlb.TLB_F32, s3, 10)
-        extra["d3q19_256cube_spinodal_f32"] = dict(
-            mlups=r["mlups"], ms_per_step=r["ms_per_step"], achieved_GBps=r["achieved_GBps"],
-            frac_of_hbm=r["achieved_GBps"] / HBM_PEAK_GBS, steps=s3, launch=r["launch"])
-        sb = max(100, min(5000, args.steps // 2))
-        print(f"[bench] batched 512 domains f32, {sb} steps", file=sys.stderr, flush=True)
-        extra["batched_512_domains_f32"] = run_batched(tlb, torch, sb)
+        r["note"] = "working set 226 MB fits the 256 MB Infinity Cache (cache-assisted)"
+        add("d2q9_1024x1024_spinodal_f32", r)
+    if sel == "d3q19" or every:
+        s3 = args.steps if sel else max(50, min(2000, args.steps // 20))
+        print(f"[bench] d3q19 256^3 f32: {s3} steps", file=sys.stderr, flush=True)
+        add("d3q19_256cube_spinodal_f32", run_plain(tlb, torch, inputs.spinodal_3d(256, s3), tlb.TLB_F32, s3, 10))
+    if sel == "batched" or every:
+        sb = args.steps if sel else max(100, min(5000, args.steps // 2))
+        print(f"[bench] batched 512 domains f32: {sb} steps", file=sys.stderr, flush=True)
+        add("batched_512_domains_f32", run_batched(tlb, torch, sb))
+    for name, prec in (("f64", tlb.TLB_F64), ("f32", tlb.TLB_F32)):
+        if sel == "adjoint" + name[1:] or every:
+            sa = args.steps if sel else max(100, min(2000, args.steps // 5))
+            print(f"[bench] adjoint 512^2 {name}: {sa} reverse steps + one 2000-step gradient", file=sys.stderr,
+                  flush=True)
+            add(f"adjoint_512x512_wall_drop_{name}", run_adjoint(tlb, torch, prec, sa))
+    if not res:
+        sys.exit(f"unknown --only {sel!r}")
 
-    extra["copy_kernel_GBps"] = copy_ceiling(tlb, torch)
+    copy_gbps = copy_ceiling(tlb, torch)
+    hname = next(iter(res))
+    head = res.pop(hname)
     line = {
         "metric": "ternary LB MLUPS + % HBM BW; batched & adjoint vs plain step, same GPU",
         "value": head["mlups"],
         "unit": "MLUPS",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": head["steps"],
         "warmup": args.warmup,
         "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.only in (None, "f64") else "f32",
-        "data": "synthetic (seeded spinodal noise, no dataset)",
-        "config": {"workload": "d2q9_1024x1024_spinodal" if args.only != "d3q19" else "d3q19_256cube_spinodal",
-                   "lattice": "D2Q9" if args.only != "d3q19" else "D3Q19", "nx": 1024, "ny": 1024,
-                   "boundary": "periodic", "kappa": [0.01, 0.015, 0.02], "alpha": 1.0, "tau": 1.0,
-                   "mobility": 0.1, "launch": head["launch"]},
+        "dtype": hname.rsplit("_", 1)[1],
+        "data": "synthetic (seeded initial fields, no dataset)",
+        "config": {"workload": hname, **WORKLOAD_CONFIG.get(hname, {}), "launch": head.get("launch")},
         "roofline": {"bound": "hbm", "achieved": head["achieved_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": head["achieved_GBps"] / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_step2d (fused pull-stream + collide)",
-                     "bytes_per_launch": head["bytes_per_launch"]},
-        "check": {"nonfinite": head["nonfinite"], "mass": head["mass"]},
+                     "frac": head["frac_of_hbm"], "traffic": head["traffic"],
+                     "kernel": head.get("kernel"), "bytes_per_launch": head["bytes_per_launch"],
+                     "frac_of_copy_kernel": head["achieved_GBps"] / copy_gbps},
+        "check": {"nonfinite": head.get("nonfinite"), "mass": head.get("mass")},
     }
-    if not args.no_cpu and args.only in (None, "f64"):
+    if not args.no_cpu and hname == "d2q9_1024x1024_spinodal_f64":
         print(f"[bench] cpu oracle, {args.cpu_steps} steps", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(w2, args.cpu_steps)
-    line["roofline"]["frac_of_copy_kernel"] = head["achieved_GBps"] / extra["copy_kernel_GBps"]
-    line["extra"] = extra
+    res["copy_kernel_GBps"] = copy_gbps
+    line["extra"] = res
     print(json.dumps(line))
+
+
+WORKLOAD_CONFIG = {
+    "d2q9_1024x1024_spinodal_f64": dict(lattice="D2Q9", nx=1024, ny=1024, boundary="periodic",
+                                        kappa=[0.01, 0.015, 0.02], alpha=1.0, tau=1.0, mobility=0.1),
+    "d2q9_1024x1024_spinodal_f32": dict(lattice="D2Q9", nx=1024, ny=1024, boundary="periodic",
+                                        kappa=[0.01, 0.015, 0.02], alpha=1.0, tau=1.0, mobility=0.1),
+    "d3q19_256cube_spinodal_f32": dict(lattice="D3Q19", nx=256, ny=256, nz=256, boundary="periodic",
+                                       kappa=[0.01, 0.01, 0.01], alpha=1.0, tau=0.8, mobility=0.05),
+    "batched_512_domains_f32": dict(lattice="D2Q9", domains=512, side=[32, 256], boundary="walls_y"),
+    "adjoint_512x512_wall_drop_f64": dict(lattice="D2Q9", nx=512, ny=512, boundary="walls_y", form="reverse step"),
+    "adjoint_512x512_wall_drop_f32": dict(lattice="D2Q9", nx=512, ny=512, boundary="walls_y", form="reverse step"),
+}
 
 
 if __name__ == "__main__":

@@ -294,20 +294,37 @@ __global__ void k_fill0(double* p, int64_t n)
     if (i < n) p[i] = 0.0;
 }
 
-// Fixed-order reduction of the kappa field [3][N] into out[3] (+=): one block per component.
-__global__ __launch_bounds__(256) void k_reduce3(const double* __restrict__ f, int64_t N, double* __restrict__ out)
+// Fixed-order reduction of the kappa field [3][N] into out[3] (+=) in two passes: kRedBlocks blocks per
+// component sum fixed contiguous ranges into part[3][kRedBlocks], then one block per component sums those.
+__device__ __forceinline__ double block_sum256(double v, double* red)
 {
-    __shared__ double red[256];
-    const int m = blockIdx.x;
-    double acc = 0.0;
-    for (int64_t i = threadIdx.x; i < N; i += 256) acc += f[m * N + i];
-    red[threadIdx.x] = acc;
+    red[threadIdx.x] = v;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
         if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) out[m] += red[0];
+    return red[0];
+}
+
+__global__ __launch_bounds__(256) void k_reduce3a(const double* __restrict__ f, int64_t N, double* __restrict__ part)
+{
+    __shared__ double red[256];
+    const int m = blockIdx.x / kRedBlocks, j = blockIdx.x % kRedBlocks;
+    const int64_t per = (N + kRedBlocks - 1) / kRedBlocks;
+    const int64_t lo = j * per, hi = lo + per < N ? lo + per : N;
+    double acc = 0.0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += 256) acc += f[m * N + i];
+    const double t = block_sum256(acc, red);
+    if (threadIdx.x == 0) part[m * kRedBlocks + j] = t;
+}
+
+__global__ __launch_bounds__(256) void k_reduce3b(const double* __restrict__ part, double* __restrict__ out)
+{
+    __shared__ double red[256];
+    static_assert(kRedBlocks == 256, "one partial per lane");
+    const double t = block_sum256(part[blockIdx.x * kRedBlocks + threadIdx.x], red);
+    if (threadIdx.x == 0) out[blockIdx.x] += t;
 }
 
 inline dim3 gridN(int64_t N) { return dim3((unsigned)((N + 255) / 256)); }
@@ -337,9 +354,10 @@ hipError_t launch_fill0(double* p, int64_t n, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_reduce3(const double* f, int64_t N, double* out, hipStream_t s)
+hipError_t launch_reduce3(const double* f, int64_t N, double* part, double* out, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_reduce3, dim3(3), dim3(256), 0, s, f, N, out);
+    hipLaunchKernelGGL(k_reduce3a, dim3(3 * kRedBlocks), dim3(256), 0, s, f, N, part);
+    hipLaunchKernelGGL(k_reduce3b, dim3(3), dim3(256), 0, s, part, out);
     return hipGetLastError();
 }
 

@@ -676,7 +676,7 @@ static tlb_status adj_alloc(tlb_sim* s, int64_t seg_states)
         if (!s->lam[b]) HIPCHK(hipMalloc(&s->lam[b], sb));
     if (!s->adjF) HIPCHK(hipMalloc(&s->adjF, (size_t)8 * s->N * s->esize));
     if (!s->adjA) HIPCHK(hipMalloc(&s->adjA, (size_t)17 * s->N * s->esize));
-    if (!s->kfield) HIPCHK(hipMalloc((void**)&s->kfield, (size_t)3 * s->N * sizeof(double)));
+    if (!s->kfield) HIPCHK(hipMalloc((void**)&s->kfield, ((size_t)3 * s->N + 3 * kRedBlocks) * sizeof(double)));
     if (!s->dhs) HIPCHK(hipMalloc((void**)&s->dhs, (size_t)6 * s->p.nx * s->p.nz * sizeof(double)));
     if (seg_states > s->seg_cap) {
         if (s->seg) {
@@ -729,7 +729,7 @@ extern "C" tlb_status tlb_adjoint_step_dev(tlb_sim* s, const void* state, const 
     HIPCHK(launch_fill0(s->kfield, 3 * s->N, s->stream));
     st = adj_step_any(s, state, lam_in, lam_out, dh_target(s, dh), s->kfield);
     if (st) return st;
-    if (dkappa) HIPCHK(launch_reduce3(s->kfield, s->N, dkappa, s->stream));
+    if (dkappa) HIPCHK(launch_reduce3(s->kfield, s->N, s->kfield + 3 * s->N, dkappa, s->stream));
     return TLB_OK;
 }
 
@@ -795,6 +795,6 @@ extern "C" tlb_status tlb_adjoint_backward(tlb_sim* s, int64_t nsteps, int64_t e
             cur ^= 1;
         }
     }
-    if (dkappa) HIPCHK(launch_reduce3(s->kfield, s->N, dkappa, s->stream));
+    if (dkappa) HIPCHK(launch_reduce3(s->kfield, s->N, s->kfield + 3 * s->N, dkappa, s->stream));
     return TLB_OK;
 }

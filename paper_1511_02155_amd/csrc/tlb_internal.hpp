@@ -74,7 +74,9 @@ hipError_t launch_adjoint_step(const AuxGeom& g, const Phys<T>& P, const T* u, c
 template <typename T>
 hipError_t launch_adjoint_seed(const AuxGeom& g, const T* dC, T* lam, hipStream_t s);
 hipError_t launch_fill0(double* p, int64_t n, hipStream_t s);
-hipError_t launch_reduce3(const double* f, int64_t N, double* out, hipStream_t s);
+// kappa-field reduction; part holds 3 * kRedBlocks doubles of scratch
+constexpr int kRedBlocks = 256;
+hipError_t launch_reduce3(const double* f, int64_t N, double* part, double* out, hipStream_t s);
 template <typename TIn, typename TOut>
 hipError_t launch_convert(const TIn* in, TOut* out, int64_t n, hipStream_t s);
 
