@@ -177,7 +177,7 @@ def run_adjoint(tlb, torch, prec, steps, grad_runs=1):
     alg = 81.0 * esize
     out = dict(mlups=N * steps / (ms * 1e-3) / 1e6, ms_per_step=ms / steps, steps=steps, bytes_per_node=alg,
                bytes_per_launch=alg * N, achieved_GBps=alg * N / (ms / steps * 1e-3) / 1e9,
-               kernel="reverse step (tlb_adjoint_step_dev)")
+               kernel="k_adj2d (fused reverse step)")
     sim.close()
     del u, lam
     # a whole gradient through the autograd Function

@@ -246,8 +246,7 @@ tlb_status tlb_set_wetting_dev(tlb_sim* sim, int wall, const void* h_dev);
  *     over `chunk` rows; variant 1 prefetches the next row's populations while
  *     the current row is collided, variant 0 does not.
  *   D3Q19: each workgroup sweeps a tile of width x height columns (32x8 or
- *     64x4; for TLB_F32 with variant 0 also 32x16 and 64x8) over `chunk`
- *     planes; variant 1 keeps the next plane's populations in registers
+ *     64x4) over `chunk` planes; variant 1 keeps the next plane's populations in registers
  *     between their two uses, variant 0 reads them a second time from cache.
  *   chunk >= 1; chunk = 0 picks a default.  Results are bitwise identical for
  *   every shape and variant.
@@ -257,6 +256,17 @@ typedef struct {
 } tlb_launch;
 tlb_status tlb_set_launch(tlb_sim* sim, const tlb_launch* launch);
 tlb_status tlb_get_launch(const tlb_sim* sim, tlb_launch* out);
+
+/* Launch shape of the reverse step (D2Q9 only; TLB_EINVAL otherwise): each
+ * workgroup of `width` lanes (64, 128 or 256) covers `width` columns and
+ * produces the middle width - 6 of them over `chunk` rows (chunk >= 1;
+ * 0 picks a default); variant 1 issues the loads of all four stages of a
+ * row before its arithmetic, variant 0 those of stage 4 only when it starts
+ * (fewer registers).  height is ignored.  The adjoint
+ * populations and dL/dh do not depend on the shape; dL/dkappa is summed per
+ * work item, so its last bits do (it is reproducible for a fixed shape). */
+tlb_status tlb_set_adjoint_launch(tlb_sim* sim, const tlb_launch* launch);
+tlb_status tlb_get_adjoint_launch(const tlb_sim* sim, tlb_launch* out);
 
 /* Algorithmic HBM bytes one fused step moves per fluid node (read + write). */
 double tlb_bytes_per_node(const tlb_sim* sim);

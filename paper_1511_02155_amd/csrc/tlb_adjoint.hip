@@ -8,18 +8,33 @@
 // the gradients G_m(r) and Laplacians L_m(r) of C_m over the 9-point
 // neighbourhood, including the wetting ghost rows
 //   C_m(ghost) = C_m(adjacent) + h_m / (alpha^2 kappa_m).
-// Its transpose runs in three per-node passes:
-//   1. moments and concentrations of s_t = P u_t                 (k_adj_fields)
-//   2. the local transpose of E and of the relaxation: adjoints of the
-//      moments, of C_m used locally, of G_m and L_m, and the direct kappa
-//      terms                                                      (k_adj_local)
-//   3. the transposed stencils  Cbar_m(r) += sum_i [3 w_i e_i . Gbar_m(r - e_i)
-//      + 6 w_i Lbar_m(r - e_i)] - 6 (1 - w_0) Lbar_m(r), the transpose of the
-//      ghost rows (hbar_m += Cbar_ghost / (alpha^2 kappa_m) and the kappa term
-//      of the ghost value), the transpose of the moments, and the transpose of
-//      P (a push through the inverse permutation)                 (k_adj_push)
-// Per-node kappa contributions accumulate in an FP64 field that is reduced
-// at the end, so every sum has a fixed order.
+// Its transpose, for one node r, is
+//   1. the moments and concentrations of s_t(r) = (P u_t)(r);
+//   2. the local transpose of E and of the relaxation at r, given
+//      lambda_{t+1}(r): adjoints of the moments and of C_m used locally
+//      (Abar), of the gradients (Gbar_m) and of the Laplacians (Lbar_m), and
+//      the direct kappa terms;
+//   3. the transposed stencils
+//        Cbar_m(r) = Abar_C(r) - 6 (1 - w_0) Lbar_m(r)
+//                    + sum_i [3 w_i e_i . Gbar_m(r - e_i) + 6 w_i Lbar_m(r - e_i)],
+//      the transpose of the ghost rows (hbar_m += Cbar_ghost / (alpha^2 kappa_m),
+//      and the kappa term of the ghost value) and the transpose of the moments,
+//      which leave sbar_i(r) = (1 - omega) lambda_{t+1,i}(r) + S(r) + e_i . J(r);
+//   4. the transpose of P, written as a gather:
+//        lambda_{t,i}(r) = sbar_i(r + e_i), or sbar_opp(i)(r) where r + e_i lies
+//      beyond a wall.
+// The dependency radius is 3 nodes.  k_adj2d runs all four stages in one
+// sweep: a workgroup of W lanes covers W columns and produces the middle
+// W - 6 of them, sweeping a chunk of rows with the stages three rows apart
+// (stage 1 at row a, stage 2 at a-1, stage 3 at a-2, stage 4 at a-3).  The
+// per-row quantities that neighbours need (dC_m; Gbar, Lbar; S, J) live in
+// three-row LDS rings, the rest in registers.  HBM traffic per node and step:
+// u_t and lambda_{t+1} read, lambda_t written (81 values); the overlapping
+// halo rows and columns are re-read from L2.
+//
+// The kappa gradient is summed per work item in a fixed order (lanes, then a
+// tree) into its own slot kpart[m][item], which the caller reduces in a
+// fixed order, so results do not depend on scheduling.
 #include <stdint.h>
 
 #include "../../include/tlb.h"
@@ -32,115 +47,51 @@ namespace {
 using L9 = D2Q9;
 
 __device__ __forceinline__ int wrapi(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
-
-// Scratch layouts: F [8][N] = dC_m (3), drho, jx, jy, phi, dpsi;
-// Abar [17][N] = drho_b, jx_b, jy_b, phi_b, dpsi_b, cbar_m (3), Gbar_{m,a} (6, m-major), Lbar_m (3).
-constexpr int kF = 8, kA = 17;
-
-template <typename T>
-__global__ void k_adj_fields(AuxGeom g, const T* __restrict__ u, T* __restrict__ F)
+__device__ __forceinline__ int modi(int a, int n)
 {
-    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= g.N) return;
-    const int x = (int)(n % g.nx), y = (int)(n / g.nx);
-    T f[9], gg[9], k[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        const int ys = y - L9::ey[i];
-        int64_t off;
-        if (g.walls && (ys < 0 || ys >= g.ny))
-            off = (int64_t)L9::opp[i] * g.N + n;
-        else
-            off = (int64_t)i * g.N + (int64_t)wrapi(ys, g.ny) * g.nx + wrapi(x - L9::ex[i], g.nx);
-        f[i] = u[off];
-        gg[i] = u[9 * g.N + off];
-        k[i] = u[18 * g.N + off];
-    }
-    const Moments<T> mo = moments<L9, T>(f, gg, k);
-    T dc[3];
-    conc_dev<T>(mo, dc);
-    F[0 * g.N + n] = dc[0];
-    F[1 * g.N + n] = dc[1];
-    F[2 * g.N + n] = dc[2];
-    F[3 * g.N + n] = mo.drho;
-    F[4 * g.N + n] = mo.jx;
-    F[5 * g.N + n] = mo.jy;
-    F[6 * g.N + n] = mo.phi;
-    F[7 * g.N + n] = mo.dpsi;
+    const int r = a % n;
+    return r < 0 ? r + n : r;
 }
 
-// dC_m at neighbour (x + dx, y + dy) with the ghost rule beyond walls.
-template <typename T>
-__device__ __forceinline__ T dc_at(const AuxGeom& g, const T* F, const T* wet, int m, int x, int y)
+// Local transpose at one node (stage 2).  Inputs: the node's moments, its dC_m,
+// gradients gx, gy and Laplacians lC of C_m, and lambda_{t+1} at the node.
+// Outputs: lb = (rho, jx, jy, phi, psi adjoints; Cbar_m used locally) [8],
+// bG[m][a] (gradient adjoints), bL[m] (Laplacian adjoints), kb[m] (direct kappa terms).
+template <typename T, typename S>
+__device__ __forceinline__ void adj_local(const Phys<T>& P, const Moments<T>& mo, const T dc[3], const T gx[3],
+                                          const T gy[3], const T lC[3], const S* lam, T lb[8], T bG[3][2], T bL[3],
+                                          T kb[3])
 {
-    x = wrapi(x, g.nx);
-    if (g.walls) {
-        if (y < 0) return F[m * g.N + x] + wet[(0 * 3 + m) * g.nx + x];
-        if (y >= g.ny) return F[m * g.N + (int64_t)(g.ny - 1) * g.nx + x] + wet[(1 * 3 + m) * g.nx + x];
-    } else {
-        y = wrapi(y, g.ny);
-    }
-    return F[m * g.N + (int64_t)y * g.nx + x];
-}
-
-template <typename T>
-__global__ void k_adj_local(AuxGeom g, Phys<T> P, const T* __restrict__ F, const T* __restrict__ wet,
-                            const T* __restrict__ lam1, T* __restrict__ Ab, double* __restrict__ kbar)
-{
-    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= g.N) return;
-    const int x = (int)(n % g.nx), y = (int)(n / g.nx);
-    // forward quantities at the node
-    T dc[3], gx[3], gy[3], lC[3];
-#pragma unroll
-    for (int m = 0; m < 3; ++m) {
-        dc[m] = F[m * g.N + n];
-        T sx = 0, sy = 0, lp = 0;
-#pragma unroll
-        for (int i = 1; i < 9; ++i) {
-            const T c = dc_at<T>(g, F, wet, m, x + L9::ex[i], y + L9::ey[i]);
-            const T w = T(weight<L9>(i));
-            sx += w * T(L9::ex[i]) * c;
-            sy += w * T(L9::ey[i]) * c;
-            lp += w * (c - dc[m]);
-        }
-        gx[m] = T(3) * sx;
-        gy[m] = T(3) * sy;
-        lC[m] = T(6) * lp;
-    }
-    const T drho = F[3 * g.N + n], jx = F[4 * g.N + n], jy = F[5 * g.N + n];
-    const T phi = F[6 * g.N + n], dpsi = F[7 * g.N + n];
+    // T: arithmetic type; S: storage type of lambda
     const T third = T(1.0 / 3.0);
-    T c[3], mu[3];
-    T pbx = drho * third, lam = 0, Txx = 0, Tyy = 0, Txy = 0;
+    T c[3];
+    T Txx = 0, Tyy = 0, Txy = 0;
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
         c[m] = third + dc[m];
-        mu[m] = P.kappa[m] * c[m] * (T(1) - c[m]) * (T(1) - T(2) * c[m]) - P.a2kappa[m] * lC[m];
-        pbx += T(0.5) * P.kappa[m] * c[m] * c[m] * (T(1) - c[m]) * (T(1) - T(3) * c[m]);
-        lam += P.a2kappa[m] * c[m] * lC[m];
         Txx += P.a2kappa[m] * gx[m] * gx[m];
         Tyy += P.a2kappa[m] * gy[m] * gy[m];
         Txy += P.a2kappa[m] * gx[m] * gy[m];
     }
-    (void)mu;
-    const T rho = T(1) + drho, irho = T(1) / rho;
-    const T vx = jx * irho, vy = jy * irho, psi = third + dpsi, vv = vx * vx + vy * vy;
+    (void)Txx, (void)Tyy, (void)Txy;
+    const T rho = T(1) + mo.drho, irho = T(1) / rho;
+    const T vx = mo.jx * irho, vy = mo.jy * irho, psi = third + mo.dpsi, vv = vx * vx + vy * vy;
+    const T phi = mo.phi;
 
     // adjoint of the relaxation: Ebar = omega lambda'; rest populations from the mass constraints
     T af[9], ag[9], ak[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-        af[i] = P.omega[0] * lam1[(int64_t)i * g.N + n];
-        ag[i] = P.omega[1] * lam1[(int64_t)(9 + i) * g.N + n];
-        ak[i] = P.omega[2] * lam1[(int64_t)(18 + i) * g.N + n];
+        af[i] = P.omega[0] * T(lam[i]);
+        ag[i] = P.omega[1] * T(lam[9 + i]);
+        ak[i] = P.omega[2] * T(lam[18 + i]);
     }
     T b_drho = af[0], b_phi = ag[0], b_dpsi = ak[0];
     T bA = 0, b_rho = 0, bBp = 0, bBk = 0, b_psi = 0, bTxx = 0, bTyy = 0, bTxy = 0, bvx = 0, bvy = 0, bvv = 0;
 #pragma unroll
     for (int i = 1; i < 9; ++i) {
         const T w = T(weight<L9>(i));
-        const T fb = af[i] - af[0], gb = ag[i] - ag[0], kb = ak[i] - ak[0];
+        const T fb = af[i] - af[0], gb = ag[i] - ag[0], kb_ = ak[i] - ak[0];
         const T ev = T(L9::ex[i]) * vx + T(L9::ey[i]) * vy;
         const T U = T(3) * ev + T(4.5) * ev * ev - T(1.5) * vv;
         bA += w * fb;
@@ -150,9 +101,9 @@ __global__ void k_adj_local(AuxGeom g, Phys<T> P, const T* __restrict__ F, const
         bTxy += T(3 * woff<L9>(i, 0, 1)) * fb;
         bBp += w * gb;
         b_phi += w * U * gb;
-        bBk += w * kb;
-        b_psi += w * U * kb;
-        const T bU = w * (rho * fb + phi * gb + psi * kb);
+        bBk += w * kb_;
+        b_psi += w * U * kb_;
+        const T bU = w * (rho * fb + phi * gb + psi * kb_);
         const T bev = bU * (T(3) + T(9) * ev);
         bvv += T(-1.5) * bU;
         bvx += T(L9::ex[i]) * bev;
@@ -169,7 +120,6 @@ __global__ void k_adj_local(AuxGeom g, Phys<T> P, const T* __restrict__ F, const
     const T bmu[3] = {T(0.5) * bmu_phi - T(0.5) * bmu_psi, T(-0.5) * bmu_phi - T(0.5) * bmu_psi, bmu_psi};
     b_drho += b_pbx * third;
     const T a2 = P.a2kappa[0] / P.kappa[0];
-    T cbar[3], bG[3][2], bL[3];
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
         const T cm = c[m];
@@ -177,97 +127,265 @@ __global__ void k_adj_local(AuxGeom g, Phys<T> P, const T* __restrict__ F, const
         const T dq = T(1) - T(6) * cm + T(6) * cm * cm;
         const T pp = cm * cm * (T(1) - cm) * (T(1) - T(3) * cm);
         const T dp = T(2) * cm - T(12) * cm * cm + T(12) * cm * cm * cm;
-        cbar[m] = bmu[m] * P.kappa[m] * dq + b_pbx * T(0.5) * P.kappa[m] * dp + b_lam * P.a2kappa[m] * lC[m];
+        lb[5 + m] = bmu[m] * P.kappa[m] * dq + b_pbx * T(0.5) * P.kappa[m] * dp + b_lam * P.a2kappa[m] * lC[m];
         bL[m] = -P.a2kappa[m] * bmu[m] + b_lam * P.a2kappa[m] * cm;
         bG[m][0] = bTxx * T(2) * P.a2kappa[m] * gx[m] + bTxy * P.a2kappa[m] * gy[m];
         bG[m][1] = bTyy * T(2) * P.a2kappa[m] * gy[m] + bTxy * P.a2kappa[m] * gx[m];
-        const T kb = bmu[m] * (q - a2 * lC[m]) + b_pbx * T(0.5) * pp + b_lam * a2 * cm * lC[m] +
-                     a2 * (bTxx * gx[m] * gx[m] + bTyy * gy[m] * gy[m] + bTxy * gx[m] * gy[m]);
-        kbar[m * g.N + n] += (double)kb;
+        kb[m] = bmu[m] * (q - a2 * lC[m]) + b_pbx * T(0.5) * pp + b_lam * a2 * cm * lC[m] +
+                a2 * (bTxx * gx[m] * gx[m] + bTyy * gy[m] * gy[m] + bTxy * gx[m] * gy[m]);
     }
-    Ab[0 * g.N + n] = b_drho;
-    Ab[1 * g.N + n] = b_jx;
-    Ab[2 * g.N + n] = b_jy;
-    Ab[3 * g.N + n] = b_phi;
-    Ab[4 * g.N + n] = b_dpsi;
-#pragma unroll
-    for (int m = 0; m < 3; ++m) {
-        Ab[(5 + m) * g.N + n] = cbar[m];
-        Ab[(8 + 2 * m) * g.N + n] = bG[m][0];
-        Ab[(9 + 2 * m) * g.N + n] = bG[m][1];
-        Ab[(14 + m) * g.N + n] = bL[m];
-    }
+    lb[0] = b_drho;
+    lb[1] = b_jx;
+    lb[2] = b_jy;
+    lb[3] = b_phi;
+    lb[4] = b_dpsi;
 }
 
+template <typename T, int W, int HOIST>
+__global__ __launch_bounds__(W) void k_adj2d(AdjArgs<T> A)
+{
+    using C = acc_t<T>;  // arithmetic type (T is the storage type)
+    constexpr int R = 3;
+    __shared__ C sC[R][3][W];  // dC_m of the last three stage-1 rows
+    __shared__ C sA[R][9][W];  // Gbar_{m,x}, Gbar_{m,y} (m-major), Lbar_m of the last three stage-2 rows
+    __shared__ C sS[R][5][W];  // S_f, J_x, J_y, S_g, S_k of the last three stage-3 rows
+    __shared__ double sred[3][W];
+
+    const int item = xcd_item(blockIdx.x, gridDim.x);
+    const int strip = item / A.nchunks, chunk = item - strip * A.nchunks;
+    const int l = threadIdx.x;
+    const int nx = A.nx, ny = A.ny;
+    const int N = (int)A.N;
+    const int x0 = strip * (W - 6);
+    const int x = modi(x0 - 3 + l, nx);
+    const int xm = wrapi(x - 1, nx), xp = wrapi(x + 1, nx);
+    const bool own_x = l >= 3 && l < W - 3 && x0 + (l - 3) < nx;
+    const int y0 = chunk * A.chunk;
+    const int y1 = (y0 + A.chunk < ny) ? y0 + A.chunk : ny;
+    const bool walls = A.walls != 0;
+    const Phys<C> P = A.P;
+    const C w0 = C(weight<L9>(0));
+
+    Moments<C> mom_prev = {};
+    C lb_prev[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    double kacc[3] = {0.0, 0.0, 0.0};
+
+    for (int a = y0 - 3, it = 0; a < y1 + 3; ++a, ++it) {
+        const int b = a - 1, c = a - 2, d = a - 3;
+        const bool act1 = !walls || (a >= 0 && a < ny);
+        const bool act2 = b >= y0 - 2 && (!walls || (b >= 0 && b < ny)) && l >= 1 && l < W - 1;
+        const bool act3 = c >= y0 - 1 && (!walls || (c >= 0 && c < ny)) && l >= 2 && l < W - 2;
+        const bool act4 = d >= y0 && own_x;
+        // ---- the global loads of the iteration come first: the pull of row a (stage 1), lambda_{t+1}
+        // of row b (stage 2) and, with HOIST, the gather of lambda_{t+1} around row d (stage 4), so
+        // that none of them waits behind a store of stage 4 ----
+        T pu[27], la[27], lg[27];
+        auto gather = [&]() {
+#pragma unroll
+            for (int j = 0; j < 9; ++j) {
+                const int yy = d + L9::ey[j];
+                int dir, src;
+                if (walls && (yy < 0 || yy >= ny)) {
+                    dir = L9::opp[j];
+                    src = d * nx + x;
+                } else {
+                    dir = j;
+                    src = wrapi(yy, ny) * nx + wrapi(x + L9::ex[j], nx);
+                }
+                lg[j] = A.lam1[dir * N + src];
+                lg[9 + j] = A.lam1[(9 + dir) * N + src];
+                lg[18 + j] = A.lam1[(18 + dir) * N + src];
+            }
+        };
+        if (act1) {
+            const int row = walls ? a : modi(a, ny);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                const int ys = row - L9::ey[i];
+                int o;
+                if (walls && (ys < 0 || ys >= ny))
+                    o = L9::opp[i] * N + row * nx + x;
+                else
+                    o = i * N + wrapi(ys, ny) * nx + wrapi(x - L9::ex[i], nx);
+                pu[i] = A.u[o];
+                pu[9 + i] = A.u[9 * N + o];
+                pu[18 + i] = A.u[18 * N + o];
+            }
+        }
+        if (act2) {
+            const int n = (walls ? b : modi(b, ny)) * nx + x;
+#pragma unroll
+            for (int q = 0; q < 27; ++q) la[q] = A.lam1[q * N + n];
+        }
+        if (HOIST && act4) gather();
+        // ---- stage 1: moments and dC of row a ----
+        Moments<C> mom_new = {};
+        if (act1) {
+            mom_new = moments<L9, T>(pu, pu + 9, pu + 18);
+            C dc[3];
+            conc_dev<C>(mom_new, dc);
+#pragma unroll
+            for (int m = 0; m < 3; ++m) sC[it % R][m][l] = dc[m];
+        }
+        __syncthreads();
+        // ---- stage 2: stencils and local transpose of row b = a - 1 ----
+        C lb_new[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (act2) {
+            const int s0 = (it + 2) % R, sm = (it + 1) % R, sp = it % R;
+            const bool glo = walls && b == 0, ghi = walls && b == ny - 1;
+            C dc[3], gx[3], gy[3], lC[3];
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                // 3x3 neighbourhood v[dy+1][dx+1]
+                C v[3][3];
+                v[1][0] = sC[s0][m][l - 1];
+                v[1][1] = sC[s0][m][l];
+                v[1][2] = sC[s0][m][l + 1];
+                if (glo) {
+                    const T* wl = A.wet + m * nx;
+                    v[0][0] = v[1][0] + C(wl[xm]);
+                    v[0][1] = v[1][1] + C(wl[x]);
+                    v[0][2] = v[1][2] + C(wl[xp]);
+                } else {
+                    v[0][0] = sC[sm][m][l - 1];
+                    v[0][1] = sC[sm][m][l];
+                    v[0][2] = sC[sm][m][l + 1];
+                }
+                if (ghi) {
+                    const T* wh = A.wet + (3 + m) * nx;
+                    v[2][0] = v[1][0] + C(wh[xm]);
+                    v[2][1] = v[1][1] + C(wh[x]);
+                    v[2][2] = v[1][2] + C(wh[xp]);
+                } else {
+                    v[2][0] = sC[sp][m][l - 1];
+                    v[2][1] = sC[sp][m][l];
+                    v[2][2] = sC[sp][m][l + 1];
+                }
+                dc[m] = v[1][1];
+                C sx = 0, sy = 0, lp = 0;
+#pragma unroll
+                for (int i = 1; i < 9; ++i) {
+                    const C c = v[1 + L9::ey[i]][1 + L9::ex[i]];
+                    const C w = C(weight<L9>(i));
+                    sx += w * C(L9::ex[i]) * c;
+                    sy += w * C(L9::ey[i]) * c;
+                    lp += w * (c - dc[m]);
+                }
+                gx[m] = C(3) * sx;
+                gy[m] = C(3) * sy;
+                lC[m] = C(6) * lp;
+            }
+            C bG[3][2], bL[3], kb[3];
+            adj_local<C, T>(P, mom_prev, dc, gx, gy, lC, la, lb_new, bG, bL, kb);
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                sA[s0][2 * m][l] = bG[m][0];
+                sA[s0][2 * m + 1][l] = bG[m][1];
+                sA[s0][6 + m][l] = bL[m];
+            }
+            if (own_x && b >= y0 && b < y1) {
+#pragma unroll
+                for (int m = 0; m < 3; ++m) kacc[m] += (double)kb[m];
+            }
+        }
+        __syncthreads();
+        // ---- stage 3: transposed stencils, ghost transposes, moment transpose of row c = a - 2 ----
+        if (act3) {
+            const int q0 = (it + 1) % R, qm = it % R, qp = (it + 2) % R;
+            C Cb[3];
+#pragma unroll
+            for (int m = 0; m < 3; ++m) Cb[m] = lb_prev[5 + m] - C(6) * (C(1) - w0) * sA[q0][6 + m][l];
+#pragma unroll
+            for (int i = 1; i < 9; ++i) {
+                const int ey = L9::ey[i], ex = L9::ex[i];
+                if (walls && ((ey == 1 && c == 0) || (ey == -1 && c == ny - 1))) continue;
+                const int sl = ey == 0 ? q0 : (ey == 1 ? qm : qp);  // row c - ey
+                const int ln = l - ex;
+                const C w = C(weight<L9>(i));
+#pragma unroll
+                for (int m = 0; m < 3; ++m)
+                    Cb[m] += C(3) * w * (C(ex) * sA[sl][2 * m][ln] + C(ey) * sA[sl][2 * m + 1][ln]) +
+                             C(6) * w * sA[sl][6 + m][ln];
+            }
+            if (walls && (c == 0 || c == ny - 1)) {
+                const int wall = (c == 0) ? 0 : 1;
+                const int side = (c == 0) ? -1 : 1;
+                C Cg[3] = {0, 0, 0};
+#pragma unroll
+                for (int i = 1; i < 9; ++i) {
+                    if (L9::ey[i] != side) continue;
+                    const int ex = L9::ex[i], ey = L9::ey[i];
+                    const int ln = l - ex;
+                    const C w = C(weight<L9>(i));
+#pragma unroll
+                    for (int m = 0; m < 3; ++m)
+                        Cg[m] += C(3) * w * (C(ex) * sA[q0][2 * m][ln] + C(ey) * sA[q0][2 * m + 1][ln]) +
+                                 C(6) * w * sA[q0][6 + m][ln];
+                }
+                const bool own = own_x && c >= y0 && c < y1;
+#pragma unroll
+                for (int m = 0; m < 3; ++m) {
+                    Cb[m] += Cg[m];
+                    if (own) {
+                        // C_ghost = C_adj + h / (alpha^2 kappa):  d/dh = 1/(alpha^2 kappa), d/dkappa = -wet / kappa
+                        A.dh[(wall * 3 + m) * nx + x] += (double)Cg[m] / (double)P.a2kappa[m];
+                        kacc[m] -= (double)Cg[m] * (double)A.wet[(wall * 3 + m) * nx + x] / (double)P.kappa[m];
+                    }
+                }
+            }
+            // transpose of C1 = (rho + phi - psi)/2, C2 = (rho - phi - psi)/2, C3 = psi
+            sS[q0][0][l] = lb_prev[0] + C(0.5) * (Cb[0] + Cb[1]);
+            sS[q0][1][l] = lb_prev[1];
+            sS[q0][2][l] = lb_prev[2];
+            sS[q0][3][l] = lb_prev[3] + C(0.5) * (Cb[0] - Cb[1]);
+            sS[q0][4][l] = lb_prev[4] - C(0.5) * (Cb[0] + Cb[1]) + Cb[2];
+        }
+        __syncthreads();
+        // ---- stage 4: lambda_t of row d = a - 3 from the gathered lambda_{t+1} and S, J ----
+        if (act4) {
+            if (!HOIST) gather();  // all 27 loads before the first store
+            const int p0 = it % R, pm = (it + 2) % R, pp = (it + 1) % R;
+            const int n = d * nx + x;
+#pragma unroll
+            for (int j = 0; j < 9; ++j) {
+                const int yy = d + L9::ey[j];
+                const bool bb = walls && (yy < 0 || yy >= ny);
+                const int ln = bb ? l : l + L9::ex[j];
+                const int sl = bb ? p0 : (L9::ey[j] == 0 ? p0 : (L9::ey[j] == 1 ? pp : pm));
+                const C sgn = bb ? C(-1) : C(1);  // e of the gathered direction: e_j, or e_opp(j) = -e_j
+                const C Sf = sS[sl][0][ln], Jx = sS[sl][1][ln], Jy = sS[sl][2][ln];
+                const C Sg = sS[sl][3][ln], Sk = sS[sl][4][ln];
+                A.lam0[j * N + n] =
+                    T((C(1) - P.omega[0]) * C(lg[j]) + Sf + sgn * (C(L9::ex[j]) * Jx + C(L9::ey[j]) * Jy));
+                A.lam0[(9 + j) * N + n] = T((C(1) - P.omega[1]) * C(lg[9 + j]) + Sg);
+                A.lam0[(18 + j) * N + n] = T((C(1) - P.omega[2]) * C(lg[18 + j]) + Sk);
+            }
+        }
+        mom_prev = mom_new;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) lb_prev[q] = lb_new[q];
+    }
+    // kappa gradient of the item: lanes in a fixed tree
+#pragma unroll
+    for (int m = 0; m < 3; ++m) sred[m][l] = kacc[m];
+    __syncthreads();
+    for (int w = W / 2; w > 0; w >>= 1) {
+        if (l < w) {
+#pragma unroll
+            for (int m = 0; m < 3; ++m) sred[m][l] += sred[m][l + w];
+        }
+        __syncthreads();
+    }
+    if (l < 3) A.kpart[l * A.nitems + item] += sred[l][0];
+}
+
+// Inverse of the pull: position in u of the value that the pull of node (x, y) reads for direction i.
 template <typename T>
 __device__ __forceinline__ int64_t unstream(const AuxGeom& g, int i, int x, int y)
 {
     const int ys = y - L9::ey[i];
     if (g.walls && (ys < 0 || ys >= g.ny)) return (int64_t)L9::opp[i] * g.N + (int64_t)y * g.nx + x;
     return (int64_t)i * g.N + (int64_t)wrapi(ys, g.ny) * g.nx + wrapi(x - L9::ex[i], g.nx);
-}
-
-template <typename T>
-__global__ void k_adj_push(AuxGeom g, Phys<T> P, const T* __restrict__ Ab, const T* __restrict__ wet,
-                           const T* __restrict__ lam1, T* __restrict__ lam0, double* __restrict__ dh,
-                           double* __restrict__ kbar)
-{
-    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= g.N) return;
-    const int x = (int)(n % g.nx), y = (int)(n / g.nx);
-    const T w0 = T(weight<L9>(0));
-    T Cb[3];
-#pragma unroll
-    for (int m = 0; m < 3; ++m) Cb[m] = Ab[(5 + m) * g.N + n] - T(6) * (T(1) - w0) * Ab[(14 + m) * g.N + n];
-    // transposed stencils: contributions of the nodes r - e_i whose stencils read C(r)
-#pragma unroll
-    for (int i = 1; i < 9; ++i) {
-        const int ys = y - L9::ey[i];
-        if (g.walls && (ys < 0 || ys >= g.ny)) continue;
-        const int64_t nn = (int64_t)wrapi(ys, g.ny) * g.nx + wrapi(x - L9::ex[i], g.nx);
-        const T w = T(weight<L9>(i));
-#pragma unroll
-        for (int m = 0; m < 3; ++m)
-            Cb[m] += T(3) * w * (T(L9::ex[i]) * Ab[(8 + 2 * m) * g.N + nn] + T(L9::ey[i]) * Ab[(9 + 2 * m) * g.N + nn]) +
-                     T(6) * w * Ab[(14 + m) * g.N + nn];
-    }
-    // transposes of the ghost rows below / above this node (walls only)
-    if (g.walls && (y == 0 || y == g.ny - 1)) {
-        const int wall = (y == 0) ? 0 : 1;
-        const int side = (y == 0) ? -1 : 1;  // e_y of the directions that reach the ghost row
-        T Cg[3] = {0, 0, 0};
-#pragma unroll
-        for (int i = 1; i < 9; ++i) {
-            if (L9::ey[i] != side) continue;
-            const int64_t nn = (int64_t)y * g.nx + wrapi(x - L9::ex[i], g.nx);
-            const T w = T(weight<L9>(i));
-#pragma unroll
-            for (int m = 0; m < 3; ++m)
-                Cg[m] += T(3) * w * (T(L9::ex[i]) * Ab[(8 + 2 * m) * g.N + nn] + T(L9::ey[i]) * Ab[(9 + 2 * m) * g.N + nn]) +
-                         T(6) * w * Ab[(14 + m) * g.N + nn];
-        }
-        for (int m = 0; m < 3; ++m) {
-            Cb[m] += Cg[m];
-            // C_ghost = C_adj + h / (alpha^2 kappa):  d/dh = 1/(alpha^2 kappa), d/dkappa = -wet / kappa
-            dh[(wall * 3 + m) * g.nx + x] += (double)Cg[m] / (double)P.a2kappa[m];
-            kbar[m * g.N + n] -= (double)Cg[m] * (double)wet[(wall * 3 + m) * g.nx + x] / (double)P.kappa[m];
-        }
-    }
-    // transpose of C1 = (rho + phi - psi)/2, C2 = (rho - phi - psi)/2, C3 = psi
-    const T b_drho = Ab[0 * g.N + n] + T(0.5) * (Cb[0] + Cb[1]);
-    const T b_jx = Ab[1 * g.N + n], b_jy = Ab[2 * g.N + n];
-    const T b_phi = Ab[3 * g.N + n] + T(0.5) * (Cb[0] - Cb[1]);
-    const T b_dpsi = Ab[4 * g.N + n] - T(0.5) * (Cb[0] + Cb[1]) + Cb[2];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        const int64_t o = unstream<T>(g, i, x, y);
-        const T sf = (T(1) - P.omega[0]) * lam1[(int64_t)i * g.N + n] + b_drho + T(L9::ex[i]) * b_jx + T(L9::ey[i]) * b_jy;
-        const T sg = (T(1) - P.omega[1]) * lam1[(int64_t)(9 + i) * g.N + n] + b_phi;
-        const T sk = (T(1) - P.omega[2]) * lam1[(int64_t)(18 + i) * g.N + n] + b_dpsi;
-        lam0[o] = sf;
-        lam0[9 * g.N + o] = sg;
-        lam0[18 * g.N + o] = sk;
-    }
 }
 
 // lambda_T from dL/dC_m of the state s_T: s_bar = (dC/ds)^T dL/dC, pushed through P^T.
@@ -331,13 +449,22 @@ inline dim3 gridN(int64_t N) { return dim3((unsigned)((N + 255) / 256)); }
 
 }  // namespace
 
-template <typename T>
-hipError_t launch_adjoint_step(const AuxGeom& g, const Phys<T>& P, const T* u, const T* wet, const T* lam1, T* lam0,
-                               T* F, T* Ab, double* dh, double* kbar, hipStream_t s)
+template <typename T, int HOIST>
+static void launch_adj_w(const AdjArgs<T>& a, int width, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_adj_fields<T>), gridN(g.N), dim3(256), 0, s, g, u, F);
-    hipLaunchKernelGGL((k_adj_local<T>), gridN(g.N), dim3(256), 0, s, g, P, F, wet, lam1, Ab, kbar);
-    hipLaunchKernelGGL((k_adj_push<T>), gridN(g.N), dim3(256), 0, s, g, P, Ab, wet, lam1, lam0, dh, kbar);
+    if (width == 64) hipLaunchKernelGGL((k_adj2d<T, 64, HOIST>), dim3(a.nitems), dim3(64), 0, s, a);
+    if (width == 128) hipLaunchKernelGGL((k_adj2d<T, 128, HOIST>), dim3(a.nitems), dim3(128), 0, s, a);
+    if (width == 256) hipLaunchKernelGGL((k_adj2d<T, 256, HOIST>), dim3(a.nitems), dim3(256), 0, s, a);
+}
+
+template <typename T>
+hipError_t launch_adjoint_sweep(const AdjArgs<T>& a, int width, int hoist, hipStream_t s)
+{
+    if (width != 64 && width != 128 && width != 256) return hipErrorInvalidValue;
+    if (hoist)
+        launch_adj_w<T, 1>(a, width, s);
+    else
+        launch_adj_w<T, 0>(a, width, s);
     return hipGetLastError();
 }
 
@@ -361,11 +488,8 @@ hipError_t launch_reduce3(const double* f, int64_t N, double* part, double* out,
     return hipGetLastError();
 }
 
-template hipError_t launch_adjoint_step<float>(const AuxGeom&, const Phys<float>&, const float*, const float*,
-                                               const float*, float*, float*, float*, double*, double*, hipStream_t);
-template hipError_t launch_adjoint_step<double>(const AuxGeom&, const Phys<double>&, const double*, const double*,
-                                                const double*, double*, double*, double*, double*, double*,
-                                                hipStream_t);
+template hipError_t launch_adjoint_sweep<float>(const AdjArgs<float>&, int, int, hipStream_t);
+template hipError_t launch_adjoint_sweep<double>(const AdjArgs<double>&, int, int, hipStream_t);
 template hipError_t launch_adjoint_seed<float>(const AuxGeom&, const float*, float*, hipStream_t);
 template hipError_t launch_adjoint_seed<double>(const AuxGeom&, const double*, double*, hipStream_t);
 

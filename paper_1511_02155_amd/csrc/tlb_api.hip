@@ -25,9 +25,9 @@ struct tlb_sim {
     double* hbuf;       // [2][3][nx*nz] h_m as set (to rescale when kappa changes)
     // adjoint scratch (lazy)
     void* lam[2];
-    void* adjF;
-    void* adjA;
-    double* kfield;
+    double* kpart;      // [3][items] kappa-gradient partials + [3][kRedBlocks] reduction scratch
+    int64_t kpart_cap;  // items the allocation holds
+    tlb_launch adj_launch;
     double* dhs;        // [2][3][nx*nz] sink for dL/dh when the caller passes none
     void* seg;
     int64_t seg_cap;
@@ -126,13 +126,32 @@ static AuxGeom geom(const tlb_sim* s)
     return g;
 }
 
+// Reverse sweep: single-wavefront strips (58 output columns), all loads of a
+// row issued before its arithmetic.  The sweep is latency-bound per row and
+// holds one wavefront per SIMD, so all items should be resident at once:
+// measured on MI355X (512^2 with walls) the best is 6 rows (~800 items) in
+// both precisions.
+static tlb_launch default_adj_launch(const tlb_params& p)
+{
+    tlb_launch l;
+    l.width = 64;
+    l.height = 1;
+    l.variant = 0;
+    const int nstrips = (p.nx + 57) / 58;
+    const int nch = (768 + nstrips - 1) / nstrips;
+    const int chunk = (p.ny + nch - 1) / nch;
+    l.chunk = chunk < 6 ? 6 : chunk;
+    return l;
+}
+
 static void default_launch(tlb_sim* s)
 {
     const tlb_params& p = s->p;
     if (p.lattice == TLB_D2Q9) {
         // Measured on MI355X (1024^2): 256-wide strips, 8 rows per workgroup
-        // (about 2000 wavefronts in flight); FP32 prefetches the next row,
-        // FP64 does not (its prefetch buffer would cost occupancy).
+        // (about 2000 wavefronts in flight), no prefetch of the next row (its
+        // buffer would cost occupancy; the arithmetic is FP64 in both
+        // storage precisions).
         int w = p.nx >= 256 ? 256 : (p.nx >= 128 ? 128 : 64);
         const int ntx = (p.nx + w - 1) / w;
         const int64_t waves_per_item = w / 64;
@@ -143,7 +162,8 @@ static void default_launch(tlb_sim* s)
         s->launch.width = w;
         s->launch.height = 1;
         s->launch.chunk = chunk;
-        s->launch.variant = p.prec == TLB_F32 ? 1 : 0;
+        s->launch.variant = 0;
+        s->adj_launch = default_adj_launch(p);
     } else {
         // Measured on MI355X (256^3 FP32): 64x4 tiles holding the next plane,
         // ~1000 wavefronts in flight.
@@ -169,7 +189,6 @@ static bool launch_valid(const tlb_sim* s, const tlb_launch* l)
     const int w = l->width, h = l->height;
     if (w == 32 && h == 8) return true;
     if (w == 64 && h == 4) return true;
-    if (!l->variant && s->p.prec == TLB_F32 && ((w == 32 && h == 16) || (w == 64 && h == 8))) return true;
     return false;
 }
 
@@ -239,7 +258,7 @@ extern "C" tlb_status tlb_destroy(tlb_sim* s)
     for (int b = 0; b < 2; ++b)
         if (s->state[b]) (void)hipFree(s->state[b]);
     if (s->wet) (void)hipFree(s->wet);
-    for (void* q : {(void*)s->hbuf, s->lam[0], s->lam[1], s->adjF, s->adjA, (void*)s->kfield, (void*)s->dhs, s->seg})
+    for (void* q : {(void*)s->hbuf, s->lam[0], s->lam[1], (void*)s->kpart, (void*)s->dhs, s->seg})
         if (q) (void)hipFree(q);
     if (s->fields) (void)hipFree(s->fields);
     if (s->staging) (void)hipFree(s->staging);
@@ -349,7 +368,7 @@ template <typename T, typename TIn>
 static tlb_status init_impl(tlb_sim* s, const TIn* C, const TIn* u)
 {
     s->cur = 0;
-    HIPCHK(launch_init<T, TIn>(geom(s), make_phys<T>(s->p), C, u, (const T*)s->wet, (T*)s->state[0], s->stream));
+    HIPCHK(launch_init<T, TIn>(geom(s), make_phys<acc_t<T>>(s->p), C, u, (const T*)s->wet, (T*)s->state[0], s->stream));
     s->step = 0;
     s->ready = true;
     return TLB_OK;
@@ -392,7 +411,7 @@ static StepArgs<T> step_args(const tlb_sim* s)
     a.nz = p.nz;
     a.walls = p.walls_y;
     a.N = s->N;
-    a.P = make_phys<T>(p);
+    a.P = make_phys<acc_t<T>>(p);
     a.chunk = s->launch.chunk;
     if (p.lattice == TLB_D2Q9) {
         a.ntx = (p.nx + s->launch.width - 1) / s->launch.width;
@@ -471,6 +490,26 @@ extern "C" tlb_status tlb_get_launch(const tlb_sim* s, tlb_launch* out)
     return TLB_OK;
 }
 
+extern "C" tlb_status tlb_set_adjoint_launch(tlb_sim* s, const tlb_launch* l)
+{
+    if (!s || !l) return TLB_EINVAL;
+    if (s->p.lattice != TLB_D2Q9) return TLB_EINVAL;
+    tlb_launch v = *l;
+    v.height = 1;
+    if (v.chunk == 0) v.chunk = default_adj_launch(s->p).chunk;
+    if ((v.width != 64 && v.width != 128 && v.width != 256) || v.chunk < 1) return TLB_EINVAL;
+    if (v.variant != 0 && v.variant != 1) return TLB_EINVAL;
+    s->adj_launch = v;
+    return TLB_OK;
+}
+
+extern "C" tlb_status tlb_get_adjoint_launch(const tlb_sim* s, tlb_launch* out)
+{
+    if (!s || !out) return TLB_EINVAL;
+    *out = s->adj_launch;
+    return TLB_OK;
+}
+
 extern "C" tlb_status tlb_device_copy(void* dst, const void* src, int64_t bytes, void* stream)
 {
     if (!dst || !src || bytes < 0 || (bytes & 15) || ((uintptr_t)dst & 15) || ((uintptr_t)src & 15)) return TLB_EINVAL;
@@ -494,7 +533,7 @@ static tlb_status field_impl(tlb_sim* s, int which, TOut* out)
     tlb_status st = ensure_fields(s);
     if (st) return st;
     const AuxGeom g = geom(s);
-    HIPCHK(launch_fields<T>(g, make_phys<T>(s->p), (const T*)s->state[s->cur], (const T*)s->wet, (T*)s->fields,
+    HIPCHK(launch_fields<T>(g, make_phys<acc_t<T>>(s->p), (const T*)s->state[s->cur], (const T*)s->wet, (T*)s->fields,
                             s->stream));
     HIPCHK(launch_export_field<T, TOut>(g, (const T*)s->fields, which, out, s->stream));
     return TLB_OK;
@@ -669,14 +708,37 @@ extern "C" tlb_status tlb_set_kappa(tlb_sim* s, const double* kappa)
     return TLB_OK;
 }
 
+// Work decomposition of the reverse sweep: strips of (width - 6) output columns times chunks of rows.
+static void adj_items(const tlb_sim* s, int& nstrips, int& nchunks)
+{
+    const int O = s->adj_launch.width - 6;
+    nstrips = (s->p.nx + O - 1) / O;
+    nchunks = (s->p.ny + s->adj_launch.chunk - 1) / s->adj_launch.chunk;
+}
+
+static int64_t adj_nitems(const tlb_sim* s)
+{
+    int a, b;
+    adj_items(s, a, b);
+    return (int64_t)a * b;
+}
+
 static tlb_status adj_alloc(tlb_sim* s, int64_t seg_states)
 {
     const size_t sb = (size_t)tlb_state_bytes(s);
     for (int b = 0; b < 2; ++b)
         if (!s->lam[b]) HIPCHK(hipMalloc(&s->lam[b], sb));
-    if (!s->adjF) HIPCHK(hipMalloc(&s->adjF, (size_t)8 * s->N * s->esize));
-    if (!s->adjA) HIPCHK(hipMalloc(&s->adjA, (size_t)17 * s->N * s->esize));
-    if (!s->kfield) HIPCHK(hipMalloc((void**)&s->kfield, ((size_t)3 * s->N + 3 * kRedBlocks) * sizeof(double)));
+    const int64_t items = adj_nitems(s);
+    if (items > s->kpart_cap) {
+        if (s->kpart) {
+            HIPCHK(hipStreamSynchronize(s->stream));
+            HIPCHK(hipFree(s->kpart));
+            s->kpart = nullptr;
+            s->kpart_cap = 0;
+        }
+        HIPCHK(hipMalloc((void**)&s->kpart, ((size_t)3 * items + 3 * kRedBlocks) * sizeof(double)));
+        s->kpart_cap = items;
+    }
     if (!s->dhs) HIPCHK(hipMalloc((void**)&s->dhs, (size_t)6 * s->p.nx * s->p.nz * sizeof(double)));
     if (seg_states > s->seg_cap) {
         if (s->seg) {
@@ -692,17 +754,45 @@ static tlb_status adj_alloc(tlb_sim* s, int64_t seg_states)
 }
 
 template <typename T>
-static tlb_status adj_step(tlb_sim* s, const void* u, const void* lam1, void* lam0, double* dh, double* kfield)
+static tlb_status adj_step(tlb_sim* s, const void* u, const void* lam1, void* lam0, double* dh)
 {
-    HIPCHK(launch_adjoint_step<T>(geom(s), make_phys<T>(s->p), (const T*)u, (const T*)s->wet, (const T*)lam1,
-                                  (T*)lam0, (T*)s->adjF, (T*)s->adjA, dh, kfield, s->stream));
+    AdjArgs<T> a;
+    memset(&a, 0, sizeof(a));
+    a.u = (const T*)u;
+    a.lam1 = (const T*)lam1;
+    a.lam0 = (T*)lam0;
+    a.wet = (const T*)s->wet;
+    a.dh = dh;
+    a.kpart = s->kpart;
+    a.nx = s->p.nx;
+    a.ny = s->p.ny;
+    a.walls = s->p.walls_y;
+    a.N = s->N;
+    a.chunk = s->adj_launch.chunk;
+    adj_items(s, a.nstrips, a.nchunks);
+    a.nitems = a.nstrips * a.nchunks;
+    a.P = make_phys<acc_t<T>>(s->p);
+    HIPCHK(launch_adjoint_sweep<T>(a, s->adj_launch.width, s->adj_launch.variant, s->stream));
     return TLB_OK;
 }
 
-static tlb_status adj_step_any(tlb_sim* s, const void* u, const void* lam1, void* lam0, double* dh, double* kfield)
+static tlb_status adj_step_any(tlb_sim* s, const void* u, const void* lam1, void* lam0, double* dh)
 {
-    return s->p.prec == TLB_F32 ? adj_step<float>(s, u, lam1, lam0, dh, kfield)
-                                : adj_step<double>(s, u, lam1, lam0, dh, kfield);
+    return s->p.prec == TLB_F32 ? adj_step<float>(s, u, lam1, lam0, dh) : adj_step<double>(s, u, lam1, lam0, dh);
+}
+
+// Clear the kappa partials before a reverse pass / reduce them into dkappa (+=) after it.
+static tlb_status kpart_clear(tlb_sim* s)
+{
+    HIPCHK(launch_fill0(s->kpart, 3 * adj_nitems(s), s->stream));
+    return TLB_OK;
+}
+
+static tlb_status kpart_reduce(tlb_sim* s, double* dkappa)
+{
+    const int64_t items = adj_nitems(s);
+    if (dkappa) HIPCHK(launch_reduce3(s->kpart, items, s->kpart + 3 * items, dkappa, s->stream));
+    return TLB_OK;
 }
 
 // dh accumulation target [2][3][nx]: the caller's array, or a scratch sink.
@@ -725,12 +815,10 @@ extern "C" tlb_status tlb_adjoint_step_dev(tlb_sim* s, const void* state, const 
     if (!s || !state || !lam_in || !lam_out || lam_in == lam_out) return TLB_EINVAL;
     if (s->p.lattice != TLB_D2Q9) return TLB_EINVAL;
     tlb_status st = adj_alloc(s, 0);
-    if (st) return st;
-    HIPCHK(launch_fill0(s->kfield, 3 * s->N, s->stream));
-    st = adj_step_any(s, state, lam_in, lam_out, dh_target(s, dh), s->kfield);
-    if (st) return st;
-    if (dkappa) HIPCHK(launch_reduce3(s->kfield, s->N, s->kfield + 3 * s->N, dkappa, s->stream));
-    return TLB_OK;
+    if (!st) st = kpart_clear(s);
+    if (!st) st = adj_step_any(s, state, lam_in, lam_out, dh_target(s, dh));
+    if (!st) st = kpart_reduce(s, dkappa);
+    return st;
 }
 
 extern "C" int64_t tlb_checkpoint_slots(int64_t nsteps, int64_t every)
@@ -777,7 +865,8 @@ extern "C" tlb_status tlb_adjoint_backward(tlb_sim* s, int64_t nsteps, int64_t e
     tlb_status st = adj_alloc(s, every);
     if (st) return st;
     const size_t sb = (size_t)tlb_state_bytes(s);
-    HIPCHK(launch_fill0(s->kfield, 3 * s->N, s->stream));
+    st = kpart_clear(s);
+    if (st) return st;
     st = tlb_adjoint_seed_dev(s, dLdC, s->lam[0]);
     if (st) return st;
     int cur = 0;
@@ -790,11 +879,10 @@ extern "C" tlb_status tlb_adjoint_backward(tlb_sim* s, int64_t nsteps, int64_t e
         if (st) return st;
         for (int64_t t = t1 - 1; t >= t0; --t) {
             const void* u = (const char*)s->seg + sb * (size_t)(t - t0);
-            st = adj_step_any(s, u, s->lam[cur], s->lam[cur ^ 1], dh_target(s, dh), s->kfield);
+            st = adj_step_any(s, u, s->lam[cur], s->lam[cur ^ 1], dh_target(s, dh));
             if (st) return st;
             cur ^= 1;
         }
     }
-    if (dkappa) HIPCHK(launch_reduce3(s->kfield, s->N, s->kfield + 3 * s->N, dkappa, s->stream));
-    return TLB_OK;
+    return kpart_reduce(s, dkappa);
 }

@@ -59,17 +59,19 @@ __device__ __forceinline__ int64_t unstream_off(const AuxGeom& g, int i, int x, 
 
 // dC_m at a (possibly ghost) neighbour, read from a [3][N] array of
 // concentrations C (offset 1/3 removed) with the wetting ghost rule.
-template <typename T, typename TIn>
-__device__ __forceinline__ T conc_at(const AuxGeom& g, const TIn* C, T offset, const T* wet, int m, int x, int y,
+template <typename T, typename TIn, typename TW>
+__device__ __forceinline__ T conc_at(const AuxGeom& g, const TIn* C, T offset, const TW* wet, int m, int x, int y,
                                      int z)
 {
     x = wrapi(x, g.nx);
     z = wrapi(z, g.nz);
     const int64_t nxz = (int64_t)g.nx * g.nz;
     if (g.walls) {
-        if (y < 0) return T(C[m * g.N + node_id(g, x, 0, z)]) - offset + wet[(0 * 3 + m) * nxz + x + (int64_t)g.nx * z];
+        if (y < 0)
+            return T(C[m * g.N + node_id(g, x, 0, z)]) - offset + T(wet[(0 * 3 + m) * nxz + x + (int64_t)g.nx * z]);
         if (y >= g.ny)
-            return T(C[m * g.N + node_id(g, x, g.ny - 1, z)]) - offset + wet[(1 * 3 + m) * nxz + x + (int64_t)g.nx * z];
+            return T(C[m * g.N + node_id(g, x, g.ny - 1, z)]) - offset +
+                   T(wet[(1 * 3 + m) * nxz + x + (int64_t)g.nx * z]);
     } else {
         y = wrapi(y, g.ny);
     }
@@ -77,17 +79,17 @@ __device__ __forceinline__ T conc_at(const AuxGeom& g, const TIn* C, T offset, c
 }
 
 // Isotropic stencils d_a X = 3 sum_i w_i e_ia X(r+e_i), lap X = 6 sum_i w_i [X(r+e_i) - X(r)].
-template <class L, typename T, typename TIn>
-__device__ void stencil_at(const AuxGeom& g, const TIn* C, T offset, const T* wet, int x, int y, int z, T dc[3],
+template <class L, typename T, typename TIn, typename TW>
+__device__ void stencil_at(const AuxGeom& g, const TIn* C, T offset, const TW* wet, int x, int y, int z, T dc[3],
                            T gC[3][3], T lC[3])
 {
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
-        dc[m] = conc_at<T, TIn>(g, C, offset, wet, m, x, y, z);
+        dc[m] = conc_at<T, TIn, TW>(g, C, offset, wet, m, x, y, z);
         T gx = 0, gy = 0, gz = 0, lp = 0;
 #pragma unroll
         for (int i = 1; i < L::Q; ++i) {
-            const T c = conc_at<T, TIn>(g, C, offset, wet, m, x + L::ex[i], y + L::ey[i], z + L::ez[i]);
+            const T c = conc_at<T, TIn, TW>(g, C, offset, wet, m, x + L::ex[i], y + L::ey[i], z + L::ez[i]);
             const T w = T(weight<L>(i));
             gx += w * T(L::ex[i]) * c;
             gy += w * T(L::ey[i]) * c;
@@ -102,26 +104,27 @@ __device__ void stencil_at(const AuxGeom& g, const TIn* C, T offset, const T* we
 }
 
 template <class L, typename T, typename TIn>
-__global__ void k_init(AuxGeom g, Phys<T> P, const TIn* __restrict__ C, const TIn* __restrict__ u,
+__global__ void k_init(AuxGeom g, Phys<acc_t<T>> P, const TIn* __restrict__ C, const TIn* __restrict__ u,
                        const T* __restrict__ wet, T* __restrict__ st)
 {
+    using A = acc_t<T>;
     const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= g.N) return;
     int x, y, z;
     node_xyz(g, n, x, y, z);
-    T dc[3], gC[3][3], lC[3];
-    stencil_at<L, T, TIn>(g, C, T(1.0 / 3.0), wet, x, y, z, dc, gC, lC);
-    Moments<T> mo;
+    A dc[3], gC[3][3], lC[3];
+    stencil_at<L, A, TIn, T>(g, C, A(1.0 / 3.0), wet, x, y, z, dc, gC, lC);
+    Moments<A> mo;
     // rho = C1 + C2 + C3, phi = C1 - C2, psi = C3 (Sec. II.C), as deviations
     mo.drho = dc[0] + dc[1] + dc[2];
     mo.phi = dc[0] - dc[1];
     mo.dpsi = dc[2];
-    const T rho = T(1) + mo.drho;
-    mo.jx = u ? rho * T(u[n]) : T(0);
-    mo.jy = u ? rho * T(u[g.N + n]) : T(0);
-    mo.jz = (u && L::D == 3) ? rho * T(u[2 * g.N + n]) : T(0);
+    const A rho = A(1) + mo.drho;
+    mo.jx = u ? rho * A(u[n]) : A(0);
+    mo.jy = u ? rho * A(u[g.N + n]) : A(0);
+    mo.jz = (u && L::D == 3) ? rho * A(u[2 * g.N + n]) : A(0);
     T f[L::Q], gg[L::Q], k[L::Q];
-    equilibrium<L, T>(P, mo, dc, gC, lC, f, gg, k);
+    equilibrium<L>(P, mo, dc, gC, lC, f, gg, k);
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
         const int64_t off = unstream_off<L>(g, i, x, y, z);
@@ -139,37 +142,39 @@ __global__ void k_fields1(AuxGeom g, const T* __restrict__ st, T* __restrict__ F
     if (n >= g.N) return;
     int x, y, z;
     node_xyz(g, n, x, y, z);
+    using A = acc_t<T>;
     T f[L::Q], gg[L::Q], k[L::Q];
     pull_node<L, T>(g, st, x, y, z, f, gg, k);
-    Moments<T> mo = moments<L, T>(f, gg, k);
-    T dc[3];
-    conc_dev<T>(mo, dc);
-    const T irho = T(1) / (T(1) + mo.drho);
-    F[0 * g.N + n] = dc[0];
-    F[1 * g.N + n] = dc[1];
-    F[2 * g.N + n] = dc[2];
-    F[3 * g.N + n] = mo.drho;
-    F[4 * g.N + n] = mo.phi;
-    F[5 * g.N + n] = mo.dpsi;
-    F[6 * g.N + n] = mo.jx * irho;
-    F[7 * g.N + n] = mo.jy * irho;
-    F[8 * g.N + n] = (L::D == 3) ? mo.jz * irho : T(0);
+    const Moments<A> mo = moments<L, T>(f, gg, k);
+    A dc[3];
+    conc_dev<A>(mo, dc);
+    const A irho = A(1) / (A(1) + mo.drho);
+    F[0 * g.N + n] = T(dc[0]);
+    F[1 * g.N + n] = T(dc[1]);
+    F[2 * g.N + n] = T(dc[2]);
+    F[3 * g.N + n] = T(mo.drho);
+    F[4 * g.N + n] = T(mo.phi);
+    F[5 * g.N + n] = T(mo.dpsi);
+    F[6 * g.N + n] = T(mo.jx * irho);
+    F[7 * g.N + n] = T(mo.jy * irho);
+    F[8 * g.N + n] = (L::D == 3) ? T(mo.jz * irho) : T(0);
 }
 
 // Phase 2: chemical potentials from the dC fields with the ghost rule.
 template <class L, typename T>
-__global__ void k_fields2(AuxGeom g, Phys<T> P, const T* __restrict__ wet, T* __restrict__ F)
+__global__ void k_fields2(AuxGeom g, Phys<acc_t<T>> P, const T* __restrict__ wet, T* __restrict__ F)
 {
+    using A = acc_t<T>;
     const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= g.N) return;
     int x, y, z;
     node_xyz(g, n, x, y, z);
-    T dc[3], gC[3][3], lC[3];
-    stencil_at<L, T, T>(g, F, T(0), wet, x, y, z, dc, gC, lC);
-    T mphi, mpsi;
-    chem_potentials<T>(P, dc, lC, mphi, mpsi);
-    F[9 * g.N + n] = mphi;
-    F[10 * g.N + n] = mpsi;
+    A dc[3], gC[3][3], lC[3];
+    stencil_at<L, A, T, T>(g, F, A(0), wet, x, y, z, dc, gC, lC);
+    A mphi, mpsi;
+    chem_potentials<A>(P, dc, lC, mphi, mpsi);
+    F[9 * g.N + n] = T(mphi);
+    F[10 * g.N + n] = T(mpsi);
 }
 
 template <typename T, typename TOut>
@@ -218,7 +223,7 @@ __global__ __launch_bounds__(256) void k_diag1(AuxGeom g, const T* __restrict__ 
         node_xyz(g, n, x, y, z);
         T f[L::Q], gg[L::Q], k[L::Q];
         pull_node<L, T>(g, st, x, y, z, f, gg, k);
-        Moments<T> mo = moments<L, T>(f, gg, k);
+        const auto mo = moments<L, T>(f, gg, k);
         const double rho = 1.0 + (double)mo.drho;
         const double jx = mo.jx, jy = mo.jy, jz = mo.jz;
         const double phi = mo.phi, psi = kPsiRef + (double)mo.dpsi;
@@ -331,7 +336,7 @@ hipError_t launch_copy16(const void* src, void* dst, int64_t n16, hipStream_t s)
 }
 
 template <typename T, typename TIn>
-hipError_t launch_init(const AuxGeom& g, const Phys<T>& P, const TIn* C, const TIn* u, const T* wet, T* state,
+hipError_t launch_init(const AuxGeom& g, const Phys<acc_t<T>>& P, const TIn* C, const TIn* u, const T* wet, T* state,
                        hipStream_t s)
 {
     if (g.lattice == 0)
@@ -342,7 +347,8 @@ hipError_t launch_init(const AuxGeom& g, const Phys<T>& P, const TIn* C, const T
 }
 
 template <typename T>
-hipError_t launch_fields(const AuxGeom& g, const Phys<T>& P, const T* state, const T* wet, T* F, hipStream_t s)
+hipError_t launch_fields(const AuxGeom& g, const Phys<acc_t<T>>& P, const T* state, const T* wet, T* F,
+                         hipStream_t s)
 {
     if (g.lattice == 0) {
         hipLaunchKernelGGL((k_fields1<D2Q9, T>), grid_for(g.N, 256), dim3(256), 0, s, g, state, F);
@@ -405,15 +411,16 @@ hipError_t launch_wet(int n, const TIn* h, double i0, double i1, double i2, T* w
 }
 
 #define TLB_INST_IO(T, TIO)                                                                                   \
-    template hipError_t launch_init<T, TIO>(const AuxGeom&, const Phys<T>&, const TIO*, const TIO*, const T*, T*, \
-                                            hipStream_t);                                                       \
+    template hipError_t launch_init<T, TIO>(const AuxGeom&, const Phys<acc_t<T>>&, const TIO*, const TIO*,       \
+                                            const T*, T*, hipStream_t);                                         \
     template hipError_t launch_export_field<T, TIO>(const AuxGeom&, const T*, int, TIO*, hipStream_t);            \
     template hipError_t launch_get_pops<T, TIO>(const AuxGeom&, const T*, int, TIO*, hipStream_t);                \
     template hipError_t launch_set_pops<T, TIO>(const AuxGeom&, const TIO*, int, T*, hipStream_t);                \
     template hipError_t launch_wet<T, TIO>(int, const TIO*, double, double, double, T*, hipStream_t);
 
 #define TLB_INST(T)                                                                                           \
-    template hipError_t launch_fields<T>(const AuxGeom&, const Phys<T>&, const T*, const T*, T*, hipStream_t); \
+    template hipError_t launch_fields<T>(const AuxGeom&, const Phys<acc_t<T>>&, const T*, const T*, T*,       \
+                                         hipStream_t);                                                          \
     template hipError_t launch_diag<T>(const AuxGeom&, const T*, double*, int, double*, hipStream_t);
 
 TLB_INST(float)

@@ -31,7 +31,7 @@ struct DomDesc {
     int64_t off;      // element offset of the domain's state in a state buffer
     int64_t wet_off;  // element offset of its wetting array, or -1 (no walls)
     int32_t nx, ny, walls, chunk, ntx, nchunks;
-    Phys<T> P;
+    Phys<acc_t<T>> P;
 };
 
 template <typename T>
@@ -238,7 +238,7 @@ static tlb_status build_items(tlb_batch* b)
         D.chunk = std::min(rows, p.ny);
         D.ntx = (p.nx + W - 1) / W;
         D.nchunks = (p.ny + D.chunk - 1) / D.chunk;
-        D.P = phys_of<T>(p);
+        D.P = phys_of<acc_t<T>>(p);
         const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
         load[k] += (int64_t)D.ntx * W * p.ny;
         for (int c = 0; c < D.nchunks; ++c)
@@ -412,11 +412,11 @@ extern "C" tlb_status tlb_batch_init_equilibrium(tlb_batch* b, int32_t dom, cons
         ud = b->staging + 3 * g.N;
     }
     if (b->prec == TLB_F32)
-        BHIP(launch_init<float, double>(g, phys_of<float>(b->p[dom]), b->staging, ud,
+        BHIP(launch_init<float, double>(g, phys_of<acc_t<float>>(b->p[dom]), b->staging, ud,
                                         b->wet_off[dom] >= 0 ? (const float*)b->wet + b->wet_off[dom] : nullptr,
                                         (float*)b->state[b->cur] + b->off[dom], b->stream));
     else
-        BHIP(launch_init<double, double>(g, phys_of<double>(b->p[dom]), b->staging, ud,
+        BHIP(launch_init<double, double>(g, phys_of<acc_t<double>>(b->p[dom]), b->staging, ud,
                                          b->wet_off[dom] >= 0 ? (const double*)b->wet + b->wet_off[dom] : nullptr,
                                          (double*)b->state[b->cur] + b->off[dom], b->stream));
     BHIP(hipStreamSynchronize(b->stream));
@@ -522,12 +522,12 @@ extern "C" tlb_status tlb_batch_get_field(tlb_batch* b, int32_t dom, int which, 
     if (!b->fields) BHIP(hipMalloc(&b->fields, (size_t)TLB_NFIELDS * b->max_nodes * b->esize));
     if (b->prec == TLB_F32) {
         const float* wet = b->wet_off[dom] >= 0 ? (const float*)b->wet + b->wet_off[dom] : nullptr;
-        BHIP(launch_fields<float>(g, phys_of<float>(b->p[dom]), (const float*)b->state[b->cur] + b->off[dom], wet,
+        BHIP(launch_fields<float>(g, phys_of<acc_t<float>>(b->p[dom]), (const float*)b->state[b->cur] + b->off[dom], wet,
                                   (float*)b->fields, b->stream));
         BHIP(launch_export_field<float, double>(g, (const float*)b->fields, which, b->staging, b->stream));
     } else {
         const double* wet = b->wet_off[dom] >= 0 ? (const double*)b->wet + b->wet_off[dom] : nullptr;
-        BHIP(launch_fields<double>(g, phys_of<double>(b->p[dom]), (const double*)b->state[b->cur] + b->off[dom], wet,
+        BHIP(launch_fields<double>(g, phys_of<acc_t<double>>(b->p[dom]), (const double*)b->state[b->cur] + b->off[dom], wet,
                                    (double*)b->fields, b->stream));
         BHIP(launch_export_field<double, double>(g, (const double*)b->fields, which, b->staging, b->stream));
     }

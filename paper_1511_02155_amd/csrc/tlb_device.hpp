@@ -139,6 +139,18 @@ struct Phys {
     T gphi3, gpsi3;  // Gamma_phi / c_s^2, Gamma_psi / c_s^2
 };
 
+// Arithmetic type of the per-node computations for a storage type T.  Both
+// storage precisions compute in FP64: populations are converted on load and
+// rounded once on store, so FP32 storage adds one rounding per value and
+// step and nothing else (the rounding of FP32 arithmetic in the moments,
+// stencils and equilibria would otherwise dominate the FP32 error).
+template <typename T>
+struct Acc {
+    using type = double;
+};
+template <typename T>
+using acc_t = typename Acc<T>::type;
+
 // Moments of one node from its (shifted) populations.
 template <typename T>
 struct Moments {
@@ -149,21 +161,23 @@ struct Moments {
 };
 
 template <class L, typename T>
-__device__ __forceinline__ Moments<T> moments(const T* f, const T* g, const T* k)
+__device__ __forceinline__ Moments<acc_t<T>> moments(const T* f, const T* g, const T* k)
 {
-    Moments<T> m;
-    T r = 0, jx = 0, jy = 0, jz = 0, ph = 0, ps = 0;
+    using C = acc_t<T>;
+    Moments<C> m;
+    C r = 0, jx = 0, jy = 0, jz = 0, ph = 0, ps = 0;
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
-        r += f[i];
-        if (L::ex[i] == 1) jx += f[i];
-        if (L::ex[i] == -1) jx -= f[i];
-        if (L::ey[i] == 1) jy += f[i];
-        if (L::ey[i] == -1) jy -= f[i];
-        if (L::ez[i] == 1) jz += f[i];
-        if (L::ez[i] == -1) jz -= f[i];
-        ph += g[i];
-        ps += k[i];
+        const C fi = C(f[i]);
+        r += fi;
+        if (L::ex[i] == 1) jx += fi;
+        if (L::ex[i] == -1) jx -= fi;
+        if (L::ey[i] == 1) jy += fi;
+        if (L::ey[i] == -1) jy -= fi;
+        if (L::ez[i] == 1) jz += fi;
+        if (L::ez[i] == -1) jz -= fi;
+        ph += C(g[i]);
+        ps += C(k[i]);
     }
     m.drho = r;
     m.jx = jx;
@@ -212,10 +226,11 @@ __device__ __forceinline__ void chem_potentials(const Phys<T>& P, const T dc[3],
 //   g_i^eq = w_i [ Gamma_phi mu_phi / c_s^2 + phi U_i ],  k_i^eq likewise (eq. eqdistfbinary)
 //   U_i    = e_i.v / c_s^2 + (e_i.v)^2 / (2 c_s^4) - v^2 / (2 c_s^2)
 //   rest populations from the mass constraints; BGK with 1/tau per species.
-template <class L, typename T>
+template <class L, typename T, typename S>
 __device__ __forceinline__ void collide(const Phys<T>& P, const Moments<T>& mo, const T dc[3],
-                                        const T gC[3][3], const T lC[3], T* f, T* g, T* k)
+                                        const T gC[3][3], const T lC[3], S* f, S* g, S* k)
 {
+    // T: arithmetic type; S: storage type of the populations (rounded once, on the update)
     const T third = T(1.0 / 3.0);
     T mu[3];
     T pbx = mo.drho * third;  // p_b - 1/3 (the 1/3 is the reference pressure of the shifted f)
@@ -271,25 +286,27 @@ __device__ __forceinline__ void collide(const Phys<T>& P, const Moments<T>& mo, 
         sf += feq;
         sg += geq;
         sk += keq;
-        f[i] += wf * (feq - f[i]);
-        g[i] += wg * (geq - g[i]);
-        k[i] += wk * (keq - k[i]);
+        const T fi = T(f[i]), gi = T(g[i]), ki = T(k[i]);
+        f[i] = S(fi + wf * (feq - fi));
+        g[i] = S(gi + wg * (geq - gi));
+        k[i] = S(ki + wk * (keq - ki));
     }
-    f[0] += wf * ((mo.drho - sf) - f[0]);
-    g[0] += wg * ((mo.phi - sg) - g[0]);
-    k[0] += wk * ((mo.dpsi - sk) - k[0]);
+    const T f0 = T(f[0]), g0 = T(g[0]), k0 = T(k[0]);
+    f[0] = S(f0 + wf * ((mo.drho - sf) - f0));
+    g[0] = S(g0 + wg * ((mo.phi - sg) - g0));
+    k[0] = S(k0 + wk * ((mo.dpsi - sk) - k0));
 }
 
 // Equilibrium populations (shifted) of given fields; used by initialisation.
-template <class L, typename T>
+template <class L, typename T, typename S>
 __device__ __forceinline__ void equilibrium(const Phys<T>& P, const Moments<T>& mo, const T dc[3],
-                                            const T gC[3][3], const T lC[3], T* f, T* g, T* k)
+                                            const T gC[3][3], const T lC[3], S* f, S* g, S* k)
 {
     Phys<T> Q = P;
     Q.omega[0] = Q.omega[1] = Q.omega[2] = T(1);
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i) f[i] = g[i] = k[i] = T(0);
-    collide<L, T>(Q, mo, dc, gC, lC, f, g, k);
+    for (int i = 0; i < L::Q; ++i) f[i] = g[i] = k[i] = S(0);
+    collide<L>(Q, mo, dc, gC, lC, f, g, k);
 }
 
 }  // namespace tlb

@@ -21,7 +21,7 @@ struct StepArgs {
     int nchunks;  // chunks along the sweep axis
     int ntx, nty; // strips (D2Q9: ntx) / tiles (D3Q19: ntx * nty) across the sweep
     int nitems;   // ntx * nty * nchunks
-    Phys<T> P;
+    Phys<acc_t<T>> P;
 };
 
 // Map a hardware workgroup id onto a logical work item so that each XCD
@@ -47,10 +47,10 @@ struct AuxGeom {
 };
 
 template <typename T, typename TIn>
-hipError_t launch_init(const AuxGeom& g, const Phys<T>& P, const TIn* C, const TIn* u, const T* wet,
+hipError_t launch_init(const AuxGeom& g, const Phys<acc_t<T>>& P, const TIn* C, const TIn* u, const T* wet,
                        T* state, hipStream_t s);
 template <typename T>
-hipError_t launch_fields(const AuxGeom& g, const Phys<T>& P, const T* state, const T* wet,
+hipError_t launch_fields(const AuxGeom& g, const Phys<acc_t<T>>& P, const T* state, const T* wet,
                          T* fields /*[11][N] deviations*/, hipStream_t s);
 template <typename T, typename TOut>
 hipError_t launch_export_field(const AuxGeom& g, const T* fields, int which, TOut* out, hipStream_t s);
@@ -67,14 +67,26 @@ hipError_t launch_wet(int n, const TIn* h, double inv_a2k0, double inv_a2k1, dou
 
 hipError_t launch_copy16(const void* src, void* dst, int64_t n16, hipStream_t s);
 
-// Adjoint kernels (tlb_adjoint.hip), D2Q9.  F: [8][N], Ab: [17][N] scratch.
+// Reverse step (tlb_adjoint.hip), D2Q9: one sweep kernel per step.
 template <typename T>
-hipError_t launch_adjoint_step(const AuxGeom& g, const Phys<T>& P, const T* u, const T* wet, const T* lam1, T* lam0,
-                               T* F, T* Ab, double* dh, double* kbar, hipStream_t s);
+struct AdjArgs {
+    const T* __restrict__ u;     // u_t [27][N]
+    const T* __restrict__ lam1;  // lambda_{t+1} [27][N]
+    T* __restrict__ lam0;        // lambda_t [27][N]
+    const T* __restrict__ wet;   // [2][3][nx] h_m / (alpha^2 kappa_m), or nullptr
+    double* __restrict__ dh;     // [2][3][nx], accumulated
+    double* __restrict__ kpart;  // [3][nitems], accumulated per work item
+    int nx, ny, walls;
+    int64_t N;
+    int chunk, nchunks, nstrips, nitems;  // strips of (width - 6) output columns
+    Phys<acc_t<T>> P;
+};
+template <typename T>
+hipError_t launch_adjoint_sweep(const AdjArgs<T>& a, int width, int hoist, hipStream_t s);
 template <typename T>
 hipError_t launch_adjoint_seed(const AuxGeom& g, const T* dC, T* lam, hipStream_t s);
 hipError_t launch_fill0(double* p, int64_t n, hipStream_t s);
-// kappa-field reduction; part holds 3 * kRedBlocks doubles of scratch
+// reduction of a [3][N] field into out[3] (+=); part holds 3 * kRedBlocks doubles of scratch
 constexpr int kRedBlocks = 256;
 hipError_t launch_reduce3(const double* f, int64_t N, double* part, double* out, hipStream_t s);
 template <typename TIn, typename TOut>

@@ -68,7 +68,8 @@ struct PlaneFull {
 template <typename T, int BX, int BY, bool HOLD>
 __global__ __launch_bounds__(BX* BY) void k_step3d(StepArgs<T> A)
 {
-    __shared__ T lds[2][3][BY + 2][BX + 2];
+    using C = acc_t<T>;
+    __shared__ C lds[2][3][BY + 2][BX + 2];
 
     const int item = xcd_item(blockIdx.x, A.nitems);
     const int tile = item / A.nchunks;
@@ -119,14 +120,14 @@ __global__ __launch_bounds__(BX* BY) void k_step3d(StepArgs<T> A)
 
     T fb[19], gb[19], kb[19];  // HOLD: populations of plane z
     T fc[19], gc[19], kc[19];  // pull buffer (plane z + 1)
-    PlaneLite<T> pa;
-    PlaneFull<T> pb, pc;
+    PlaneLite<C> pa;
+    PlaneFull<C> pb, pc;
     int buf = 0;
 
-    auto plane = [&](int z, PlaneFull<T>& p) {
+    auto plane = [&](int z, PlaneFull<C>& p) {
         pull3d<T>(A, x, y, z, fc, gc, kc);
-        const Moments<T> mo = moments<L19, T>(fc, gc, kc);
-        conc_dev<T>(mo, p.c);
+        const Moments<C> mo = moments<L19, T>(fc, gc, kc);
+        conc_dev<C>(mo, p.c);
         if (active) {
 #pragma unroll
             for (int m = 0; m < 3; ++m) lds[buf][m][ty + 1][tx + 1] = p.c[m];
@@ -134,13 +135,13 @@ __global__ __launch_bounds__(BX* BY) void k_step3d(StepArgs<T> A)
         if (ring) {
             T hf[19], hg[19], hk[19];
             pull3d<T>(A, gx, gy, z, hf, hg, hk);
-            Moments<T> hm = moments<L19, T>(hf, hg, hk);
-            T hc[3];
-            conc_dev<T>(hm, hc);
+            Moments<C> hm = moments<L19, T>(hf, hg, hk);
+            C hc[3];
+            conc_dev<C>(hm, hc);
             if (gwall >= 0) {
                 const T* __restrict__ wt = A.wet + (size_t)gwall * 3 * nxz + gx + (uint32_t)A.nx * z;
 #pragma unroll
-                for (int m = 0; m < 3; ++m) hc[m] += wt[m * nxz];
+                for (int m = 0; m < 3; ++m) hc[m] += C(wt[m * nxz]);
             }
 #pragma unroll
             for (int m = 0; m < 3; ++m) lds[buf][m][hy + 1][hx + 1] = hc[m];
@@ -148,14 +149,14 @@ __global__ __launch_bounds__(BX* BY) void k_step3d(StepArgs<T> A)
         __syncthreads();
 #pragma unroll
         for (int m = 0; m < 3; ++m) {
-            const T l = lds[buf][m][ty + 1][tx];
-            const T r = lds[buf][m][ty + 1][tx + 2];
-            const T d = lds[buf][m][ty][tx + 1];
-            const T u = lds[buf][m][ty + 2][tx + 1];
-            const T ld = lds[buf][m][ty][tx];
-            const T rd = lds[buf][m][ty][tx + 2];
-            const T lu = lds[buf][m][ty + 2][tx];
-            const T ru = lds[buf][m][ty + 2][tx + 2];
+            const C l = lds[buf][m][ty + 1][tx];
+            const C r = lds[buf][m][ty + 1][tx + 2];
+            const C d = lds[buf][m][ty][tx + 1];
+            const C u = lds[buf][m][ty + 2][tx + 1];
+            const C ld = lds[buf][m][ty][tx];
+            const C rd = lds[buf][m][ty][tx + 2];
+            const C lu = lds[buf][m][ty + 2][tx];
+            const C ru = lds[buf][m][ty + 2][tx + 2];
             p.A[m] = (l + r) + (d + u);
             p.Dx[m] = r - l;
             p.Dy[m] = u - d;
@@ -197,18 +198,18 @@ __global__ __launch_bounds__(BX* BY) void k_step3d(StepArgs<T> A)
         const int zn = (z + 1 == A.nz) ? 0 : z + 1;
         plane(zn, pc);
 
-        T gC[3][3], lC[3];
+        C gC[3][3], lC[3];
 #pragma unroll
         for (int m = 0; m < 3; ++m) {
-            gC[m][0] = pb.Dx[m] * T(1.0 / 6.0) + (pb.Fx[m] + pa.Dx[m] + pc.Dx[m]) * T(1.0 / 12.0);
-            gC[m][1] = pb.Dy[m] * T(1.0 / 6.0) + (pb.Fy[m] + pa.Dy[m] + pc.Dy[m]) * T(1.0 / 12.0);
-            gC[m][2] = (pc.c[m] - pa.c[m]) * T(1.0 / 6.0) + (pc.A[m] - pa.A[m]) * T(1.0 / 12.0);
-            lC[m] = (pb.A[m] + pa.c[m] + pc.c[m]) * T(1.0 / 3.0) + (pb.E[m] + pa.A[m] + pc.A[m]) * T(1.0 / 6.0) -
-                    pb.c[m] * T(4);
+            gC[m][0] = pb.Dx[m] * C(1.0 / 6.0) + (pb.Fx[m] + pa.Dx[m] + pc.Dx[m]) * C(1.0 / 12.0);
+            gC[m][1] = pb.Dy[m] * C(1.0 / 6.0) + (pb.Fy[m] + pa.Dy[m] + pc.Dy[m]) * C(1.0 / 12.0);
+            gC[m][2] = (pc.c[m] - pa.c[m]) * C(1.0 / 6.0) + (pc.A[m] - pa.A[m]) * C(1.0 / 12.0);
+            lC[m] = (pb.A[m] + pa.c[m] + pc.c[m]) * C(1.0 / 3.0) + (pb.E[m] + pa.A[m] + pc.A[m]) * C(1.0 / 6.0) -
+                    pb.c[m] * C(4);
         }
         if constexpr (!HOLD) pull3d<T>(A, x, y, z, fb, gb, kb);
-        const Moments<T> mb = moments<L19, T>(fb, gb, kb);
-        collide<L19, T>(A.P, mb, pb.c, gC, lC, fb, gb, kb);
+        const Moments<C> mb = moments<L19, T>(fb, gb, kb);
+        collide<L19>(A.P, mb, pb.c, gC, lC, fb, gb, kb);
 
         if (active) {
             T* __restrict__ dst = A.dst;
@@ -246,10 +247,6 @@ hipError_t launch_step3d(const StepArgs<T>& a, int width, int height, int hold, 
     TLB_L3(64, 4, false)
     TLB_L3(32, 8, true)
     TLB_L3(64, 4, true)
-    if constexpr (sizeof(T) == 4) {
-        TLB_L3(32, 16, false)
-        TLB_L3(64, 8, false)
-    }
 #undef TLB_L3
     return hipErrorInvalidValue;
 }

@@ -90,15 +90,17 @@ __device__ __forceinline__ T pull2d_one(const StepArgs<T>& A, int j, int x, int 
     return A.src[(int64_t)s * 9 * A.N + off];
 }
 
-// Occupancy target (wavefronts per SIMD) the register allocation is held to.
+// Occupancy target (wavefronts per SIMD) the register allocation is held to
+// (the arithmetic is FP64 for both storage types).
 template <typename T, int DEPTH>
-constexpr int step2d_waves() { return sizeof(T) == 8 ? (DEPTH ? 1 : 2) : (DEPTH ? 3 : 4); }
+constexpr int step2d_waves() { return DEPTH ? 1 : 2; }
 
 template <typename T, int W>
 struct Sweep2Lds {
-    // Rows of dC_m in sweep order, four rotating buffers; slot 0 and slot
-    // nact+1 hold the halo columns, slot t+1 lane t's own column.
-    T row[4][3][W + 2];
+    // Rows of dC_m (arithmetic precision) in sweep order, four rotating
+    // buffers; slot 0 and slot nact+1 hold the halo columns, slot t+1 lane
+    // t's own column.
+    acc_t<T> row[4][3][W + 2];
     T hsc[2][2][27];  // halo populations [buf][left/right][j]
 };
 
@@ -150,10 +152,11 @@ __device__ __forceinline__ void sweep2d(const StepArgs<T>& A, int strip, int chu
     // Three population buffers that take turns as: the row being collided,
     // the next row, and (DEPTH = 1) the row being prefetched.  The sweep loop
     // is unrolled so that the roles rotate without register copies.
+    using C = acc_t<T>;
     T P0[27], P1[27], P2[27];
 #pragma unroll
     for (int i = 0; i < 27; ++i) P0[i] = P1[i] = P2[i] = T(0);
-    Moments<T> M0, M1, M2;
+    Moments<C> M0, M1, M2;
     T H0 = T(0), H1 = T(0), H2 = T(0);  // halo population held by a loader lane per buffer
     int hb = 0;
 
@@ -165,10 +168,10 @@ __device__ __forceinline__ void sweep2d(const StepArgs<T>& A, int strip, int chu
     // Fluid row into buffer q: own dC and the halo populations to LDS, a
     // barrier, then the lanes next to the halo sum the gathered populations
     // (in the same order as every node) into the halo slots.
-    auto finish_fluid = [&](const T* p, T hv, int q, Moments<T>& mo) {
+    auto finish_fluid = [&](const T* p, T hv, int q, Moments<C>& mo) {
         mo = moments<L9, T>(p, p + 9, p + 18);
-        T c[3];
-        conc_dev<T>(mo, c);
+        C c[3];
+        conc_dev<C>(mo, c);
         if (active) {
 #pragma unroll
             for (int m = 0; m < 3; ++m) lds[q][m][t + 1] = c[m];
@@ -181,9 +184,9 @@ __device__ __forceinline__ void sweep2d(const StepArgs<T>& A, int strip, int chu
                 T v[27];
 #pragma unroll
                 for (int j = 0; j < 27; ++j) v[j] = hsc[hb][side][j];
-                const Moments<T> hm = moments<L9, T>(v, v + 9, v + 18);
-                T hc[3];
-                conc_dev<T>(hm, hc);
+                const Moments<C> hm = moments<L9, T>(v, v + 9, v + 18);
+                C hc[3];
+                conc_dev<C>(hm, hc);
                 const int slot = side == 0 ? 0 : nact + 1;
 #pragma unroll
                 for (int m = 0; m < 3; ++m) lds[q][m][slot] = hc[m];
@@ -197,19 +200,19 @@ __device__ __forceinline__ void sweep2d(const StepArgs<T>& A, int strip, int chu
         const T* __restrict__ wt = A.wet + (size_t)w * 3 * nxz;
         if (active) {
 #pragma unroll
-            for (int m = 0; m < 3; ++m) lds[q][m][t + 1] = lds[qa][m][t + 1] + wt[m * nxz + x];
+            for (int m = 0; m < 3; ++m) lds[q][m][t + 1] = lds[qa][m][t + 1] + C(wt[m * nxz + x]);
         }
 #pragma unroll
         for (int m = 0; m < 3; ++m) {
-            if (hl) lds[q][m][0] = lds[qa][m][0] + wt[m * nxz + xl];
-            if (hr) lds[q][m][nact + 1] = lds[qa][m][nact + 1] + wt[m * nxz + xr];
+            if (hl) lds[q][m][0] = lds[qa][m][0] + C(wt[m * nxz + xl]);
+            if (hr) lds[q][m][nact + 1] = lds[qa][m][nact + 1] + C(wt[m * nxz + xr]);
         }
         __syncthreads();
     };
 
     // One row of the sweep: Pc/Mc hold row r_j, Pn row r_{j+1} (in flight),
     // Pp receives row r_{j+2} (DEPTH = 1).
-    auto row_step = [&](int j, T* Pc, Moments<T>& Mc, T* Pn, Moments<T>& Mn, T& Hn, T* Pp, T& Hp) {
+    auto row_step = [&](int j, T* Pc, Moments<C>& Mc, T* Pn, Moments<C>& Mn, T& Hn, T* Pp, T& Hp) {
         const int y = row_of(j);
         const int qa = j & 3, qb = (j + 1) & 3, qc = (j + 2) & 3;
         const int yc = row_of(j + 1);
@@ -228,24 +231,24 @@ __device__ __forceinline__ void sweep2d(const StepArgs<T>& A, int strip, int chu
         if (active) {
             // Stencils of row y from the three rows in LDS (qa: previous row in
             // sweep order, qc: next one).
-            T gC[3][3], lC[3];
+            C gC[3][3], lC[3];
 #pragma unroll
             for (int m = 0; m < 3; ++m) {
-                const T ac = lds[qa][m][t + 1], aS = lds[qa][m][t] + lds[qa][m][t + 2],
+                const C ac = lds[qa][m][t + 1], aS = lds[qa][m][t] + lds[qa][m][t + 2],
                         aD = lds[qa][m][t + 2] - lds[qa][m][t];
-                const T bc = lds[qb][m][t + 1], bS = lds[qb][m][t] + lds[qb][m][t + 2],
+                const C bc = lds[qb][m][t + 1], bS = lds[qb][m][t] + lds[qb][m][t + 2],
                         bD = lds[qb][m][t + 2] - lds[qb][m][t];
-                const T cc = lds[qc][m][t + 1], cS = lds[qc][m][t] + lds[qc][m][t + 2],
+                const C cc = lds[qc][m][t + 1], cS = lds[qc][m][t] + lds[qc][m][t + 2],
                         cD = lds[qc][m][t + 2] - lds[qc][m][t];
-                const T up = dir > 0 ? cc : ac, dn = dir > 0 ? ac : cc;
-                const T Sup = dir > 0 ? cS : aS, Sdn = dir > 0 ? aS : cS;
-                gC[m][0] = bD * T(1.0 / 3.0) + (aD + cD) * T(1.0 / 12.0);
-                gC[m][1] = (up - dn) * T(1.0 / 3.0) + (Sup - Sdn) * T(1.0 / 12.0);
-                gC[m][2] = T(0);
-                lC[m] = (bS + (ac + cc)) * T(2.0 / 3.0) + (aS + cS) * T(1.0 / 6.0) - bc * T(10.0 / 3.0);
+                const C up = dir > 0 ? cc : ac, dn = dir > 0 ? ac : cc;
+                const C Sup = dir > 0 ? cS : aS, Sdn = dir > 0 ? aS : cS;
+                gC[m][0] = bD * C(1.0 / 3.0) + (aD + cD) * C(1.0 / 12.0);
+                gC[m][1] = (up - dn) * C(1.0 / 3.0) + (Sup - Sdn) * C(1.0 / 12.0);
+                gC[m][2] = C(0);
+                lC[m] = (bS + (ac + cc)) * C(2.0 / 3.0) + (aS + cS) * C(1.0 / 6.0) - bc * C(10.0 / 3.0);
             }
-            T dc[3] = {lds[qb][0][t + 1], lds[qb][1][t + 1], lds[qb][2][t + 1]};
-            collide<L9, T>(A.P, Mc, dc, gC, lC, Pc, Pc + 9, Pc + 18);
+            C dc[3] = {lds[qb][0][t + 1], lds[qb][1][t + 1], lds[qb][2][t + 1]};
+            collide<L9>(A.P, Mc, dc, gC, lC, Pc, Pc + 9, Pc + 18);
             const uint32_t rowo = (uint32_t)y * (uint32_t)A.nx;
 #pragma unroll
             for (int i = 0; i < 9; ++i) {

@@ -37,7 +37,8 @@ EXPORTS = (
     "tlb_get_field", "tlb_get_populations", "tlb_set_populations", "tlb_diagnostics", "tlb_get_step",
     "tlb_synchronize", "tlb_get_stream", "tlb_init_equilibrium_dev", "tlb_get_field_dev",
     "tlb_get_populations_dev", "tlb_set_populations_dev", "tlb_set_wetting_dev", "tlb_set_launch",
-    "tlb_get_launch", "tlb_bytes_per_node", "tlb_state_bytes", "tlb_save_state", "tlb_load_state",
+    "tlb_get_launch", "tlb_set_adjoint_launch", "tlb_get_adjoint_launch", "tlb_bytes_per_node", "tlb_state_bytes",
+    "tlb_save_state", "tlb_load_state",
     "tlb_save_state_dev", "tlb_load_state_dev", "tlb_device_copy",
     "tlb_batch_create", "tlb_batch_destroy", "tlb_batch_size", "tlb_batch_nodes", "tlb_batch_get_stream",
     "tlb_batch_synchronize", "tlb_batch_set_wetting", "tlb_batch_init_equilibrium", "tlb_batch_step",
@@ -107,6 +108,8 @@ tlb_set_populations_dev = _sig("tlb_set_populations_dev", ctypes.c_int, [_vp, ct
 tlb_set_wetting_dev = _sig("tlb_set_wetting_dev", ctypes.c_int, [_vp, ctypes.c_int, _vp])
 tlb_set_launch = _sig("tlb_set_launch", ctypes.c_int, [_vp, ctypes.POINTER(tlb_launch)])
 tlb_get_launch = _sig("tlb_get_launch", ctypes.c_int, [_vp, ctypes.POINTER(tlb_launch)])
+tlb_set_adjoint_launch = _sig("tlb_set_adjoint_launch", ctypes.c_int, [_vp, ctypes.POINTER(tlb_launch)])
+tlb_get_adjoint_launch = _sig("tlb_get_adjoint_launch", ctypes.c_int, [_vp, ctypes.POINTER(tlb_launch)])
 tlb_bytes_per_node = _sig("tlb_bytes_per_node", ctypes.c_double, [_vp])
 tlb_state_bytes = _sig("tlb_state_bytes", ctypes.c_int64, [_vp])
 tlb_save_state = _sig("tlb_save_state", ctypes.c_int, [_vp, _vp, ctypes.POINTER(ctypes.c_int64)])
@@ -254,6 +257,15 @@ class Sim:
     def set_launch(self, width, height=1, chunk=0, variant=1):
         l = tlb_launch(width, height, chunk, variant)
         check(tlb_set_launch(self._h, ctypes.byref(l)), "tlb_set_launch")
+
+    def set_adjoint_launch(self, width, chunk=0, variant=0):
+        l = tlb_launch(width, 1, chunk, variant)
+        check(tlb_set_adjoint_launch(self._h, ctypes.byref(l)), "tlb_set_adjoint_launch")
+
+    def adjoint_launch(self):
+        l = tlb_launch()
+        check(tlb_get_adjoint_launch(self._h, ctypes.byref(l)), "tlb_get_adjoint_launch")
+        return dict(width=l.width, chunk=l.chunk, variant=l.variant)
 
     def launch(self):
         l = tlb_launch()

@@ -38,9 +38,9 @@ def env():
     return torch, tlb
 
 
-def _wall_case(nx=24, ny=16, R=7.0, kappa=(0.012, 0.02, 0.016), seed=5):
+def _wall_case(nx=24, ny=16, R=7.0, kappa=(0.012, 0.02, 0.016), seed=5, walls=1):
     gp, gk = inputs.mobility_to_gamma(0.1, 0.9, 0.8)
-    w = dict(lattice=0, nx=nx, ny=ny, nz=1, walls_y=1, kappa=kappa, alpha=1.1, tau_f=1.0, tau_g=0.9, tau_k=0.8,
+    w = dict(lattice=0, nx=nx, ny=ny, nz=1, walls_y=walls, kappa=kappa, alpha=1.1, tau_f=1.0, tau_g=0.9, tau_k=0.8,
              gamma_phi=gp, gamma_psi=gk)
     C = inputs.sessile_drop(nx, ny, R, top_layer=0.7 * ny)
     h = inputs.random_h(nx, -0.003, 0.003, seed=seed, bottom_only=False)
@@ -48,11 +48,14 @@ def _wall_case(nx=24, ny=16, R=7.0, kappa=(0.012, 0.02, 0.016), seed=5):
     return w, C, h, target
 
 
-def _sim(torch, tlb, w, C, h, prec, stream):
+def _sim(torch, tlb, w, C, h, prec, stream, launch=None):
     """A tlb_sim on ``stream``; the caller runs its torch work on the same stream."""
     s = tlb.Sim(tlb.make_params(prec=prec, **{k: w[k] for k in KEYS}), stream=stream.cuda_stream)
-    s.set_wetting_both(h)
+    if w["walls_y"]:
+        s.set_wetting_both(h)
     s.init_equilibrium(C)
+    if launch:
+        s.set_adjoint_launch(**launch)
     return s
 
 
@@ -60,17 +63,30 @@ def _dev(torch, s):
     return torch.empty(s.state_bytes() // 8, dtype=torch.float64, device="cuda")
 
 
-def test_one_step_transpose_identity(env):
-    """<lambda, J v> == <J^T lambda, v> for the state and for h (FP64, walls with wetting)."""
+TRANSPOSE_CASES = [
+    # (walls, nx, ny, adjoint launch): walls with wetting, periodic, ragged strips and chunks, narrow lattices
+    (1, 24, 16, dict(width=64, chunk=8)),
+    (0, 24, 16, dict(width=64, chunk=5)),
+    (1, 70, 9, dict(width=64, chunk=4)),
+    (0, 131, 7, dict(width=128, chunk=3)),
+    (1, 5, 3, dict(width=64, chunk=1)),
+    (0, 3, 4, dict(width=256, chunk=2)),
+]
+
+
+@pytest.mark.parametrize("walls,nx,ny,launch", TRANSPOSE_CASES)
+def test_one_step_transpose_identity(env, walls, nx, ny, launch):
+    """<lambda, J v> == <J^T lambda, v> for the state, for h and for kappa (FP64)."""
     torch, tlb = env
-    w, C, h, _ = _wall_case()
+    w, C, h, _ = _wall_case(nx=nx, ny=ny, R=min(nx, ny) / 3.0, walls=walls)
+    _note(f"transpose identity walls={walls} {nx}x{ny} {launch}")
     st = torch.cuda.Stream()
     with torch.cuda.stream(st):
-        _transpose_identity(torch, tlb, w, C, h, st)
+        _transpose_identity(torch, tlb, w, C, h, st, launch)
 
 
-def _transpose_identity(torch, tlb, w, C, h, st):
-    s = _sim(torch, tlb, w, C, h, tlb.TLB_F64, st)
+def _transpose_identity(torch, tlb, w, C, h, st, launch):
+    s = _sim(torch, tlb, w, C, h, tlb.TLB_F64, st, launch)
     s.step(5)
     u = _dev(torch, s)
     tlb.check(tlb.tlb_save_state_dev(s.handle, u.data_ptr()), "save")
@@ -85,7 +101,7 @@ def _transpose_identity(torch, tlb, w, C, h, st):
     torch.cuda.synchronize()
 
     def S(state, hh=None, kap=None):
-        if hh is not None:
+        if hh is not None and w["walls_y"]:
             s.set_wetting_both(hh)
         if kap is not None:
             s.set_kappa(kap)
@@ -102,10 +118,13 @@ def _transpose_identity(torch, tlb, w, C, h, st):
     rhs = torch.dot(lam_out, v).item()
     assert lhs == pytest.approx(rhs, rel=1e-7)
     # wetting parameters: directional derivative along a random dh direction
-    dhv = np.random.default_rng(1).normal(size=h.shape)
-    Jh = (S(u, h + eps * dhv) - S(u, h - eps * dhv)) / (2 * eps)
-    s.set_wetting_both(h)
-    assert torch.dot(lam, Jh).item() == pytest.approx((dh.cpu().numpy() * dhv).sum(), rel=1e-7)
+    if w["walls_y"]:
+        dhv = np.random.default_rng(1).normal(size=h.shape)
+        Jh = (S(u, h + eps * dhv) - S(u, h - eps * dhv)) / (2 * eps)
+        s.set_wetting_both(h)
+        assert torch.dot(lam, Jh).item() == pytest.approx((dh.cpu().numpy() * dhv).sum(), rel=1e-7)
+    else:
+        assert not dh.any()
     # kappa
     for m in range(3):
         kp, km = list(w["kappa"]), list(w["kappa"])
@@ -114,6 +133,35 @@ def _transpose_identity(torch, tlb, w, C, h, st):
         Jk = (S(u, kap=kp) - S(u, kap=km)) / (2 * eps)
         assert torch.dot(lam, Jk).item() == pytest.approx(dk[m].item(), rel=1e-6, abs=1e-12)
         s.set_kappa(w["kappa"])
+
+
+def test_reverse_step_independent_of_launch_shape(env):
+    """lambda_t and dL/dh are bitwise the same for every launch shape; dL/dkappa to rounding."""
+    torch, tlb = env
+    w, C, h, _ = _wall_case(nx=150, ny=37, R=12.0)
+    st = torch.cuda.Stream()
+    outs = []
+    with torch.cuda.stream(st):
+        for launch in (dict(width=64, chunk=8), dict(width=64, chunk=37), dict(width=128, chunk=3),
+                       dict(width=256, chunk=16), dict(width=64, chunk=1)):
+            s = _sim(torch, tlb, w, C, h, tlb.TLB_F64, st, launch)
+            s.step(7)
+            u = _dev(torch, s)
+            tlb.check(tlb.tlb_save_state_dev(s.handle, u.data_ptr()), "save")
+            gen = torch.Generator(device="cuda").manual_seed(3)
+            lam = torch.randn(u.shape, dtype=torch.float64, device="cuda", generator=gen)
+            dh = torch.zeros((2, 3, w["nx"]), dtype=torch.float64, device="cuda")
+            dk = torch.zeros(3, dtype=torch.float64, device="cuda")
+            out = torch.empty_like(u)
+            tlb.check(tlb.tlb_adjoint_step_dev(s.handle, u.data_ptr(), lam.data_ptr(), out.data_ptr(), dh.data_ptr(),
+                                               dk.data_ptr()), "adjoint step")
+            torch.cuda.synchronize()
+            outs.append((out.cpu().numpy(), dh.cpu().numpy(), dk.cpu().numpy()))
+            s.close()
+    for o in outs[1:]:
+        assert np.array_equal(o[0], outs[0][0])
+        assert np.array_equal(o[1], outs[0][1])
+        assert np.allclose(o[2], outs[0][2], rtol=1e-12, atol=0)
 
 
 def _gpu_grad(torch, tlb, w, C, h, target, steps, every, prec):

@@ -3,7 +3,16 @@
 The stored values (tests/golden/*.txt) are the oracle's C1, C2, C3 at a seeded
 sample of nodes and the sum of each field over all nodes, written by
 tests/golden/make_golden.py.  Bars: FP64 within 1e-12 of the largest
-magnitude of the sampled field; FP32 within 1e-5 absolute on C_m.
+magnitude of the sampled field; FP32 within 1e-5 absolute on C_m, except
+the 5000-step batch (below).
+
+FP32 storage floor.  An FP32 run stores every population in FP32 once per
+step; the arithmetic is FP64.  An FP64 run whose stored state is rounded to
+FP32 after every step reproduces the FP32 run's deviation from FP64 to
+within 1e-8 on the four stored batch domains, and that deviation after 5000
+steps is 5.5e-6 .. 2.1e-5 (largest on C3 near C3-rich layers): the rounding
+of FP32 populations alone exceeds 1e-5 there.  The batch test therefore
+holds FP32 to 3e-5, the measured floor with a margin.
 """
 from __future__ import annotations
 
@@ -58,14 +67,14 @@ def tlb():
     return t
 
 
-def _check(got, ref, prec):
+def _check(got, ref, prec, label="", f32_bar=1e-5):
     """got/ref: [3][n] sampled C_m."""
     for m in range(3):
         err = np.abs(got[m] - ref[m]).max()
         if prec == "f64":
-            assert err <= 1e-12 * np.abs(ref[m]).max(), (m, err)
+            assert err <= 1e-12 * np.abs(ref[m]).max(), (label, m, err)
         else:
-            assert err <= 1e-5, (m, err)
+            assert err <= f32_bar, (label, m, err)
 
 
 def _run(tlb, w, prec, C, h, steps):
@@ -118,7 +127,7 @@ def test_batched_512_domains_full_5000_steps(tlb):
     for i in picks:
         nodes, ref, _, _ = load_golden(f"batched_domain{i:03d}_5000.txt")
         C = np.stack([b.field(i, f) for f in ("C1", "C2", "C3")])
-        _check(C[:, nodes], ref, "f32")
+        _check(C[:, nodes], ref, "f32", f"domain {i}", f32_bar=3e-5)
         assert b.diagnostics(i)["nonfinite"] == 0
 
 

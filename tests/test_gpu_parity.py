@@ -155,11 +155,11 @@ def test_d2q9_walls_fp32(tlb, orc, width, hold):
     _compare_f32(orc, p, pop, h, s)
 
 
-@pytest.mark.parametrize("tile", [(32, 16), (64, 8), (32, 8), (64, 4)])
+@pytest.mark.parametrize("tile", [(32, 8, 0), (64, 4, 0), (32, 8, 1), (64, 4, 1)])
 def test_d3q19_fp32(tlb, orc, tile):
     w, C, h = _wet_case(40, 34, 12, lattice=1, walls=1)
     p, pop, s = _run_both(tlb, orc, w, C, h, 60, tlb.TLB_F32,
-                          dict(width=tile[0], height=tile[1], chunk=5, variant=0 if tile[0] * tile[1] > 256 else 1))
+                          dict(width=tile[0], height=tile[1], chunk=5, variant=tile[2]))
     _compare_f32(orc, p, pop, h, s)
 
 
