@@ -84,6 +84,16 @@ def sessile_drop(nx, ny, R, x0=None, alpha=1.0, top_layer=None):
     return np.stack([c1, c2, c3])
 
 
+def cap(nx, ny, R, theta_deg, x0=None, alpha=1.0):
+    """C1 circular cap of radius R on the wall below y = 0 (half-way, at y = -1/2) meeting it at
+    theta_deg (measured through C1), in C2; C3 = 0."""
+    x, y, _ = _coords(nx, ny)
+    cx = nx / 2.0 if x0 is None else x0
+    cy = -0.5 - R * np.cos(np.radians(theta_deg))
+    c1 = tanh_profile(np.hypot(x - cx, y - cy), R, alpha)
+    return np.stack([c1, 1.0 - c1, np.zeros_like(c1)])
+
+
 def lens(nx, ny, R, alpha=1.0, y_interface=None):
     """C1 disc of radius R at the interface between C2 (below) and C3 (above)."""
     x, y, _ = _coords(nx, ny)
