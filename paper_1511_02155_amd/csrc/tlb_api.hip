@@ -129,8 +129,8 @@ static AuxGeom geom(const tlb_sim* s)
 // Reverse sweep: single-wavefront strips (58 output columns), all loads of a
 // row issued before its arithmetic.  The sweep is latency-bound per row and
 // holds one wavefront per SIMD, so all items should be resident at once:
-// measured on MI355X (512^2 with walls) the best is 6 rows (~800 items) in
-// both precisions.
+// chunks sized for at most ~1000 work items (measured on MI355X, 512^2 with
+// walls: 5 rows, ~930 items, in both precisions).
 static tlb_launch default_adj_launch(const tlb_params& p)
 {
     tlb_launch l;
@@ -138,9 +138,10 @@ static tlb_launch default_adj_launch(const tlb_params& p)
     l.height = 1;
     l.variant = 0;
     const int nstrips = (p.nx + 57) / 58;
-    const int nch = (768 + nstrips - 1) / nstrips;
+    int nch = 1000 / nstrips;
+    if (nch < 1) nch = 1;
     const int chunk = (p.ny + nch - 1) / nch;
-    l.chunk = chunk < 6 ? 6 : chunk;
+    l.chunk = chunk < 5 ? 5 : chunk;
     return l;
 }
 
