@@ -107,3 +107,61 @@ def test_sessile_cap_relaxes_toward_young_angle(orc, h):
     got = _cap_angle(orc, h, 90.0, 10000)
     gap0, gap = want - 90.0, want - got
     assert gap * gap0 > 0 and abs(gap) <= 0.6 * abs(gap0), (got, want)
+
+
+def _mode_decay(orc, channel, tau, M=0.5, nx=16, c0=0.9, amp=1e-4, kappa=0.01):
+    """Small cosine perturbation of C1 (channel 'phi': C2 = 1 - C1, C3 = 0) or of C3 (channel 'psi':
+    C1 = 1 - C3, C2 = 0) about the stable bulk value c0; returns (fitted decay rate, max |C2|)."""
+    gp, gk = inputs.mobility_to_gamma(M, tau, tau)
+    ny = 3
+    p = orc.Params(lattice=0, nx=nx, ny=ny, walls_y=0, kappa=(kappa,) * 3, alpha=1.0, tau_f=tau, tau_g=tau,
+                   tau_k=tau, gamma_phi=gp, gamma_psi=gk)
+    k = 2 * math.pi / nx
+    x = np.tile(np.arange(nx, dtype=float), ny)
+    c = c0 + amp * np.cos(k * x)
+    if channel == "phi":
+        C = np.stack([c, 1 - c, np.zeros_like(c)])
+        name = "C1"
+    else:
+        C = np.stack([1 - c, np.zeros_like(c), c])
+        name = "C3"
+    pop = orc.init_equilibrium(p, C)
+    steps = (500, 1000, 1500, 2000)
+    amps, done, c2 = [amp], 0, 0.0
+    for s in steps:
+        orc.step(p, pop, s - done)
+        done = s
+        F = orc.fields(p, pop)
+        d = F[name][:nx] - F[name][:nx].mean()
+        amps.append(2 * abs(np.dot(d, np.cos(k * np.arange(nx)))) / nx)
+        c2 = max(c2, float(np.abs(F["C2"]).max()))
+    rate = -np.polyfit(np.array((0,) + steps, dtype=float), np.log(amps), 1)[0]
+    return rate, c2, k
+
+
+def _ch_rate(M_eff, k, c0, kappa):
+    """Linearised Cahn-Hilliard decay rate M_eff * kappa * L (F''(c0) + alpha^2 L) of a cosine mode,
+    with the eigenvalue L = 2 (1 - cos k) of the isotropic lattice Laplacian (reading R7)."""
+    L = 2.0 * (1.0 - math.cos(k))
+    return M_eff * kappa * L * ((1 - 6 * c0 + 6 * c0 ** 2) + L)
+
+
+@pytest.mark.parametrize("tau", [1.0, 0.7])
+def test_phi_mode_decays_at_cahn_hilliard_rate(orc, tau):
+    """A binary C1/C2 perturbation evolves by the Cahn-Hilliard equation for phi (Sec. III) with
+    mobility M_phi = Gamma_phi (tau_g - 1/2) (Sec. IV) = 2M (appendix A); mu_phi of the binary state
+    is (kappa/2)(F'(C1) - alpha^2 lap C1) with phi = 2 C1 - 1, so the C1 mode decays at
+    M kappa L (F''(c0) + L)."""
+    M, c0, kappa = 0.5, 0.9, 0.01
+    rate, _, k = _mode_decay(orc, "phi", tau, M=M, c0=c0, kappa=kappa)
+    assert rate == pytest.approx(_ch_rate(M, k, c0, kappa), rel=0.05)
+
+
+def test_psi_mode_decay_keeps_absent_component_absent(orc):
+    """A C1/C3 perturbation with C2 = 0 moves phi and psi together; C2 stays zero only because
+    M_phi = 2M and M_psi = 2M/3 give every component the same mobility M (appendix A, reading R10),
+    and the C3 mode then decays at M kappa L (F''(c0) + L)."""
+    M, c0, kappa = 0.5, 0.9, 0.01
+    rate, c2, k = _mode_decay(orc, "psi", 1.0, M=M, c0=c0, kappa=kappa)
+    assert rate == pytest.approx(_ch_rate(M, k, c0, kappa), rel=0.05)
+    assert c2 < 0.01 * 1e-4
