@@ -45,16 +45,18 @@ def kernel_sha(kind):
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload):
+def measured_traffic(workload, launch=None):
     """HBM bytes per launch (read + write) of a workload's dominant kernel from the committed counter
     summary (FETCH_SIZE and WRITE_SIZE scaled by the copy-kernel calibration), or None when there is no
-    reading or the kernel's sources changed since it was taken."""
+    reading, the kernel's sources changed since it was taken, or it was taken at another launch shape."""
     try:
         with open(TRAFFIC_FILE) as fh:
             rec = json.load(fh)[workload]
     except (OSError, KeyError, ValueError):
         return None
     if rec.get("source_sha") != kernel_sha(rec["kind"]):
+        return None
+    if launch is not None and rec.get("launch") != launch:
         return None
     return rec["read_bytes_per_launch"] + rec["write_bytes_per_launch"]
 
@@ -178,6 +180,7 @@ def run_adjoint(tlb, torch, prec, steps, grad_runs=1):
     out = dict(mlups=N * steps / (ms * 1e-3) / 1e6, ms_per_step=ms / steps, steps=steps, bytes_per_node=alg,
                bytes_per_launch=alg * N, achieved_GBps=alg * N / (ms / steps * 1e-3) / 1e9,
                kernel="k_adj2d (fused reverse step)")
+    out["launch"] = sim.adjoint_launch()
     sim.close()
     del u, lam
     # a whole gradient through the autograd Function
@@ -272,7 +275,7 @@ def main():
 
     def add(name, r):
         r["frac_of_hbm"] = r["achieved_GBps"] / HBM_PEAK_GBS
-        t = measured_traffic(name)
+        t = measured_traffic(name, r.get("launch"))
         r["traffic"] = t
         if t is not None:
             r["traffic_over_algorithmic"] = t / r["bytes_per_launch"]
