@@ -201,6 +201,31 @@ tlb_status tlb_load_state_dev(tlb_sim* sim, const void* dev_src, int64_t step);
 tlb_status tlb_set_kappa(tlb_sim* sim, const double* kappa);
 
 /* ------------------------------------------------------------------------ */
+/* Contact angles and wetting parameters (host-only helpers; no GPU use)    */
+/* ------------------------------------------------------------------------ */
+/*
+ * Young's law cos(theta_mn) = (gamma_sn - gamma_sm) / gamma_mn with the
+ * fluid-fluid tensions gamma_mn = alpha (kappa_m + kappa_n) / 6 (Sec. II.A)
+ * and the solid-fluid tensions of the surface free energy (Sec. II.B, eq.
+ * solidST) reduces to
+ *   cos(theta_mn) = (Phi_m - Phi_n) / (2 (kappa_m + kappa_n)),
+ *   Phi_m = kappa_m (s+^3 - s-^3),  s+- = sqrt(1 +- 4 h_m / (alpha kappa_m)).
+ * (The inversion formula printed in Sec. II.D has the opposite sign and an
+ * extra factor alpha; these helpers use the relation above.)  Angles are in
+ * degrees, theta_mn measured through fluid m; kappa[3] > 0, alpha > 0.
+ *
+ * tlb_contact_angles: theta_out = (theta_12, theta_23, theta_31) for h[3]
+ *   with |4 h_m / (alpha kappa_m)| <= 1 (TLB_EINVAL otherwise).
+ * tlb_wetting_from_angles: h_out[3] that gives theta_12 and theta_23 (theta_31
+ *   follows from the Girifalco-Good relation) with the redundancy condition
+ *   sum_m h_m / kappa_m = 0 of Sec. II.D (zero density gradient at the wall);
+ *   TLB_EINVAL if no such h exists within |4 h_m / (alpha kappa_m)| <= 1.
+ */
+tlb_status tlb_contact_angles(const double* kappa, double alpha, const double* h, double* theta_out);
+tlb_status tlb_wetting_from_angles(const double* kappa, double alpha, double theta12, double theta23,
+                                   double* h_out);
+
+/* ------------------------------------------------------------------------ */
 /* Reverse mode (D2Q9; TLB_EINVAL for D3Q19)                                 */
 /* ------------------------------------------------------------------------ */
 /*

@@ -695,6 +695,101 @@ extern "C" tlb_status tlb_load_state_dev(tlb_sim* s, const void* src, int64_t st
 // ---------------------------------------------------------------------------
 // Parameters that may change between runs, and the adjoint
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// Contact angles <-> wetting parameters (Sec. II.B, II.D), host only.
+// ---------------------------------------------------------------------------
+// Phi(h) = kappa (s+^3 - s-^3), s+- = sqrt(1 +- 4h/(alpha kappa)): the solid tension difference
+// gamma_sn - gamma_sm equals alpha (Phi_m - Phi_n) / 12; Phi is increasing on |h| <= alpha kappa / 4.
+static double wet_phi(double k, double a, double h)
+{
+    const double r = 4.0 * h / (a * k);
+    const double sp = sqrt(fmax(0.0, 1.0 + r)), sm = sqrt(fmax(0.0, 1.0 - r));
+    return k * (sp * sp * sp - sm * sm * sm);
+}
+
+static bool wet_params_ok(const double* kappa, double alpha)
+{
+    if (!kappa || !(alpha > 0.0) || !isfinite(alpha)) return false;
+    for (int m = 0; m < 3; ++m)
+        if (!(kappa[m] > 0.0) || !isfinite(kappa[m])) return false;
+    return true;
+}
+
+// h with Phi(h) = phi by bisection on [-alpha kappa/4, alpha kappa/4]; false if out of range.
+static bool wet_h_of_phi(double k, double a, double phi, double* h)
+{
+    double lo = -0.25 * a * k, hi = 0.25 * a * k;
+    if (phi < wet_phi(k, a, lo) || phi > wet_phi(k, a, hi)) return false;
+    for (int it = 0; it < 200; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (wet_phi(k, a, mid) < phi)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    *h = 0.5 * (lo + hi);
+    return true;
+}
+
+extern "C" tlb_status tlb_contact_angles(const double* kappa, double alpha, const double* h, double* theta_out)
+{
+    if (!wet_params_ok(kappa, alpha) || !h || !theta_out) return TLB_EINVAL;
+    double phi[3];
+    for (int m = 0; m < 3; ++m) {
+        if (!isfinite(h[m]) || fabs(4.0 * h[m] / (alpha * kappa[m])) > 1.0) return TLB_EINVAL;
+        phi[m] = wet_phi(kappa[m], alpha, h[m]);
+    }
+    const double rad = 180.0 / 3.14159265358979323846;
+    for (int j = 0; j < 3; ++j) {
+        const int m = j, n = (j + 1) % 3;
+        double c = (phi[m] - phi[n]) / (2.0 * (kappa[m] + kappa[n]));
+        c = c > 1.0 ? 1.0 : (c < -1.0 ? -1.0 : c);
+        theta_out[j] = acos(c) * rad;
+    }
+    return TLB_OK;
+}
+
+extern "C" tlb_status tlb_wetting_from_angles(const double* kappa, double alpha, double theta12, double theta23,
+                                              double* h_out)
+{
+    if (!wet_params_ok(kappa, alpha) || !h_out || !isfinite(theta12) || !isfinite(theta23)) return TLB_EINVAL;
+    if (theta12 < 0.0 || theta12 > 180.0 || theta23 < 0.0 || theta23 > 180.0) return TLB_EINVAL;
+    const double deg = 3.14159265358979323846 / 180.0;
+    // Phi_1 - Phi_2 and Phi_2 - Phi_3 are fixed by the angles; Phi_3 = t is the remaining freedom,
+    // chosen so that sum_m h_m / kappa_m = 0 (which increases with t).
+    const double d12 = 2.0 * (kappa[0] + kappa[1]) * cos(theta12 * deg);
+    const double d23 = 2.0 * (kappa[1] + kappa[2]) * cos(theta23 * deg);
+    const double off[3] = {d12 + d23, d23, 0.0};
+    double lo = -1e300, hi = 1e300;
+    for (int m = 0; m < 3; ++m) {  // t range on which every Phi_m stays attainable
+        const double pmin = wet_phi(kappa[m], alpha, -0.25 * alpha * kappa[m]);
+        const double pmax = wet_phi(kappa[m], alpha, 0.25 * alpha * kappa[m]);
+        lo = fmax(lo, pmin - off[m]);
+        hi = fmin(hi, pmax - off[m]);
+    }
+    if (!(lo <= hi)) return TLB_EINVAL;
+    auto redundancy = [&](double t, double* h) {
+        double g = 0.0;
+        for (int m = 0; m < 3; ++m) {
+            if (!wet_h_of_phi(kappa[m], alpha, t + off[m], &h[m])) h[m] = (t + off[m] > 0 ? 0.25 : -0.25) * alpha * kappa[m];
+            g += h[m] / kappa[m];
+        }
+        return g;
+    };
+    double h[3];
+    if (redundancy(lo, h) > 0.0 || redundancy(hi, h) < 0.0) return TLB_EINVAL;
+    for (int it = 0; it < 200; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (redundancy(mid, h) < 0.0)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    redundancy(0.5 * (lo + hi), h);
+    for (int m = 0; m < 3; ++m) h_out[m] = h[m];
+    return TLB_OK;
+}
+
 extern "C" tlb_status tlb_set_kappa(tlb_sim* s, const double* kappa)
 {
     if (!s || !kappa) return TLB_EINVAL;

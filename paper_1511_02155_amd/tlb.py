@@ -45,7 +45,7 @@ EXPORTS = (
     "tlb_batch_get_field", "tlb_batch_get_populations", "tlb_batch_diagnostics", "tlb_batch_set_launch",
     "tlb_batch_get_launch", "tlb_batch_autotune", "tlb_batch_set_graph",
     "tlb_set_kappa", "tlb_adjoint_seed_dev", "tlb_adjoint_step_dev", "tlb_checkpoint_slots",
-    "tlb_forward_checkpointed", "tlb_adjoint_backward",
+    "tlb_forward_checkpointed", "tlb_adjoint_backward", "tlb_contact_angles", "tlb_wetting_from_angles",
 )
 
 
@@ -108,6 +108,9 @@ tlb_set_populations_dev = _sig("tlb_set_populations_dev", ctypes.c_int, [_vp, ct
 tlb_set_wetting_dev = _sig("tlb_set_wetting_dev", ctypes.c_int, [_vp, ctypes.c_int, _vp])
 tlb_set_launch = _sig("tlb_set_launch", ctypes.c_int, [_vp, ctypes.POINTER(tlb_launch)])
 tlb_get_launch = _sig("tlb_get_launch", ctypes.c_int, [_vp, ctypes.POINTER(tlb_launch)])
+tlb_contact_angles = _sig("tlb_contact_angles", ctypes.c_int, [_dp, ctypes.c_double, _dp, _dp])
+tlb_wetting_from_angles = _sig("tlb_wetting_from_angles", ctypes.c_int,
+                               [_dp, ctypes.c_double, ctypes.c_double, ctypes.c_double, _dp])
 tlb_set_adjoint_launch = _sig("tlb_set_adjoint_launch", ctypes.c_int, [_vp, ctypes.POINTER(tlb_launch)])
 tlb_get_adjoint_launch = _sig("tlb_get_adjoint_launch", ctypes.c_int, [_vp, ctypes.POINTER(tlb_launch)])
 tlb_bytes_per_node = _sig("tlb_bytes_per_node", ctypes.c_double, [_vp])
@@ -173,6 +176,24 @@ def make_params(lattice, nx, ny, nz=1, prec=TLB_F64, walls_y=0, kappa=(0.01, 0.0
     p.alpha, p.tau_f, p.tau_g, p.tau_k = alpha, tau_f, tau_g, tau_k
     p.gamma_phi, p.gamma_psi = gamma_phi, gamma_psi
     return p
+
+
+def contact_angles(kappa, alpha, h):
+    """(theta_12, theta_23, theta_31) in degrees for wetting parameters h[3] (tlb_contact_angles)."""
+    k, hh = _arr(kappa, 3), _arr(h, 3)
+    out = np.zeros(3)
+    check(tlb_contact_angles(k.ctypes.data_as(_dp), float(alpha), hh.ctypes.data_as(_dp), out.ctypes.data_as(_dp)),
+          "tlb_contact_angles")
+    return tuple(float(v) for v in out)
+
+
+def wetting_from_angles(kappa, alpha, theta12, theta23):
+    """h[3] giving theta_12, theta_23 with sum h_m / kappa_m = 0 (tlb_wetting_from_angles)."""
+    k = _arr(kappa, 3)
+    out = np.zeros(3)
+    check(tlb_wetting_from_angles(k.ctypes.data_as(_dp), float(alpha), float(theta12), float(theta23),
+                                  out.ctypes.data_as(_dp)), "tlb_wetting_from_angles")
+    return tuple(float(v) for v in out)
 
 
 class Sim:

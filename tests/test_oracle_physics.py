@@ -13,6 +13,7 @@ import numpy as np
 import pytest
 
 import analytic
+import shapes
 from paper_1511_02155_amd import inputs
 
 KAPPA = (0.01, 0.015, 0.02)
@@ -55,30 +56,6 @@ def test_laplace_pressure_gives_pair_surface_tensions(orc, m, n):
     assert slope == pytest.approx(g, rel=0.03)
 
 
-def _fit_angle(c1, nx, ny):
-    """Contact angle (degrees, through C1) of the circle fitted to the C1 = 1/2 contour above the
-    first three rows; the wall is the half-way plane y = -1/2."""
-    px, py = [], []
-    for y in range(3, ny):
-        row = c1[y]
-        for x in range(nx - 1):
-            if (row[x] - 0.5) * (row[x + 1] - 0.5) < 0:
-                px.append(x + (0.5 - row[x]) / (row[x + 1] - row[x]))
-                py.append(float(y))
-    for x in range(nx):
-        col = c1[:, x]
-        for y in range(3, ny - 1):
-            if (col[y] - 0.5) * (col[y + 1] - 0.5) < 0:
-                px.append(float(x))
-                py.append(y + (0.5 - col[y]) / (col[y + 1] - col[y]))
-    px, py = np.array(px), np.array(py)
-    A = np.stack([px, py, np.ones_like(px)], 1)
-    c, *_ = np.linalg.lstsq(A, px ** 2 + py ** 2, rcond=None)
-    xc, yc = c[0] / 2, c[1] / 2
-    R = math.sqrt(c[2] + xc ** 2 + yc ** 2)
-    return math.degrees(math.acos(max(-1.0, min(1.0, (-0.5 - yc) / R))))
-
-
 def _cap_angle(orc, h, theta0, steps, nx=80, ny=40, R0=16.0, M=0.2):
     kappa = (0.01, 0.01, 0.01)
     gp, gk = inputs.mobility_to_gamma(M, 1.0, 1.0)
@@ -87,7 +64,7 @@ def _cap_angle(orc, h, theta0, steps, nx=80, ny=40, R0=16.0, M=0.2):
     hh = inputs.uniform_h(nx, (h, -h, 0.0))
     pop = orc.init_equilibrium(p, inputs.cap(nx, ny, R0, theta0), None, hh)
     orc.step(p, pop, steps, hh)
-    return _fit_angle(orc.fields(p, pop, hh)["C1"].reshape(ny, nx), nx, ny)
+    return shapes.fit_contact_angle(orc.fields(p, pop, hh)["C1"].reshape(ny, nx), nx, ny)
 
 
 @pytest.mark.parametrize("h", [0.001, -0.001])
