@@ -85,7 +85,8 @@ enum {
 /*
  * Simulation parameters.
  *   lattice   TLB_D2Q9 (requires nz == 1) or TLB_D3Q19 (requires nz >= 3).
- *   prec      TLB_F32 or TLB_F64: storage and arithmetic precision.
+ *   prec      TLB_F32 or TLB_F64: storage precision of the populations (the
+ *             arithmetic is FP64 for both; FP32 rounds each population once per step).
  *   nx, ny    lattice size, each >= 3; nz >= 1.
  *   walls_y   0: periodic in y; 1: half-way walls below y = 0 and above y = ny-1.
  *   kappa[m]  bulk coefficients kappa_1..3 > 0 (Sec. II.A); kappa'_m = alpha^2 kappa_m.
@@ -93,6 +94,11 @@ enum {
  *   tau_f, tau_g, tau_k   relaxation times of f, g, k, each > 1/2 (Sec. IV).
  *   gamma_phi, gamma_psi  the tunable Gamma_phi, Gamma_psi of the g and k
  *             equilibria; mobilities are M = Gamma (tau - 1/2) (Sec. IV).
+ *   no_advection  0: the g and k equilibria carry the fluid velocity (advective
+ *             Cahn-Hilliard equations, Sec. III); 1: their velocity terms are left
+ *             out, which removes advection from the Cahn-Hilliard equations (the
+ *             diffusive coarsening runs of Sec. V.C).  Zero-initialised
+ *             parameters keep the advective model.
  */
 typedef struct {
     int32_t lattice;
@@ -103,6 +109,7 @@ typedef struct {
     double alpha;
     double tau_f, tau_g, tau_k;
     double gamma_phi, gamma_psi;
+    int32_t no_advection;
 } tlb_params;
 
 /* Conservation and stability check of the current state s_t (all sums in FP64). */
@@ -112,6 +119,11 @@ typedef struct {
     double max_speed;   /* max |v| */
     int64_t nonfinite;  /* number of nodes with a non-finite moment */
     int64_t step;       /* time steps taken since initialisation */
+    /* sum over fluid nodes of C_m^2 (1 - C_m)^2.  A flat interface of the profile of eq. (tanh)
+     * contributes alpha/6 per unit length (area in 3D), so 6 * interface[m] / alpha estimates the
+     * length (area) of the boundary of component m and chi_m of Sec. V.C is its value divided by
+     * the side of a square domain; the typical domain size is the domain area over that length. */
+    double interface[3];
 } tlb_diag;
 
 typedef struct tlb_sim tlb_sim;
@@ -120,7 +132,7 @@ typedef struct tlb_sim tlb_sim;
 const char* tlb_status_str(int status);
 /* HIP error code of the last TLB_EHIP returned on this thread (0 if none). */
 int tlb_last_hip_error(void);
-/* ABI version (major * 100 + minor). */
+/* ABI version (major * 100 + minor); 2xx: tlb_params.no_advection and tlb_diag.interface. */
 int tlb_version(void);
 
 /*

@@ -38,6 +38,7 @@ class OrcParams(ctypes.Structure):
         ("tau_k", ctypes.c_double),
         ("gamma_phi", ctypes.c_double),
         ("gamma_psi", ctypes.c_double),
+        ("no_advection", ctypes.c_int32),
     ]
 
 
@@ -91,7 +92,7 @@ class Params:
     """Physical and lattice parameters of one simulation (plain Python)."""
 
     def __init__(self, lattice, nx, ny, nz=1, walls_y=0, kappa=(0.01, 0.01, 0.01), alpha=1.0,
-                 tau_f=1.0, tau_g=1.0, tau_k=1.0, gamma_phi=1.0, gamma_psi=1.0):
+                 tau_f=1.0, tau_g=1.0, tau_k=1.0, gamma_phi=1.0, gamma_psi=1.0, no_advection=0):
         self.lattice = int(lattice)
         self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
         self.walls_y = int(walls_y)
@@ -99,6 +100,7 @@ class Params:
         self.alpha = float(alpha)
         self.tau_f, self.tau_g, self.tau_k = float(tau_f), float(tau_g), float(tau_k)
         self.gamma_phi, self.gamma_psi = float(gamma_phi), float(gamma_psi)
+        self.no_advection = int(no_advection)
 
     @property
     def Q(self):
@@ -119,12 +121,14 @@ class Params:
             p.kappa[m] = self.kappa[m]
         p.alpha, p.tau_f, p.tau_g, p.tau_k = self.alpha, self.tau_f, self.tau_g, self.tau_k
         p.gamma_phi, p.gamma_psi = self.gamma_phi, self.gamma_psi
+        p.no_advection = self.no_advection
         return p
 
     def replace(self, **kw):
         d = dict(lattice=self.lattice, nx=self.nx, ny=self.ny, nz=self.nz, walls_y=self.walls_y,
                  kappa=self.kappa, alpha=self.alpha, tau_f=self.tau_f, tau_g=self.tau_g,
-                 tau_k=self.tau_k, gamma_phi=self.gamma_phi, gamma_psi=self.gamma_psi)
+                 tau_k=self.tau_k, gamma_phi=self.gamma_phi, gamma_psi=self.gamma_psi,
+                 no_advection=self.no_advection)
         d.update(kw)
         return Params(**d)
 

@@ -58,6 +58,7 @@ typedef struct {
     double alpha;
     double tau_f, tau_g, tau_k;
     double gamma_phi, gamma_psi;
+    int32_t no_advection; /* 1: g^eq and k^eq without the velocity terms (diffusive Cahn-Hilliard) */
 } orc_params;
 
 typedef struct {
@@ -169,7 +170,10 @@ static void local_thermo(const orc_params* P, double rho, const double C[3], con
 
 /* Equilibria f^eq, g^eq, k^eq of Sec. IV (eq. eqdistfbinary) for i > 0 with
  * readings R3, R4; the rest populations follow from the mass constraints
- * sum_i f^eq_i = rho, sum_i g^eq_i = phi, sum_i k^eq_i = psi. */
+ * sum_i f^eq_i = rho, sum_i g^eq_i = phi, sum_i k^eq_i = psi.  With
+ * no_advection the velocity terms of g^eq and k^eq are left out, which
+ * removes the advection term from the Cahn-Hilliard equations (the diffusive
+ * runs of Sec. V.C). */
 static void equilibria(const orc_params* P, const orc_lattice* L, double rho, const double v[3],
                        double phi, double psi, const double C[3], const double gradC[3][3],
                        const double lapC[3], double* feq, double* geq, double* keq)
@@ -192,8 +196,9 @@ static void equilibria(const orc_params* P, const orc_lattice* L, double rho, co
         for (int c = 0; c < 6; ++c)
             grad += L->wab[i][c] * T[c];
         feq[i] = L->w[i] * ((pb - lam) / cs2 + rho * vel) + grad / cs2;
-        geq[i] = L->w[i] * (P->gamma_phi * mu_phi / cs2 + phi * vel);
-        keq[i] = L->w[i] * (P->gamma_psi * mu_psi / cs2 + psi * vel);
+        const double cvel = P->no_advection ? 0.0 : vel;
+        geq[i] = L->w[i] * (P->gamma_phi * mu_phi / cs2 + phi * cvel);
+        keq[i] = L->w[i] * (P->gamma_psi * mu_psi / cs2 + psi * cvel);
         fs += feq[i];
         gs += geq[i];
         ks += keq[i];
@@ -345,6 +350,8 @@ int orc_check_params(const orc_params* P)
     if (!(P->tau_f > 0.5 && P->tau_g > 0.5 && P->tau_k > 0.5))
         return -1;
     if (!(P->alpha > 0.0))
+        return -1;
+    if (P->no_advection != 0 && P->no_advection != 1)
         return -1;
     for (int m = 0; m < 3; ++m)
         if (!(P->kappa[m] > 0.0))

@@ -94,16 +94,17 @@ __device__ __forceinline__ void adj_local(const Phys<T>& P, const Moments<T>& mo
         const T fb = af[i] - af[0], gb = ag[i] - ag[0], kb_ = ak[i] - ak[0];
         const T ev = T(L9::ex[i]) * vx + T(L9::ey[i]) * vy;
         const T U = T(3) * ev + T(4.5) * ev * ev - T(1.5) * vv;
+        const T Ua = P.adv * U;  // velocity terms of g^eq, k^eq (absent without advection)
         bA += w * fb;
         b_rho += w * U * fb;
         bTxx += T(3 * wdiag<L9>(i, 0)) * fb;
         bTyy += T(3 * wdiag<L9>(i, 1)) * fb;
         bTxy += T(3 * woff<L9>(i, 0, 1)) * fb;
         bBp += w * gb;
-        b_phi += w * U * gb;
+        b_phi += w * Ua * gb;
         bBk += w * kb_;
-        b_psi += w * U * kb_;
-        const T bU = w * (rho * fb + phi * gb + psi * kb_);
+        b_psi += w * Ua * kb_;
+        const T bU = w * (rho * fb + P.adv * (phi * gb + psi * kb_));
         const T bev = bU * (T(3) + T(9) * ev);
         bvv += T(-1.5) * bU;
         bvx += T(L9::ex[i]) * bev;

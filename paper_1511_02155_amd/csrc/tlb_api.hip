@@ -70,7 +70,7 @@ extern "C" const char* tlb_status_str(int s)
 }
 
 extern "C" int tlb_last_hip_error(void) { return g_last_hip; }
-extern "C" int tlb_version(void) { return 100; }
+extern "C" int tlb_version(void) { return 200; }
 
 static bool params_valid(const tlb_params* p)
 {
@@ -87,6 +87,7 @@ static bool params_valid(const tlb_params* p)
     if (!(p->tau_f > 0.5 && p->tau_g > 0.5 && p->tau_k > 0.5)) return false;
     if (!isfinite(p->tau_f) || !isfinite(p->tau_g) || !isfinite(p->tau_k)) return false;
     if (!isfinite(p->gamma_phi) || !isfinite(p->gamma_psi)) return false;
+    if (p->no_advection != 0 && p->no_advection != 1) return false;
     const int64_t N = (int64_t)p->nx * p->ny * p->nz;
     const int Q = p->lattice == TLB_D2Q9 ? 9 : 19;
     // one species array must stay addressable by 32-bit byte offsets
@@ -111,6 +112,7 @@ static Phys<T> make_phys(const tlb_params& p)
     P.omega[2] = T(1.0 / p.tau_k);
     P.gphi3 = T(3.0 * p.gamma_phi);
     P.gpsi3 = T(3.0 * p.gamma_psi);
+    P.adv = p.no_advection ? T(0) : T(1);
     return P;
 }
 
@@ -640,6 +642,7 @@ extern "C" tlb_status tlb_diagnostics(tlb_sim* s, tlb_diag* out)
     for (int m = 0; m < 3; ++m) {
         out->mass[m] = h[m];
         out->momentum[m] = h[3 + m];
+        out->interface[m] = h[8 + m];
     }
     out->max_speed = h[6];
     out->nonfinite = (int64_t)h[7];

@@ -238,6 +238,10 @@ __global__ __launch_bounds__(256) void k_diag1(AuxGeom g, const T* __restrict__ 
             acc[5] += jz;
             const double sp = sqrt(jx * jx + jy * jy + jz * jz) / rho;
             acc[6] = fmax(acc[6], sp);
+            // interface measure: C_m^2 (1 - C_m)^2 with C1 = (rho + phi - psi)/2, C2 = (rho - phi - psi)/2, C3 = psi
+            const double c[3] = {0.5 * (rho + phi - psi), 0.5 * (rho - phi - psi), psi};
+#pragma unroll
+            for (int m = 0; m < 3; ++m) acc[8 + m] += c[m] * c[m] * (1.0 - c[m]) * (1.0 - c[m]);
         } else {
             acc[7] += 1.0;
         }

@@ -189,6 +189,7 @@ static Phys<T> phys_of(const tlb_params& p)
     P.omega[2] = T(1.0 / p.tau_k);
     P.gphi3 = T(3.0 * p.gamma_phi);
     P.gpsi3 = T(3.0 * p.gamma_psi);
+    P.adv = p.no_advection ? T(0) : T(1);
     return P;
 }
 
@@ -290,6 +291,7 @@ extern "C" tlb_status tlb_batch_create(const tlb_params* per_dom, int32_t ndom, 
         if (!(p.tau_f > 0.5 && p.tau_g > 0.5 && p.tau_k > 0.5)) return TLB_EINVAL;
         if (!isfinite(p.tau_f) || !isfinite(p.tau_g) || !isfinite(p.tau_k)) return TLB_EINVAL;
         if (!isfinite(p.gamma_phi) || !isfinite(p.gamma_psi)) return TLB_EINVAL;
+        if (p.no_advection != 0 && p.no_advection != 1) return TLB_EINVAL;
         if (prec != TLB_F32 && prec != TLB_F64) return TLB_EINVAL;
         const int64_t bytes = (int64_t)27 * p.nx * p.ny * (prec == TLB_F32 ? 4 : 8);
         if (bytes > (int64_t)0xFFFFFF00) return TLB_EINVAL;
@@ -571,6 +573,7 @@ extern "C" tlb_status tlb_batch_diagnostics(tlb_batch* b, int32_t dom, tlb_diag*
     for (int m = 0; m < 3; ++m) {
         out->mass[m] = h[m];
         out->momentum[m] = h[3 + m];
+        out->interface[m] = h[8 + m];
     }
     out->max_speed = h[6];
     out->nonfinite = (int64_t)h[7];

@@ -137,6 +137,7 @@ struct Phys {
     T a2kappa[3];  // alpha^2 kappa_m
     T omega[3];    // 1/tau for f, g, k
     T gphi3, gpsi3;  // Gamma_phi / c_s^2, Gamma_psi / c_s^2
+    T adv;           // 1: g^eq, k^eq carry the velocity terms; 0: diffusive Cahn-Hilliard
 };
 
 // Arithmetic type of the per-node computations for a storage type T.  Both
@@ -281,8 +282,9 @@ __device__ __forceinline__ void collide(const Phys<T>& P, const Moments<T>& mo, 
             G += T(3 * wdiag<L>(i, 2)) * Tzz + T(3 * woff<L>(i, 1, 2)) * Tyz +
                  T(3 * woff<L>(i, 2, 0)) * Tzx;
         const T feq = w * (A + rho * U) + G;
-        const T geq = w * (Bp + mo.phi * U);
-        const T keq = w * (Bk + psi * U);
+        const T Ua = P.adv * U;
+        const T geq = w * (Bp + mo.phi * Ua);
+        const T keq = w * (Bk + psi * Ua);
         sf += feq;
         sg += geq;
         sk += keq;

@@ -93,6 +93,6 @@ template <typename TIn, typename TOut>
 hipError_t launch_convert(const TIn* in, TOut* out, int64_t n, hipStream_t s);
 
 constexpr int kDiagBlocks = 1024;
-constexpr int kDiagSlots = 8;  // mass[3], momentum[3], max|v|, nonfinite
+constexpr int kDiagSlots = 11;  // mass[3], momentum[3], max|v|, nonfinite, interface[3]
 
 }  // namespace tlb

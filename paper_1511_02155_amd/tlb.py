@@ -57,6 +57,7 @@ class tlb_params(ctypes.Structure):
         ("kappa", ctypes.c_double * 3), ("alpha", ctypes.c_double),
         ("tau_f", ctypes.c_double), ("tau_g", ctypes.c_double), ("tau_k", ctypes.c_double),
         ("gamma_phi", ctypes.c_double), ("gamma_psi", ctypes.c_double),
+        ("no_advection", ctypes.c_int32),
     ]
 
 
@@ -64,6 +65,7 @@ class tlb_diag(ctypes.Structure):
     _fields_ = [
         ("mass", ctypes.c_double * 3), ("momentum", ctypes.c_double * 3),
         ("max_speed", ctypes.c_double), ("nonfinite", ctypes.c_int64), ("step", ctypes.c_int64),
+        ("interface", ctypes.c_double * 3),
     ]
 
 
@@ -168,14 +170,23 @@ def _arr(a, n=None):
 
 
 def make_params(lattice, nx, ny, nz=1, prec=TLB_F64, walls_y=0, kappa=(0.01, 0.01, 0.01), alpha=1.0,
-                tau_f=1.0, tau_g=1.0, tau_k=1.0, gamma_phi=1.0, gamma_psi=1.0, **_ignored):
+                tau_f=1.0, tau_g=1.0, tau_k=1.0, gamma_phi=1.0, gamma_psi=1.0, no_advection=0, **_ignored):
     p = tlb_params()
     p.lattice, p.prec, p.nx, p.ny, p.nz, p.walls_y = lattice, prec, nx, ny, nz, walls_y
     for m in range(3):
         p.kappa[m] = kappa[m]
     p.alpha, p.tau_f, p.tau_g, p.tau_k = alpha, tau_f, tau_g, tau_k
     p.gamma_phi, p.gamma_psi = gamma_phi, gamma_psi
+    p.no_advection = int(no_advection)
     return p
+
+
+def interface_measures(interface_sum, alpha, area):
+    """From the diagnostics' sum of C_m^2 (1 - C_m)^2: the boundary length (area in 3D) of each
+    component, 6 * sum / alpha (a flat interface of the tanh profile contributes alpha / 6 per unit
+    length), and the typical domain size area / length (volume / area in 3D) of Sec. V.C."""
+    length = [6.0 * s / alpha for s in interface_sum]
+    return dict(length=length, domain_size=[area / l if l > 0 else float("inf") for l in length])
 
 
 def contact_angles(kappa, alpha, h):
@@ -273,7 +284,7 @@ class Sim:
         if rc != TLB_OK and not (allow_nan and rc == TLB_ENAN):
             check(rc, "tlb_diagnostics")
         return dict(mass=list(d.mass), momentum=list(d.momentum), max_speed=d.max_speed,
-                    nonfinite=d.nonfinite, step=d.step)
+                    nonfinite=d.nonfinite, step=d.step, interface=list(d.interface))
 
     def set_launch(self, width, height=1, chunk=0, variant=1):
         l = tlb_launch(width, height, chunk, variant)
@@ -389,7 +400,7 @@ class Batch:
         dg = tlb_diag()
         check(tlb_batch_diagnostics(self._h, d, ctypes.byref(dg)), "tlb_batch_diagnostics")
         return dict(mass=list(dg.mass), momentum=list(dg.momentum), max_speed=dg.max_speed,
-                    nonfinite=dg.nonfinite, step=dg.step)
+                    nonfinite=dg.nonfinite, step=dg.step, interface=list(dg.interface))
 
     def set_launch(self, width, chunk, variant=1):
         l = tlb_launch(width, 1, chunk, variant)

@@ -18,7 +18,8 @@ from paper_1511_02155_amd import inputs
 
 pytestmark = pytest.mark.gpu
 
-KEYS = ("lattice", "nx", "ny", "nz", "walls_y", "kappa", "alpha", "tau_f", "tau_g", "tau_k", "gamma_phi", "gamma_psi")
+KEYS = ("lattice", "nx", "ny", "nz", "walls_y", "kappa", "alpha", "tau_f", "tau_g", "tau_k", "gamma_phi", "gamma_psi",
+        "no_advection")
 
 
 def _note(msg):
@@ -38,10 +39,10 @@ def env():
     return torch, tlb
 
 
-def _wall_case(nx=24, ny=16, R=7.0, kappa=(0.012, 0.02, 0.016), seed=5, walls=1):
+def _wall_case(nx=24, ny=16, R=7.0, kappa=(0.012, 0.02, 0.016), seed=5, walls=1, no_advection=0):
     gp, gk = inputs.mobility_to_gamma(0.1, 0.9, 0.8)
     w = dict(lattice=0, nx=nx, ny=ny, nz=1, walls_y=walls, kappa=kappa, alpha=1.1, tau_f=1.0, tau_g=0.9, tau_k=0.8,
-             gamma_phi=gp, gamma_psi=gk)
+             gamma_phi=gp, gamma_psi=gk, no_advection=no_advection)
     C = inputs.sessile_drop(nx, ny, R, top_layer=0.7 * ny)
     h = inputs.random_h(nx, -0.003, 0.003, seed=seed, bottom_only=False)
     target = inputs.sessile_drop(nx, ny, R + 1.5, x0=nx / 2 + 1.0)[0]
@@ -50,7 +51,7 @@ def _wall_case(nx=24, ny=16, R=7.0, kappa=(0.012, 0.02, 0.016), seed=5, walls=1)
 
 def _sim(torch, tlb, w, C, h, prec, stream, launch=None):
     """A tlb_sim on ``stream``; the caller runs its torch work on the same stream."""
-    s = tlb.Sim(tlb.make_params(prec=prec, **{k: w[k] for k in KEYS}), stream=stream.cuda_stream)
+    s = tlb.Sim(tlb.make_params(prec=prec, **{k: w[k] for k in KEYS if k in w}), stream=stream.cuda_stream)
     if w["walls_y"]:
         s.set_wetting_both(h)
     s.init_equilibrium(C)
@@ -66,6 +67,7 @@ def _dev(torch, s):
 TRANSPOSE_CASES = [
     # (walls, nx, ny, adjoint launch): walls with wetting, periodic, ragged strips and chunks, narrow lattices
     (1, 24, 16, dict(width=64, chunk=8)),
+    (2, 24, 16, dict(width=64, chunk=8)),  # walls, no advection in the Cahn-Hilliard equilibria
     (0, 24, 16, dict(width=64, chunk=5)),
     (1, 70, 9, dict(width=64, chunk=4)),
     (0, 131, 7, dict(width=128, chunk=3)),
@@ -78,7 +80,7 @@ TRANSPOSE_CASES = [
 def test_one_step_transpose_identity(env, walls, nx, ny, launch):
     """<lambda, J v> == <J^T lambda, v> for the state, for h and for kappa (FP64)."""
     torch, tlb = env
-    w, C, h, _ = _wall_case(nx=nx, ny=ny, R=min(nx, ny) / 3.0, walls=walls)
+    w, C, h, _ = _wall_case(nx=nx, ny=ny, R=min(nx, ny) / 3.0, walls=min(walls, 1), no_advection=int(walls == 2))
     _note(f"transpose identity walls={walls} {nx}x{ny} {launch}")
     st = torch.cuda.Stream()
     with torch.cuda.stream(st):
@@ -167,7 +169,7 @@ def test_reverse_step_independent_of_launch_shape(env):
 def _gpu_grad(torch, tlb, w, C, h, target, steps, every, prec):
     from paper_1511_02155_amd.autograd import Runner, TernaryLB
 
-    p = tlb.make_params(prec=prec, **{k: w[k] for k in KEYS})
+    p = tlb.make_params(prec=prec, **{k: w[k] for k in KEYS if k in w})
     r = Runner(p, C, steps, every=every, h=h)
     dt = torch.float64 if prec == tlb.TLB_F64 else torch.float32
     hb = torch.tensor(h[0], dtype=dt, device="cuda", requires_grad=True)
@@ -188,7 +190,7 @@ def test_gradients_match_autodiff_reference(env, orc):
     w, C, h, target = _wall_case()
     steps = 30
     L, dh, dk = _gpu_grad(torch, tlb, w, C, h, target, steps, 6, tlb.TLB_F64)
-    p = orc.Params(**{k: w[k] for k in KEYS})
+    p = orc.Params(**{k: w[k] for k in KEYS if k in w})
     pop0 = orc.init_equilibrium(p, C, None, h)
     t0 = torch.tensor(pop0.reshape(3, 9, w["ny"], w["nx"]))
     hh = torch.tensor(h.reshape(2, 3, w["nx"]))
@@ -227,7 +229,7 @@ def test_adjoint_512_full_size_vs_finite_differences(env):
     w = inputs.adjoint_drop_512()
     _note("adjoint 512^2 fp64 2000 steps")
     L, dh, dk = _gpu_grad(torch, tlb, w, w["C"], w["h"], w["target"], w["steps"], 45, tlb.TLB_F64)
-    p = tlb.make_params(prec=tlb.TLB_F64, **{k: w[k] for k in KEYS})
+    p = tlb.make_params(prec=tlb.TLB_F64, **{k: w[k] for k in KEYS if k in w})
     s = tlb.Sim(p)
     s.set_wetting_both(w["h"])
     s.init_equilibrium(w["C"])

@@ -15,7 +15,8 @@ from paper_1511_02155_amd import inputs
 
 pytestmark = pytest.mark.gpu
 
-KEYS = ("lattice", "nx", "ny", "nz", "walls_y", "kappa", "alpha", "tau_f", "tau_g", "tau_k", "gamma_phi", "gamma_psi")
+KEYS = ("lattice", "nx", "ny", "nz", "walls_y", "kappa", "alpha", "tau_f", "tau_g", "tau_k", "gamma_phi", "gamma_psi",
+        "no_advection")
 
 
 def _note(msg):
@@ -37,15 +38,17 @@ def tlb():
 
 def _small_batch(ndom=10, seed=21):
     doms = inputs.batched_walls(ndom=ndom, lo=20, hi=140, seed=seed)
-    # make a few domains periodic in y to cover both boundary kinds
+    # make a few domains periodic in y to cover both boundary kinds, and a few diffusive
     for d in range(0, ndom, 3):
         doms[d]["walls_y"] = 0
         doms[d]["h"] = None
+    for i, dom in enumerate(doms):
+        dom["no_advection"] = 1 if i % 4 == 1 else 0
     return doms
 
 
 def _make_batch(tlb, doms, prec, launch=None, graph=0):
-    b = tlb.Batch([tlb.make_params(prec=prec, **{k: d[k] for k in KEYS}) for d in doms])
+    b = tlb.Batch([tlb.make_params(prec=prec, **{k: d[k] for k in KEYS if k in d}) for d in doms])
     if launch:
         b.set_launch(**launch)
     if graph:
@@ -59,7 +62,7 @@ def _make_batch(tlb, doms, prec, launch=None, graph=0):
 
 
 def _single(tlb, d, prec, steps):
-    s = tlb.Sim(tlb.make_params(prec=prec, **{k: d[k] for k in KEYS}))
+    s = tlb.Sim(tlb.make_params(prec=prec, **{k: d[k] for k in KEYS if k in d}))
     if d["h"] is not None:
         s.set_wetting_both(d["h"])
     s.init_equilibrium(d["C"])
@@ -119,7 +122,7 @@ def test_batch_small_domains_vs_oracle(tlb, orc):
     b = _make_batch(tlb, doms, tlb.TLB_F64)
     b.step(150)
     for i, d in enumerate(doms):
-        p = orc.Params(**{k: d[k] for k in KEYS})
+        p = orc.Params(**{k: d[k] for k in KEYS if k in d})
         pop = orc.init_equilibrium(p, d["C"], None, d["h"])
         orc.step(p, pop, 150, d["h"])
         got = b.all_populations(i)
@@ -139,7 +142,7 @@ def test_batch_512_domains_sampled(tlb, orc):
     for i in sorted(pick):
         d = doms[i]
         _note(f"domain {i} {d['nx']}x{d['ny']}")
-        p = orc.Params(**{k: d[k] for k in KEYS})
+        p = orc.Params(**{k: d[k] for k in KEYS if k in d})
         pop = orc.init_equilibrium(p, d["C"], None, d["h"])
         orc.step(p, pop, 4, d["h"])
         F = orc.fields(p, pop, d["h"])

@@ -36,16 +36,16 @@ def tlb():
     return t
 
 
+_PKEYS = ("lattice", "nx", "ny", "nz", "walls_y", "kappa", "alpha", "tau_f", "tau_g", "tau_k", "gamma_phi",
+          "gamma_psi", "no_advection")
+
+
 def _oparams(orc, w):
-    keys = ("lattice", "nx", "ny", "nz", "walls_y", "kappa", "alpha", "tau_f", "tau_g", "tau_k",
-            "gamma_phi", "gamma_psi")
-    return orc.Params(**{k: w[k] for k in keys})
+    return orc.Params(**{k: w[k] for k in _PKEYS if k in w})
 
 
 def _gsim(tlb, w, prec, launch=None):
-    p = tlb.make_params(prec=prec, **{k: v for k, v in w.items() if k in (
-        "lattice", "nx", "ny", "nz", "walls_y", "kappa", "alpha", "tau_f", "tau_g", "tau_k", "gamma_phi",
-        "gamma_psi")})
+    p = tlb.make_params(prec=prec, **{k: v for k, v in w.items() if k in _PKEYS})
     s = tlb.Sim(p)
     if launch:
         s.set_launch(**launch)
@@ -312,3 +312,41 @@ def test_spinodal_256cube_full_size_sampled(tlb, orc):
         n = c[0] + 256 * (c[1] + 256 * c[2])
         for sp in range(3):
             assert np.abs(gpu_pops[sp][:, n] - pop[sp][:, ic]).max() < 2e-7, (c, sp)
+
+
+# --------------------------------------------------------------------------
+# Diffusive Cahn-Hilliard (no advection) and the interface diagnostics
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("lattice,walls", [(0, 1), (0, 0), (1, 1)])
+def test_no_advection_fp64(tlb, orc, lattice, walls):
+    """g^eq and k^eq without velocity terms (tlb_params.no_advection), against the oracle, with a
+    non-zero initial flow so that the dropped terms matter."""
+    dims = (40, 27, 1) if lattice == 0 else (20, 17, 9)
+    w, C, h = _wet_case(*dims, lattice=lattice, walls=walls, seed=7)
+    w["no_advection"] = 1
+    _note(f"no advection lattice={lattice} walls={walls}")
+    p = _oparams(orc, w)
+    N = p.N
+    rng = np.random.default_rng(8)
+    u = rng.uniform(-0.02, 0.02, size=(p.D, N))
+    pop = orc.init_equilibrium(p, C, u, h)
+    orc.step(p, pop, 40, h)
+    s = _gsim(tlb, w, tlb.TLB_F64)
+    if h is not None:
+        s.set_wetting_both(h)
+    s.init_equilibrium(C, u)
+    s.step(40)
+    _compare_f64(orc, p, pop, h, s)
+
+
+@pytest.mark.parametrize("lattice", [0, 1])
+def test_interface_diagnostics_match_oracle_fields(tlb, orc, lattice):
+    """tlb_diag.interface[m] = sum over nodes of C_m^2 (1 - C_m)^2 of the current state."""
+    dims = (50, 31, 1) if lattice == 0 else (18, 14, 11)
+    w, C, h = _wet_case(*dims, lattice=lattice, walls=1, seed=9)
+    p, pop, s = _run_both(tlb, orc, w, C, h, 25, tlb.TLB_F64)
+    F = orc.fields(p, pop, h)
+    d = s.diagnostics()
+    for m, name in enumerate(("C1", "C2", "C3")):
+        want = float(np.sum(F[name] ** 2 * (1 - F[name]) ** 2))
+        assert d["interface"][m] == pytest.approx(want, rel=1e-12)

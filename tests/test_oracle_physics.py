@@ -142,3 +142,54 @@ def test_psi_mode_decay_keeps_absent_component_absent(orc):
     rate, c2, k = _mode_decay(orc, "psi", 1.0, M=M, c0=c0, kappa=kappa)
     assert rate == pytest.approx(_ch_rate(M, k, c0, kappa), rel=0.05)
     assert c2 < 0.01 * 1e-4
+
+
+def _mode_phase(orc, no_advection, u0=0.02, nx=32, steps=600, c0=0.9, amp=1e-4):
+    """Phase (radians) of the C1 cosine mode after `steps` in a uniform flow u0 along x."""
+    gp, gk = inputs.mobility_to_gamma(0.1, 1.0, 1.0)
+    ny = 3
+    p = orc.Params(lattice=0, nx=nx, ny=ny, walls_y=0, kappa=(0.01,) * 3, alpha=1.0, tau_f=1.0, tau_g=1.0,
+                   tau_k=1.0, gamma_phi=gp, gamma_psi=gk, no_advection=no_advection)
+    k = 2 * math.pi / nx
+    x = np.tile(np.arange(nx, dtype=float), ny)
+    c = c0 + amp * np.cos(k * x)
+    C = np.stack([c, 1 - c, np.zeros_like(c)])
+    u = np.stack([np.full(nx * ny, u0), np.zeros(nx * ny)])
+    pop = orc.init_equilibrium(p, C, u)
+    orc.step(p, pop, steps)
+    d = orc.fields(p, pop)["C1"][:nx]
+    z = np.sum((d - d.mean()) * np.exp(-1j * k * np.arange(nx)))
+    return float(np.angle(z)), k * u0 * steps
+
+
+def test_no_advection_leaves_patterns_in_place(orc):
+    """With the velocity terms of g^eq and k^eq (the advective Cahn-Hilliard equations of Sec. III) a
+    C1 mode in a uniform flow u moves by u t; without them (the diffusive runs of Sec. V.C) it stays."""
+    moved, expect = _mode_phase(orc, 0)
+    still, _ = _mode_phase(orc, 1)
+    assert -moved == pytest.approx(expect, rel=0.05)
+    assert abs(still) < 0.01 * expect
+
+
+def _slab_interface_length(orc, alpha):
+    nx, ny = int(48 * alpha), 5
+    kappa = (0.04 / alpha ** 2,) * 3
+    gp, gk = inputs.mobility_to_gamma(0.2, 1.0, 1.0)
+    p = orc.Params(lattice=0, nx=nx, ny=ny, walls_y=0, kappa=kappa, alpha=alpha, tau_f=1.0, tau_g=1.0, tau_k=1.0,
+                   gamma_phi=gp, gamma_psi=gk)
+    x = np.tile(np.arange(nx, dtype=float), ny)
+    c1 = inputs.tanh_profile(np.abs(x - nx / 2.0 + 0.5), nx / 4.0, alpha)
+    pop = orc.init_equilibrium(p, np.stack([c1, 1 - c1, np.zeros_like(c1)]))
+    orc.step(p, pop, 4000)
+    C1 = orc.fields(p, pop)["C1"]
+    return 6.0 * np.sum(C1 ** 2 * (1 - C1) ** 2) / alpha, 2.0 * ny
+
+
+def test_interface_measure_converges_to_flat_interface_length(orc):
+    """A relaxed binary slab: the sum over nodes of C1^2 (1 - C1)^2 is alpha/6 per unit interface
+    length for the tanh profile of eq. (tanh), so 6 sum / alpha -> 2 ny (two interfaces), with the
+    discretisation error of the profile falling at second order in 1/alpha."""
+    l1, want = _slab_interface_length(orc, 1.0)
+    l2, _ = _slab_interface_length(orc, 2.0)
+    e1, e2 = abs(l1 / want - 1), abs(l2 / want - 1)
+    assert e1 < 0.04 and e2 < 0.01 and e2 < e1 / 3.0, (e1, e2)
