@@ -294,14 +294,19 @@ typedef struct {
 tlb_status tlb_set_launch(tlb_sim* sim, const tlb_launch* launch);
 tlb_status tlb_get_launch(const tlb_sim* sim, tlb_launch* out);
 
-/* Launch shape of the reverse step (D2Q9 only; TLB_EINVAL otherwise): each
- * workgroup of `width` lanes (64, 128 or 256) covers `width` columns and
- * produces the middle width - 6 of them over `chunk` rows (chunk >= 1;
- * 0 picks a default); variant 1 issues the loads of all four stages of a
- * row before its arithmetic, variant 0 those of stage 4 only when it starts
- * (fewer registers).  height is ignored.  The adjoint
- * populations and dL/dh do not depend on the shape; dL/dkappa is summed per
- * work item, so its last bits do (it is reproducible for a fixed shape). */
+/* Launch shape of the reverse step (D2Q9 only; TLB_EINVAL otherwise).  A
+ * workgroup holds `height` row groups (1, 2 or 4; 0 means 1) of `width` lanes
+ * (64, 128 or 256; width * height <= 256).  It covers `width` columns,
+ * produces the middle width - 6 of them, and sweeps `chunk` rows (chunk >= 1;
+ * 0 picks a default), height rows per iteration.  Variant 0 issues the loads
+ * of stage 4 (the gather of lambda_{t+1}) when that stage starts; variant 1
+ * issues the loads of all four stages of a row before its arithmetic;
+ * variant 2 is variant 0 that also loads the next iteration's pull and
+ * lambda_{t+1} rows during the current one.  For a given variant the adjoint
+ * populations and dL/dh are bitwise the same for every shape; the variants
+ * fuse multiply-adds differently and agree to rounding.  dL/dkappa is summed
+ * per work item, so its last bits depend on the shape (it is reproducible for
+ * a fixed shape). */
 tlb_status tlb_set_adjoint_launch(tlb_sim* sim, const tlb_launch* launch);
 tlb_status tlb_get_adjoint_launch(const tlb_sim* sim, tlb_launch* out);
 

@@ -142,19 +142,29 @@ __device__ __forceinline__ void adj_local(const Phys<T>& P, const Moments<T>& mo
     lb[4] = b_dpsi;
 }
 
-template <typename T, int W, int HOIST>
-__global__ __launch_bounds__(W) void k_adj2d(AdjArgs<T> A)
+// K row groups of W lanes: in iteration j, group k runs stage 1 on row a0 + k, stage 2 on
+// a0 + k - 1, stage 3 on a0 + k - 2 and stage 4 on a0 + k - 3, with a0 = y0 - 3 + j K, so an item of
+// `chunk` rows takes (chunk + 6) / K iterations.  With K > 1 the moments (stage 1 -> 2) and the local
+// transposes (stage 2 -> 3) of a row are made by one group and used by the next, so they go through
+// LDS rings too; with K = 1 they stay in registers.  Every node runs the same arithmetic for every
+// W and K.
+template <typename T, int W, int K, int HOIST>
+__global__ __launch_bounds__(W * K) void k_adj2d(AdjArgs<T> A)
 {
     using C = acc_t<T>;  // arithmetic type (T is the storage type)
-    constexpr int R = 3;
-    __shared__ C sC[R][3][W];  // dC_m of the last three stage-1 rows
-    __shared__ C sA[R][9][W];  // Gbar_{m,x}, Gbar_{m,y} (m-major), Lbar_m of the last three stage-2 rows
-    __shared__ C sS[R][5][W];  // S_f, J_x, J_y, S_g, S_k of the last three stage-3 rows
-    __shared__ double sred[3][W];
+    constexpr int R = K + 2;              // ring rows
+    constexpr int RX = K > 1 ? R : 1;     // rings of moments and local transposes (K > 1 only)
+    __shared__ C sC[R][3][W];  // dC_m of stage-1 rows
+    __shared__ C sA[R][9][W];  // Gbar_{m,x}, Gbar_{m,y} (m-major), Lbar_m of stage-2 rows
+    __shared__ C sS[R][5][W];  // S_f, J_x, J_y, S_g, S_k of stage-3 rows
+    __shared__ C sM[RX][5][K > 1 ? W : 1];  // drho, jx, jy, phi, dpsi of stage-1 rows
+    __shared__ C sL[RX][8][K > 1 ? W : 1];  // local-transpose outputs of stage-2 rows
+    __shared__ double sred[3][W * K];
 
     const int item = xcd_item(blockIdx.x, gridDim.x);
     const int strip = item / A.nchunks, chunk = item - strip * A.nchunks;
-    const int l = threadIdx.x;
+    const int l = threadIdx.x % W;
+    const int grp = __builtin_amdgcn_readfirstlane(threadIdx.x / W);
     const int nx = A.nx, ny = A.ny;
     const int N = (int)A.N;
     const int x0 = strip * (W - 6);
@@ -170,69 +180,123 @@ __global__ __launch_bounds__(W) void k_adj2d(AdjArgs<T> A)
     Moments<C> mom_prev = {};
     C lb_prev[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     double kacc[3] = {0.0, 0.0, 0.0};
+    // ring slot of row r (every row touched is >= y0 - 3)
+    auto slot = [&](int r) { return (r - y0 + 3) % R; };
+    // Global accesses are raw buffer accesses: one descriptor per 27 N array, a per-lane column
+    // offset and a wavefront-uniform (scalar) offset for the species, direction and row.
+    constexpr uint32_t ES = sizeof(T);
+    const uint32_t nxu = (uint32_t)nx, Nu = (uint32_t)N, NB = Nu * ES;
+    const Rsrc ru = make_rsrc(A.u, 27u * NB), rl1 = make_rsrc(A.lam1, 27u * NB), rl0 = make_rsrc(A.lam0, 27u * NB);
+    const uint32_t vx0 = (uint32_t)x * ES, vxm = (uint32_t)xm * ES, vxp = (uint32_t)xp * ES;
 
-    for (int a = y0 - 3, it = 0; a < y1 + 3; ++a, ++it) {
-        const int b = a - 1, c = a - 2, d = a - 3;
-        const bool act1 = !walls || (a >= 0 && a < ny);
-        const bool act2 = b >= y0 - 2 && (!walls || (b >= 0 && b < ny)) && l >= 1 && l < W - 1;
-        const bool act3 = c >= y0 - 1 && (!walls || (c >= 0 && c < ny)) && l >= 2 && l < W - 2;
-        const bool act4 = d >= y0 && own_x;
+    // stage 1 and stage 2 run on rows a and a - 1 of a group when these are inside the item's reach
+    auto act12 = [&](int a_, bool& g1, bool& g2) {
+        const int b_ = a_ - 1;
+        const bool live_ = a_ < y1 + 3;
+        g1 = live_ && (!walls || (a_ >= 0 && a_ < ny));
+        g2 = live_ && b_ >= y0 - 2 && (!walls || (b_ >= 0 && b_ < ny)) && l >= 1 && l < W - 1;
+    };
+    // pull of row a_: direction i from r - e_i, or opp(i) at r where r - e_i lies beyond a wall
+    auto load_pull = [&](int a_, T* pu) {
+        const int row = walls ? a_ : modi(a_, ny);
+        const uint32_t ym = row == 0 ? ny - 1 : row - 1, yp = row == ny - 1 ? 0 : row + 1;
+        const bool blo = walls && row == 0, bhi = walls && row == ny - 1;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const int ex = L9::ex[i], ey = L9::ey[i];
+            const bool bb = (ey == 1) ? blo : (ey == -1) ? bhi : false;
+            const uint32_t ys = ey == 0 ? (uint32_t)row : (ey == 1 ? ym : yp);
+            const uint32_t so = bb ? (uint32_t)L9::opp[i] * NB + (uint32_t)row * nxu * ES : (uint32_t)i * NB + ys * nxu * ES;
+            const uint32_t v = bb ? vx0 : (ex == 0 ? vx0 : (ex == 1 ? vxm : vxp));
+            pu[i] = bload<T>(ru, v, so);
+            pu[9 + i] = bload<T>(ru, v, so + 9u * NB);
+            pu[18 + i] = bload<T>(ru, v, so + 18u * NB);
+        }
+    };
+    // lambda_{t+1} of row b_
+    auto load_lam = [&](int b_, T* la) {
+        const uint32_t so = (uint32_t)(walls ? b_ : modi(b_, ny)) * nxu * ES;
+#pragma unroll
+        for (int q = 0; q < 27; ++q) la[q] = bload<T>(rl1, vx0, so + (uint32_t)q * NB);
+    };
+    // HOIST == 2: the pull and lambda_{t+1} rows of the next iteration are loaded during this one
+    T pn[HOIST == 2 ? 27 : 1], ln[HOIST == 2 ? 27 : 1];
+    if constexpr (HOIST == 2) {
+        bool g1, g2;
+        act12(y0 - 3 + grp, g1, g2);
+        if (g1) load_pull(y0 - 3 + grp, pn);
+        if (g2) load_lam(y0 - 4 + grp, ln);
+    }
+
+    for (int a0 = y0 - 3; a0 < y1 + 3; a0 += K) {
+        const int a = a0 + grp, b = a - 1, c = a - 2, d = a - 3;
+        const bool live = a < y1 + 3;
+        bool act1, act2;
+        act12(a, act1, act2);
+        const bool act3 = live && c >= y0 - 1 && (!walls || (c >= 0 && c < ny)) && l >= 2 && l < W - 2;
+        const bool act4 = live && d >= y0 && own_x;
         // ---- the global loads of the iteration come first: the pull of row a (stage 1), lambda_{t+1}
-        // of row b (stage 2) and, with HOIST, the gather of lambda_{t+1} around row d (stage 4), so
+        // of row b (stage 2) and, with HOIST == 1, the gather of lambda_{t+1} around row d (stage 4), so
         // that none of them waits behind a store of stage 4 ----
         T pu[27], la[27], lg[27];
+        // lambda_{t+1} around row d (d is a fluid row): direction j from r + e_j, or opp(j) at r where
+        // r + e_j lies beyond a wall
         auto gather = [&]() {
+            const uint32_t dm = d == 0 ? ny - 1 : d - 1, dp = d == ny - 1 ? 0 : d + 1;
+            const bool blo = walls && d == 0, bhi = walls && d == ny - 1;
 #pragma unroll
             for (int j = 0; j < 9; ++j) {
-                const int yy = d + L9::ey[j];
-                int dir, src;
-                if (walls && (yy < 0 || yy >= ny)) {
-                    dir = L9::opp[j];
-                    src = d * nx + x;
-                } else {
-                    dir = j;
-                    src = wrapi(yy, ny) * nx + wrapi(x + L9::ex[j], nx);
-                }
-                lg[j] = A.lam1[dir * N + src];
-                lg[9 + j] = A.lam1[(9 + dir) * N + src];
-                lg[18 + j] = A.lam1[(18 + dir) * N + src];
+                const int ex = L9::ex[j], ey = L9::ey[j];
+                const bool bb = (ey == -1) ? blo : (ey == 1) ? bhi : false;
+                const uint32_t yy = ey == 0 ? (uint32_t)d : (ey == 1 ? dp : dm);
+                const uint32_t so = bb ? (uint32_t)L9::opp[j] * NB + (uint32_t)d * nxu * ES : (uint32_t)j * NB + yy * nxu * ES;
+                const uint32_t v = bb ? vx0 : (ex == 0 ? vx0 : (ex == 1 ? vxp : vxm));
+                lg[j] = bload<T>(rl1, v, so);
+                lg[9 + j] = bload<T>(rl1, v, so + 9u * NB);
+                lg[18 + j] = bload<T>(rl1, v, so + 18u * NB);
             }
         };
-        if (act1) {
-            const int row = walls ? a : modi(a, ny);
+        if constexpr (HOIST == 2) {
 #pragma unroll
-            for (int i = 0; i < 9; ++i) {
-                const int ys = row - L9::ey[i];
-                int o;
-                if (walls && (ys < 0 || ys >= ny))
-                    o = L9::opp[i] * N + row * nx + x;
-                else
-                    o = i * N + wrapi(ys, ny) * nx + wrapi(x - L9::ex[i], nx);
-                pu[i] = A.u[o];
-                pu[9 + i] = A.u[9 * N + o];
-                pu[18 + i] = A.u[18 * N + o];
+            for (int q = 0; q < 27; ++q) {
+                pu[q] = pn[q];
+                la[q] = ln[q];
             }
+        } else {
+            if (act1) load_pull(a, pu);
+            if (act2) load_lam(b, la);
         }
-        if (act2) {
-            const int n = (walls ? b : modi(b, ny)) * nx + x;
-#pragma unroll
-            for (int q = 0; q < 27; ++q) la[q] = A.lam1[q * N + n];
-        }
-        if (HOIST && act4) gather();
+        if (HOIST == 1 && act4) gather();
         // ---- stage 1: moments and dC of row a ----
         Moments<C> mom_new = {};
         if (act1) {
             mom_new = moments<L9, T>(pu, pu + 9, pu + 18);
             C dc[3];
             conc_dev<C>(mom_new, dc);
+            const int sa = slot(a);
 #pragma unroll
-            for (int m = 0; m < 3; ++m) sC[it % R][m][l] = dc[m];
+            for (int m = 0; m < 3; ++m) sC[sa][m][l] = dc[m];
+            if constexpr (K > 1) {
+                sM[sa][0][l] = mom_new.drho;
+                sM[sa][1][l] = mom_new.jx;
+                sM[sa][2][l] = mom_new.jy;
+                sM[sa][3][l] = mom_new.phi;
+                sM[sa][4][l] = mom_new.dpsi;
+            }
         }
         __syncthreads();
         // ---- stage 2: stencils and local transpose of row b = a - 1 ----
         C lb_new[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         if (act2) {
-            const int s0 = (it + 2) % R, sm = (it + 1) % R, sp = it % R;
+            const int s0 = slot(b), sm = slot(b - 1), sp = slot(a);
+            if constexpr (K > 1) {
+                mom_prev.drho = sM[s0][0][l];
+                mom_prev.jx = sM[s0][1][l];
+                mom_prev.jy = sM[s0][2][l];
+                mom_prev.jz = C(0);
+                mom_prev.phi = sM[s0][3][l];
+                mom_prev.dpsi = sM[s0][4][l];
+            }
             const bool glo = walls && b == 0, ghi = walls && b == ny - 1;
             C dc[3], gx[3], gy[3], lC[3];
 #pragma unroll
@@ -284,15 +348,30 @@ __global__ __launch_bounds__(W) void k_adj2d(AdjArgs<T> A)
                 sA[s0][2 * m + 1][l] = bG[m][1];
                 sA[s0][6 + m][l] = bL[m];
             }
+            if constexpr (K > 1) {
+#pragma unroll
+                for (int q = 0; q < 8; ++q) sL[s0][q][l] = lb_new[q];
+            }
             if (own_x && b >= y0 && b < y1) {
 #pragma unroll
                 for (int m = 0; m < 3; ++m) kacc[m] += (double)kb[m];
             }
         }
+        // variant 2: the next iteration's pull and lambda rows, whose latency stages 3 and 4 cover
+        if constexpr (HOIST == 2) {
+            bool g1, g2;
+            act12(a + K, g1, g2);
+            if (g1) load_pull(a + K, pn);
+            if (g2) load_lam(b + K, ln);
+        }
         __syncthreads();
         // ---- stage 3: transposed stencils, ghost transposes, moment transpose of row c = a - 2 ----
         if (act3) {
-            const int q0 = (it + 1) % R, qm = it % R, qp = (it + 2) % R;
+            const int q0 = slot(c), qm = slot(c - 1), qp = slot(b);
+            if constexpr (K > 1) {
+#pragma unroll
+                for (int q = 0; q < 8; ++q) lb_prev[q] = sL[q0][q][l];
+            }
             C Cb[3];
 #pragma unroll
             for (int m = 0; m < 3; ++m) Cb[m] = lb_prev[5 + m] - C(6) * (C(1) - w0) * sA[q0][6 + m][l];
@@ -344,9 +423,9 @@ __global__ __launch_bounds__(W) void k_adj2d(AdjArgs<T> A)
         __syncthreads();
         // ---- stage 4: lambda_t of row d = a - 3 from the gathered lambda_{t+1} and S, J ----
         if (act4) {
-            if (!HOIST) gather();  // all 27 loads before the first store
-            const int p0 = it % R, pm = (it + 2) % R, pp = (it + 1) % R;
-            const int n = d * nx + x;
+            if (HOIST != 1) gather();  // all 27 loads before the first store
+            const int p0 = slot(d), pm = slot(d - 1), pp = slot(c);
+            const uint32_t so = (uint32_t)d * nxu * ES;
 #pragma unroll
             for (int j = 0; j < 9; ++j) {
                 const int yy = d + L9::ey[j];
@@ -356,28 +435,31 @@ __global__ __launch_bounds__(W) void k_adj2d(AdjArgs<T> A)
                 const C sgn = bb ? C(-1) : C(1);  // e of the gathered direction: e_j, or e_opp(j) = -e_j
                 const C Sf = sS[sl][0][ln], Jx = sS[sl][1][ln], Jy = sS[sl][2][ln];
                 const C Sg = sS[sl][3][ln], Sk = sS[sl][4][ln];
-                A.lam0[j * N + n] =
-                    T((C(1) - P.omega[0]) * C(lg[j]) + Sf + sgn * (C(L9::ex[j]) * Jx + C(L9::ey[j]) * Jy));
-                A.lam0[(9 + j) * N + n] = T((C(1) - P.omega[1]) * C(lg[9 + j]) + Sg);
-                A.lam0[(18 + j) * N + n] = T((C(1) - P.omega[2]) * C(lg[18 + j]) + Sk);
+                bstore<T>(T((C(1) - P.omega[0]) * C(lg[j]) + Sf + sgn * (C(L9::ex[j]) * Jx + C(L9::ey[j]) * Jy)), rl0,
+                          vx0, so + (uint32_t)j * NB);
+                bstore<T>(T((C(1) - P.omega[1]) * C(lg[9 + j]) + Sg), rl0, vx0, so + (uint32_t)(9 + j) * NB);
+                bstore<T>(T((C(1) - P.omega[2]) * C(lg[18 + j]) + Sk), rl0, vx0, so + (uint32_t)(18 + j) * NB);
             }
         }
-        mom_prev = mom_new;
+        if constexpr (K == 1) {
+            mom_prev = mom_new;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) lb_prev[q] = lb_new[q];
+            for (int q = 0; q < 8; ++q) lb_prev[q] = lb_new[q];
+        }
     }
-    // kappa gradient of the item: lanes in a fixed tree
+    // kappa gradient of the item: threads in a fixed tree
+    const int t = threadIdx.x;
 #pragma unroll
-    for (int m = 0; m < 3; ++m) sred[m][l] = kacc[m];
+    for (int m = 0; m < 3; ++m) sred[m][t] = kacc[m];
     __syncthreads();
-    for (int w = W / 2; w > 0; w >>= 1) {
-        if (l < w) {
+    for (int w = W * K / 2; w > 0; w >>= 1) {
+        if (t < w) {
 #pragma unroll
-            for (int m = 0; m < 3; ++m) sred[m][l] += sred[m][l + w];
+            for (int m = 0; m < 3; ++m) sred[m][t] += sred[m][t + w];
         }
         __syncthreads();
     }
-    if (l < 3) A.kpart[l * A.nitems + item] += sred[l][0];
+    if (t < 3) A.kpart[t * A.nitems + item] += sred[t][0];
 }
 
 // Inverse of the pull: position in u of the value that the pull of node (x, y) reads for direction i.
@@ -451,21 +533,26 @@ inline dim3 gridN(int64_t N) { return dim3((unsigned)((N + 255) / 256)); }
 }  // namespace
 
 template <typename T, int HOIST>
-static void launch_adj_w(const AdjArgs<T>& a, int width, hipStream_t s)
+static bool launch_adj_w(const AdjArgs<T>& a, int width, int rows, hipStream_t s)
 {
-    if (width == 64) hipLaunchKernelGGL((k_adj2d<T, 64, HOIST>), dim3(a.nitems), dim3(64), 0, s, a);
-    if (width == 128) hipLaunchKernelGGL((k_adj2d<T, 128, HOIST>), dim3(a.nitems), dim3(128), 0, s, a);
-    if (width == 256) hipLaunchKernelGGL((k_adj2d<T, 256, HOIST>), dim3(a.nitems), dim3(256), 0, s, a);
+    const dim3 g(a.nitems);
+    if (width == 64 && rows == 1) hipLaunchKernelGGL((k_adj2d<T, 64, 1, HOIST>), g, dim3(64), 0, s, a);
+    else if (width == 64 && rows == 2) hipLaunchKernelGGL((k_adj2d<T, 64, 2, HOIST>), g, dim3(128), 0, s, a);
+    else if (width == 64 && rows == 4) hipLaunchKernelGGL((k_adj2d<T, 64, 4, HOIST>), g, dim3(256), 0, s, a);
+    else if (width == 128 && rows == 1) hipLaunchKernelGGL((k_adj2d<T, 128, 1, HOIST>), g, dim3(128), 0, s, a);
+    else if (width == 128 && rows == 2) hipLaunchKernelGGL((k_adj2d<T, 128, 2, HOIST>), g, dim3(256), 0, s, a);
+    else if (width == 256 && rows == 1) hipLaunchKernelGGL((k_adj2d<T, 256, 1, HOIST>), g, dim3(256), 0, s, a);
+    else return false;
+    return true;
 }
 
 template <typename T>
-hipError_t launch_adjoint_sweep(const AdjArgs<T>& a, int width, int hoist, hipStream_t s)
+hipError_t launch_adjoint_sweep(const AdjArgs<T>& a, int width, int rows, int variant, hipStream_t s)
 {
-    if (width != 64 && width != 128 && width != 256) return hipErrorInvalidValue;
-    if (hoist)
-        launch_adj_w<T, 1>(a, width, s);
-    else
-        launch_adj_w<T, 0>(a, width, s);
+    const bool ok = variant == 2   ? launch_adj_w<T, 2>(a, width, rows, s)
+                    : variant == 1 ? launch_adj_w<T, 1>(a, width, rows, s)
+                                   : launch_adj_w<T, 0>(a, width, rows, s);
+    if (!ok) return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
@@ -489,8 +576,8 @@ hipError_t launch_reduce3(const double* f, int64_t N, double* part, double* out,
     return hipGetLastError();
 }
 
-template hipError_t launch_adjoint_sweep<float>(const AdjArgs<float>&, int, int, hipStream_t);
-template hipError_t launch_adjoint_sweep<double>(const AdjArgs<double>&, int, int, hipStream_t);
+template hipError_t launch_adjoint_sweep<float>(const AdjArgs<float>&, int, int, int, hipStream_t);
+template hipError_t launch_adjoint_sweep<double>(const AdjArgs<double>&, int, int, int, hipStream_t);
 template hipError_t launch_adjoint_seed<float>(const AuxGeom&, const float*, float*, hipStream_t);
 template hipError_t launch_adjoint_seed<double>(const AuxGeom&, const double*, double*, hipStream_t);
 

@@ -82,7 +82,7 @@ struct AdjArgs {
     Phys<acc_t<T>> P;
 };
 template <typename T>
-hipError_t launch_adjoint_sweep(const AdjArgs<T>& a, int width, int hoist, hipStream_t s);
+hipError_t launch_adjoint_sweep(const AdjArgs<T>& a, int width, int rows, int hoist, hipStream_t s);
 template <typename T>
 hipError_t launch_adjoint_seed(const AuxGeom& g, const T* dC, T* lam, hipStream_t s);
 hipError_t launch_fill0(double* p, int64_t n, hipStream_t s);

@@ -290,14 +290,14 @@ class Sim:
         l = tlb_launch(width, height, chunk, variant)
         check(tlb_set_launch(self._h, ctypes.byref(l)), "tlb_set_launch")
 
-    def set_adjoint_launch(self, width, chunk=0, variant=0):
-        l = tlb_launch(width, 1, chunk, variant)
+    def set_adjoint_launch(self, width, chunk=0, variant=0, rows=1):
+        l = tlb_launch(width, rows, chunk, variant)
         check(tlb_set_adjoint_launch(self._h, ctypes.byref(l)), "tlb_set_adjoint_launch")
 
     def adjoint_launch(self):
         l = tlb_launch()
         check(tlb_get_adjoint_launch(self._h, ctypes.byref(l)), "tlb_get_adjoint_launch")
-        return dict(width=l.width, chunk=l.chunk, variant=l.variant)
+        return dict(width=l.width, rows=l.height, chunk=l.chunk, variant=l.variant)
 
     def launch(self):
         l = tlb_launch()

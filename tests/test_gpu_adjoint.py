@@ -73,6 +73,16 @@ TRANSPOSE_CASES = [
     (0, 131, 7, dict(width=128, chunk=3)),
     (1, 5, 3, dict(width=64, chunk=1)),
     (0, 3, 4, dict(width=256, chunk=2)),
+    # several row groups per workgroup: (chunk + 6) not a multiple of rows, rows beyond the lattice
+    (1, 24, 16, dict(width=64, rows=4, chunk=8)),
+    (2, 70, 9, dict(width=64, rows=4, chunk=5)),
+    (0, 70, 9, dict(width=64, rows=2, chunk=3)),
+    (1, 131, 11, dict(width=128, rows=2, chunk=5, variant=1)),
+    (1, 5, 3, dict(width=64, rows=4, chunk=1)),
+    # variant 2: the next iteration's pull and lambda rows are loaded during the current one
+    (1, 24, 16, dict(width=64, chunk=5, variant=2)),
+    (0, 131, 7, dict(width=64, rows=4, chunk=3, variant=2)),
+    (2, 70, 9, dict(width=128, rows=2, chunk=2, variant=2)),
 ]
 
 
@@ -138,32 +148,57 @@ def _transpose_identity(torch, tlb, w, C, h, st, launch):
 
 
 def test_reverse_step_independent_of_launch_shape(env):
-    """lambda_t and dL/dh are bitwise the same for every launch shape; dL/dkappa to rounding."""
+    """lambda_t and dL/dh are bitwise the same for every launch shape of a variant, and the variants agree to
+    rounding (they fuse multiply-adds differently); dL/dkappa to rounding."""
     torch, tlb = env
     w, C, h, _ = _wall_case(nx=150, ny=37, R=12.0)
     st = torch.cuda.Stream()
-    outs = []
+    shapes = (dict(width=64, chunk=8), dict(width=64, chunk=37), dict(width=128, chunk=3), dict(width=256, chunk=16),
+              dict(width=64, chunk=1), dict(width=64, rows=4, chunk=19), dict(width=64, rows=4, chunk=2),
+              dict(width=64, rows=2, chunk=7), dict(width=128, rows=2, chunk=4))
+    outs = {}
     with torch.cuda.stream(st):
-        for launch in (dict(width=64, chunk=8), dict(width=64, chunk=37), dict(width=128, chunk=3),
-                       dict(width=256, chunk=16), dict(width=64, chunk=1)):
-            s = _sim(torch, tlb, w, C, h, tlb.TLB_F64, st, launch)
-            s.step(7)
-            u = _dev(torch, s)
-            tlb.check(tlb.tlb_save_state_dev(s.handle, u.data_ptr()), "save")
-            gen = torch.Generator(device="cuda").manual_seed(3)
-            lam = torch.randn(u.shape, dtype=torch.float64, device="cuda", generator=gen)
-            dh = torch.zeros((2, 3, w["nx"]), dtype=torch.float64, device="cuda")
-            dk = torch.zeros(3, dtype=torch.float64, device="cuda")
-            out = torch.empty_like(u)
-            tlb.check(tlb.tlb_adjoint_step_dev(s.handle, u.data_ptr(), lam.data_ptr(), out.data_ptr(), dh.data_ptr(),
-                                               dk.data_ptr()), "adjoint step")
-            torch.cuda.synchronize()
-            outs.append((out.cpu().numpy(), dh.cpu().numpy(), dk.cpu().numpy()))
-            s.close()
-    for o in outs[1:]:
-        assert np.array_equal(o[0], outs[0][0])
-        assert np.array_equal(o[1], outs[0][1])
-        assert np.allclose(o[2], outs[0][2], rtol=1e-12, atol=0)
+        for variant in (0, 1, 2):
+            for shape in shapes:
+                s = _sim(torch, tlb, w, C, h, tlb.TLB_F64, st, dict(shape, variant=variant))
+                s.step(7)
+                u = _dev(torch, s)
+                tlb.check(tlb.tlb_save_state_dev(s.handle, u.data_ptr()), "save")
+                gen = torch.Generator(device="cuda").manual_seed(3)
+                lam = torch.randn(u.shape, dtype=torch.float64, device="cuda", generator=gen)
+                dh = torch.zeros((2, 3, w["nx"]), dtype=torch.float64, device="cuda")
+                dk = torch.zeros(3, dtype=torch.float64, device="cuda")
+                out = torch.empty_like(u)
+                tlb.check(tlb.tlb_adjoint_step_dev(s.handle, u.data_ptr(), lam.data_ptr(), out.data_ptr(),
+                                                   dh.data_ptr(), dk.data_ptr()), "adjoint step")
+                torch.cuda.synchronize()
+                outs.setdefault(variant, []).append((out.cpu().numpy(), dh.cpu().numpy(), dk.cpu().numpy()))
+                s.close()
+    ref = outs[0][0]
+    for variant, runs in outs.items():
+        for o in runs:
+            assert np.array_equal(o[0], runs[0][0]), variant
+            assert np.array_equal(o[1], runs[0][1]), variant
+            assert np.allclose(o[2], runs[0][2], rtol=1e-12, atol=0)
+        assert np.allclose(runs[0][0], ref[0], rtol=0, atol=1e-13 * np.abs(ref[0]).max())
+        assert np.allclose(runs[0][1], ref[1], rtol=0, atol=1e-13 * np.abs(ref[1]).max())
+        assert np.allclose(runs[0][2], ref[2], rtol=1e-12, atol=0)
+
+
+def test_adjoint_launch_validation(env):
+    """Row groups of 1, 2 or 4 with width * rows <= 256; anything else is TLB_EINVAL and keeps the shape."""
+    torch, tlb = env
+    w, C, h, _ = _wall_case()
+    st = torch.cuda.Stream()
+    s = _sim(torch, tlb, w, C, h, tlb.TLB_F64, st)
+    s.set_adjoint_launch(64, chunk=9, rows=4)
+    assert s.adjoint_launch() == dict(width=64, rows=4, chunk=9, variant=0)
+    for bad in (dict(width=64, rows=3), dict(width=256, rows=2), dict(width=128, rows=4), dict(width=32),
+                dict(width=64, rows=2, variant=3)):
+        with pytest.raises(tlb.TLBError):
+            s.set_adjoint_launch(**bad)
+    assert s.adjoint_launch() == dict(width=64, rows=4, chunk=9, variant=0)
+    s.close()
 
 
 def _gpu_grad(torch, tlb, w, C, h, target, steps, every, prec):
