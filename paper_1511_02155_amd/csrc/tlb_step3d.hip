@@ -22,34 +22,57 @@ namespace tlb {
 
 using L19 = D3Q19;
 
+// Pull of node (x, y, z) through buffer accesses: one descriptor per species
+// array, a per-lane byte offset of the in-plane source column and a
+// wavefront-uniform byte offset of direction and z plane.  col[dy + 1][dx + 1]
+// holds the offset of column (x + dx, y + dy) (periodic wrap), so direction i
+// reads col[1 - e_y][1 - e_x].  Where r - e_i lies beyond a y wall the lane
+// reads opp(i) at its own node instead (half-way bounce-back); only lanes on
+// a wall row of a tile touching a wall (wall_tile) take that branch.
 template <typename T>
-__device__ __forceinline__ void pull3d(const StepArgs<T>& A, int x, int y, int z, T* f, T* g, T* k)
+__device__ __forceinline__ void pull3d(const StepArgs<T>& A, const Rsrc* rs, const uint32_t (&col)[3][3], int z,
+                                       bool wall_tile, bool blo, bool bhi, T* f, T* g, T* k)
 {
-    const int nx = A.nx, ny = A.ny, nz = A.nz;
-    const int xm = (x == 0) ? nx - 1 : x - 1;
-    const int xp = (x == nx - 1) ? 0 : x + 1;
-    const int ym = (y == 0) ? ny - 1 : y - 1;
-    const int yp = (y == ny - 1) ? 0 : y + 1;
-    const int zm = (z == 0) ? nz - 1 : z - 1;
-    const int zp = (z == nz - 1) ? 0 : z + 1;
-    const bool blo = A.walls && y == 0;
-    const bool bhi = A.walls && y == ny - 1;
-    const uint32_t N = (uint32_t)A.N;
-    const uint32_t n0 = (uint32_t)x + (uint32_t)nx * ((uint32_t)y + (uint32_t)ny * z);
+    constexpr uint32_t ES = sizeof(T);
+    const int nz = A.nz;
+    const uint32_t PB = (uint32_t)A.nx * (uint32_t)A.ny * ES;  // bytes of one z plane
+    const uint32_t NB = (uint32_t)A.N * ES;                    // bytes of one direction array
+    const uint32_t zm = (z == 0) ? nz - 1 : z - 1;
+    const uint32_t zp = (z == nz - 1) ? 0 : z + 1;
 #pragma unroll
     for (int s = 0; s < 3; ++s) {
-        const T* __restrict__ b = A.src + (int64_t)s * 19 * A.N;
         T* out = (s == 0) ? f : (s == 1) ? g : k;
 #pragma unroll
         for (int i = 0; i < 19; ++i) {
             const int ex = L19::ex[i], ey = L19::ey[i], ez = L19::ez[i];
-            const bool bb = (ey == 1) ? blo : (ey == -1) ? bhi : false;
-            const int xs = ex == 0 ? x : (ex == 1 ? xm : xp);
-            const int ys = ey == 0 ? y : (ey == 1 ? ym : yp);
-            const int zs = ez == 0 ? z : (ez == 1 ? zm : zp);
-            const uint32_t off = bb ? (uint32_t)L19::opp[i] * N + n0
-                                    : (uint32_t)i * N + (uint32_t)xs + (uint32_t)nx * ((uint32_t)ys + (uint32_t)ny * zs);
-            out[i] = b[off];
+            const uint32_t zs = ez == 0 ? (uint32_t)z : (ez == 1 ? zm : zp);
+            out[i] = bload<T>(rs[s], col[1 - ey][1 - ex], (uint32_t)i * NB + zs * PB);
+        }
+        if (wall_tile) {
+#pragma unroll
+            for (int i = 0; i < 19; ++i) {
+                const int ey = L19::ey[i];
+                if (ey == 0) continue;
+                if ((ey == 1 && blo) || (ey == -1 && bhi))
+                    out[i] = bload<T>(rs[s], col[1][1], (uint32_t)L19::opp[i] * NB + (uint32_t)z * PB);
+            }
+        }
+    }
+}
+
+// Byte offsets of the nine in-plane columns around (x, y), periodic in x and y.
+template <typename T>
+__device__ __forceinline__ void columns(int x, int y, int nx, int ny, uint32_t (&col)[3][3])
+{
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy) {
+        int yy = y + dy;
+        yy = yy < 0 ? yy + ny : (yy >= ny ? yy - ny : yy);
+#pragma unroll
+        for (int dx = -1; dx <= 1; ++dx) {
+            int xx = x + dx;
+            xx = xx < 0 ? xx + nx : (xx >= nx ? xx - nx : xx);
+            col[dy + 1][dx + 1] = ((uint32_t)xx + (uint32_t)nx * (uint32_t)yy) * (uint32_t)sizeof(T);
         }
     }
 }
@@ -118,6 +141,18 @@ __global__ __launch_bounds__(BX* BY) void k_step3d(StepArgs<T> A)
     }
     const uint32_t nxz = (uint32_t)A.nx * A.nz;
 
+    // buffer descriptors of the three species arrays of the source and destination states
+    const uint32_t SB = 19u * (uint32_t)A.N * (uint32_t)sizeof(T);
+    const Rsrc rs[3] = {make_rsrc(A.src, SB), make_rsrc(A.src + 19 * A.N, SB), make_rsrc(A.src + 38 * A.N, SB)};
+    const Rsrc rd[3] = {make_rsrc(A.dst, SB), make_rsrc(A.dst + 19 * A.N, SB), make_rsrc(A.dst + 38 * A.N, SB)};
+    uint32_t col[3][3], hcol[3][3];
+    columns<T>(x, y, A.nx, A.ny, col);
+    columns<T>(gx, gy, A.nx, A.ny, hcol);
+    // a tile touches a wall when its rows or its ring rows (y0 - 1 .. y0 + ay) include y = 0 or y = ny - 1
+    const bool wall_tile = A.walls && (y0 <= 1 || y0 + ay >= A.ny - 1);
+    const bool blo = A.walls && y == 0, bhi = A.walls && y == A.ny - 1;
+    const bool hblo = A.walls && gy == 0, hbhi = A.walls && gy == A.ny - 1;
+
     T fb[19], gb[19], kb[19];  // HOLD: populations of plane z
     T fc[19], gc[19], kc[19];  // pull buffer (plane z + 1)
     PlaneLite<C> pa;
@@ -125,7 +160,7 @@ __global__ __launch_bounds__(BX* BY) void k_step3d(StepArgs<T> A)
     int buf = 0;
 
     auto plane = [&](int z, PlaneFull<C>& p) {
-        pull3d<T>(A, x, y, z, fc, gc, kc);
+        pull3d<T>(A, rs, col, z, wall_tile, blo, bhi, fc, gc, kc);
         const Moments<C> mo = moments<L19, T>(fc, gc, kc);
         conc_dev<C>(mo, p.c);
         if (active) {
@@ -134,7 +169,7 @@ __global__ __launch_bounds__(BX* BY) void k_step3d(StepArgs<T> A)
         }
         if (ring) {
             T hf[19], hg[19], hk[19];
-            pull3d<T>(A, gx, gy, z, hf, hg, hk);
+            pull3d<T>(A, rs, hcol, z, wall_tile, hblo, hbhi, hf, hg, hk);
             Moments<C> hm = moments<L19, T>(hf, hg, hk);
             C hc[3];
             conc_dev<C>(hm, hc);
@@ -207,18 +242,18 @@ __global__ __launch_bounds__(BX* BY) void k_step3d(StepArgs<T> A)
             lC[m] = (pb.A[m] + pa.c[m] + pc.c[m]) * C(1.0 / 3.0) + (pb.E[m] + pa.A[m] + pc.A[m]) * C(1.0 / 6.0) -
                     pb.c[m] * C(4);
         }
-        if constexpr (!HOLD) pull3d<T>(A, x, y, z, fb, gb, kb);
+        if constexpr (!HOLD) pull3d<T>(A, rs, col, z, wall_tile, blo, bhi, fb, gb, kb);
         const Moments<C> mb = moments<L19, T>(fb, gb, kb);
         collide<L19>(A.P, mb, pb.c, gC, lC, fb, gb, kb);
 
         if (active) {
-            T* __restrict__ dst = A.dst;
-            const uint32_t n0 = (uint32_t)x + (uint32_t)A.nx * ((uint32_t)y + (uint32_t)A.ny * z);
+            const uint32_t so = (uint32_t)z * (uint32_t)A.nx * (uint32_t)A.ny * (uint32_t)sizeof(T);
+            const uint32_t NB = N * (uint32_t)sizeof(T);
 #pragma unroll
             for (int i = 0; i < 19; ++i) {
-                dst[(uint32_t)i * N + n0] = fb[i];
-                dst[(int64_t)19 * A.N + (uint32_t)i * N + n0] = gb[i];
-                dst[(int64_t)38 * A.N + (uint32_t)i * N + n0] = kb[i];
+                bstore<T>(fb[i], rd[0], col[1][1], so + (uint32_t)i * NB);
+                bstore<T>(gb[i], rd[1], col[1][1], so + (uint32_t)i * NB);
+                bstore<T>(kb[i], rd[2], col[1][1], so + (uint32_t)i * NB);
             }
         }
 
