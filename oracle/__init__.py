@@ -39,6 +39,9 @@ class OrcParams(ctypes.Structure):
         ("gamma_phi", ctypes.c_double),
         ("gamma_psi", ctypes.c_double),
         ("no_advection", ctypes.c_int32),
+        ("collision", ctypes.c_int32),
+        ("tau_bulk", ctypes.c_double),
+        ("tau_ghost", ctypes.c_double),
     ]
 
 
@@ -74,6 +77,7 @@ def lib():
         L.orc_init_equilibrium.argtypes = [P, dp, dp, dp, dp]
         L.orc_step.argtypes = [P, dp, dp, ctypes.c_long]
         L.orc_fields.argtypes = [P, dp, dp, dp]
+        L.orc_mrt_basis.argtypes = [ctypes.c_int, dp, ip]
         _lib = L
     return _lib
 
@@ -92,7 +96,8 @@ class Params:
     """Physical and lattice parameters of one simulation (plain Python)."""
 
     def __init__(self, lattice, nx, ny, nz=1, walls_y=0, kappa=(0.01, 0.01, 0.01), alpha=1.0,
-                 tau_f=1.0, tau_g=1.0, tau_k=1.0, gamma_phi=1.0, gamma_psi=1.0, no_advection=0):
+                 tau_f=1.0, tau_g=1.0, tau_k=1.0, gamma_phi=1.0, gamma_psi=1.0, no_advection=0, collision=0,
+                 tau_bulk=1.0, tau_ghost=1.0):
         self.lattice = int(lattice)
         self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
         self.walls_y = int(walls_y)
@@ -101,6 +106,8 @@ class Params:
         self.tau_f, self.tau_g, self.tau_k = float(tau_f), float(tau_g), float(tau_k)
         self.gamma_phi, self.gamma_psi = float(gamma_phi), float(gamma_psi)
         self.no_advection = int(no_advection)
+        self.collision = int(collision)
+        self.tau_bulk, self.tau_ghost = float(tau_bulk), float(tau_ghost)
 
     @property
     def Q(self):
@@ -122,13 +129,15 @@ class Params:
         p.alpha, p.tau_f, p.tau_g, p.tau_k = self.alpha, self.tau_f, self.tau_g, self.tau_k
         p.gamma_phi, p.gamma_psi = self.gamma_phi, self.gamma_psi
         p.no_advection = self.no_advection
+        p.collision, p.tau_bulk, p.tau_ghost = self.collision, self.tau_bulk, self.tau_ghost
         return p
 
     def replace(self, **kw):
         d = dict(lattice=self.lattice, nx=self.nx, ny=self.ny, nz=self.nz, walls_y=self.walls_y,
                  kappa=self.kappa, alpha=self.alpha, tau_f=self.tau_f, tau_g=self.tau_g,
                  tau_k=self.tau_k, gamma_phi=self.gamma_phi, gamma_psi=self.gamma_psi,
-                 no_advection=self.no_advection)
+                 no_advection=self.no_advection, collision=self.collision, tau_bulk=self.tau_bulk,
+                 tau_ghost=self.tau_ghost)
         d.update(kw)
         return Params(**d)
 
@@ -148,6 +157,18 @@ def lattice_info(lattice):
     lib().orc_lattice_info(lattice, ctypes.byref(q), e.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
                            _dp(w), _dp(wab), opp.ctypes.data_as(ctypes.POINTER(ctypes.c_int)))
     return dict(Q=q.value, e=e, w=w, wab=wab, opp=opp)
+
+
+def mrt_basis(lattice):
+    """Moment basis of the multiple-relaxation-time collision: M[Q][Q] (row k = moment k over the
+    velocities) and the class of each moment (0 conserved, 1 energy, 2 viscous stress, 3 other)."""
+    Q = 9 if lattice == 0 else 19
+    M = np.zeros((Q, Q))
+    cls = (ctypes.c_int * Q)()
+    q = lib().orc_mrt_basis(int(lattice), _dp(M), cls)
+    if q != Q:
+        raise ValueError("oracle mrt_basis failed")
+    return M, np.array(cls[:], dtype=int)
 
 
 def node_thermo(p: Params, rho, C, lapC):

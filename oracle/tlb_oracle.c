@@ -42,6 +42,13 @@
  *       on a half-way wall through a ghost row:
  *       C_m(ghost) = C_m(adjacent fluid node) + h_m / (alpha^2 kappa_m).
  *   R9  bounce-back is the half-way, stationary-wall rule in pull form.
+ *   R18 the multiple-relaxation-time collision (Sec. IV names the extension,
+ *       after the binary model's, without a moment basis) acts on f only:
+ *       f* = f - M^-1 S M (f - f^eq) with the orthogonal polynomial bases of
+ *       Lallemand & Luo (D2Q9) and d'Humieres et al. (D3Q19); the viscous
+ *       stress moments relax at 1/tau_f, the energy moment at 1/tau_bulk and
+ *       every other moment at 1/tau_ghost (the conserved ones have no
+ *       non-equilibrium part).  g and k keep the BGK rule.
  */
 #include <math.h>
 #include <stdint.h>
@@ -59,6 +66,8 @@ typedef struct {
     double tau_f, tau_g, tau_k;
     double gamma_phi, gamma_psi;
     int32_t no_advection; /* 1: g^eq and k^eq without the velocity terms (diffusive Cahn-Hilliard) */
+    int32_t collision;    /* 0: BGK; 1: multiple relaxation times for f (reading R18) */
+    double tau_bulk, tau_ghost; /* MRT relaxation times of the energy moment and of the other moments */
 } orc_params;
 
 typedef struct {
@@ -337,6 +346,111 @@ static void propagate(const orc_params* P, const orc_lattice* L, const double* p
 /* Exported API.                                                             */
 /* ------------------------------------------------------------------------ */
 
+/* ------------------------------------------------------------------------ */
+/* Moment basis of the multiple-relaxation-time collision (reading R18).     */
+/* Row k of M holds moment k as a polynomial of the velocity c = e_i; cls[k] */
+/* is its class: 0 conserved, 1 energy (bulk viscosity), 2 viscous stress,   */
+/* 3 other.                                                                   */
+/*   D2Q9:  rho, e, eps, jx, qx, jy, qy, pxx, pxy                             */
+/*   D3Q19: rho, e, eps, jx, qx, jy, qy, jz, qz, 3pxx, 3pixx, pww, piww,      */
+/*          pxy, pyz, pxz, mx, my, mz                                          */
+/* ------------------------------------------------------------------------ */
+static void mrt_basis(const orc_lattice* L, double M[ORC_MAXQ][ORC_MAXQ], int cls[ORC_MAXQ])
+{
+    for (int i = 0; i < L->Q; ++i) {
+        const double x = L->e[i][0], y = L->e[i][1], z = L->e[i][2];
+        const double c2 = x * x + y * y + z * z;
+        double r[ORC_MAXQ];
+        if (L->Q == 9) {
+            r[0] = 1.0;
+            r[1] = -4.0 + 3.0 * c2;
+            r[2] = 4.0 - 10.5 * c2 + 4.5 * c2 * c2;
+            r[3] = x;
+            r[4] = (-5.0 + 3.0 * c2) * x;
+            r[5] = y;
+            r[6] = (-5.0 + 3.0 * c2) * y;
+            r[7] = x * x - y * y;
+            r[8] = x * y;
+        } else {
+            r[0] = 1.0;
+            r[1] = 19.0 * c2 - 30.0;
+            r[2] = (21.0 * c2 * c2 - 53.0 * c2 + 24.0) / 2.0;
+            r[3] = x;
+            r[4] = (5.0 * c2 - 9.0) * x;
+            r[5] = y;
+            r[6] = (5.0 * c2 - 9.0) * y;
+            r[7] = z;
+            r[8] = (5.0 * c2 - 9.0) * z;
+            r[9] = 3.0 * x * x - c2;
+            r[10] = (3.0 * c2 - 5.0) * (3.0 * x * x - c2);
+            r[11] = y * y - z * z;
+            r[12] = (3.0 * c2 - 5.0) * (y * y - z * z);
+            r[13] = x * y;
+            r[14] = y * z;
+            r[15] = x * z;
+            r[16] = (y * y - z * z) * x;
+            r[17] = (z * z - x * x) * y;
+            r[18] = (x * x - y * y) * z;
+        }
+        for (int k = 0; k < L->Q; ++k)
+            M[k][i] = r[k];
+    }
+    static const int c9[9] = {0, 1, 3, 0, 3, 0, 3, 2, 2};
+    static const int c19[19] = {0, 1, 3, 0, 3, 0, 3, 0, 3, 2, 3, 2, 3, 2, 2, 2, 3, 3, 3};
+    for (int k = 0; k < L->Q; ++k)
+        cls[k] = L->Q == 9 ? c9[k] : c19[k];
+}
+
+/* Inverse of an n x n matrix by Gauss-Jordan elimination with partial pivoting; 0 on success. */
+static int invert(int n, double A[ORC_MAXQ][ORC_MAXQ], double X[ORC_MAXQ][ORC_MAXQ])
+{
+    double W[ORC_MAXQ][2 * ORC_MAXQ];
+    for (int r = 0; r < n; ++r)
+        for (int c = 0; c < 2 * n; ++c)
+            W[r][c] = c < n ? A[r][c] : (c - n == r ? 1.0 : 0.0);
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < n; ++r)
+            if (fabs(W[r][c]) > fabs(W[piv][c]))
+                piv = r;
+        if (W[piv][c] == 0.0)
+            return -1;
+        for (int k = 0; k < 2 * n; ++k) {
+            const double t = W[c][k];
+            W[c][k] = W[piv][k];
+            W[piv][k] = t;
+        }
+        const double d = W[c][c];
+        for (int k = 0; k < 2 * n; ++k)
+            W[c][k] /= d;
+        for (int r = 0; r < n; ++r)
+            if (r != c && W[r][c] != 0.0) {
+                const double f = W[r][c];
+                for (int k = 0; k < 2 * n; ++k)
+                    W[r][k] -= f * W[c][k];
+            }
+    }
+    for (int r = 0; r < n; ++r)
+        for (int c = 0; c < n; ++c)
+            X[r][c] = W[r][n + c];
+    return 0;
+}
+
+/* Moment basis of a lattice for the tests: M[Q][Q] (row = moment) and the classes. */
+int orc_mrt_basis(int lattice, double* M, int* cls)
+{
+    if (lattice != 0 && lattice != 1)
+        return -1;
+    orc_lattice L;
+    build_lattice(lattice, &L);
+    double B[ORC_MAXQ][ORC_MAXQ];
+    mrt_basis(&L, B, cls);
+    for (int k = 0; k < L.Q; ++k)
+        for (int i = 0; i < L.Q; ++i)
+            M[k * L.Q + i] = B[k][i];
+    return L.Q;
+}
+
 int orc_check_params(const orc_params* P)
 {
     if (!P || (P->lattice != 0 && P->lattice != 1))
@@ -352,6 +466,10 @@ int orc_check_params(const orc_params* P)
     if (!(P->alpha > 0.0))
         return -1;
     if (P->no_advection != 0 && P->no_advection != 1)
+        return -1;
+    if (P->collision != 0 && P->collision != 1)
+        return -1;
+    if (P->collision == 1 && !(P->tau_bulk > 0.5 && P->tau_ghost > 0.5))
         return -1;
     for (int m = 0; m < 3; ++m)
         if (!(P->kappa[m] > 0.0))
@@ -488,7 +606,8 @@ int orc_init_equilibrium(const orc_params* P, const double* h, const double* C, 
 
 /* Advance the state s_t (post-propagation populations [3][Q][N]) by nsteps
  * time steps: moments, ghosts, stencils, thermodynamics, equilibria, BGK
- * collision (eq. latboltCollision) and propagation. */
+ * collision (eq. latboltCollision; multiple relaxation times for f with
+ * collision == 1, reading R18) and propagation. */
 int orc_step(const orc_params* P, const double* h, double* pop, long nsteps)
 {
     if (orc_check_params(P))
@@ -507,6 +626,27 @@ int orc_step(const orc_params* P, const double* h, double* pop, long nsteps)
         return -2;
     }
     const double itau[3] = {1.0 / P->tau_f, 1.0 / P->tau_g, 1.0 / P->tau_k};
+    /* multiple relaxation times for f (reading R18): K = M^-1 S M */
+    double K[ORC_MAXQ][ORC_MAXQ];
+    if (P->collision == 1) {
+        double M[ORC_MAXQ][ORC_MAXQ], Mi[ORC_MAXQ][ORC_MAXQ];
+        int cls[ORC_MAXQ];
+        mrt_basis(&L, M, cls);
+        if (invert(L.Q, M, Mi)) {
+            free(post), free(rho), free(vel), free(phi), free(psi), free(Cg);
+            return -3;
+        }
+        double S[ORC_MAXQ];
+        for (int k = 0; k < L.Q; ++k)
+            S[k] = cls[k] == 2 ? 1.0 / P->tau_f : (cls[k] == 1 ? 1.0 / P->tau_bulk : 1.0 / P->tau_ghost);
+        for (int i = 0; i < L.Q; ++i)
+            for (int j = 0; j < L.Q; ++j) {
+                double a = 0.0;
+                for (int k = 0; k < L.Q; ++k)
+                    a += Mi[i][k] * S[k] * M[k][j];
+                K[i][j] = a;
+            }
+    }
     for (long t = 0; t < nsteps; ++t) {
         moments(P, &L, pop, rho, vel, phi, psi, Cg);
         fill_ghosts(P, h, Cg);
@@ -522,11 +662,24 @@ int orc_step(const orc_params* P, const double* h, double* pop, long nsteps)
                         v[a] = vel[a * N + n];
                     double eq[3][ORC_MAXQ];
                     equilibria(P, &L, rho[n], v, phi[n], psi[n], C, gc, lc, eq[0], eq[1], eq[2]);
-                    for (int s = 0; s < 3; ++s)
+                    for (int s = 0; s < 3; ++s) {
+                        if (s == 0 && P->collision == 1) {
+                            double d[ORC_MAXQ];
+                            for (int j = 0; j < L.Q; ++j)
+                                d[j] = pop[(long)j * N + n] - eq[0][j];
+                            for (int i = 0; i < L.Q; ++i) {
+                                double r = 0.0;
+                                for (int j = 0; j < L.Q; ++j)
+                                    r += K[i][j] * d[j];
+                                post[(long)i * N + n] = pop[(long)i * N + n] - r;
+                            }
+                            continue;
+                        }
                         for (int i = 0; i < L.Q; ++i) {
                             long a = ((long)s * L.Q + i) * N + n;
                             post[a] = pop[a] - itau[s] * (pop[a] - eq[s][i]);
                         }
+                    }
                 }
         propagate(P, &L, post, pop);
     }

@@ -10,7 +10,7 @@ map to rounding) and to central finite differences of the C oracle.
 
 Only the test suite may import it.  It shares no code with the C oracle or
 with the GPU library.  Readings of the paper are those of tlb_oracle.c
-(R1-R9); the state is the post-propagation populations [species][q][ny][nx].
+(R1-R9, R18); the state is the post-propagation populations [species][q][ny][nx].
 """
 from __future__ import annotations
 
@@ -37,9 +37,28 @@ def _shift(a, dx, dy):
     return torch.roll(a, shifts=(-dy, -dx), dims=(-2, -1))
 
 
-def step(pop, h, kappa, alpha, tau, gamma, walls):
+def _relax_f_mrt(f, feq, tau_f, tau_bulk, tau_ghost):
+    """Multiple relaxation times for f (reading R18), written as projections: with the orthogonal
+    moment basis, M^-1 S M = s_ghost I + (s_shear - s_ghost) P_stress + (s_bulk - s_ghost) P_energy,
+    where P_x projects onto the span of the rows of class x.  D2Q9 stress rows e_x^2 - e_y^2 and
+    e_x e_y, energy row -4 + 3 |e|^2."""
+    rows_stress = [[e[0] * e[0] - e[1] * e[1] for e in E], [e[0] * e[1] for e in E]]
+    row_energy = [-4.0 + 3.0 * (e[0] * e[0] + e[1] * e[1]) for e in E]
+    d = f - feq
+    sg, sn, sb = 1.0 / tau_ghost, 1.0 / tau_f, 1.0 / tau_bulk
+    out = f - sg * d
+    for rows, rate in ((rows_stress, sn), ([row_energy], sb)):
+        for r in rows:
+            rt = torch.tensor(r, dtype=f.dtype).view(9, 1, 1)
+            m = (rt * d).sum(0) / float(sum(v * v for v in r))
+            out = out - (rate - sg) * rt * m
+    return out
+
+
+def step(pop, h, kappa, alpha, tau, gamma, walls, mrt=None):
     """One step s_t -> s_{t+1}.  pop: [3][9][ny][nx]; h: [2][3][nx] (walls) or None;
-    kappa: [3] tensor; tau = (tau_f, tau_g, tau_k); gamma = (Gamma_phi, Gamma_psi)."""
+    kappa: [3] tensor; tau = (tau_f, tau_g, tau_k); gamma = (Gamma_phi, Gamma_psi);
+    mrt = (tau_bulk, tau_ghost) for multiple relaxation times of f, or None for BGK."""
     f, g, k = pop[0], pop[1], pop[2]
     ny = pop.shape[-2]
     ex = torch.tensor([e[0] for e in E], dtype=pop.dtype).view(9, 1, 1)
@@ -95,6 +114,8 @@ def step(pop, h, kappa, alpha, tau, gamma, walls):
     eq = torch.stack([feq, geq, keq])
     itau = torch.tensor([1.0 / t for t in tau], dtype=pop.dtype).view(3, 1, 1, 1)
     post = pop - itau * (pop - eq)
+    if mrt is not None:
+        post = torch.stack([_relax_f_mrt(f, feq, tau[0], mrt[0], mrt[1]), post[1], post[2]])
     # pull propagation with half-way bounce-back at the y walls
     out = []
     for i in range(9):
@@ -113,10 +134,10 @@ def concentrations(pop):
     return torch.stack([0.5 * (rho + phi - psi), 0.5 * (rho - phi - psi), psi])
 
 
-def run(pop0, h, kappa, alpha, tau, gamma, walls, nsteps):
+def run(pop0, h, kappa, alpha, tau, gamma, walls, nsteps, mrt=None):
     pop = pop0
     for _ in range(nsteps):
-        pop = step(pop, h, kappa, alpha, tau, gamma, walls)
+        pop = step(pop, h, kappa, alpha, tau, gamma, walls, mrt)
     return pop
 
 
