@@ -77,8 +77,8 @@ def run_plain(tlb, torch, w, prec, steps, warmup, launch=None):
     """Time `steps` fused steps of workload w; returns a dict of measurements."""
     stream = torch.cuda.Stream()
     keys = ("lattice", "nx", "ny", "nz", "walls_y", "kappa", "alpha", "tau_f", "tau_g", "tau_k", "gamma_phi",
-            "gamma_psi")
-    sim = tlb.Sim(tlb.make_params(prec=prec, **{k: w[k] for k in keys}), stream=stream.cuda_stream)
+            "gamma_psi", "no_advection", "collision", "tau_bulk", "tau_ghost")
+    sim = tlb.Sim(tlb.make_params(prec=prec, **{k: w[k] for k in keys if k in w}), stream=stream.cuda_stream)
     if launch:
         sim.set_launch(**launch)
     sim.init_equilibrium(w["C"]())
@@ -254,7 +254,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle timing")
     ap.add_argument("--cpu-steps", type=int, default=300)
     ap.add_argument("--quick", action="store_true", help="headline only (no extra workloads)")
-    ap.add_argument("--only", default=None, help="run a single workload: f64, f32, d3q19, batched, adjoint64, adjoint32")
+    ap.add_argument("--only", default=None,
+                    help="run a single workload: f64, f32, d3q19, batched, mrt, adjoint64, adjoint32")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -298,6 +299,16 @@ def main():
         sb = args.steps if sel else max(100, min(5000, args.steps // 2))
         print(f"[bench] batched 512 domains f32: {sb} steps", file=sys.stderr, flush=True)
         add("batched_512_domains_f32", run_batched(tlb, torch, sb))
+    if sel == "mrt" or every:
+        # multiple relaxation times for f: same workloads, distinct bulk and ghost rates
+        mrt = dict(collision=1, tau_bulk=0.8, tau_ghost=1.2)
+        sm = args.steps if sel else max(200, min(2000, args.steps // 5))
+        print(f"[bench] d2q9 1024^2 f64 MRT: {sm} steps", file=sys.stderr, flush=True)
+        add("d2q9_1024x1024_spinodal_f64_mrt", run_plain(tlb, torch, dict(w2, **mrt), tlb.TLB_F64, sm, 10))
+        s3 = args.steps if sel else max(50, min(2000, args.steps // 20))
+        print(f"[bench] d3q19 256^3 f32 MRT: {s3} steps", file=sys.stderr, flush=True)
+        add("d3q19_256cube_spinodal_f32_mrt",
+            run_plain(tlb, torch, dict(inputs.spinodal_3d(256, s3), **mrt), tlb.TLB_F32, s3, 10))
     for name, prec in (("f64", tlb.TLB_F64), ("f32", tlb.TLB_F32)):
         if sel == "adjoint" + name[1:] or every:
             sa = args.steps if sel else max(100, min(2000, args.steps // 5))
@@ -345,6 +356,12 @@ WORKLOAD_CONFIG = {
                                         kappa=[0.01, 0.015, 0.02], alpha=1.0, tau=1.0, mobility=0.1),
     "d3q19_256cube_spinodal_f32": dict(lattice="D3Q19", nx=256, ny=256, nz=256, boundary="periodic",
                                        kappa=[0.01, 0.01, 0.01], alpha=1.0, tau=0.8, mobility=0.05),
+    "d2q9_1024x1024_spinodal_f64_mrt": dict(lattice="D2Q9", nx=1024, ny=1024, boundary="periodic",
+                                            kappa=[0.01, 0.015, 0.02], alpha=1.0, tau=1.0, mobility=0.1,
+                                            collision="MRT", tau_bulk=0.8, tau_ghost=1.2),
+    "d3q19_256cube_spinodal_f32_mrt": dict(lattice="D3Q19", nx=256, ny=256, nz=256, boundary="periodic",
+                                           kappa=[0.01, 0.01, 0.01], alpha=1.0, tau=0.8, mobility=0.05,
+                                           collision="MRT", tau_bulk=0.8, tau_ghost=1.2),
     "batched_512_domains_f32": dict(lattice="D2Q9", domains=512, side=[32, 256], boundary="walls_y"),
     "adjoint_512x512_wall_drop_f64": dict(lattice="D2Q9", nx=512, ny=512, boundary="walls_y", form="reverse step"),
     "adjoint_512x512_wall_drop_f32": dict(lattice="D2Q9", nx=512, ny=512, boundary="walls_y", form="reverse step"),

@@ -65,6 +65,7 @@ typedef enum {
 
 enum { TLB_D2Q9 = 0, TLB_D3Q19 = 1 };
 enum { TLB_F32 = 0, TLB_F64 = 1 };
+enum { TLB_BGK = 0, TLB_MRT = 1 };
 
 /* Field selectors of tlb_get_field. */
 enum {
@@ -99,6 +100,18 @@ enum {
  *             out, which removes advection from the Cahn-Hilliard equations (the
  *             diffusive coarsening runs of Sec. V.C).  Zero-initialised
  *             parameters keep the advective model.
+ *   collision TLB_BGK (single relaxation time, eq. latboltCollision) or
+ *             TLB_MRT: f relaxes with multiple relaxation times, the
+ *             extension Sec. IV names, f* = f - M^-1 S M (f - f^eq) in the
+ *             orthogonal polynomial moment basis of the lattice (Lallemand &
+ *             Luo for D2Q9, d'Humieres et al. for D3Q19); the viscous stress
+ *             moments relax at 1/tau_f (shear viscosity (tau_f - 1/2)/3), the
+ *             energy moment at 1/tau_bulk (bulk viscosity
+ *             (2/D)(tau_bulk - 1/2)/3) and all other moments at 1/tau_ghost.
+ *             g and k always relax with BGK.  With tau_bulk = tau_ghost =
+ *             tau_f, MRT is BGK.  The batched step and the reverse step take
+ *             BGK only (TLB_EINVAL otherwise).
+ *   tau_bulk, tau_ghost  MRT relaxation times, each > 1/2 (ignored for BGK).
  */
 typedef struct {
     int32_t lattice;
@@ -110,6 +123,8 @@ typedef struct {
     double tau_f, tau_g, tau_k;
     double gamma_phi, gamma_psi;
     int32_t no_advection;
+    int32_t collision;
+    double tau_bulk, tau_ghost;
 } tlb_params;
 
 /* Conservation and stability check of the current state s_t (all sums in FP64). */
@@ -132,7 +147,8 @@ typedef struct tlb_sim tlb_sim;
 const char* tlb_status_str(int status);
 /* HIP error code of the last TLB_EHIP returned on this thread (0 if none). */
 int tlb_last_hip_error(void);
-/* ABI version (major * 100 + minor); 2xx: tlb_params.no_advection and tlb_diag.interface. */
+/* ABI version (major * 100 + minor); 2xx: tlb_params.no_advection and tlb_diag.interface;
+ * 3xx: tlb_params.collision, tau_bulk, tau_ghost. */
 int tlb_version(void);
 
 /*

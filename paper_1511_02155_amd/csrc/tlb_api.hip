@@ -71,7 +71,7 @@ extern "C" const char* tlb_status_str(int s)
 }
 
 extern "C" int tlb_last_hip_error(void) { return g_last_hip; }
-extern "C" int tlb_version(void) { return 200; }
+extern "C" int tlb_version(void) { return 300; }
 
 static bool params_valid(const tlb_params* p)
 {
@@ -89,6 +89,11 @@ static bool params_valid(const tlb_params* p)
     if (!isfinite(p->tau_f) || !isfinite(p->tau_g) || !isfinite(p->tau_k)) return false;
     if (!isfinite(p->gamma_phi) || !isfinite(p->gamma_psi)) return false;
     if (p->no_advection != 0 && p->no_advection != 1) return false;
+    if (p->collision != TLB_BGK && p->collision != TLB_MRT) return false;
+    if (p->collision == TLB_MRT) {
+        if (!(p->tau_bulk > 0.5 && p->tau_ghost > 0.5)) return false;
+        if (!isfinite(p->tau_bulk) || !isfinite(p->tau_ghost)) return false;
+    }
     const int64_t N = (int64_t)p->nx * p->ny * p->nz;
     const int Q = p->lattice == TLB_D2Q9 ? 9 : 19;
     // one species array must stay addressable by 32-bit byte offsets
@@ -114,6 +119,12 @@ static Phys<T> make_phys(const tlb_params& p)
     P.gphi3 = T(3.0 * p.gamma_phi);
     P.gpsi3 = T(3.0 * p.gamma_psi);
     P.adv = p.no_advection ? T(0) : T(1);
+    P.mrt_sg = P.mrt_dv = P.mrt_db = T(0);
+    if (p.collision == TLB_MRT) {
+        P.mrt_sg = T(1.0 / p.tau_ghost);
+        P.mrt_dv = T(1.0 / p.tau_f - 1.0 / p.tau_ghost);
+        P.mrt_db = T(1.0 / p.tau_bulk - 1.0 / p.tau_ghost);
+    }
     return P;
 }
 
@@ -439,8 +450,9 @@ template <typename T>
 static hipError_t launch_one(const tlb_sim* s, const StepArgs<T>& a)
 {
     return (s->p.lattice == TLB_D2Q9)
-               ? launch_step2d<T>(a, s->launch.width, s->launch.variant, s->stream)
-               : launch_step3d<T>(a, s->launch.width, s->launch.height, s->launch.variant, s->stream);
+               ? launch_step2d<T>(a, s->launch.width, s->launch.variant, s->p.collision == TLB_MRT, s->stream)
+               : launch_step3d<T>(a, s->launch.width, s->launch.height, s->launch.variant,
+                                  s->p.collision == TLB_MRT, s->stream);
 }
 
 template <typename T>
@@ -907,7 +919,7 @@ static double* dh_target(tlb_sim* s, double* dh) { return dh ? dh : s->dhs; }
 extern "C" tlb_status tlb_adjoint_seed_dev(tlb_sim* s, const void* dLdC, void* lam)
 {
     if (!s || !lam) return TLB_EINVAL;
-    if (s->p.lattice != TLB_D2Q9) return TLB_EINVAL;
+    if (s->p.lattice != TLB_D2Q9 || s->p.collision != TLB_BGK) return TLB_EINVAL;
     const AuxGeom g = geom(s);
     hipError_t e = (s->p.prec == TLB_F32) ? launch_adjoint_seed<float>(g, (const float*)dLdC, (float*)lam, s->stream)
                                           : launch_adjoint_seed<double>(g, (const double*)dLdC, (double*)lam, s->stream);
@@ -919,7 +931,7 @@ extern "C" tlb_status tlb_adjoint_step_dev(tlb_sim* s, const void* state, const 
                                            double* dh, double* dkappa)
 {
     if (!s || !state || !lam_in || !lam_out || lam_in == lam_out) return TLB_EINVAL;
-    if (s->p.lattice != TLB_D2Q9) return TLB_EINVAL;
+    if (s->p.lattice != TLB_D2Q9 || s->p.collision != TLB_BGK) return TLB_EINVAL;
     tlb_status st = adj_alloc(s, 0);
     if (!st) st = kpart_clear(s);
     if (!st) st = adj_step_any(s, state, lam_in, lam_out, dh_target(s, dh));
@@ -967,7 +979,7 @@ extern "C" tlb_status tlb_adjoint_backward(tlb_sim* s, int64_t nsteps, int64_t e
                                            const void* dLdC, double* dh, double* dkappa)
 {
     if (!s || !ckpt || nsteps < 1 || every < 1) return TLB_EINVAL;
-    if (s->p.lattice != TLB_D2Q9) return TLB_EINVAL;
+    if (s->p.lattice != TLB_D2Q9 || s->p.collision != TLB_BGK) return TLB_EINVAL;
     tlb_status st = adj_alloc(s, every);
     if (st) return st;
     const size_t sb = (size_t)tlb_state_bytes(s);

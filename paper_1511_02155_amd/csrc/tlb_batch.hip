@@ -190,6 +190,7 @@ static Phys<T> phys_of(const tlb_params& p)
     P.gphi3 = T(3.0 * p.gamma_phi);
     P.gpsi3 = T(3.0 * p.gamma_psi);
     P.adv = p.no_advection ? T(0) : T(1);
+    P.mrt_sg = P.mrt_dv = P.mrt_db = T(0);
     return P;
 }
 
@@ -292,6 +293,7 @@ extern "C" tlb_status tlb_batch_create(const tlb_params* per_dom, int32_t ndom, 
         if (!isfinite(p.tau_f) || !isfinite(p.tau_g) || !isfinite(p.tau_k)) return TLB_EINVAL;
         if (!isfinite(p.gamma_phi) || !isfinite(p.gamma_psi)) return TLB_EINVAL;
         if (p.no_advection != 0 && p.no_advection != 1) return TLB_EINVAL;
+        if (p.collision != TLB_BGK) return TLB_EINVAL;  // the batched step collides with BGK
         if (prec != TLB_F32 && prec != TLB_F64) return TLB_EINVAL;
         const int64_t bytes = (int64_t)27 * p.nx * p.ny * (prec == TLB_F32 ? 4 : 8);
         if (bytes > (int64_t)0xFFFFFF00) return TLB_EINVAL;

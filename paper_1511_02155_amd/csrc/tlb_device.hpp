@@ -79,6 +79,46 @@ __host__ __device__ constexpr double woff(int i, int a, int b)
     return e2<L>(i) == 2 ? ecomp<L>(i, a) * ecomp<L>(i, b) / 12.0 : 0.0;
 }
 
+// Moments of the multiple-relaxation-time collision of f that relax at a rate
+// of their own (the others all share the ghost rate): the energy moment
+// (D2Q9 3|e|^2 - 4, D3Q19 19|e|^2 - 30; bulk viscosity) and the viscous stress
+// moments, a basis of the traceless second moments (D2Q9 e_x^2 - e_y^2,
+// e_x e_y; D3Q19 3e_x^2 - |e|^2, e_y^2 - e_z^2, e_x e_y, e_y e_z, e_x e_z).
+// In an orthogonal moment basis containing them, the collision is
+//   f* = f - s_g d - (s_v - s_g) P_stress d - (s_b - s_g) P_energy d,
+// d = f - f^eq, with P the orthogonal projections onto their spans.
+template <class L>
+__host__ __device__ constexpr double mrt_energy(int i)
+{
+    return L::D == 2 ? 3.0 * e2<L>(i) - 4.0 : 19.0 * e2<L>(i) - 30.0;
+}
+template <class L>
+__host__ __device__ constexpr int mrt_nstress()
+{
+    return L::D == 2 ? 2 : 5;
+}
+template <class L>
+__host__ __device__ constexpr double mrt_stress(int k, int i)
+{
+    const int x = L::ex[i], y = L::ey[i], z = L::ez[i];
+    if (L::D == 2) return k == 0 ? x * x - y * y : x * y;
+    return k == 0 ? 3 * x * x - e2<L>(i) : k == 1 ? y * y - z * z : k == 2 ? x * y : k == 3 ? y * z : x * z;
+}
+template <class L>
+__host__ __device__ constexpr double mrt_energy_norm()
+{
+    double s = 0.0;
+    for (int i = 0; i < L::Q; ++i) s += mrt_energy<L>(i) * mrt_energy<L>(i);
+    return s;
+}
+template <class L>
+__host__ __device__ constexpr double mrt_stress_norm(int k)
+{
+    double s = 0.0;
+    for (int i = 0; i < L::Q; ++i) s += mrt_stress<L>(k, i) * mrt_stress<L>(k, i);
+    return s;
+}
+
 // Storage reference r_{s,i} (see the header comment).
 template <class L>
 __host__ __device__ constexpr double ref(int s, int i)
@@ -138,6 +178,9 @@ struct Phys {
     T omega[3];    // 1/tau for f, g, k
     T gphi3, gpsi3;  // Gamma_phi / c_s^2, Gamma_psi / c_s^2
     T adv;           // 1: g^eq, k^eq carry the velocity terms; 0: diffusive Cahn-Hilliard
+    // multiple relaxation times of f: the ghost rate s_g = 1/tau_ghost and the differences
+    // s_v - s_g (stress moments, s_v = 1/tau_f) and s_b - s_g (energy moment, s_b = 1/tau_bulk)
+    T mrt_sg, mrt_dv, mrt_db;
 };
 
 // Arithmetic type of the per-node computations for a storage type T.  Both
@@ -227,11 +270,12 @@ __device__ __forceinline__ void chem_potentials(const Phys<T>& P, const T dc[3],
 //   g_i^eq = w_i [ Gamma_phi mu_phi / c_s^2 + phi U_i ],  k_i^eq likewise (eq. eqdistfbinary)
 //   U_i    = e_i.v / c_s^2 + (e_i.v)^2 / (2 c_s^4) - v^2 / (2 c_s^2)
 //   rest populations from the mass constraints; BGK with 1/tau per species.
-template <class L, typename T, typename S>
+template <class L, bool MRT = false, typename T, typename S>
 __device__ __forceinline__ void collide(const Phys<T>& P, const Moments<T>& mo, const T dc[3],
                                         const T gC[3][3], const T lC[3], S* f, S* g, S* k)
 {
-    // T: arithmetic type; S: storage type of the populations (rounded once, on the update)
+    // T: arithmetic type; S: storage type of the populations (rounded once, on the update).
+    // MRT: f relaxes with multiple relaxation times (g and k always with BGK).
     const T third = T(1.0 / 3.0);
     T mu[3];
     T pbx = mo.drho * third;  // p_b - 1/3 (the 1/3 is the reference pressure of the shifted f)
@@ -271,6 +315,13 @@ __device__ __forceinline__ void collide(const Phys<T>& P, const Moments<T>& mo, 
     // i > 0: equilibrium and relaxation in place; the rest population last,
     // from the mass constraints.
     T sf = 0, sg = 0, sk = 0;
+    constexpr int NS = mrt_nstress<L>();
+    T dq[MRT ? L::Q : 1];         // MRT: f_i - f_i^eq
+    T me = 0, ms[MRT ? NS : 1];   // MRT: energy and stress moments of f - f^eq
+    if constexpr (MRT) {
+#pragma unroll
+        for (int q = 0; q < NS; ++q) ms[q] = 0;
+    }
 #pragma unroll
     for (int i = 1; i < L::Q; ++i) {
         const T w = T(weight<L>(i));
@@ -289,12 +340,37 @@ __device__ __forceinline__ void collide(const Phys<T>& P, const Moments<T>& mo, 
         sg += geq;
         sk += keq;
         const T fi = T(f[i]), gi = T(g[i]), ki = T(k[i]);
-        f[i] = S(fi + wf * (feq - fi));
+        if constexpr (MRT) {
+            const T di = fi - feq;
+            dq[i] = di;
+            me += T(mrt_energy<L>(i)) * di;
+#pragma unroll
+            for (int q = 0; q < NS; ++q) ms[q] += T(mrt_stress<L>(q, i)) * di;
+        } else {
+            f[i] = S(fi + wf * (feq - fi));
+        }
         g[i] = S(gi + wg * (geq - gi));
         k[i] = S(ki + wk * (keq - ki));
     }
     const T f0 = T(f[0]), g0 = T(g[0]), k0 = T(k[0]);
-    f[0] = S(f0 + wf * ((mo.drho - sf) - f0));
+    if constexpr (MRT) {
+        // the rest population has no stress moment; it enters the energy moment
+        dq[0] = f0 - (mo.drho - sf);
+        me += T(mrt_energy<L>(0)) * dq[0];
+        me *= P.mrt_db * T(1.0 / mrt_energy_norm<L>());
+#pragma unroll
+        for (int q = 0; q < NS; ++q) ms[q] *= P.mrt_dv * T(1.0 / mrt_stress_norm<L>(q));
+#pragma unroll
+        for (int i = 0; i < L::Q; ++i) {
+            T r = T(f[i]) - P.mrt_sg * dq[i] - T(mrt_energy<L>(i)) * me;
+#pragma unroll
+            for (int q = 0; q < NS; ++q)
+                if (mrt_stress<L>(q, i) != 0.0) r -= T(mrt_stress<L>(q, i)) * ms[q];
+            f[i] = S(r);
+        }
+    } else {
+        f[0] = S(f0 + wf * ((mo.drho - sf) - f0));
+    }
     g[0] = S(g0 + wg * ((mo.phi - sg) - g0));
     k[0] = S(k0 + wk * ((mo.dpsi - sk) - k0));
 }

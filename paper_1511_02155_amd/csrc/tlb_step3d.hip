@@ -88,7 +88,7 @@ struct PlaneFull {
 
 // HOLD selects between keeping the pulled populations of plane z+1 in
 // registers and pulling plane z again (from cache) when it is collided.
-template <typename T, int BX, int BY, bool HOLD>
+template <typename T, int BX, int BY, bool HOLD, bool MRT>
 __global__ __launch_bounds__(BX* BY) void k_step3d(StepArgs<T> A)
 {
     using C = acc_t<T>;
@@ -244,7 +244,7 @@ __global__ __launch_bounds__(BX* BY) void k_step3d(StepArgs<T> A)
         }
         if constexpr (!HOLD) pull3d<T>(A, rs, col, z, wall_tile, blo, bhi, fb, gb, kb);
         const Moments<C> mb = moments<L19, T>(fb, gb, kb);
-        collide<L19>(A.P, mb, pb.c, gC, lC, fb, gb, kb);
+        collide<L19, MRT>(A.P, mb, pb.c, gC, lC, fb, gb, kb);
 
         if (active) {
             const uint32_t so = (uint32_t)z * (uint32_t)A.nx * (uint32_t)A.ny * (uint32_t)sizeof(T);
@@ -270,23 +270,27 @@ __global__ __launch_bounds__(BX* BY) void k_step3d(StepArgs<T> A)
 }
 
 template <typename T>
-hipError_t launch_step3d(const StepArgs<T>& a, int width, int height, int hold, hipStream_t s)
+hipError_t launch_step3d(const StepArgs<T>& a, int width, int height, int hold, bool mrt, hipStream_t s)
 {
     dim3 grid(a.nitems);
-#define TLB_L3(BX, BY, H)                                                              \
-    if (width == BX && height == BY && (hold != 0) == H) {                             \
-        hipLaunchKernelGGL((k_step3d<T, BX, BY, H>), grid, dim3(BX * BY), 0, s, a);    \
+#define TLB_L3(BX, BY, H, M)                                                           \
+    if (width == BX && height == BY && (hold != 0) == H && mrt == M) {                 \
+        hipLaunchKernelGGL((k_step3d<T, BX, BY, H, M>), grid, dim3(BX * BY), 0, s, a); \
         return hipGetLastError();                                                      \
     }
-    TLB_L3(32, 8, false)
-    TLB_L3(64, 4, false)
-    TLB_L3(32, 8, true)
-    TLB_L3(64, 4, true)
+    TLB_L3(32, 8, false, false)
+    TLB_L3(64, 4, false, false)
+    TLB_L3(32, 8, true, false)
+    TLB_L3(64, 4, true, false)
+    TLB_L3(32, 8, false, true)
+    TLB_L3(64, 4, false, true)
+    TLB_L3(32, 8, true, true)
+    TLB_L3(64, 4, true, true)
 #undef TLB_L3
     return hipErrorInvalidValue;
 }
 
-template hipError_t launch_step3d<float>(const StepArgs<float>&, int, int, int, hipStream_t);
-template hipError_t launch_step3d<double>(const StepArgs<double>&, int, int, int, hipStream_t);
+template hipError_t launch_step3d<float>(const StepArgs<float>&, int, int, int, bool, hipStream_t);
+template hipError_t launch_step3d<double>(const StepArgs<double>&, int, int, int, bool, hipStream_t);
 
 }  // namespace tlb

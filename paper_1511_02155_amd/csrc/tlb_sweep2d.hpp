@@ -107,7 +107,7 @@ struct Sweep2Lds {
 // One work item: strip `strip` (W columns) of rows [chunk*A.chunk, ...) of
 // the lattice described by A, swept in the direction given by the chunk's
 // parity.  Every lane of the workgroup must call it.
-template <typename T, int W, int DEPTH>
+template <typename T, int W, int DEPTH, bool MRT = false>
 __device__ __forceinline__ void sweep2d(const StepArgs<T>& A, int strip, int chunk, Sweep2Lds<T, W>& S)
 {
     auto& lds = S.row;
@@ -248,7 +248,7 @@ __device__ __forceinline__ void sweep2d(const StepArgs<T>& A, int strip, int chu
                 lC[m] = (bS + (ac + cc)) * C(2.0 / 3.0) + (aS + cS) * C(1.0 / 6.0) - bc * C(10.0 / 3.0);
             }
             C dc[3] = {lds[qb][0][t + 1], lds[qb][1][t + 1], lds[qb][2][t + 1]};
-            collide<L9>(A.P, Mc, dc, gC, lC, Pc, Pc + 9, Pc + 18);
+            collide<L9, MRT>(A.P, Mc, dc, gC, lC, Pc, Pc + 9, Pc + 18);
             const uint32_t rowo = (uint32_t)y * (uint32_t)A.nx;
 #pragma unroll
             for (int i = 0; i < 9; ++i) {

@@ -27,6 +27,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 TLB_OK, TLB_EINVAL, TLB_ENOMEM, TLB_EHIP, TLB_ENAN, TLB_ESTATE = 0, -1, -2, -3, -4, -5
 TLB_D2Q9, TLB_D3Q19 = 0, 1
 TLB_F32, TLB_F64 = 0, 1
+TLB_BGK, TLB_MRT = 0, 1
 FIELDS = ("C1", "C2", "C3", "rho", "phi", "psi", "ux", "uy", "uz", "mu_phi", "mu_psi")
 FIELD_INDEX = {name: i for i, name in enumerate(FIELDS)}
 
@@ -58,6 +59,9 @@ class tlb_params(ctypes.Structure):
         ("tau_f", ctypes.c_double), ("tau_g", ctypes.c_double), ("tau_k", ctypes.c_double),
         ("gamma_phi", ctypes.c_double), ("gamma_psi", ctypes.c_double),
         ("no_advection", ctypes.c_int32),
+        ("collision", ctypes.c_int32),
+        ("tau_bulk", ctypes.c_double),
+        ("tau_ghost", ctypes.c_double),
     ]
 
 
@@ -170,7 +174,8 @@ def _arr(a, n=None):
 
 
 def make_params(lattice, nx, ny, nz=1, prec=TLB_F64, walls_y=0, kappa=(0.01, 0.01, 0.01), alpha=1.0,
-                tau_f=1.0, tau_g=1.0, tau_k=1.0, gamma_phi=1.0, gamma_psi=1.0, no_advection=0, **_ignored):
+                tau_f=1.0, tau_g=1.0, tau_k=1.0, gamma_phi=1.0, gamma_psi=1.0, no_advection=0, collision=0,
+                tau_bulk=1.0, tau_ghost=1.0, **_ignored):
     p = tlb_params()
     p.lattice, p.prec, p.nx, p.ny, p.nz, p.walls_y = lattice, prec, nx, ny, nz, walls_y
     for m in range(3):
@@ -178,6 +183,8 @@ def make_params(lattice, nx, ny, nz=1, prec=TLB_F64, walls_y=0, kappa=(0.01, 0.0
     p.alpha, p.tau_f, p.tau_g, p.tau_k = alpha, tau_f, tau_g, tau_k
     p.gamma_phi, p.gamma_psi = gamma_phi, gamma_psi
     p.no_advection = int(no_advection)
+    p.collision = int(collision)
+    p.tau_bulk, p.tau_ghost = float(tau_bulk), float(tau_ghost)
     return p
 
 

@@ -61,6 +61,8 @@ def test_status_strings():
     dict(tau_f=0.5), dict(tau_g=0.4), dict(tau_k=-1.0), dict(kappa=(0.01, 0.0, 0.01)),
     dict(kappa=(0.01, 0.01, -0.1)), dict(alpha=0.0), dict(nx=2), dict(ny=2), dict(nz=2),
     dict(prec=7), dict(lattice=5), dict(walls_y=2), dict(alpha=float("nan")), dict(no_advection=2),
+    dict(collision=2), dict(collision=1, tau_bulk=0.5), dict(collision=1, tau_ghost=0.3),
+    dict(collision=1, tau_bulk=float("inf")),
 ])
 def test_create_rejects_invalid_parameters(bad):
     from paper_1511_02155_amd import tlb

@@ -37,7 +37,7 @@ def tlb():
 
 
 _PKEYS = ("lattice", "nx", "ny", "nz", "walls_y", "kappa", "alpha", "tau_f", "tau_g", "tau_k", "gamma_phi",
-          "gamma_psi", "no_advection")
+          "gamma_psi", "no_advection", "collision", "tau_bulk", "tau_ghost")
 
 
 def _oparams(orc, w):
@@ -350,3 +350,78 @@ def test_interface_diagnostics_match_oracle_fields(tlb, orc, lattice):
     for m, name in enumerate(("C1", "C2", "C3")):
         want = float(np.sum(F[name] ** 2 * (1 - F[name]) ** 2))
         assert d["interface"][m] == pytest.approx(want, rel=1e-12)
+
+
+# --------------------------------------------------------------------------
+# Multiple relaxation times for f (tlb_params.collision = TLB_MRT)
+# --------------------------------------------------------------------------
+_MRT_LAUNCH = {0: [dict(width=64, chunk=5, variant=0), dict(width=128, chunk=7, variant=1),
+                   dict(width=256, chunk=3, variant=0)],
+               1: [dict(width=32, height=8, chunk=4, variant=0), dict(width=64, height=4, chunk=3, variant=1)]}
+
+
+@pytest.mark.parametrize("lattice,walls,li", [(0, 1, 0), (0, 1, 1), (0, 0, 2), (1, 1, 0), (1, 0, 1)])
+def test_mrt_fp64(tlb, orc, lattice, walls, li):
+    """Distinct stress, bulk and ghost rates against the oracle's M^-1 S M collision, with an initial flow
+    (ragged strips and tiles, walls with wetting)."""
+    dims = (70, 23, 1) if lattice == 0 else (37, 21, 9)
+    w, C, h = _wet_case(*dims, lattice=lattice, walls=walls, seed=9, tau=(0.8, 0.9, 0.8))
+    w.update(collision=1, tau_bulk=0.65, tau_ghost=1.3)
+    launch = _MRT_LAUNCH[lattice][li]
+    _note(f"mrt fp64 lattice={lattice} walls={walls} launch={launch}")
+    p = _oparams(orc, w)
+    u = np.random.default_rng(10).uniform(-0.02, 0.02, size=(p.D, p.N))
+    pop = orc.init_equilibrium(p, C, u, h)
+    orc.step(p, pop, 30, h)
+    s = _gsim(tlb, w, tlb.TLB_F64, launch)
+    if h is not None:
+        s.set_wetting_both(h)
+    s.init_equilibrium(C, u)
+    s.step(30)
+    _compare_f64(orc, p, pop, h, s)
+
+
+@pytest.mark.parametrize("lattice", [0, 1])
+def test_mrt_fp32(tlb, orc, lattice):
+    dims = (64, 40, 1) if lattice == 0 else (24, 20, 12)
+    w, C, h = _wet_case(*dims, lattice=lattice, walls=1, seed=11, tau=(0.8, 0.9, 0.8))
+    w.update(collision=1, tau_bulk=1.2, tau_ghost=0.7)
+    p, pop, s = _run_both(tlb, orc, w, C, h, 200, tlb.TLB_F32)
+    _compare_f32(orc, p, pop, h, s)
+
+
+@pytest.mark.parametrize("lattice", [0, 1])
+def test_mrt_with_equal_rates_is_bgk_on_the_gpu(tlb, lattice):
+    dims = (40, 19, 1) if lattice == 0 else (20, 13, 7)
+    w, C, h = _wet_case(*dims, lattice=lattice, walls=1, seed=12, tau=(0.85, 0.9, 0.8))
+    out = []
+    for col in (0, 1):
+        w2 = dict(w, collision=col, tau_bulk=0.85, tau_ghost=0.85)
+        s = _gsim(tlb, w2, tlb.TLB_F64)
+        s.set_wetting_both(h)
+        s.init_equilibrium(C)
+        s.step(25)
+        out.append(s.all_populations())
+        s.close()
+    assert np.abs(out[0] - out[1]).max() <= 1e-13 * np.abs(out[0]).max()
+
+
+def test_mrt_is_rejected_by_the_batch_and_the_reverse_step(tlb):
+    import ctypes
+
+    w, C, h = _wet_case(24, 16, walls=1, seed=13)
+    w.update(collision=1, tau_bulk=0.7, tau_ghost=1.1)
+    p = tlb.make_params(prec=tlb.TLB_F64, **{k: v for k, v in w.items() if k in _PKEYS})
+    ps = (tlb.tlb_params * 1)(p)
+    hb = ctypes.c_void_p()
+    assert tlb.tlb_batch_create(ps, 1, None, ctypes.byref(hb)) == tlb.TLB_EINVAL
+    s = tlb.Sim(p)
+    s.init_equilibrium(C)
+    n = s.state_bytes()
+    import torch
+
+    u = torch.zeros(n // 8, dtype=torch.float64, device="cuda")
+    l0, l1 = torch.zeros_like(u), torch.zeros_like(u)
+    assert tlb.tlb_adjoint_step_dev(s.handle, u.data_ptr(), l0.data_ptr(), l1.data_ptr(), None, None) == \
+        tlb.TLB_EINVAL
+    s.close()
