@@ -55,22 +55,16 @@ def _relax_f_mrt(f, feq, tau_f, tau_bulk, tau_ghost):
     return out
 
 
-def step(pop, h, kappa, alpha, tau, gamma, walls, mrt=None):
-    """One step s_t -> s_{t+1}.  pop: [3][9][ny][nx]; h: [2][3][nx] (walls) or None;
-    kappa: [3] tensor; tau = (tau_f, tau_g, tau_k); gamma = (Gamma_phi, Gamma_psi);
-    mrt = (tau_bulk, tau_ghost) for multiple relaxation times of f, or None for BGK."""
-    f, g, k = pop[0], pop[1], pop[2]
-    ny = pop.shape[-2]
-    ex = torch.tensor([e[0] for e in E], dtype=pop.dtype).view(9, 1, 1)
-    ey = torch.tensor([e[1] for e in E], dtype=pop.dtype).view(9, 1, 1)
-    rho = f.sum(0)
-    vx = (f * ex).sum(0) / rho
-    vy = (f * ey).sum(0) / rho
-    phi = g.sum(0)
-    psi = k.sum(0)
-    C = torch.stack([0.5 * (rho + phi - psi), 0.5 * (rho - phi - psi), psi])  # [3][ny][nx]
+def equilibria(C, vx, vy, h, kappa, alpha, gamma, walls):
+    """Equilibrium populations [NC][9][ny][nx] of concentration fields C[NC][ny][nx] (NC >= 3: rho =
+    sum_m C_m, phi = C1 - C2, psi_l = C_l for l >= 3, Sec. II.E) and velocity (vx, vy), with the
+    gradient terms of the fields and the wetting ghost rows h[2][NC][nx] (walls)."""
+    NC, ny, nx = C.shape
+    rho = C.sum(0)
+    phi = C[0] - C[1]
+    psis = C[2:]
     a2 = alpha * alpha
-    a2k = (a2 * kappa).view(3, 1)
+    a2k = (a2 * kappa).view(NC, 1)
     # neighbour values C_m(r + e_i), with ghost rows beyond the walls (reading R8)
     if walls:
         below = C[:, :1, :] + (h[0] / a2k).unsqueeze(1)
@@ -90,10 +84,11 @@ def step(pop, h, kappa, alpha, tau, gamma, walls, mrt=None):
         gx = gx + 3.0 * W[i] * E[i][0] * c
         gy = gy + 3.0 * W[i] * E[i][1] * c
         lap = lap + 6.0 * W[i] * (c - C)
-    km = kappa.view(3, 1, 1)
+    km = kappa.view(NC, 1, 1)
     mu = km * C * (1 - C) * (1 - 2 * C) - a2 * km * lap
+    # chemical potentials of the transformed variables (chain rule through C_1 and C_2)
     mu_phi = 0.5 * (mu[0] - mu[1])
-    mu_psi = mu[2] - 0.5 * (mu[0] + mu[1])
+    mu_psi = mu[2:] - 0.5 * (mu[0] + mu[1])  # [NC-2]
     pb = rho / 3.0 + (0.5 * km * C * C * (1 - C) * (1 - 3 * C)).sum(0)
     lam = (a2 * km * C * lap).sum(0)
     Txx = (a2 * km * gx * gx).sum(0)
@@ -107,15 +102,40 @@ def step(pop, h, kappa, alpha, tau, gamma, walls, mrt=None):
         wxx, wyy, wxy = _wab(i)
         feq.append(W[i] * (3.0 * (pb - lam) + rho * U) + 3.0 * (wxx * Txx + wyy * Tyy + wxy * Txy))
         geq.append(W[i] * (3.0 * gamma[0] * mu_phi + phi * U))
-        keq.append(W[i] * (3.0 * gamma[1] * mu_psi + psi * U))
+        keq.append(W[i] * (3.0 * gamma[1] * mu_psi + psis * U))  # [NC-2][ny][nx]
     feq = torch.stack([rho - sum(feq)] + feq)
     geq = torch.stack([phi - sum(geq)] + geq)
-    keq = torch.stack([psi - sum(keq)] + keq)
-    eq = torch.stack([feq, geq, keq])
-    itau = torch.tensor([1.0 / t for t in tau], dtype=pop.dtype).view(3, 1, 1, 1)
+    keq = torch.stack([psis - sum(keq)] + keq, dim=1)  # [NC-2][9][ny][nx]
+    return torch.cat([torch.stack([feq, geq]), keq])
+
+
+def equilibrium_state(C, h, kappa, alpha, gamma, walls, u=None):
+    """Initial state: the equilibria of C[NC][ny][nx] and velocity u[2][ny][nx] (None: at rest)."""
+    z = torch.zeros_like(C[0])
+    vx, vy = (z, z) if u is None else (u[0], u[1])
+    return equilibria(C, vx, vy, h, kappa, alpha, gamma, walls)
+
+
+def step(pop, h, kappa, alpha, tau, gamma, walls, mrt=None):
+    """One step s_t -> s_{t+1}.  pop: [NC][9][ny][nx] for NC >= 3 components (f, g, then one k_l per
+    psi_l = C_l, l >= 3; Sec. II.E); h: [2][NC][nx] (walls) or None; kappa: [NC] tensor;
+    tau = (tau_f, tau_g, tau_k) (every k_l relaxes with tau_k); gamma = (Gamma_phi, Gamma_psi)
+    (every k_l uses Gamma_psi); mrt = (tau_bulk, tau_ghost) for multiple relaxation times of f, or
+    None for BGK."""
+    NC = pop.shape[0]
+    ny = pop.shape[-2]
+    f = pop[0]
+    ex = torch.tensor([e[0] for e in E], dtype=pop.dtype).view(9, 1, 1)
+    ey = torch.tensor([e[1] for e in E], dtype=pop.dtype).view(9, 1, 1)
+    rho = f.sum(0)
+    vx = (f * ex).sum(0) / rho
+    vy = (f * ey).sum(0) / rho
+    C = concentrations(pop)
+    eq = equilibria(C, vx, vy, h, kappa, alpha, gamma, walls)
+    itau = torch.tensor([1.0 / tau[0], 1.0 / tau[1]] + [1.0 / tau[2]] * (NC - 2), dtype=pop.dtype).view(NC, 1, 1, 1)
     post = pop - itau * (pop - eq)
     if mrt is not None:
-        post = torch.stack([_relax_f_mrt(f, feq, tau[0], mrt[0], mrt[1]), post[1], post[2]])
+        post = torch.cat([_relax_f_mrt(f, eq[0], tau[0], mrt[0], mrt[1]).unsqueeze(0), post[1:]])
     # pull propagation with half-way bounce-back at the y walls
     out = []
     for i in range(9):
@@ -130,8 +150,10 @@ def step(pop, h, kappa, alpha, tau, gamma, walls, mrt=None):
 
 
 def concentrations(pop):
-    rho, phi, psi = pop[0].sum(0), pop[1].sum(0), pop[2].sum(0)
-    return torch.stack([0.5 * (rho + phi - psi), 0.5 * (rho - phi - psi), psi])
+    """C[NC][ny][nx] of a state: C1 = (rho + phi - sum psi)/2, C2 = (rho - phi - sum psi)/2, C_l = psi_l."""
+    rho, phi, psis = pop[0].sum(0), pop[1].sum(0), pop[2:].sum(1)
+    spsi = psis.sum(0)
+    return torch.cat([torch.stack([0.5 * (rho + phi - spsi), 0.5 * (rho - phi - spsi)]), psis])
 
 
 def run(pop0, h, kappa, alpha, tau, gamma, walls, nsteps, mrt=None):
