@@ -255,7 +255,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=300)
     ap.add_argument("--quick", action="store_true", help="headline only (no extra workloads)")
     ap.add_argument("--only", default=None,
-                    help="run a single workload: f64, f32, d3q19, batched, mrt, adjoint64, adjoint32")
+                    help="run a single workload: f64, f32, d3q19, batched, mrt, ncomp, adjoint64, adjoint32")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -309,6 +309,12 @@ def main():
         print(f"[bench] d3q19 256^3 f32 MRT: {s3} steps", file=sys.stderr, flush=True)
         add("d3q19_256cube_spinodal_f32_mrt",
             run_plain(tlb, torch, dict(inputs.spinodal_3d(256, s3), **mrt), tlb.TLB_F32, s3, 10))
+    if sel == "ncomp" or every:
+        # more than three components (Sec. II.E): four-component spinodal, FP64
+        sn = args.steps if sel else max(200, min(2000, args.steps // 5))
+        print(f"[bench] d2q9 1024^2 f64 four components: {sn} steps", file=sys.stderr, flush=True)
+        add("d2q9_1024x1024_spinodal_n4_f64", run_plain(tlb, torch, inputs.spinodal_2d_nc(1024, sn, 4), tlb.TLB_F64,
+                                                        sn, 10))
     for name, prec in (("f64", tlb.TLB_F64), ("f32", tlb.TLB_F32)):
         if sel == "adjoint" + name[1:] or every:
             sa = args.steps if sel else max(100, min(2000, args.steps // 5))
@@ -362,6 +368,8 @@ WORKLOAD_CONFIG = {
     "d3q19_256cube_spinodal_f32_mrt": dict(lattice="D3Q19", nx=256, ny=256, nz=256, boundary="periodic",
                                            kappa=[0.01, 0.01, 0.01], alpha=1.0, tau=0.8, mobility=0.05,
                                            collision="MRT", tau_bulk=0.8, tau_ghost=1.2),
+    "d2q9_1024x1024_spinodal_n4_f64": dict(lattice="D2Q9", nx=1024, ny=1024, boundary="periodic", components=4,
+                                           kappa=[0.01, 0.015, 0.02, 0.025], alpha=1.0, tau=1.0, mobility=0.1),
     "batched_512_domains_f32": dict(lattice="D2Q9", domains=512, side=[32, 256], boundary="walls_y"),
     "adjoint_512x512_wall_drop_f64": dict(lattice="D2Q9", nx=512, ny=512, boundary="walls_y", form="reverse step"),
     "adjoint_512x512_wall_drop_f32": dict(lattice="D2Q9", nx=512, ny=512, boundary="walls_y", form="reverse step"),

@@ -66,6 +66,8 @@ typedef enum {
 enum { TLB_D2Q9 = 0, TLB_D3Q19 = 1 };
 enum { TLB_F32 = 0, TLB_F64 = 1 };
 enum { TLB_BGK = 0, TLB_MRT = 1 };
+/* Largest number of fluid components (tlb_params.ncomp). */
+enum { TLB_MAX_COMP = 5 };
 
 /* Field selectors of tlb_get_field. */
 enum {
@@ -79,8 +81,10 @@ enum {
     TLB_FIELD_UY = 7,
     TLB_FIELD_UZ = 8,
     TLB_FIELD_MU_PHI = 9,
-    TLB_FIELD_MU_PSI = 10,
-    TLB_NFIELDS = 11
+    TLB_FIELD_MU_PSI = 10,  /* mu of psi_3 = C3 */
+    TLB_NFIELDS = 11,       /* the selectors of a three-component simulation */
+    TLB_FIELD_C4 = 11,      /* C4, C5: simulations with ncomp >= 4, 5 */
+    TLB_FIELD_C5 = 12
 };
 
 /*
@@ -112,6 +116,16 @@ enum {
  *             tau_f, MRT is BGK.  The batched step and the reverse step take
  *             BGK only (TLB_EINVAL otherwise).
  *   tau_bulk, tau_ghost  MRT relaxation times, each > 1/2 (ignored for BGK).
+ *   ncomp     number of fluid components N, 3 .. TLB_MAX_COMP (0 means 3).
+ *             N > 3 (Sec. II.E, D2Q9 only) uses rho = sum_m C_m, phi = C1 - C2
+ *             and psi_l = C_l for l >= 3, with one k population set per psi_l
+ *             (species 2 .. N-1, all relaxing with tau_k and using gamma_psi)
+ *             and mu_psi_l = mu_l - (mu_1 + mu_2)/2.  Every per-component
+ *             array then has N rows: kappa_m (kappa[0..2] and kappa_hi[0..N-4]),
+ *             the wetting parameters [N][nx*nz], the initial fields C[N][..]
+ *             and the populations [N][Q][..].  The batched step and the reverse
+ *             step take three components only.
+ *   kappa_hi  kappa_4 .. kappa_N, each > 0 (ignored for N = 3).
  */
 typedef struct {
     int32_t lattice;
@@ -125,6 +139,8 @@ typedef struct {
     int32_t no_advection;
     int32_t collision;
     double tau_bulk, tau_ghost;
+    int32_t ncomp;
+    double kappa_hi[TLB_MAX_COMP - 3];
 } tlb_params;
 
 /* Conservation and stability check of the current state s_t (all sums in FP64). */
@@ -139,6 +155,9 @@ typedef struct {
      * length (area) of the boundary of component m and chi_m of Sec. V.C is its value divided by
      * the side of a square domain; the typical domain size is the domain area over that length. */
     double interface[3];
+    /* N > 3: sum psi_l and the interface sums of C_l for l = 4 .. N (zero beyond N) */
+    double mass_hi[TLB_MAX_COMP - 3];
+    double interface_hi[TLB_MAX_COMP - 3];
 } tlb_diag;
 
 typedef struct tlb_sim tlb_sim;
@@ -148,7 +167,8 @@ const char* tlb_status_str(int status);
 /* HIP error code of the last TLB_EHIP returned on this thread (0 if none). */
 int tlb_last_hip_error(void);
 /* ABI version (major * 100 + minor); 2xx: tlb_params.no_advection and tlb_diag.interface;
- * 3xx: tlb_params.collision, tau_bulk, tau_ghost. */
+ * 3xx: tlb_params.collision, tau_bulk, tau_ghost; 4xx: tlb_params.ncomp, kappa_hi and
+ * tlb_diag.mass_hi, interface_hi (N components). */
 int tlb_version(void);
 
 /*
@@ -163,14 +183,15 @@ tlb_status tlb_get_params(const tlb_sim* sim, tlb_params* out);
 
 /*
  * Wetting parameters h_m of one wall (Sec. II.B, eq. Cahn): wall 0 = below
- * y = 0, wall 1 = above y = ny-1; h: host array [3][nx*nz], finite values.
+ * y = 0, wall 1 = above y = ny-1; h: host array [N][nx*nz] (N components,
+ * 3 unless tlb_params.ncomp says more), finite values.
  * Requires walls_y == 1.  Takes effect from the next step (or initialisation).
  */
 tlb_status tlb_set_wetting(tlb_sim* sim, int wall, const double* h);
 
 /*
  * Initialise s_0 to the equilibria of the concentration fields C (host,
- * [3][N], rho = C1 + C2 + C3, phi = C1 - C2, psi = C3, Sec. II.C) and the
+ * [ncomp][N], rho = sum_m C_m, phi = C1 - C2, psi_l = C_l, Sec. II.C, II.E) and the
  * velocity u (host, [D][N]; NULL = at rest), with the gradient terms of the
  * equilibria evaluated from C.  Resets the step counter.
  */
@@ -189,7 +210,8 @@ tlb_status tlb_set_check_every(tlb_sim* sim, int64_t every);
 /* Macroscopic field `which` (TLB_FIELD_*) of the state s_t into host out[N]. */
 tlb_status tlb_get_field(tlb_sim* sim, int which, double* out);
 
-/* Post-propagation populations s_t of one species into host out[Q][N]. */
+/* Post-propagation populations s_t of one species (0 f, 1 g, 2 .. ncomp-1 the
+ * k sets of psi_3 ..) into host out[Q][N]. */
 tlb_status tlb_get_populations(tlb_sim* sim, int species, double* out);
 
 /* Overwrite the populations s_t of one species from host in[Q][N]. */
@@ -223,8 +245,8 @@ tlb_status tlb_save_state_dev(tlb_sim* sim, void* dev_dst);
 tlb_status tlb_load_state_dev(tlb_sim* sim, const void* dev_src, int64_t step);
 
 /*
- * Change kappa_1..3 (each > 0) between runs; the wetting ghost values
- * h_m / (alpha^2 kappa_m) are recomputed from the h_m last set.
+ * Change kappa_1..N (kappa[ncomp], each > 0) between runs; the wetting ghost
+ * values h_m / (alpha^2 kappa_m) are recomputed from the h_m last set.
  */
 tlb_status tlb_set_kappa(tlb_sim* sim, const double* kappa);
 

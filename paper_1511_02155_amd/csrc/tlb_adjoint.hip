@@ -270,7 +270,7 @@ __global__ __launch_bounds__(W * K) void k_adj2d(AdjArgs<T> A)
         // ---- stage 1: moments and dC of row a ----
         Moments<C> mom_new = {};
         if (act1) {
-            mom_new = moments<L9, T>(pu, pu + 9, pu + 18);
+            mom_new = moments<L9>(pu, pu + 9, pu + 18);
             C dc[3];
             conc_dev<C>(mom_new, dc);
             const int sa = slot(a);

@@ -19,16 +19,17 @@ struct tlb_sim {
     hipStream_t stream;
     bool own_stream;
     size_t esize;       // bytes per stored value
-    void* state[2];     // [3][Q][N] each
+    void* state[2];     // [nc][Q][N] each
     int cur;            // index of the buffer holding u_t
-    void* wet;          // [2][3][nx*nz] h_m / (alpha^2 kappa_m), or nullptr
-    double* hbuf;       // [2][3][nx*nz] h_m as set (to rescale when kappa changes)
+    void* wet;          // [2][nc][nx*nz] h_m / (alpha^2 kappa_m), or nullptr
+    double* hbuf;       // [2][nc][nx*nz] h_m as set (to rescale when kappa changes)
     // adjoint scratch (lazy)
     void* lam[2];
     double* kpart;      // [3][items] kappa-gradient partials + [3][kRedBlocks] reduction scratch
     int64_t kpart_cap;  // items the allocation holds
     tlb_launch adj_launch;
     int cus;            // compute units of the device
+    int nc;             // components (3 .. kMaxComp)
     double* dhs;        // [2][3][nx*nz] sink for dL/dh when the caller passes none
     void* seg;
     int64_t seg_cap;
@@ -71,7 +72,12 @@ extern "C" const char* tlb_status_str(int s)
 }
 
 extern "C" int tlb_last_hip_error(void) { return g_last_hip; }
-extern "C" int tlb_version(void) { return 300; }
+extern "C" int tlb_version(void) { return 400; }
+
+static int ncomp_of(const tlb_params* p) { return p->ncomp == 0 ? 3 : p->ncomp; }
+
+// kappa_m of component m (m < ncomp): kappa[0..2], then kappa_hi.
+static double kappa_of(const tlb_params& p, int m) { return m < 3 ? p.kappa[m] : p.kappa_hi[m - 3]; }
 
 static bool params_valid(const tlb_params* p)
 {
@@ -90,6 +96,12 @@ static bool params_valid(const tlb_params* p)
     if (!isfinite(p->gamma_phi) || !isfinite(p->gamma_psi)) return false;
     if (p->no_advection != 0 && p->no_advection != 1) return false;
     if (p->collision != TLB_BGK && p->collision != TLB_MRT) return false;
+    // more than three components (Sec. II.E): D2Q9 only
+    if (p->ncomp != 0 && (p->ncomp < 3 || p->ncomp > TLB_MAX_COMP)) return false;
+    const int nc = ncomp_of(p);
+    if (nc > 3 && p->lattice != TLB_D2Q9) return false;
+    for (int m = 3; m < nc; ++m)
+        if (!(p->kappa_hi[m - 3] > 0.0) || !isfinite(p->kappa_hi[m - 3])) return false;
     if (p->collision == TLB_MRT) {
         if (!(p->tau_bulk > 0.5 && p->tau_ghost > 0.5)) return false;
         if (!isfinite(p->tau_bulk) || !isfinite(p->tau_ghost)) return false;
@@ -99,8 +111,8 @@ static bool params_valid(const tlb_params* p)
     // one species array must stay addressable by 32-bit byte offsets
     const int64_t esize = p->prec == TLB_F32 ? 4 : 8;
     if ((int64_t)Q * N * esize > (int64_t)0xFFFFFF00) return false;
-    // the D2Q9 kernels address the three species of a state through one descriptor
-    if (p->lattice == TLB_D2Q9 && (int64_t)3 * Q * N * esize > (int64_t)0xFFFFFF00) return false;
+    // the D2Q9 kernels address all population sets of a state through one descriptor
+    if (p->lattice == TLB_D2Q9 && (int64_t)nc * Q * N * esize > (int64_t)0xFFFFFF00) return false;
     return true;
 }
 
@@ -109,9 +121,10 @@ static Phys<T> make_phys(const tlb_params& p)
 {
     Phys<T> P;
     const double a2 = p.alpha * p.alpha;
-    for (int m = 0; m < 3; ++m) {
-        P.kappa[m] = T(p.kappa[m]);
-        P.a2kappa[m] = T(a2 * p.kappa[m]);
+    for (int m = 0; m < kMaxComp; ++m) {
+        const double k = m < ncomp_of(&p) ? kappa_of(p, m) : 0.0;
+        P.kappa[m] = T(k);
+        P.a2kappa[m] = T(a2 * k);
     }
     P.omega[0] = T(1.0 / p.tau_f);
     P.omega[1] = T(1.0 / p.tau_g);
@@ -137,6 +150,7 @@ static AuxGeom geom(const tlb_sim* s)
     g.nz = s->p.nz;
     g.walls = s->p.walls_y;
     g.N = s->N;
+    g.nc = s->nc;
     return g;
 }
 
@@ -204,6 +218,7 @@ static void default_launch(tlb_sim* s)
 static bool launch_valid(const tlb_sim* s, const tlb_launch* l)
 {
     if (l->chunk < 1 || (l->variant != 0 && l->variant != 1)) return false;
+    if (s->nc > 3 && l->variant != 0) return false;  // more than three components: no row prefetch
     if (s->p.lattice == TLB_D2Q9) return l->width == 64 || l->width == 128 || l->width == 256;
     const int w = l->width, h = l->height;
     if (w == 32 && h == 8) return true;
@@ -223,6 +238,7 @@ extern "C" tlb_status tlb_create(const tlb_params* params, void* stream, tlb_sim
     s->D = params->lattice == TLB_D2Q9 ? 2 : 3;
     s->N = (int64_t)params->nx * params->ny * params->nz;
     s->esize = params->prec == TLB_F32 ? 4 : 8;
+    s->nc = ncomp_of(params);
     hipError_t e = hipGetDevice(&s->dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&s->cus, hipDeviceAttributeMultiprocessorCount, s->dev);
     if (e != hipSuccess) {
@@ -240,7 +256,7 @@ extern "C" tlb_status tlb_create(const tlb_params* params, void* stream, tlb_sim
         }
         s->own_stream = true;
     }
-    const size_t bytes = (size_t)3 * s->Q * s->N * s->esize;
+    const size_t bytes = (size_t)s->nc * s->Q * s->N * s->esize;
     for (int b = 0; b < 2; ++b) {
         e = hipMalloc(&s->state[b], bytes);
         if (e != hipSuccess) {
@@ -249,12 +265,11 @@ extern "C" tlb_status tlb_create(const tlb_params* params, void* stream, tlb_sim
         }
     }
     if (params->walls_y) {
-        const size_t wb = (size_t)2 * 3 * params->nx * params->nz * s->esize;
-        e = hipMalloc(&s->wet, wb);
-        if (e == hipSuccess) e = hipMemsetAsync(s->wet, 0, wb, s->stream);
-        if (e == hipSuccess) e = hipMalloc((void**)&s->hbuf, (size_t)2 * 3 * params->nx * params->nz * sizeof(double));
-        if (e == hipSuccess)
-            e = hipMemsetAsync(s->hbuf, 0, (size_t)2 * 3 * params->nx * params->nz * sizeof(double), s->stream);
+        const size_t nh = (size_t)2 * s->nc * params->nx * params->nz;
+        e = hipMalloc(&s->wet, nh * s->esize);
+        if (e == hipSuccess) e = hipMemsetAsync(s->wet, 0, nh * s->esize, s->stream);
+        if (e == hipSuccess) e = hipMalloc((void**)&s->hbuf, nh * sizeof(double));
+        if (e == hipSuccess) e = hipMemsetAsync(s->hbuf, 0, nh * sizeof(double), s->stream);
         if (e != hipSuccess) {
             tlb_destroy(s);
             return hip_fail(e);
@@ -329,7 +344,7 @@ static tlb_status ensure_staging(tlb_sim* s, size_t elems)
 static tlb_status ensure_fields(tlb_sim* s)
 {
     if (s->fields) return TLB_OK;
-    HIPCHK(hipMalloc(&s->fields, (size_t)TLB_NFIELDS * s->N * s->esize));
+    HIPCHK(hipMalloc(&s->fields, (size_t)(s->nc + 8) * s->N * s->esize));
     return TLB_OK;
 }
 
@@ -340,13 +355,15 @@ static tlb_status rescale_wet(tlb_sim* s, int wall)
 {
     const int n = s->p.nx * s->p.nz;
     const double a2 = s->p.alpha * s->p.alpha;
-    const double i0 = 1.0 / (a2 * s->p.kappa[0]), i1 = 1.0 / (a2 * s->p.kappa[1]), i2 = 1.0 / (a2 * s->p.kappa[2]);
-    const double* h = s->hbuf + (size_t)wall * 3 * n;
+    WetScale inv = {};
+    for (int m = 0; m < s->nc; ++m) inv.v[m] = 1.0 / (a2 * kappa_of(s->p, m));
+    const size_t o = (size_t)wall * s->nc * n;
+    const double* h = s->hbuf + o;
     hipError_t e;
     if (s->p.prec == TLB_F32)
-        e = launch_wet<float, double>(n, h, i0, i1, i2, (float*)s->wet + (size_t)wall * 3 * n, s->stream);
+        e = launch_wet<float, double>(n, s->nc, h, inv, (float*)s->wet + o, s->stream);
     else
-        e = launch_wet<double, double>(n, h, i0, i1, i2, (double*)s->wet + (size_t)wall * 3 * n, s->stream);
+        e = launch_wet<double, double>(n, s->nc, h, inv, (double*)s->wet + o, s->stream);
     HIPCHK(e);
     return TLB_OK;
 }
@@ -355,14 +372,14 @@ template <typename TIn>
 static tlb_status set_wet_impl(tlb_sim* s, int wall, const TIn* h_dev)
 {
     const int n = s->p.nx * s->p.nz;
-    HIPCHK(launch_convert<TIn, double>(h_dev, s->hbuf + (size_t)wall * 3 * n, 3 * (int64_t)n, s->stream));
+    HIPCHK(launch_convert<TIn, double>(h_dev, s->hbuf + (size_t)wall * s->nc * n, (int64_t)s->nc * n, s->stream));
     return rescale_wet(s, wall);
 }
 
 extern "C" tlb_status tlb_set_wetting(tlb_sim* s, int wall, const double* h)
 {
     if (!s || !h || (wall != 0 && wall != 1) || !s->p.walls_y) return TLB_EINVAL;
-    const size_t n = (size_t)3 * s->p.nx * s->p.nz;
+    const size_t n = (size_t)s->nc * s->p.nx * s->p.nz;
     for (size_t j = 0; j < n; ++j)
         if (!isfinite(h[j])) return TLB_EINVAL;
     tlb_status st = ensure_staging(s, n);
@@ -397,7 +414,7 @@ static tlb_status init_impl(tlb_sim* s, const TIn* C, const TIn* u)
 extern "C" tlb_status tlb_init_equilibrium(tlb_sim* s, const double* C, const double* u)
 {
     if (!s || !C) return TLB_EINVAL;
-    const size_t nc = (size_t)3 * s->N, nu = u ? (size_t)s->D * s->N : 0;
+    const size_t nc = (size_t)s->nc * s->N, nu = u ? (size_t)s->D * s->N : 0;
     tlb_status st = ensure_staging(s, nc + nu);
     if (st) return st;
     HIPCHK(hipMemcpyAsync(s->staging, C, nc * sizeof(double), hipMemcpyHostToDevice, s->stream));
@@ -450,7 +467,8 @@ template <typename T>
 static hipError_t launch_one(const tlb_sim* s, const StepArgs<T>& a)
 {
     return (s->p.lattice == TLB_D2Q9)
-               ? launch_step2d<T>(a, s->launch.width, s->launch.variant, s->p.collision == TLB_MRT, s->stream)
+               ? launch_step2d<T>(a, s->launch.width, s->launch.variant, s->p.collision == TLB_MRT, s->nc,
+                                  s->stream)
                : launch_step3d<T>(a, s->launch.width, s->launch.height, s->launch.variant,
                                   s->p.collision == TLB_MRT, s->stream);
 }
@@ -543,7 +561,7 @@ extern "C" tlb_status tlb_device_copy(void* dst, const void* src, int64_t bytes,
 extern "C" double tlb_bytes_per_node(const tlb_sim* s)
 {
     if (!s) return 0.0;
-    return 2.0 * 3.0 * s->Q * (double)s->esize;
+    return 2.0 * s->nc * s->Q * (double)s->esize;
 }
 
 // ---------------------------------------------------------------------------
@@ -563,7 +581,7 @@ static tlb_status field_impl(tlb_sim* s, int which, TOut* out)
 
 extern "C" tlb_status tlb_get_field(tlb_sim* s, int which, double* out)
 {
-    if (!s || !out || which < 0 || which >= TLB_NFIELDS) return TLB_EINVAL;
+    if (!s || !out || field_row(s->nc, which) < 0) return TLB_EINVAL;
     if (!s->ready) return TLB_ESTATE;
     tlb_status st = ensure_staging(s, (size_t)s->N);
     if (st) return st;
@@ -577,7 +595,7 @@ extern "C" tlb_status tlb_get_field(tlb_sim* s, int which, double* out)
 
 extern "C" tlb_status tlb_get_field_dev(tlb_sim* s, int which, void* out)
 {
-    if (!s || !out || which < 0 || which >= TLB_NFIELDS) return TLB_EINVAL;
+    if (!s || !out || field_row(s->nc, which) < 0) return TLB_EINVAL;
     if (!s->ready) return TLB_ESTATE;
     if (s->p.prec == TLB_F32) return field_impl<float, float>(s, which, (float*)out);
     return field_impl<double, double>(s, which, (double*)out);
@@ -585,7 +603,7 @@ extern "C" tlb_status tlb_get_field_dev(tlb_sim* s, int which, void* out)
 
 extern "C" tlb_status tlb_get_populations(tlb_sim* s, int species, double* out)
 {
-    if (!s || !out || species < 0 || species > 2) return TLB_EINVAL;
+    if (!s || !out || species < 0 || species >= s->nc) return TLB_EINVAL;
     if (!s->ready) return TLB_ESTATE;
     const size_t n = (size_t)s->Q * s->N;
     tlb_status st = ensure_staging(s, n);
@@ -603,7 +621,7 @@ extern "C" tlb_status tlb_get_populations(tlb_sim* s, int species, double* out)
 
 extern "C" tlb_status tlb_get_populations_dev(tlb_sim* s, int species, void* out)
 {
-    if (!s || !out || species < 0 || species > 2) return TLB_EINVAL;
+    if (!s || !out || species < 0 || species >= s->nc) return TLB_EINVAL;
     if (!s->ready) return TLB_ESTATE;
     const AuxGeom g = geom(s);
     hipError_t e = (s->p.prec == TLB_F32)
@@ -616,7 +634,7 @@ extern "C" tlb_status tlb_get_populations_dev(tlb_sim* s, int species, void* out
 
 extern "C" tlb_status tlb_set_populations(tlb_sim* s, int species, const double* in)
 {
-    if (!s || !in || species < 0 || species > 2) return TLB_EINVAL;
+    if (!s || !in || species < 0 || species >= s->nc) return TLB_EINVAL;
     const size_t n = (size_t)s->Q * s->N;
     tlb_status st = ensure_staging(s, n);
     if (st) return st;
@@ -633,7 +651,7 @@ extern "C" tlb_status tlb_set_populations(tlb_sim* s, int species, const double*
 
 extern "C" tlb_status tlb_set_populations_dev(tlb_sim* s, int species, const void* in)
 {
-    if (!s || !in || species < 0 || species > 2) return TLB_EINVAL;
+    if (!s || !in || species < 0 || species >= s->nc) return TLB_EINVAL;
     const AuxGeom g = geom(s);
     hipError_t e = (s->p.prec == TLB_F32)
                        ? launch_set_pops<float, float>(g, (const float*)in, species, (float*)s->state[s->cur], s->stream)
@@ -663,6 +681,11 @@ extern "C" tlb_status tlb_diagnostics(tlb_sim* s, tlb_diag* out)
         out->momentum[m] = h[3 + m];
         out->interface[m] = h[8 + m];
     }
+    for (int l = 0; l < TLB_MAX_COMP - 3; ++l) {
+        const bool on = l < s->nc - 3;
+        out->mass_hi[l] = on ? h[11 + l] : 0.0;
+        out->interface_hi[l] = on ? h[11 + (s->nc - 3) + l] : 0.0;
+    }
     out->max_speed = h[6];
     out->nonfinite = (int64_t)h[7];
     out->step = s->step;
@@ -674,7 +697,7 @@ extern "C" tlb_status tlb_diagnostics(tlb_sim* s, tlb_diag* out)
 // ---------------------------------------------------------------------------
 extern "C" int64_t tlb_state_bytes(const tlb_sim* s)
 {
-    return s ? (int64_t)3 * s->Q * s->N * (int64_t)s->esize : 0;
+    return s ? (int64_t)s->nc * s->Q * s->N * (int64_t)s->esize : 0;
 }
 
 extern "C" tlb_status tlb_save_state(tlb_sim* s, void* dst, int64_t* step)
@@ -815,9 +838,9 @@ extern "C" tlb_status tlb_wetting_from_angles(const double* kappa, double alpha,
 extern "C" tlb_status tlb_set_kappa(tlb_sim* s, const double* kappa)
 {
     if (!s || !kappa) return TLB_EINVAL;
-    for (int m = 0; m < 3; ++m)
+    for (int m = 0; m < s->nc; ++m)
         if (!(kappa[m] > 0.0) || !isfinite(kappa[m])) return TLB_EINVAL;
-    for (int m = 0; m < 3; ++m) s->p.kappa[m] = kappa[m];
+    for (int m = 0; m < s->nc; ++m) (m < 3 ? s->p.kappa[m] : s->p.kappa_hi[m - 3]) = kappa[m];
     if (s->p.walls_y) {
         tlb_status st = rescale_wet(s, 0);
         if (!st) st = rescale_wet(s, 1);
@@ -919,7 +942,7 @@ static double* dh_target(tlb_sim* s, double* dh) { return dh ? dh : s->dhs; }
 extern "C" tlb_status tlb_adjoint_seed_dev(tlb_sim* s, const void* dLdC, void* lam)
 {
     if (!s || !lam) return TLB_EINVAL;
-    if (s->p.lattice != TLB_D2Q9 || s->p.collision != TLB_BGK) return TLB_EINVAL;
+    if (s->p.lattice != TLB_D2Q9 || s->p.collision != TLB_BGK || s->nc != 3) return TLB_EINVAL;
     const AuxGeom g = geom(s);
     hipError_t e = (s->p.prec == TLB_F32) ? launch_adjoint_seed<float>(g, (const float*)dLdC, (float*)lam, s->stream)
                                           : launch_adjoint_seed<double>(g, (const double*)dLdC, (double*)lam, s->stream);
@@ -931,7 +954,7 @@ extern "C" tlb_status tlb_adjoint_step_dev(tlb_sim* s, const void* state, const 
                                            double* dh, double* dkappa)
 {
     if (!s || !state || !lam_in || !lam_out || lam_in == lam_out) return TLB_EINVAL;
-    if (s->p.lattice != TLB_D2Q9 || s->p.collision != TLB_BGK) return TLB_EINVAL;
+    if (s->p.lattice != TLB_D2Q9 || s->p.collision != TLB_BGK || s->nc != 3) return TLB_EINVAL;
     tlb_status st = adj_alloc(s, 0);
     if (!st) st = kpart_clear(s);
     if (!st) st = adj_step_any(s, state, lam_in, lam_out, dh_target(s, dh));
@@ -979,7 +1002,7 @@ extern "C" tlb_status tlb_adjoint_backward(tlb_sim* s, int64_t nsteps, int64_t e
                                            const void* dLdC, double* dh, double* dkappa)
 {
     if (!s || !ckpt || nsteps < 1 || every < 1) return TLB_EINVAL;
-    if (s->p.lattice != TLB_D2Q9 || s->p.collision != TLB_BGK) return TLB_EINVAL;
+    if (s->p.lattice != TLB_D2Q9 || s->p.collision != TLB_BGK || s->nc != 3) return TLB_EINVAL;
     tlb_status st = adj_alloc(s, every);
     if (st) return st;
     const size_t sb = (size_t)tlb_state_bytes(s);

@@ -28,9 +28,9 @@ __device__ __forceinline__ int64_t node_id(const AuxGeom& g, int x, int y, int z
     return (int64_t)x + (int64_t)g.nx * ((int64_t)y + (int64_t)g.ny * z);
 }
 
-// Pull of s_t at node (x, y, z) (generic lattice).
-template <class L, typename T>
-__device__ void pull_node(const AuxGeom& g, const T* __restrict__ st, int x, int y, int z, T* f, T* gg, T* k)
+// Pull of s_t at node (x, y, z) (generic lattice): p[NC][Q].
+template <class L, int NC, typename T>
+__device__ void pull_node(const AuxGeom& g, const T* __restrict__ st, int x, int y, int z, T* p)
 {
     const int64_t n0 = node_id(g, x, y, z);
 #pragma unroll
@@ -42,9 +42,8 @@ __device__ void pull_node(const AuxGeom& g, const T* __restrict__ st, int x, int
         } else {
             off = (int64_t)i * g.N + node_id(g, wrapi(x - L::ex[i], g.nx), wrapi(ys, g.ny), wrapi(z - L::ez[i], g.nz));
         }
-        f[i] = st[off];
-        gg[i] = st[(int64_t)L::Q * g.N + off];
-        k[i] = st[(int64_t)2 * L::Q * g.N + off];
+#pragma unroll
+        for (int s = 0; s < NC; ++s) p[s * L::Q + i] = st[(int64_t)s * L::Q * g.N + off];
     }
 }
 
@@ -57,8 +56,8 @@ __device__ __forceinline__ int64_t unstream_off(const AuxGeom& g, int i, int x, 
     return (int64_t)i * g.N + node_id(g, wrapi(x - L::ex[i], g.nx), wrapi(ys, g.ny), wrapi(z - L::ez[i], g.nz));
 }
 
-// dC_m at a (possibly ghost) neighbour, read from a [3][N] array of
-// concentrations C (offset 1/3 removed) with the wetting ghost rule.
+// dC_m at a (possibly ghost) neighbour, read from an [nc][N] array of
+// concentrations C (offset removed) with the wetting ghost rule; wet is [2][nc][nx*nz].
 template <typename T, typename TIn, typename TW>
 __device__ __forceinline__ T conc_at(const AuxGeom& g, const TIn* C, T offset, const TW* wet, int m, int x, int y,
                                      int z)
@@ -68,10 +67,10 @@ __device__ __forceinline__ T conc_at(const AuxGeom& g, const TIn* C, T offset, c
     const int64_t nxz = (int64_t)g.nx * g.nz;
     if (g.walls) {
         if (y < 0)
-            return T(C[m * g.N + node_id(g, x, 0, z)]) - offset + T(wet[(0 * 3 + m) * nxz + x + (int64_t)g.nx * z]);
+            return T(C[m * g.N + node_id(g, x, 0, z)]) - offset + T(wet[(0 * g.nc + m) * nxz + x + (int64_t)g.nx * z]);
         if (y >= g.ny)
             return T(C[m * g.N + node_id(g, x, g.ny - 1, z)]) - offset +
-                   T(wet[(1 * 3 + m) * nxz + x + (int64_t)g.nx * z]);
+                   T(wet[(1 * g.nc + m) * nxz + x + (int64_t)g.nx * z]);
     } else {
         y = wrapi(y, g.ny);
     }
@@ -79,12 +78,12 @@ __device__ __forceinline__ T conc_at(const AuxGeom& g, const TIn* C, T offset, c
 }
 
 // Isotropic stencils d_a X = 3 sum_i w_i e_ia X(r+e_i), lap X = 6 sum_i w_i [X(r+e_i) - X(r)].
-template <class L, typename T, typename TIn, typename TW>
-__device__ void stencil_at(const AuxGeom& g, const TIn* C, T offset, const TW* wet, int x, int y, int z, T dc[3],
-                           T gC[3][3], T lC[3])
+template <class L, int NC, typename T, typename TIn, typename TW>
+__device__ void stencil_at(const AuxGeom& g, const TIn* C, T offset, const TW* wet, int x, int y, int z, T dc[NC],
+                           T gC[NC][3], T lC[NC])
 {
 #pragma unroll
-    for (int m = 0; m < 3; ++m) {
+    for (int m = 0; m < NC; ++m) {
         dc[m] = conc_at<T, TIn, TW>(g, C, offset, wet, m, x, y, z);
         T gx = 0, gy = 0, gz = 0, lp = 0;
 #pragma unroll
@@ -103,7 +102,7 @@ __device__ void stencil_at(const AuxGeom& g, const TIn* C, T offset, const TW* w
     }
 }
 
-template <class L, typename T, typename TIn>
+template <class L, int NC, typename T, typename TIn>
 __global__ void k_init(AuxGeom g, Phys<acc_t<T>> P, const TIn* __restrict__ C, const TIn* __restrict__ u,
                        const T* __restrict__ wet, T* __restrict__ st)
 {
@@ -112,30 +111,35 @@ __global__ void k_init(AuxGeom g, Phys<acc_t<T>> P, const TIn* __restrict__ C, c
     if (n >= g.N) return;
     int x, y, z;
     node_xyz(g, n, x, y, z);
-    A dc[3], gC[3][3], lC[3];
-    stencil_at<L, A, TIn, T>(g, C, A(1.0 / 3.0), wet, x, y, z, dc, gC, lC);
-    Moments<A> mo;
-    // rho = C1 + C2 + C3, phi = C1 - C2, psi = C3 (Sec. II.C), as deviations
-    mo.drho = dc[0] + dc[1] + dc[2];
+    A dc[NC], gC[NC][3], lC[NC];
+    stencil_at<L, NC, A, TIn, T>(g, C, A(psi_ref<NC>()), wet, x, y, z, dc, gC, lC);
+    Moments<A, NC> mo;
+    // rho = sum_m C_m, phi = C1 - C2, psi_l = C_l (Sec. II.C, II.E), as deviations
+    mo.drho = dc[0];
+#pragma unroll
+    for (int m = 1; m < NC; ++m) mo.drho += dc[m];
     mo.phi = dc[0] - dc[1];
     mo.dpsi = dc[2];
+#pragma unroll
+    for (int l = 0; l < NC - 3; ++l) mo.dpsx[l] = dc[3 + l];
     const A rho = A(1) + mo.drho;
     mo.jx = u ? rho * A(u[n]) : A(0);
     mo.jy = u ? rho * A(u[g.N + n]) : A(0);
     mo.jz = (u && L::D == 3) ? rho * A(u[2 * g.N + n]) : A(0);
-    T f[L::Q], gg[L::Q], k[L::Q];
-    equilibrium<L>(P, mo, dc, gC, lC, f, gg, k);
+    T p[NC * L::Q];
+    equilibrium<L, NC>(P, mo, dc, gC, lC, p, p + L::Q, p + 2 * L::Q);
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
         const int64_t off = unstream_off<L>(g, i, x, y, z);
-        st[off] = f[i];
-        st[(int64_t)L::Q * g.N + off] = gg[i];
-        st[(int64_t)2 * L::Q * g.N + off] = k[i];
+#pragma unroll
+        for (int s = 0; s < NC; ++s) st[(int64_t)s * L::Q * g.N + off] = p[s * L::Q + i];
     }
 }
 
-// Phase 1 of the readout: moments of s_t -> fields [0..8] (deviations).
-template <class L, typename T>
+// Field rows (deviations): dC_m in rows 0 .. NC-1, then drho, phi, dpsi_3, ux, uy, uz, mu_phi, mu_psi
+// (of psi_3).  For NC = 3 these are the TLB_FIELD_* selectors in order.
+// Phase 1 of the readout: moments of s_t -> every row but the chemical potentials.
+template <class L, int NC, typename T>
 __global__ void k_fields1(AuxGeom g, const T* __restrict__ st, T* __restrict__ F)
 {
     const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -143,25 +147,24 @@ __global__ void k_fields1(AuxGeom g, const T* __restrict__ st, T* __restrict__ F
     int x, y, z;
     node_xyz(g, n, x, y, z);
     using A = acc_t<T>;
-    T f[L::Q], gg[L::Q], k[L::Q];
-    pull_node<L, T>(g, st, x, y, z, f, gg, k);
-    const Moments<A> mo = moments<L, T>(f, gg, k);
-    A dc[3];
-    conc_dev<A>(mo, dc);
+    T p[NC * L::Q];
+    pull_node<L, NC, T>(g, st, x, y, z, p);
+    const Moments<A, NC> mo = moments<L, NC>(p, p + L::Q, p + 2 * L::Q);
+    A dc[NC];
+    conc_dev<A, NC>(mo, dc);
     const A irho = A(1) / (A(1) + mo.drho);
-    F[0 * g.N + n] = T(dc[0]);
-    F[1 * g.N + n] = T(dc[1]);
-    F[2 * g.N + n] = T(dc[2]);
-    F[3 * g.N + n] = T(mo.drho);
-    F[4 * g.N + n] = T(mo.phi);
-    F[5 * g.N + n] = T(mo.dpsi);
-    F[6 * g.N + n] = T(mo.jx * irho);
-    F[7 * g.N + n] = T(mo.jy * irho);
-    F[8 * g.N + n] = (L::D == 3) ? T(mo.jz * irho) : T(0);
+#pragma unroll
+    for (int m = 0; m < NC; ++m) F[m * g.N + n] = T(dc[m]);
+    F[(NC + 0) * g.N + n] = T(mo.drho);
+    F[(NC + 1) * g.N + n] = T(mo.phi);
+    F[(NC + 2) * g.N + n] = T(mo.dpsi);
+    F[(NC + 3) * g.N + n] = T(mo.jx * irho);
+    F[(NC + 4) * g.N + n] = T(mo.jy * irho);
+    F[(NC + 5) * g.N + n] = (L::D == 3) ? T(mo.jz * irho) : T(0);
 }
 
 // Phase 2: chemical potentials from the dC fields with the ghost rule.
-template <class L, typename T>
+template <class L, int NC, typename T>
 __global__ void k_fields2(AuxGeom g, Phys<acc_t<T>> P, const T* __restrict__ wet, T* __restrict__ F)
 {
     using A = acc_t<T>;
@@ -169,12 +172,12 @@ __global__ void k_fields2(AuxGeom g, Phys<acc_t<T>> P, const T* __restrict__ wet
     if (n >= g.N) return;
     int x, y, z;
     node_xyz(g, n, x, y, z);
-    A dc[3], gC[3][3], lC[3];
-    stencil_at<L, A, T, T>(g, F, A(0), wet, x, y, z, dc, gC, lC);
+    A dc[NC], gC[NC][3], lC[NC];
+    stencil_at<L, NC, A, T, T>(g, F, A(0), wet, x, y, z, dc, gC, lC);
     A mphi, mpsi;
-    chem_potentials<A>(P, dc, lC, mphi, mpsi);
-    F[9 * g.N + n] = T(mphi);
-    F[10 * g.N + n] = T(mpsi);
+    chem_potentials<A, NC>(P, dc, lC, mphi, mpsi);
+    F[(NC + 6) * g.N + n] = T(mphi);
+    F[(NC + 7) * g.N + n] = T(mpsi);
 }
 
 template <typename T, typename TOut>
@@ -184,21 +187,20 @@ __global__ void k_export(int64_t N, const T* __restrict__ src, T offset, TOut* _
     if (n < N) out[n] = TOut(src[n]) + TOut(offset);
 }
 
-template <class L, typename T, typename TOut>
+template <class L, int NC, typename T, typename TOut>
 __global__ void k_get_pops(AuxGeom g, const T* __restrict__ st, int s, TOut* __restrict__ out)
 {
     const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= g.N) return;
     int x, y, z;
     node_xyz(g, n, x, y, z);
-    T f[L::Q], gg[L::Q], k[L::Q];
-    pull_node<L, T>(g, st, x, y, z, f, gg, k);
-    const T* v = (s == 0) ? f : (s == 1) ? gg : k;
+    T p[NC * L::Q];
+    pull_node<L, NC, T>(g, st, x, y, z, p);
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i) out[(int64_t)i * g.N + n] = TOut(v[i]) + TOut(ref<L>(s, i));
+    for (int i = 0; i < L::Q; ++i) out[(int64_t)i * g.N + n] = TOut(p[s * L::Q + i]) + TOut(ref<L, NC>(s, i));
 }
 
-template <class L, typename T, typename TIn>
+template <class L, int NC, typename T, typename TIn>
 __global__ void k_set_pops(AuxGeom g, const TIn* __restrict__ in, int s, T* __restrict__ st)
 {
     const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -208,99 +210,127 @@ __global__ void k_set_pops(AuxGeom g, const TIn* __restrict__ in, int s, T* __re
     T* base = st + (int64_t)s * L::Q * g.N;
 #pragma unroll
     for (int i = 0; i < L::Q; ++i)
-        base[unstream_off<L>(g, i, x, y, z)] = T(in[(int64_t)i * g.N + n]) - T(ref<L>(s, i));
+        base[unstream_off<L>(g, i, x, y, z)] = T(in[(int64_t)i * g.N + n]) - T(ref<L, NC>(s, i));
 }
 
-// Block-level sums of mass, momentum, max |v| and the non-finite count, in
-// FP64, with a fixed assignment of nodes to blocks (deterministic).
-template <class L, typename T>
+// Diagnostic slots (diag_slots(NC) of them): mass of rho, phi, psi_3 (0-2), momentum (3-5), max |v|
+// (6, a maximum), the non-finite count (7), the interface sums of C1 .. C3 (8-10), then for NC > 3 the
+// masses of psi_4 .. psi_NC and the interface sums of C4 .. C_NC.
+//
+// Block-level sums in FP64 with a fixed assignment of nodes to blocks (deterministic).
+template <class L, int NC, typename T>
 __global__ __launch_bounds__(256) void k_diag1(AuxGeom g, const T* __restrict__ st, double* __restrict__ partial)
 {
-    __shared__ double red[kDiagSlots][256];
-    double acc[kDiagSlots] = {0, 0, 0, 0, 0, 0, 0, 0};
+    constexpr int S = diag_slots(NC);
+    __shared__ double red[S][256];
+    double acc[S];
+#pragma unroll
+    for (int q = 0; q < S; ++q) acc[q] = 0.0;
     for (int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x; n < g.N; n += (int64_t)gridDim.x * 256) {
         int x, y, z;
         node_xyz(g, n, x, y, z);
-        T f[L::Q], gg[L::Q], k[L::Q];
-        pull_node<L, T>(g, st, x, y, z, f, gg, k);
-        const auto mo = moments<L, T>(f, gg, k);
+        T p[NC * L::Q];
+        pull_node<L, NC, T>(g, st, x, y, z, p);
+        const auto mo = moments<L, NC>(p, p + L::Q, p + 2 * L::Q);
         const double rho = 1.0 + (double)mo.drho;
         const double jx = mo.jx, jy = mo.jy, jz = mo.jz;
-        const double phi = mo.phi, psi = kPsiRef + (double)mo.dpsi;
-        const bool finite = isfinite(rho) && isfinite(jx) && isfinite(jy) && isfinite(jz) && isfinite(phi) &&
-                            isfinite(psi);
+        double psi[NC - 2];
+        psi[0] = psi_ref<NC>() + (double)mo.dpsi;
+        bool finite = isfinite(rho) && isfinite(jx) && isfinite(jy) && isfinite(jz) && isfinite((double)mo.phi) &&
+                      isfinite(psi[0]);
+        double spsi = psi[0];
+#pragma unroll
+        for (int l = 1; l < NC - 2; ++l) {
+            psi[l] = psi_ref<NC>() + (double)mo.dpsx[l - 1];
+            finite = finite && isfinite(psi[l]);
+            spsi += psi[l];
+        }
+        const double phi = mo.phi;
         if (finite) {
             acc[0] += rho;
             acc[1] += phi;
-            acc[2] += psi;
+            acc[2] += psi[0];
             acc[3] += jx;
             acc[4] += jy;
             acc[5] += jz;
             const double sp = sqrt(jx * jx + jy * jy + jz * jz) / rho;
             acc[6] = fmax(acc[6], sp);
-            // interface measure: C_m^2 (1 - C_m)^2 with C1 = (rho + phi - psi)/2, C2 = (rho - phi - psi)/2, C3 = psi
-            const double c[3] = {0.5 * (rho + phi - psi), 0.5 * (rho - phi - psi), psi};
+            // interface measure: C_m^2 (1 - C_m)^2 with C1 = (rho + phi - sum psi)/2,
+            // C2 = (rho - phi - sum psi)/2, C_l = psi_l
+            double c[NC];
+            c[0] = 0.5 * (rho + phi - spsi);
+            c[1] = 0.5 * (rho - phi - spsi);
+#pragma unroll
+            for (int l = 0; l < NC - 2; ++l) c[2 + l] = psi[l];
 #pragma unroll
             for (int m = 0; m < 3; ++m) acc[8 + m] += c[m] * c[m] * (1.0 - c[m]) * (1.0 - c[m]);
+#pragma unroll
+            for (int l = 0; l < NC - 3; ++l) {
+                acc[11 + l] += psi[1 + l];
+                acc[11 + (NC - 3) + l] += c[3 + l] * c[3 + l] * (1.0 - c[3 + l]) * (1.0 - c[3 + l]);
+            }
         } else {
             acc[7] += 1.0;
         }
     }
 #pragma unroll
-    for (int s = 0; s < kDiagSlots; ++s) red[s][threadIdx.x] = acc[s];
+    for (int q = 0; q < S; ++q) red[q][threadIdx.x] = acc[q];
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
         if (threadIdx.x < w) {
 #pragma unroll
-            for (int s = 0; s < kDiagSlots; ++s) {
-                if (s == 6)
-                    red[s][threadIdx.x] = fmax(red[s][threadIdx.x], red[s][threadIdx.x + w]);
+            for (int q = 0; q < S; ++q) {
+                if (q == 6)
+                    red[q][threadIdx.x] = fmax(red[q][threadIdx.x], red[q][threadIdx.x + w]);
                 else
-                    red[s][threadIdx.x] += red[s][threadIdx.x + w];
+                    red[q][threadIdx.x] += red[q][threadIdx.x + w];
             }
         }
         __syncthreads();
     }
-    if (threadIdx.x < kDiagSlots) partial[(int64_t)blockIdx.x * kDiagSlots + threadIdx.x] = red[threadIdx.x][0];
+    if (threadIdx.x < S) partial[(int64_t)blockIdx.x * S + threadIdx.x] = red[threadIdx.x][0];
 }
 
+template <int S>
 __global__ __launch_bounds__(256) void k_diag2(const double* __restrict__ partial, int nblocks, double* __restrict__ out)
 {
-    __shared__ double red[kDiagSlots][256];
-    double acc[kDiagSlots] = {0, 0, 0, 0, 0, 0, 0, 0};
+    __shared__ double red[S][256];
+    double acc[S];
+#pragma unroll
+    for (int q = 0; q < S; ++q) acc[q] = 0.0;
     for (int b = threadIdx.x; b < nblocks; b += 256) {
 #pragma unroll
-        for (int s = 0; s < kDiagSlots; ++s) {
-            const double v = partial[(int64_t)b * kDiagSlots + s];
-            acc[s] = (s == 6) ? fmax(acc[s], v) : acc[s] + v;
+        for (int q = 0; q < S; ++q) {
+            const double v = partial[(int64_t)b * S + q];
+            acc[q] = (q == 6) ? fmax(acc[q], v) : acc[q] + v;
         }
     }
 #pragma unroll
-    for (int s = 0; s < kDiagSlots; ++s) red[s][threadIdx.x] = acc[s];
+    for (int q = 0; q < S; ++q) red[q][threadIdx.x] = acc[q];
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
         if (threadIdx.x < w) {
 #pragma unroll
-            for (int s = 0; s < kDiagSlots; ++s) {
-                if (s == 6)
-                    red[s][threadIdx.x] = fmax(red[s][threadIdx.x], red[s][threadIdx.x + w]);
+            for (int q = 0; q < S; ++q) {
+                if (q == 6)
+                    red[q][threadIdx.x] = fmax(red[q][threadIdx.x], red[q][threadIdx.x + w]);
                 else
-                    red[s][threadIdx.x] += red[s][threadIdx.x + w];
+                    red[q][threadIdx.x] += red[q][threadIdx.x + w];
             }
         }
         __syncthreads();
     }
-    if (threadIdx.x < kDiagSlots) out[threadIdx.x] = red[threadIdx.x][0];
+    if (threadIdx.x < S) out[threadIdx.x] = red[threadIdx.x][0];
 }
 
+// wet[m][j] = h[m][j] / (alpha^2 kappa_m) for the nc components of one wall.
 template <typename T, typename TIn>
-__global__ void k_wet(int n, const TIn* __restrict__ h, double i0, double i1, double i2, T* __restrict__ wet)
+__global__ void k_wet(int n, int nc, const TIn* __restrict__ h, WetScale inv, T* __restrict__ wet)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= 3 * n) return;
+    if (j >= nc * n) return;
     const int m = j / n;
-    const double inv = (m == 0) ? i0 : (m == 1) ? i1 : i2;
-    wet[j] = T((double)h[j] * inv);
+    wet[j] = T((double)h[j] * inv.v[m]);
 }
 
 inline dim3 grid_for(int64_t N, int bs) { return dim3((unsigned)((N + bs - 1) / bs)); }
@@ -339,14 +369,27 @@ hipError_t launch_copy16(const void* src, void* dst, int64_t n16, hipStream_t s)
     return hipGetLastError();
 }
 
+// Dispatch on the lattice and the number of components (3, 4 or 5; more than
+// three on D2Q9 only).
+#define TLB_AUX_DISPATCH(KERNEL, GRID, BLOCK, S, ...)                                                       \
+    do {                                                                                                  \
+        if (g.lattice == 1)                                                                               \
+            hipLaunchKernelGGL((KERNEL<D3Q19, 3, __VA_ARGS__>), GRID, BLOCK, 0, S, ARGS);                  \
+        else if (g.nc == 3)                                                                               \
+            hipLaunchKernelGGL((KERNEL<D2Q9, 3, __VA_ARGS__>), GRID, BLOCK, 0, S, ARGS);                   \
+        else if (g.nc == 4)                                                                               \
+            hipLaunchKernelGGL((KERNEL<D2Q9, 4, __VA_ARGS__>), GRID, BLOCK, 0, S, ARGS);                   \
+        else                                                                                              \
+            hipLaunchKernelGGL((KERNEL<D2Q9, 5, __VA_ARGS__>), GRID, BLOCK, 0, S, ARGS);                   \
+    } while (0)
+
 template <typename T, typename TIn>
 hipError_t launch_init(const AuxGeom& g, const Phys<acc_t<T>>& P, const TIn* C, const TIn* u, const T* wet, T* state,
                        hipStream_t s)
 {
-    if (g.lattice == 0)
-        hipLaunchKernelGGL((k_init<D2Q9, T, TIn>), grid_for(g.N, 256), dim3(256), 0, s, g, P, C, u, wet, state);
-    else
-        hipLaunchKernelGGL((k_init<D3Q19, T, TIn>), grid_for(g.N, 256), dim3(256), 0, s, g, P, C, u, wet, state);
+#define ARGS g, P, C, u, wet, state
+    TLB_AUX_DISPATCH(k_init, grid_for(g.N, 256), dim3(256), s, T, TIn);
+#undef ARGS
     return hipGetLastError();
 }
 
@@ -354,24 +397,33 @@ template <typename T>
 hipError_t launch_fields(const AuxGeom& g, const Phys<acc_t<T>>& P, const T* state, const T* wet, T* F,
                          hipStream_t s)
 {
-    if (g.lattice == 0) {
-        hipLaunchKernelGGL((k_fields1<D2Q9, T>), grid_for(g.N, 256), dim3(256), 0, s, g, state, F);
-        hipLaunchKernelGGL((k_fields2<D2Q9, T>), grid_for(g.N, 256), dim3(256), 0, s, g, P, wet, F);
-    } else {
-        hipLaunchKernelGGL((k_fields1<D3Q19, T>), grid_for(g.N, 256), dim3(256), 0, s, g, state, F);
-        hipLaunchKernelGGL((k_fields2<D3Q19, T>), grid_for(g.N, 256), dim3(256), 0, s, g, P, wet, F);
-    }
+#define ARGS g, state, F
+    TLB_AUX_DISPATCH(k_fields1, grid_for(g.N, 256), dim3(256), s, T);
+#undef ARGS
+#define ARGS g, P, wet, F
+    TLB_AUX_DISPATCH(k_fields2, grid_for(g.N, 256), dim3(256), s, T);
+#undef ARGS
     return hipGetLastError();
+}
+
+int field_row(int nc, int which)
+{
+    if (which >= 0 && which <= 2) return which;        // C1 .. C3
+    if (which >= 3 && which <= 10) return nc + which - 3;  // rho .. mu_psi
+    if (which >= 11 && which < 11 + nc - 3) return which - 8;  // C4 .. C_nc
+    return -1;
 }
 
 template <typename T, typename TOut>
 hipError_t launch_export_field(const AuxGeom& g, const T* F, int which, TOut* out, hipStream_t s)
 {
-    // offsets of the stored deviations: C_m, psi: 1/3; rho: 1
+    const int row = field_row(g.nc, which);
+    if (row < 0) return hipErrorInvalidValue;
+    // offsets of the stored deviations: C_m and psi_3: 1/nc; rho: 1
     T off = 0;
-    if (which <= 2 || which == 5) off = T(1.0 / 3.0);
+    if (row < g.nc || which == 5) off = T(1.0 / g.nc);
     if (which == 3) off = T(1);
-    hipLaunchKernelGGL((k_export<T, TOut>), grid_for(g.N, 256), dim3(256), 0, s, g.N, F + (int64_t)which * g.N, off,
+    hipLaunchKernelGGL((k_export<T, TOut>), grid_for(g.N, 256), dim3(256), 0, s, g.N, F + (int64_t)row * g.N, off,
                        out);
     return hipGetLastError();
 }
@@ -379,38 +431,41 @@ hipError_t launch_export_field(const AuxGeom& g, const T* F, int which, TOut* ou
 template <typename T, typename TOut>
 hipError_t launch_get_pops(const AuxGeom& g, const T* state, int species, TOut* out, hipStream_t s)
 {
-    if (g.lattice == 0)
-        hipLaunchKernelGGL((k_get_pops<D2Q9, T, TOut>), grid_for(g.N, 256), dim3(256), 0, s, g, state, species, out);
-    else
-        hipLaunchKernelGGL((k_get_pops<D3Q19, T, TOut>), grid_for(g.N, 256), dim3(256), 0, s, g, state, species, out);
+#define ARGS g, state, species, out
+    TLB_AUX_DISPATCH(k_get_pops, grid_for(g.N, 256), dim3(256), s, T, TOut);
+#undef ARGS
     return hipGetLastError();
 }
 
 template <typename T, typename TIn>
 hipError_t launch_set_pops(const AuxGeom& g, const TIn* in, int species, T* state, hipStream_t s)
 {
-    if (g.lattice == 0)
-        hipLaunchKernelGGL((k_set_pops<D2Q9, T, TIn>), grid_for(g.N, 256), dim3(256), 0, s, g, in, species, state);
-    else
-        hipLaunchKernelGGL((k_set_pops<D3Q19, T, TIn>), grid_for(g.N, 256), dim3(256), 0, s, g, in, species, state);
+#define ARGS g, in, species, state
+    TLB_AUX_DISPATCH(k_set_pops, grid_for(g.N, 256), dim3(256), s, T, TIn);
+#undef ARGS
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_diag(const AuxGeom& g, const T* state, double* partial, int nblocks, double* out, hipStream_t s)
 {
-    if (g.lattice == 0)
-        hipLaunchKernelGGL((k_diag1<D2Q9, T>), dim3(nblocks), dim3(256), 0, s, g, state, partial);
+#define ARGS g, state, partial
+    TLB_AUX_DISPATCH(k_diag1, dim3(nblocks), dim3(256), s, T);
+#undef ARGS
+    if (g.nc == 3)
+        hipLaunchKernelGGL(k_diag2<diag_slots(3)>, dim3(1), dim3(256), 0, s, partial, nblocks, out);
+    else if (g.nc == 4)
+        hipLaunchKernelGGL(k_diag2<diag_slots(4)>, dim3(1), dim3(256), 0, s, partial, nblocks, out);
     else
-        hipLaunchKernelGGL((k_diag1<D3Q19, T>), dim3(nblocks), dim3(256), 0, s, g, state, partial);
-    hipLaunchKernelGGL(k_diag2, dim3(1), dim3(256), 0, s, partial, nblocks, out);
+        hipLaunchKernelGGL(k_diag2<diag_slots(5)>, dim3(1), dim3(256), 0, s, partial, nblocks, out);
     return hipGetLastError();
 }
+#undef TLB_AUX_DISPATCH
 
 template <typename T, typename TIn>
-hipError_t launch_wet(int n, const TIn* h, double i0, double i1, double i2, T* wet, hipStream_t s)
+hipError_t launch_wet(int n, int nc, const TIn* h, const WetScale& inv, T* wet, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_wet<T, TIn>), grid_for(3 * (int64_t)n, 256), dim3(256), 0, s, n, h, i0, i1, i2, wet);
+    hipLaunchKernelGGL((k_wet<T, TIn>), grid_for((int64_t)nc * n, 256), dim3(256), 0, s, n, nc, h, inv, wet);
     return hipGetLastError();
 }
 
@@ -420,7 +475,7 @@ hipError_t launch_wet(int n, const TIn* h, double i0, double i1, double i2, T* w
     template hipError_t launch_export_field<T, TIO>(const AuxGeom&, const T*, int, TIO*, hipStream_t);            \
     template hipError_t launch_get_pops<T, TIO>(const AuxGeom&, const T*, int, TIO*, hipStream_t);                \
     template hipError_t launch_set_pops<T, TIO>(const AuxGeom&, const TIO*, int, T*, hipStream_t);                \
-    template hipError_t launch_wet<T, TIO>(int, const TIO*, double, double, double, T*, hipStream_t);
+    template hipError_t launch_wet<T, TIO>(int, int, const TIO*, const WetScale&, T*, hipStream_t);
 
 #define TLB_INST(T)                                                                                           \
     template hipError_t launch_fields<T>(const AuxGeom&, const Phys<acc_t<T>>&, const T*, const T*, T*,       \

@@ -294,6 +294,7 @@ extern "C" tlb_status tlb_batch_create(const tlb_params* per_dom, int32_t ndom, 
         if (!isfinite(p.gamma_phi) || !isfinite(p.gamma_psi)) return TLB_EINVAL;
         if (p.no_advection != 0 && p.no_advection != 1) return TLB_EINVAL;
         if (p.collision != TLB_BGK) return TLB_EINVAL;  // the batched step collides with BGK
+        if (p.ncomp != 0 && p.ncomp != 3) return TLB_EINVAL;  // and holds three components
         if (prec != TLB_F32 && prec != TLB_F64) return TLB_EINVAL;
         const int64_t bytes = (int64_t)27 * p.nx * p.ny * (prec == TLB_F32 ? 4 : 8);
         if (bytes > (int64_t)0xFFFFFF00) return TLB_EINVAL;
@@ -393,12 +394,11 @@ extern "C" tlb_status tlb_batch_set_wetting(tlb_batch* b, int32_t dom, int wall,
     BHIP(hipMemcpyAsync(b->staging, h, sizeof(double) * 3 * p.nx, hipMemcpyHostToDevice, b->stream));
     const double a2 = p.alpha * p.alpha;
     const int64_t o = b->wet_off[dom] + (int64_t)wall * 3 * p.nx;
+    const WetScale inv = {{1.0 / (a2 * p.kappa[0]), 1.0 / (a2 * p.kappa[1]), 1.0 / (a2 * p.kappa[2])}};
     if (b->prec == TLB_F32)
-        BHIP(launch_wet<float, double>(p.nx, b->staging, 1.0 / (a2 * p.kappa[0]), 1.0 / (a2 * p.kappa[1]),
-                                       1.0 / (a2 * p.kappa[2]), (float*)b->wet + o, b->stream));
+        BHIP(launch_wet<float, double>(p.nx, 3, b->staging, inv, (float*)b->wet + o, b->stream));
     else
-        BHIP(launch_wet<double, double>(p.nx, b->staging, 1.0 / (a2 * p.kappa[0]), 1.0 / (a2 * p.kappa[1]),
-                                        1.0 / (a2 * p.kappa[2]), (double*)b->wet + o, b->stream));
+        BHIP(launch_wet<double, double>(p.nx, 3, b->staging, inv, (double*)b->wet + o, b->stream));
     BHIP(hipStreamSynchronize(b->stream));
     return TLB_OK;
 }

@@ -4,7 +4,12 @@
 //
 // Storage shift.  Populations are kept in HBM as deviations from a constant,
 // direction-symmetric reference r_{s,i}: f: w_i (the rest equilibrium at
-// rho = 1, v = 0); g: 0; k: psi_ref at i = 0, 0 otherwise (psi_ref = 1/3).
+// rho = 1, v = 0); g: 0; each k: psi_ref at i = 0, 0 otherwise (psi_ref =
+// 1/NC for NC components, the state with every C_m = 1/NC).
+//
+// Components (Sec. II.E): NC = 3 is the ternary model; for NC > 3 the
+// variables are rho = sum_m C_m, phi = C1 - C2 and psi_l = C_l (l >= 3), with
+// one k population set per psi_l stored after f and g.
 // Propagation and half-way bounce-back map a uniform, direction-symmetric
 // field onto itself, and collision is affine, so the deviations obey the same
 // update; keeping O(1) constants out of the stored values keeps FP32 rounding
@@ -17,7 +22,14 @@
 
 namespace tlb {
 
-constexpr double kPsiRef = 1.0 / 3.0;
+constexpr double kPsiRef = 1.0 / 3.0;  // psi_ref of the ternary model
+constexpr int kMaxComp = 5;            // largest number of components the kernels are built for
+
+template <int NC>
+__host__ __device__ constexpr double psi_ref()
+{
+    return 1.0 / NC;
+}
 
 // ---------------------------------------------------------------------------
 // Lattices (velocity order documented in include/tlb.h).
@@ -120,10 +132,10 @@ __host__ __device__ constexpr double mrt_stress_norm(int k)
 }
 
 // Storage reference r_{s,i} (see the header comment).
-template <class L>
+template <class L, int NC = 3>
 __host__ __device__ constexpr double ref(int s, int i)
 {
-    return s == 0 ? weight<L>(i) : (s == 2 && i == 0 ? kPsiRef : 0.0);
+    return s == 0 ? weight<L>(i) : (s >= 2 && i == 0 ? psi_ref<NC>() : 0.0);
 }
 
 // ---------------------------------------------------------------------------
@@ -173,8 +185,8 @@ __device__ __forceinline__ void bstore<double>(double v, Rsrc r, uint32_t voff, 
 // ---------------------------------------------------------------------------
 template <typename T>
 struct Phys {
-    T kappa[3];
-    T a2kappa[3];  // alpha^2 kappa_m
+    T kappa[kMaxComp];
+    T a2kappa[kMaxComp];  // alpha^2 kappa_m
     T omega[3];    // 1/tau for f, g, k
     T gphi3, gpsi3;  // Gamma_phi / c_s^2, Gamma_psi / c_s^2
     T adv;           // 1: g^eq, k^eq carry the velocity terms; 0: diffusive Cahn-Hilliard
@@ -196,20 +208,24 @@ template <typename T>
 using acc_t = typename Acc<T>::type;
 
 // Moments of one node from its (shifted) populations.
-template <typename T>
+template <typename T, int NC = 3>
 struct Moments {
     T drho;   // rho - 1
     T jx, jy, jz;
     T phi;
-    T dpsi;   // psi - psi_ref
+    T dpsi;   // psi_3 - psi_ref
+    T dpsx[NC > 3 ? NC - 3 : 1];  // psi_l - psi_ref for l = 4 .. NC
 };
 
-template <class L, typename T>
-__device__ __forceinline__ Moments<acc_t<T>> moments(const T* f, const T* g, const T* k)
+// k points to the NC - 2 k population sets, Q values apart.
+template <class L, int NC = 3, typename T>
+__device__ __forceinline__ Moments<acc_t<T>, NC> moments(const T* f, const T* g, const T* k)
 {
     using C = acc_t<T>;
-    Moments<C> m;
-    C r = 0, jx = 0, jy = 0, jz = 0, ph = 0, ps = 0;
+    Moments<C, NC> m;
+    C r = 0, jx = 0, jy = 0, jz = 0, ph = 0, ps[NC - 2];
+#pragma unroll
+    for (int l = 0; l < NC - 2; ++l) ps[l] = 0;
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
         const C fi = C(f[i]);
@@ -221,37 +237,45 @@ __device__ __forceinline__ Moments<acc_t<T>> moments(const T* f, const T* g, con
         if (L::ez[i] == 1) jz += fi;
         if (L::ez[i] == -1) jz -= fi;
         ph += C(g[i]);
-        ps += C(k[i]);
+#pragma unroll
+        for (int l = 0; l < NC - 2; ++l) ps[l] += C(k[l * L::Q + i]);
     }
     m.drho = r;
     m.jx = jx;
     m.jy = jy;
     m.jz = jz;
     m.phi = ph;
-    m.dpsi = ps;
+    m.dpsi = ps[0];
+#pragma unroll
+    for (int l = 1; l < NC - 2; ++l) m.dpsx[l - 1] = ps[l];
     return m;
 }
 
-// Concentration deviations dC_m = C_m - 1/3 from the moments:
-// C1 = (rho + phi - psi)/2, C2 = (rho - phi - psi)/2, C3 = psi (Sec. II.C),
-// with rho = 1 + drho and psi = 1/3 + dpsi.
-template <typename T>
-__device__ __forceinline__ void conc_dev(const Moments<T>& m, T dc[3])
+// Concentration deviations dC_m = C_m - 1/NC from the moments:
+// C1 = (rho + phi - sum psi)/2, C2 = (rho - phi - sum psi)/2, C_l = psi_l
+// (Sec. II.C, II.E), with rho = 1 + drho and psi_l = 1/NC + dpsi_l.
+template <typename T, int NC = 3>
+__device__ __forceinline__ void conc_dev(const Moments<T, NC>& m, T dc[NC])
 {
-    dc[0] = T(0.5) * (m.drho + m.phi - m.dpsi);
-    dc[1] = T(0.5) * (m.drho - m.phi - m.dpsi);
+    T sp = m.dpsi;
+#pragma unroll
+    for (int l = 0; l < NC - 3; ++l) sp += m.dpsx[l];
+    dc[0] = T(0.5) * (m.drho + m.phi - sp);
+    dc[1] = T(0.5) * (m.drho - m.phi - sp);
     dc[2] = m.dpsi;
+#pragma unroll
+    for (int l = 0; l < NC - 3; ++l) dc[3 + l] = m.dpsx[l];
 }
 
-// Chemical potentials mu_phi, mu_psi of Sec. III from dC_m and lap C_m.
-template <typename T>
-__device__ __forceinline__ void chem_potentials(const Phys<T>& P, const T dc[3], const T lC[3], T& mu_phi,
+// Chemical potentials mu_phi, mu_psi (of psi_3) of Sec. III from dC_m and lap C_m.
+template <typename T, int NC = 3>
+__device__ __forceinline__ void chem_potentials(const Phys<T>& P, const T dc[NC], const T lC[NC], T& mu_phi,
                                                 T& mu_psi)
 {
     T mu[3];
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
-        const T c = T(1.0 / 3.0) + dc[m];
+        const T c = T(psi_ref<NC>()) + dc[m];
         mu[m] = P.kappa[m] * c * (T(1) - c) * (T(1) - T(2) * c) - P.a2kappa[m] * lC[m];
     }
     mu_phi = T(0.5) * (mu[0] - mu[1]);
@@ -270,20 +294,23 @@ __device__ __forceinline__ void chem_potentials(const Phys<T>& P, const T dc[3],
 //   g_i^eq = w_i [ Gamma_phi mu_phi / c_s^2 + phi U_i ],  k_i^eq likewise (eq. eqdistfbinary)
 //   U_i    = e_i.v / c_s^2 + (e_i.v)^2 / (2 c_s^4) - v^2 / (2 c_s^2)
 //   rest populations from the mass constraints; BGK with 1/tau per species.
-template <class L, bool MRT = false, typename T, typename S>
-__device__ __forceinline__ void collide(const Phys<T>& P, const Moments<T>& mo, const T dc[3],
-                                        const T gC[3][3], const T lC[3], S* f, S* g, S* k)
+template <class L, bool MRT = false, int NC = 3, typename T, typename S>
+__device__ __forceinline__ void collide(const Phys<T>& P, const Moments<T, NC>& mo, const T dc[NC],
+                                        const T gC[NC][3], const T lC[NC], S* f, S* g, S* k)
 {
     // T: arithmetic type; S: storage type of the populations (rounded once, on the update).
     // MRT: f relaxes with multiple relaxation times (g and k always with BGK).
+    // k: the NC - 2 k population sets, Q values apart; k_l relaxes with the k rate and
+    // mu_psi_l = mu_l - (mu_1 + mu_2)/2 (Sec. II.E).
     const T third = T(1.0 / 3.0);
-    T mu[3];
+    const T cref = T(psi_ref<NC>());
+    T mu[NC];
     T pbx = mo.drho * third;  // p_b - 1/3 (the 1/3 is the reference pressure of the shifted f)
     T lam = 0;
     T Txx = 0, Tyy = 0, Tzz = 0, Txy = 0, Tyz = 0, Tzx = 0;
 #pragma unroll
-    for (int m = 0; m < 3; ++m) {
-        const T c = third + dc[m];
+    for (int m = 0; m < NC; ++m) {
+        const T c = cref + dc[m];
         const T omc = T(1) - c;
         mu[m] = P.kappa[m] * c * omc * (T(1) - T(2) * c) - P.a2kappa[m] * lC[m];
         pbx += T(0.5) * P.kappa[m] * c * c * omc * (T(1) - T(3) * c);
@@ -299,22 +326,28 @@ __device__ __forceinline__ void collide(const Phys<T>& P, const Moments<T>& mo, 
         }
     }
     const T mu_phi = T(0.5) * (mu[0] - mu[1]);
-    const T mu_psi = mu[2] - T(0.5) * (mu[0] + mu[1]);
+    constexpr int NK = NC - 2;
+    T Bk[NK], psi[NK];
+#pragma unroll
+    for (int l = 0; l < NK; ++l) {
+        Bk[l] = P.gpsi3 * (mu[2 + l] - T(0.5) * (mu[0] + mu[1]));
+        psi[l] = cref + (l == 0 ? mo.dpsi : mo.dpsx[l > 0 ? l - 1 : 0]);
+    }
 
     const T rho = T(1) + mo.drho;
     const T irho = T(1) / rho;
     const T vx = mo.jx * irho, vy = mo.jy * irho, vz = (L::D == 3) ? mo.jz * irho : T(0);
-    const T psi = T(kPsiRef) + mo.dpsi;
     const T vv = vx * vx + vy * vy + vz * vz;
 
     const T A = T(3) * (pbx - lam);
     const T Bp = P.gphi3 * mu_phi;
-    const T Bk = P.gpsi3 * mu_psi;
     const T wf = P.omega[0], wg = P.omega[1], wk = P.omega[2];
 
     // i > 0: equilibrium and relaxation in place; the rest population last,
     // from the mass constraints.
-    T sf = 0, sg = 0, sk = 0;
+    T sf = 0, sg = 0, sk[NK];
+#pragma unroll
+    for (int l = 0; l < NK; ++l) sk[l] = 0;
     constexpr int NS = mrt_nstress<L>();
     T dq[MRT ? L::Q : 1];         // MRT: f_i - f_i^eq
     T me = 0, ms[MRT ? NS : 1];   // MRT: energy and stress moments of f - f^eq
@@ -333,13 +366,18 @@ __device__ __forceinline__ void collide(const Phys<T>& P, const Moments<T>& mo, 
             G += T(3 * wdiag<L>(i, 2)) * Tzz + T(3 * woff<L>(i, 1, 2)) * Tyz +
                  T(3 * woff<L>(i, 2, 0)) * Tzx;
         const T feq = w * (A + rho * U) + G;
-        const T Ua = P.adv * U;
+        const T Ua = P.adv * U;  // velocity terms of g^eq, k^eq (absent without advection)
         const T geq = w * (Bp + mo.phi * Ua);
-        const T keq = w * (Bk + psi * Ua);
         sf += feq;
         sg += geq;
-        sk += keq;
-        const T fi = T(f[i]), gi = T(g[i]), ki = T(k[i]);
+#pragma unroll
+        for (int l = 0; l < NK; ++l) {
+            const T keq = w * (Bk[l] + psi[l] * Ua);
+            sk[l] += keq;
+            const T ki = T(k[l * L::Q + i]);
+            k[l * L::Q + i] = S(ki + wk * (keq - ki));
+        }
+        const T fi = T(f[i]), gi = T(g[i]);
         if constexpr (MRT) {
             const T di = fi - feq;
             dq[i] = di;
@@ -350,9 +388,8 @@ __device__ __forceinline__ void collide(const Phys<T>& P, const Moments<T>& mo, 
             f[i] = S(fi + wf * (feq - fi));
         }
         g[i] = S(gi + wg * (geq - gi));
-        k[i] = S(ki + wk * (keq - ki));
     }
-    const T f0 = T(f[0]), g0 = T(g[0]), k0 = T(k[0]);
+    const T f0 = T(f[0]), g0 = T(g[0]);
     if constexpr (MRT) {
         // the rest population has no stress moment; it enters the energy moment
         dq[0] = f0 - (mo.drho - sf);
@@ -372,19 +409,26 @@ __device__ __forceinline__ void collide(const Phys<T>& P, const Moments<T>& mo, 
         f[0] = S(f0 + wf * ((mo.drho - sf) - f0));
     }
     g[0] = S(g0 + wg * ((mo.phi - sg) - g0));
-    k[0] = S(k0 + wk * ((mo.dpsi - sk) - k0));
+#pragma unroll
+    for (int l = 0; l < NK; ++l) {
+        const T k0 = T(k[l * L::Q]);
+        const T dps = l == 0 ? mo.dpsi : mo.dpsx[l > 0 ? l - 1 : 0];
+        k[l * L::Q] = S(k0 + wk * ((dps - sk[l]) - k0));
+    }
 }
 
 // Equilibrium populations (shifted) of given fields; used by initialisation.
-template <class L, typename T, typename S>
-__device__ __forceinline__ void equilibrium(const Phys<T>& P, const Moments<T>& mo, const T dc[3],
-                                            const T gC[3][3], const T lC[3], S* f, S* g, S* k)
+template <class L, int NC = 3, typename T, typename S>
+__device__ __forceinline__ void equilibrium(const Phys<T>& P, const Moments<T, NC>& mo, const T dc[NC],
+                                            const T gC[NC][3], const T lC[NC], S* f, S* g, S* k)
 {
     Phys<T> Q = P;
     Q.omega[0] = Q.omega[1] = Q.omega[2] = T(1);
 #pragma unroll
-    for (int i = 0; i < L::Q; ++i) f[i] = g[i] = k[i] = S(0);
-    collide<L>(Q, mo, dc, gC, lC, f, g, k);
+    for (int i = 0; i < L::Q; ++i) f[i] = g[i] = S(0);
+#pragma unroll
+    for (int i = 0; i < (NC - 2) * L::Q; ++i) k[i] = S(0);
+    collide<L, false, NC>(Q, mo, dc, gC, lC, f, g, k);
 }
 
 }  // namespace tlb

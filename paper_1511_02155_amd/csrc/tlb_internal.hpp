@@ -35,7 +35,7 @@ __device__ __forceinline__ int xcd_item(int b, int G)
 }
 
 template <typename T>
-hipError_t launch_step2d(const StepArgs<T>& a, int width, int hold, bool mrt, hipStream_t s);
+hipError_t launch_step2d(const StepArgs<T>& a, int width, int hold, bool mrt, int nc, hipStream_t s);
 template <typename T>
 hipError_t launch_step3d(const StepArgs<T>& a, int width, int height, int hold, bool mrt, hipStream_t s);
 
@@ -44,7 +44,18 @@ struct AuxGeom {
     int lattice;  // 0 D2Q9, 1 D3Q19
     int nx, ny, nz, walls;
     int64_t N;
+    int nc = 3;   // components (3 .. kMaxComp; more than 3 on D2Q9 only)
 };
+
+// 1 / (alpha^2 kappa_m) per component, for the wetting ghost offsets.
+struct WetScale {
+    double v[kMaxComp];
+};
+
+// Row of a TLB_FIELD_* selector in the field buffer ([nc + 8][N]), or -1.
+int field_row(int nc, int which);
+// Slots of the conservation check for nc components (see k_diag1).
+constexpr int diag_slots(int nc) { return 2 * nc + 5; }
 
 template <typename T, typename TIn>
 hipError_t launch_init(const AuxGeom& g, const Phys<acc_t<T>>& P, const TIn* C, const TIn* u, const T* wet,
@@ -62,8 +73,7 @@ template <typename T>
 hipError_t launch_diag(const AuxGeom& g, const T* state, double* partial, int nblocks, double* out,
                        hipStream_t s);
 template <typename T, typename TIn>
-hipError_t launch_wet(int n, const TIn* h, double inv_a2k0, double inv_a2k1, double inv_a2k2, T* wet,
-                      hipStream_t s);
+hipError_t launch_wet(int n, int nc, const TIn* h, const WetScale& inv, T* wet, hipStream_t s);
 
 hipError_t launch_copy16(const void* src, void* dst, int64_t n16, hipStream_t s);
 
@@ -93,6 +103,6 @@ template <typename TIn, typename TOut>
 hipError_t launch_convert(const TIn* in, TOut* out, int64_t n, hipStream_t s);
 
 constexpr int kDiagBlocks = 1024;
-constexpr int kDiagSlots = 11;  // mass[3], momentum[3], max|v|, nonfinite, interface[3]
+constexpr int kDiagSlots = diag_slots(kMaxComp);  // the most slots any component count uses
 
 }  // namespace tlb

@@ -4,43 +4,42 @@
 
 namespace tlb {
 
-template <typename T, int W, int DEPTH, bool MRT>
-__global__ __launch_bounds__(W) __attribute__((amdgpu_waves_per_eu(step2d_waves<T, DEPTH>())))
+template <typename T, int W, int DEPTH, bool MRT, int NC>
+__global__ __launch_bounds__(W) __attribute__((amdgpu_waves_per_eu(step2d_waves<T, DEPTH>(NC))))
 void k_step2d(StepArgs<T> A)
 {
-    __shared__ Sweep2Lds<T, W> S;
+    __shared__ Sweep2Lds<T, W, NC> S;
     const int item = xcd_item(blockIdx.x, A.nitems);
     const int chunk = item / A.ntx;  // chunk-major: an XCD's range covers whole bands
     const int strip = item - chunk * A.ntx;
-    sweep2d<T, W, DEPTH, MRT>(A, strip, chunk, S);
+    sweep2d<T, W, DEPTH, MRT, NC>(A, strip, chunk, S);
 }
 
+// Instantiated: three components with both depths, four and five (Sec. II.E) with depth 0.
 template <typename T>
-hipError_t launch_step2d(const StepArgs<T>& a, int width, int depth, bool mrt, hipStream_t s)
+hipError_t launch_step2d(const StepArgs<T>& a, int width, int depth, bool mrt, int nc, hipStream_t s)
 {
     dim3 grid(a.nitems);
-#define TLB_L2(W, D, M)                                                            \
-    if (width == W && depth == D && mrt == M) {                                    \
-        hipLaunchKernelGGL((k_step2d<T, W, D, M>), grid, dim3(W), 0, s, a);        \
+#define TLB_L2(W, D, M, NC)                                                        \
+    if (width == W && depth == D && mrt == M && nc == NC) {                        \
+        hipLaunchKernelGGL((k_step2d<T, W, D, M, NC>), grid, dim3(W), 0, s, a);    \
         return hipGetLastError();                                                  \
     }
-    TLB_L2(64, 0, false)
-    TLB_L2(128, 0, false)
-    TLB_L2(256, 0, false)
-    TLB_L2(64, 1, false)
-    TLB_L2(128, 1, false)
-    TLB_L2(256, 1, false)
-    TLB_L2(64, 0, true)
-    TLB_L2(128, 0, true)
-    TLB_L2(256, 0, true)
-    TLB_L2(64, 1, true)
-    TLB_L2(128, 1, true)
-    TLB_L2(256, 1, true)
+#define TLB_L2W(D, M, NC) TLB_L2(64, D, M, NC) TLB_L2(128, D, M, NC) TLB_L2(256, D, M, NC)
+    TLB_L2W(0, false, 3)
+    TLB_L2W(1, false, 3)
+    TLB_L2W(0, true, 3)
+    TLB_L2W(1, true, 3)
+    TLB_L2W(0, false, 4)
+    TLB_L2W(0, true, 4)
+    TLB_L2W(0, false, 5)
+    TLB_L2W(0, true, 5)
+#undef TLB_L2W
 #undef TLB_L2
     return hipErrorInvalidValue;
 }
 
-template hipError_t launch_step2d<float>(const StepArgs<float>&, int, int, bool, hipStream_t);
-template hipError_t launch_step2d<double>(const StepArgs<double>&, int, int, bool, hipStream_t);
+template hipError_t launch_step2d<float>(const StepArgs<float>&, int, int, bool, int, hipStream_t);
+template hipError_t launch_step2d<double>(const StepArgs<double>&, int, int, bool, int, hipStream_t);
 
 }  // namespace tlb

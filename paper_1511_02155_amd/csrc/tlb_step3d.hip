@@ -161,7 +161,7 @@ __global__ __launch_bounds__(BX* BY) void k_step3d(StepArgs<T> A)
 
     auto plane = [&](int z, PlaneFull<C>& p) {
         pull3d<T>(A, rs, col, z, wall_tile, blo, bhi, fc, gc, kc);
-        const Moments<C> mo = moments<L19, T>(fc, gc, kc);
+        const Moments<C> mo = moments<L19>(fc, gc, kc);
         conc_dev<C>(mo, p.c);
         if (active) {
 #pragma unroll
@@ -170,7 +170,7 @@ __global__ __launch_bounds__(BX* BY) void k_step3d(StepArgs<T> A)
         if (ring) {
             T hf[19], hg[19], hk[19];
             pull3d<T>(A, rs, hcol, z, wall_tile, hblo, hbhi, hf, hg, hk);
-            Moments<C> hm = moments<L19, T>(hf, hg, hk);
+            Moments<C> hm = moments<L19>(hf, hg, hk);
             C hc[3];
             conc_dev<C>(hm, hc);
             if (gwall >= 0) {
@@ -243,7 +243,7 @@ __global__ __launch_bounds__(BX* BY) void k_step3d(StepArgs<T> A)
                     pb.c[m] * C(4);
         }
         if constexpr (!HOLD) pull3d<T>(A, rs, col, z, wall_tile, blo, bhi, fb, gb, kb);
-        const Moments<C> mb = moments<L19, T>(fb, gb, kb);
+        const Moments<C> mb = moments<L19>(fb, gb, kb);
         collide<L19, MRT>(A.P, mb, pb.c, gC, lC, fb, gb, kb);
 
         if (active) {

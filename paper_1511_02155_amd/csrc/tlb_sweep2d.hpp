@@ -42,7 +42,7 @@ using L9 = D2Q9;
 // f_i(r) = u_i(r - e_i), or u_opp(i)(r) when r - e_i lies beyond a wall
 // (half-way bounce-back).  vo[0..2]: byte offsets of columns x, x-1, x+1;
 // every row-dependent part of the address is wavefront-uniform.
-template <typename T>
+template <typename T, int NC = 3>
 __device__ __forceinline__ void pull2d(const StepArgs<T>& A, Rsrc src, const uint32_t* vo, int y, T* p)
 {
     const int ny = A.ny;
@@ -59,7 +59,7 @@ __device__ __forceinline__ void pull2d(const StepArgs<T>& A, Rsrc src, const uin
         const uint32_t so = (bb ? (uint32_t)L9::opp[i] * N + (uint32_t)y * nx : (uint32_t)i * N + ys * nx) * sizeof(T);
         const uint32_t v = bb ? vo[0] : vo[ex == 0 ? 0 : (ex == 1 ? 1 : 2)];
 #pragma unroll
-        for (int s = 0; s < 3; ++s) p[9 * s + i] = bload<T>(src, v, so + (uint32_t)(9 * s) * N * sizeof(T));
+        for (int s = 0; s < NC; ++s) p[9 * s + i] = bload<T>(src, v, so + (uint32_t)(9 * s) * N * sizeof(T));
     }
 }
 
@@ -93,22 +93,22 @@ __device__ __forceinline__ T pull2d_one(const StepArgs<T>& A, int j, int x, int 
 // Occupancy target (wavefronts per SIMD) the register allocation is held to
 // (the arithmetic is FP64 for both storage types).
 template <typename T, int DEPTH>
-constexpr int step2d_waves() { return DEPTH ? 1 : 2; }
+constexpr int step2d_waves(int nc = 3) { return (DEPTH || nc > 3) ? 1 : 2; }
 
-template <typename T, int W>
+template <typename T, int W, int NC = 3>
 struct Sweep2Lds {
     // Rows of dC_m (arithmetic precision) in sweep order, four rotating
     // buffers; slot 0 and slot nact+1 hold the halo columns, slot t+1 lane
     // t's own column.
-    acc_t<T> row[4][3][W + 2];
-    T hsc[2][2][27];  // halo populations [buf][left/right][j]
+    acc_t<T> row[4][NC][W + 2];
+    T hsc[2][2][9 * NC];  // halo populations [buf][left/right][j]
 };
 
 // One work item: strip `strip` (W columns) of rows [chunk*A.chunk, ...) of
 // the lattice described by A, swept in the direction given by the chunk's
 // parity.  Every lane of the workgroup must call it.
-template <typename T, int W, int DEPTH, bool MRT = false>
-__device__ __forceinline__ void sweep2d(const StepArgs<T>& A, int strip, int chunk, Sweep2Lds<T, W>& S)
+template <typename T, int W, int DEPTH, bool MRT = false, int NC = 3>
+__device__ __forceinline__ void sweep2d(const StepArgs<T>& A, int strip, int chunk, Sweep2Lds<T, W, NC>& S)
 {
     auto& lds = S.row;
     auto& hsc = S.hsc;
@@ -126,13 +126,14 @@ __device__ __forceinline__ void sweep2d(const StepArgs<T>& A, int strip, int chu
     const bool hr = (t == nact - 1);
     const int xl = (x0 == 0) ? A.nx - 1 : x0 - 1;
     const int xr = (x0 + nact == A.nx) ? 0 : x0 + nact;
-    // cooperative halo loaders
+    // cooperative halo loaders: the J = 9 NC populations of the left halo node
+    // are pulled by lanes 0 .. J-1 of the first wavefront, those of the right
+    // one by lanes 64-J .. 63 of the last (with one wavefront, a lane may do both)
+    constexpr int J = 9 * NC;
     const int lane = t & 63;
-    const bool ldl = (t < 64) && lane < 27;
-    const bool ldr = (t >= W - 64) && lane >= 32 && lane < 59;
-    const int hj = ldl ? lane : lane - 32;
-    const int hx = ldl ? xl : xr;
-    const int hside = ldl ? 0 : 1;
+    const bool ldl = (t < 64) && lane < J;
+    const bool ldr = (t >= W - 64) && lane >= 64 - J;
+    const int hjl = lane, hjr = lane - (64 - J);
     const uint32_t nxz = (uint32_t)A.nx;  // nz == 1
     const uint32_t N = (uint32_t)A.N;
 
@@ -141,8 +142,8 @@ __device__ __forceinline__ void sweep2d(const StepArgs<T>& A, int strip, int chu
     auto ghost_of = [&](int y) { return (A.walls && y < 0) ? 0 : ((A.walls && y >= A.ny) ? 1 : -1); };
     auto wrap_y = [&](int y) { return y < 0 ? y + A.ny : (y >= A.ny ? y - A.ny : y); };
 
-    // buffer resources of the source and destination states (27 N values each)
-    const uint32_t sbytes = (uint32_t)(27 * A.N * (int64_t)sizeof(T));
+    // buffer resources of the source and destination states (9 NC N values each)
+    const uint32_t sbytes = (uint32_t)(J * A.N * (int64_t)sizeof(T));
     const Rsrc rs = make_rsrc(A.src, sbytes);
     const Rsrc rd = make_rsrc(A.dst, sbytes);
     const uint32_t vo[3] = {(uint32_t)x * (uint32_t)sizeof(T),
@@ -153,43 +154,46 @@ __device__ __forceinline__ void sweep2d(const StepArgs<T>& A, int strip, int chu
     // the next row, and (DEPTH = 1) the row being prefetched.  The sweep loop
     // is unrolled so that the roles rotate without register copies.
     using C = acc_t<T>;
-    T P0[27], P1[27], P2[27];
+    T P0[J], P1[J], P2[J];
 #pragma unroll
-    for (int i = 0; i < 27; ++i) P0[i] = P1[i] = P2[i] = T(0);
-    Moments<C> M0, M1, M2;
-    T H0 = T(0), H1 = T(0), H2 = T(0);  // halo population held by a loader lane per buffer
+    for (int i = 0; i < J; ++i) P0[i] = P1[i] = P2[i] = T(0);
+    Moments<C, NC> M0, M1, M2;
+    // halo populations held by a loader lane per buffer (left, right)
+    T H0[2] = {T(0), T(0)}, H1[2] = {T(0), T(0)}, H2[2] = {T(0), T(0)};
     int hb = 0;
 
-    auto load_row = [&](int y, T* p, T& hv) {
-        if (active) pull2d<T>(A, rs, vo, y, p);
-        if (ldl || ldr) hv = pull2d_one<T>(A, hj, hx, y);
+    auto load_row = [&](int y, T* p, T* hv) {
+        if (active) pull2d<T, NC>(A, rs, vo, y, p);
+        if (ldl) hv[0] = pull2d_one<T>(A, hjl, xl, y);
+        if (ldr) hv[1] = pull2d_one<T>(A, hjr, xr, y);
     };
 
     // Fluid row into buffer q: own dC and the halo populations to LDS, a
     // barrier, then the lanes next to the halo sum the gathered populations
     // (in the same order as every node) into the halo slots.
-    auto finish_fluid = [&](const T* p, T hv, int q, Moments<C>& mo) {
-        mo = moments<L9, T>(p, p + 9, p + 18);
-        C c[3];
-        conc_dev<C>(mo, c);
+    auto finish_fluid = [&](const T* p, const T* hv, int q, Moments<C, NC>& mo) {
+        mo = moments<L9, NC>(p, p + 9, p + 18);
+        C c[NC];
+        conc_dev<C, NC>(mo, c);
         if (active) {
 #pragma unroll
-            for (int m = 0; m < 3; ++m) lds[q][m][t + 1] = c[m];
+            for (int m = 0; m < NC; ++m) lds[q][m][t + 1] = c[m];
         }
-        if (ldl || ldr) hsc[hb][hside][hj] = hv;
+        if (ldl) hsc[hb][0][hjl] = hv[0];
+        if (ldr) hsc[hb][1][hjr] = hv[1];
         __syncthreads();
 #pragma unroll
         for (int side = 0; side < 2; ++side) {
             if ((side == 0 && hl) || (side == 1 && hr)) {
-                T v[27];
+                T v[J];
 #pragma unroll
-                for (int j = 0; j < 27; ++j) v[j] = hsc[hb][side][j];
-                const Moments<C> hm = moments<L9, T>(v, v + 9, v + 18);
-                C hc[3];
-                conc_dev<C>(hm, hc);
+                for (int j = 0; j < J; ++j) v[j] = hsc[hb][side][j];
+                const Moments<C, NC> hm = moments<L9, NC>(v, v + 9, v + 18);
+                C hc[NC];
+                conc_dev<C, NC>(hm, hc);
                 const int slot = side == 0 ? 0 : nact + 1;
 #pragma unroll
-                for (int m = 0; m < 3; ++m) lds[q][m][slot] = hc[m];
+                for (int m = 0; m < NC; ++m) lds[q][m][slot] = hc[m];
             }
         }
         hb ^= 1;
@@ -197,13 +201,13 @@ __device__ __forceinline__ void sweep2d(const StepArgs<T>& A, int strip, int chu
     // Ghost row beyond wall w into buffer q from the adjacent fluid row in
     // buffer qa (reading R8): C_m(ghost) = C_m(adjacent) + h_m / (alpha^2 kappa_m).
     auto finish_ghost = [&](int w, int qa, int q) {
-        const T* __restrict__ wt = A.wet + (size_t)w * 3 * nxz;
+        const T* __restrict__ wt = A.wet + (size_t)w * NC * nxz;
         if (active) {
 #pragma unroll
-            for (int m = 0; m < 3; ++m) lds[q][m][t + 1] = lds[qa][m][t + 1] + C(wt[m * nxz + x]);
+            for (int m = 0; m < NC; ++m) lds[q][m][t + 1] = lds[qa][m][t + 1] + C(wt[m * nxz + x]);
         }
 #pragma unroll
-        for (int m = 0; m < 3; ++m) {
+        for (int m = 0; m < NC; ++m) {
             if (hl) lds[q][m][0] = lds[qa][m][0] + C(wt[m * nxz + xl]);
             if (hr) lds[q][m][nact + 1] = lds[qa][m][nact + 1] + C(wt[m * nxz + xr]);
         }
@@ -212,7 +216,7 @@ __device__ __forceinline__ void sweep2d(const StepArgs<T>& A, int strip, int chu
 
     // One row of the sweep: Pc/Mc hold row r_j, Pn row r_{j+1} (in flight),
     // Pp receives row r_{j+2} (DEPTH = 1).
-    auto row_step = [&](int j, T* Pc, Moments<C>& Mc, T* Pn, Moments<C>& Mn, T& Hn, T* Pp, T& Hp) {
+    auto row_step = [&](int j, T* Pc, Moments<C, NC>& Mc, T* Pn, Moments<C, NC>& Mn, T* Hn, T* Pp, T* Hp) {
         const int y = row_of(j);
         const int qa = j & 3, qb = (j + 1) & 3, qc = (j + 2) & 3;
         const int yc = row_of(j + 1);
@@ -231,9 +235,9 @@ __device__ __forceinline__ void sweep2d(const StepArgs<T>& A, int strip, int chu
         if (active) {
             // Stencils of row y from the three rows in LDS (qa: previous row in
             // sweep order, qc: next one).
-            C gC[3][3], lC[3];
+            C gC[NC][3], lC[NC];
 #pragma unroll
-            for (int m = 0; m < 3; ++m) {
+            for (int m = 0; m < NC; ++m) {
                 const C ac = lds[qa][m][t + 1], aS = lds[qa][m][t] + lds[qa][m][t + 2],
                         aD = lds[qa][m][t + 2] - lds[qa][m][t];
                 const C bc = lds[qb][m][t + 1], bS = lds[qb][m][t] + lds[qb][m][t + 2],
@@ -247,14 +251,16 @@ __device__ __forceinline__ void sweep2d(const StepArgs<T>& A, int strip, int chu
                 gC[m][2] = C(0);
                 lC[m] = (bS + (ac + cc)) * C(2.0 / 3.0) + (aS + cS) * C(1.0 / 6.0) - bc * C(10.0 / 3.0);
             }
-            C dc[3] = {lds[qb][0][t + 1], lds[qb][1][t + 1], lds[qb][2][t + 1]};
-            collide<L9, MRT>(A.P, Mc, dc, gC, lC, Pc, Pc + 9, Pc + 18);
+            C dc[NC];
+#pragma unroll
+            for (int m = 0; m < NC; ++m) dc[m] = lds[qb][m][t + 1];
+            collide<L9, MRT, NC>(A.P, Mc, dc, gC, lC, Pc, Pc + 9, Pc + 18);
             const uint32_t rowo = (uint32_t)y * (uint32_t)A.nx;
 #pragma unroll
             for (int i = 0; i < 9; ++i) {
                 const uint32_t so = ((uint32_t)i * N + rowo) * (uint32_t)sizeof(T);
 #pragma unroll
-                for (int s = 0; s < 3; ++s) bstore<T>(Pc[9 * s + i], rd, vo[0], so + (uint32_t)(9 * s) * N * sizeof(T));
+                for (int s = 0; s < NC; ++s) bstore<T>(Pc[9 * s + i], rd, vo[0], so + (uint32_t)(9 * s) * N * sizeof(T));
             }
         }
     };

@@ -156,6 +156,22 @@ def spinodal_2d(n=1024, steps=10000, seed=2):
     return w
 
 
+def spinodal_nc(nx, ny, nc, delta=0.01, seed=0):
+    """nc components: C_m = 1/nc + U(-delta, delta) for m < nc - 1, the last one closing the sum."""
+    rng = np.random.default_rng(seed)
+    C = 1.0 / nc + rng.uniform(-delta, delta, size=(nc - 1, nx * ny))
+    return np.concatenate([C, (1.0 - C.sum(0))[None]])
+
+
+def spinodal_2d_nc(n=1024, steps=10000, nc=4, seed=7):
+    """D2Q9 n x n periodic spinodal of nc components (Sec. II.E); kappa_m = 0.01 + 0.005 m, tau=1, M=0.1."""
+    w = _params(0, n, n, 1, 0, tuple(0.01 + 0.005 * m for m in range(nc)), 1.0, 1.0, 0.1, steps)
+    w["name"] = f"d2q9_{n}x{n}_spinodal_n{nc}"
+    w["C"] = lambda: spinodal_nc(n, n, nc, seed=seed)
+    w["h"] = None
+    return w
+
+
 def spinodal_3d(n=256, steps=2000, seed=3):
     """D3Q19 n^3 periodic spinodal; kappa=0.01, tau=0.8, M=0.05."""
     w = _params(1, n, n, n, 0, (0.01, 0.01, 0.01), 1.0, 0.8, 0.05, steps)

@@ -28,8 +28,10 @@ TLB_OK, TLB_EINVAL, TLB_ENOMEM, TLB_EHIP, TLB_ENAN, TLB_ESTATE = 0, -1, -2, -3, 
 TLB_D2Q9, TLB_D3Q19 = 0, 1
 TLB_F32, TLB_F64 = 0, 1
 TLB_BGK, TLB_MRT = 0, 1
+TLB_MAX_COMP = 5
 FIELDS = ("C1", "C2", "C3", "rho", "phi", "psi", "ux", "uy", "uz", "mu_phi", "mu_psi")
 FIELD_INDEX = {name: i for i, name in enumerate(FIELDS)}
+FIELD_INDEX.update(C4=11, C5=12)  # simulations with more than three components
 
 # Every symbol declared in include/tlb.h.
 EXPORTS = (
@@ -62,6 +64,8 @@ class tlb_params(ctypes.Structure):
         ("collision", ctypes.c_int32),
         ("tau_bulk", ctypes.c_double),
         ("tau_ghost", ctypes.c_double),
+        ("ncomp", ctypes.c_int32),
+        ("kappa_hi", ctypes.c_double * 2),
     ]
 
 
@@ -70,6 +74,7 @@ class tlb_diag(ctypes.Structure):
         ("mass", ctypes.c_double * 3), ("momentum", ctypes.c_double * 3),
         ("max_speed", ctypes.c_double), ("nonfinite", ctypes.c_int64), ("step", ctypes.c_int64),
         ("interface", ctypes.c_double * 3),
+        ("mass_hi", ctypes.c_double * 2), ("interface_hi", ctypes.c_double * 2),
     ]
 
 
@@ -176,10 +181,18 @@ def _arr(a, n=None):
 def make_params(lattice, nx, ny, nz=1, prec=TLB_F64, walls_y=0, kappa=(0.01, 0.01, 0.01), alpha=1.0,
                 tau_f=1.0, tau_g=1.0, tau_k=1.0, gamma_phi=1.0, gamma_psi=1.0, no_advection=0, collision=0,
                 tau_bulk=1.0, tau_ghost=1.0, **_ignored):
+    """kappa has one coefficient per component: three for the ternary model, up to TLB_MAX_COMP
+    (Sec. II.E; tlb_params.ncomp is set from its length)."""
     p = tlb_params()
     p.lattice, p.prec, p.nx, p.ny, p.nz, p.walls_y = lattice, prec, nx, ny, nz, walls_y
+    kappa = [float(k) for k in kappa]
+    if not 3 <= len(kappa) <= TLB_MAX_COMP:
+        raise ValueError(f"expected 3 .. {TLB_MAX_COMP} kappa values, got {len(kappa)}")
     for m in range(3):
         p.kappa[m] = kappa[m]
+    p.ncomp = len(kappa)
+    for m in range(3, len(kappa)):
+        p.kappa_hi[m - 3] = kappa[m]
     p.alpha, p.tau_f, p.tau_g, p.tau_k = alpha, tau_f, tau_g, tau_k
     p.gamma_phi, p.gamma_psi = gamma_phi, gamma_psi
     p.no_advection = int(no_advection)
@@ -224,6 +237,7 @@ class Sim:
         self.Q = 9 if params.lattice == TLB_D2Q9 else 19
         self.D = 2 if params.lattice == TLB_D2Q9 else 3
         self.N = params.nx * params.ny * params.nz
+        self.nc = params.ncomp if params.ncomp else 3
 
     @property
     def handle(self):
@@ -241,17 +255,17 @@ class Sim:
             pass
 
     def set_wetting(self, wall, h):
-        h = _arr(h, 3 * self.params.nx * self.params.nz)
+        h = _arr(h, self.nc * self.params.nx * self.params.nz)
         check(tlb_set_wetting(self._h, wall, h.ctypes.data_as(_dp)), "tlb_set_wetting")
 
     def set_wetting_both(self, h):
-        """h: [2][3][nx*nz] (wall 0 = below y=0, wall 1 = above y=ny-1)."""
+        """h: [2][ncomp][nx*nz] (wall 0 = below y=0, wall 1 = above y=ny-1)."""
         h = _arr(h).reshape(2, -1)
         self.set_wetting(0, h[0])
         self.set_wetting(1, h[1])
 
     def init_equilibrium(self, C, u=None):
-        C = _arr(C, 3 * self.N)
+        C = _arr(C, self.nc * self.N)
         up = None
         if u is not None:
             u = _arr(u, self.D * self.N)
@@ -271,7 +285,10 @@ class Sim:
         return out
 
     def fields(self):
-        return {name: self.field(i) for i, name in enumerate(FIELDS)}
+        out = {name: self.field(i) for i, name in enumerate(FIELDS)}
+        for m in range(3, self.nc):
+            out[f"C{m + 1}"] = self.field(f"C{m + 1}")
+        return out
 
     def populations(self, species):
         out = np.empty((self.Q, self.N))
@@ -279,7 +296,7 @@ class Sim:
         return out
 
     def all_populations(self):
-        return np.stack([self.populations(s) for s in range(3)])
+        return np.stack([self.populations(s) for s in range(self.nc)])
 
     def set_populations(self, species, pop):
         pop = _arr(pop, self.Q * self.N)
@@ -290,8 +307,9 @@ class Sim:
         rc = tlb_diagnostics(self._h, ctypes.byref(d))
         if rc != TLB_OK and not (allow_nan and rc == TLB_ENAN):
             check(rc, "tlb_diagnostics")
-        return dict(mass=list(d.mass), momentum=list(d.momentum), max_speed=d.max_speed,
-                    nonfinite=d.nonfinite, step=d.step, interface=list(d.interface))
+        extra = self.nc - 3
+        return dict(mass=list(d.mass) + list(d.mass_hi)[:extra], momentum=list(d.momentum), max_speed=d.max_speed,
+                    nonfinite=d.nonfinite, step=d.step, interface=list(d.interface) + list(d.interface_hi)[:extra])
 
     def set_launch(self, width, height=1, chunk=0, variant=1):
         l = tlb_launch(width, height, chunk, variant)
@@ -331,10 +349,13 @@ class Sim:
         return tlb_state_bytes(self._h)
 
     def set_kappa(self, kappa):
-        k = _arr(kappa, 3)
+        k = _arr(kappa, self.nc)
         check(tlb_set_kappa(self._h, k.ctypes.data_as(_dp)), "tlb_set_kappa")
-        for m in range(3):
-            self.params.kappa[m] = float(k[m])
+        for m in range(self.nc):
+            if m < 3:
+                self.params.kappa[m] = float(k[m])
+            else:
+                self.params.kappa_hi[m - 3] = float(k[m])
 
     def stream(self):
         return tlb_get_stream(self._h)

@@ -92,3 +92,25 @@ def test_null_handles_are_rejected():
     assert tlb.tlb_destroy(None) == tlb.TLB_EINVAL
     assert tlb.tlb_get_field(None, 0, None) == tlb.TLB_EINVAL
     assert tlb.tlb_bytes_per_node(None) == 0.0
+
+
+def test_create_rejects_invalid_component_counts():
+    """ncomp in 3 .. TLB_MAX_COMP (0 = 3), more than three on D2Q9 only, every kappa_m > 0."""
+    from paper_1511_02155_amd import tlb
+
+    def rc(p):
+        h = ctypes.c_void_p()
+        r = tlb.tlb_create(ctypes.byref(p), None, ctypes.byref(h))
+        assert r != tlb.TLB_OK or h.value  # a successful create would need a GPU; only errors are expected here
+        return r
+
+    p = tlb.make_params(lattice=tlb.TLB_D3Q19, nx=8, ny=8, nz=8, kappa=(0.01,) * 4)
+    assert rc(p) == tlb.TLB_EINVAL
+    for n, bad in ((6, None), (2, None), (4, 0.0), (5, float("nan"))):
+        p = tlb.make_params(lattice=tlb.TLB_D2Q9, nx=8, ny=8, kappa=(0.01,) * 5)
+        p.ncomp = n
+        if bad is not None:
+            p.kappa_hi[n - 4] = bad
+        assert rc(p) == tlb.TLB_EINVAL, (n, bad)
+    with pytest.raises(ValueError):
+        tlb.make_params(lattice=tlb.TLB_D2Q9, nx=8, ny=8, kappa=(0.01,) * 6)
