@@ -66,7 +66,9 @@ void k_batch2d(BatchArgs<T> B)
             s_item = (idx < B.qstart[q + 1]) ? idx : -1;
         }
         __syncthreads();
-        const int it = s_item;
+        // the item is the same for the whole workgroup: keep it (and the domain's parameters) in
+        // scalar registers
+        const int it = __builtin_amdgcn_readfirstlane(s_item);
         __syncthreads();
         if (it < 0) {
             q = (q + 1) & (kQueues - 1);

@@ -368,16 +368,16 @@ __device__ __forceinline__ void collide(const Phys<T>& P, const Moments<T, NC>& 
         const T feq = w * (A + rho * U) + G;
         const T Ua = P.adv * U;  // velocity terms of g^eq, k^eq (absent without advection)
         const T geq = w * (Bp + mo.phi * Ua);
+        T keq[NK], ki[NK];
+#pragma unroll
+        for (int l = 0; l < NK; ++l) keq[l] = w * (Bk[l] + psi[l] * Ua);
         sf += feq;
         sg += geq;
 #pragma unroll
-        for (int l = 0; l < NK; ++l) {
-            const T keq = w * (Bk[l] + psi[l] * Ua);
-            sk[l] += keq;
-            const T ki = T(k[l * L::Q + i]);
-            k[l * L::Q + i] = S(ki + wk * (keq - ki));
-        }
+        for (int l = 0; l < NK; ++l) sk[l] += keq[l];
         const T fi = T(f[i]), gi = T(g[i]);
+#pragma unroll
+        for (int l = 0; l < NK; ++l) ki[l] = T(k[l * L::Q + i]);
         if constexpr (MRT) {
             const T di = fi - feq;
             dq[i] = di;
@@ -388,6 +388,8 @@ __device__ __forceinline__ void collide(const Phys<T>& P, const Moments<T, NC>& 
             f[i] = S(fi + wf * (feq - fi));
         }
         g[i] = S(gi + wg * (geq - gi));
+#pragma unroll
+        for (int l = 0; l < NK; ++l) k[l * L::Q + i] = S(ki[l] + wk * (keq[l] - ki[l]));
     }
     const T f0 = T(f[0]), g0 = T(g[0]);
     if constexpr (MRT) {

@@ -128,12 +128,16 @@ __device__ __forceinline__ void sweep2d(const StepArgs<T>& A, int strip, int chu
     const int xr = (x0 + nact == A.nx) ? 0 : x0 + nact;
     // cooperative halo loaders: the J = 9 NC populations of the left halo node
     // are pulled by lanes 0 .. J-1 of the first wavefront, those of the right
-    // one by lanes 64-J .. 63 of the last (with one wavefront, a lane may do both)
+    // one by lanes 32 .. 32+J-1 of the last when J <= 32 (distinct lanes, one
+    // held value per lane), else by lanes 64-J .. 63 (with one wavefront a lane
+    // may then load for both sides and holds two values)
     constexpr int J = 9 * NC;
+    constexpr bool one_held = J <= 32;
+    constexpr int HR = one_held ? 0 : 1;  // slot of the right-side value
     const int lane = t & 63;
     const bool ldl = (t < 64) && lane < J;
-    const bool ldr = (t >= W - 64) && lane >= 64 - J;
-    const int hjl = lane, hjr = lane - (64 - J);
+    const bool ldr = one_held ? ((t >= W - 64) && lane >= 32 && lane < 32 + J) : ((t >= W - 64) && lane >= 64 - J);
+    const int hjl = lane, hjr = one_held ? lane - 32 : lane - (64 - J);
     const uint32_t nxz = (uint32_t)A.nx;  // nz == 1
     const uint32_t N = (uint32_t)A.N;
 
@@ -158,14 +162,20 @@ __device__ __forceinline__ void sweep2d(const StepArgs<T>& A, int strip, int chu
 #pragma unroll
     for (int i = 0; i < J; ++i) P0[i] = P1[i] = P2[i] = T(0);
     Moments<C, NC> M0, M1, M2;
-    // halo populations held by a loader lane per buffer (left, right)
-    T H0[2] = {T(0), T(0)}, H1[2] = {T(0), T(0)}, H2[2] = {T(0), T(0)};
+    // halo populations held by a loader lane per buffer (left, and right in slot HR)
+    T Hb0[HR + 1], Hb1[HR + 1], Hb2[HR + 1];
+#pragma unroll
+    for (int q = 0; q <= HR; ++q) Hb0[q] = Hb1[q] = Hb2[q] = T(0);
     int hb = 0;
 
     auto load_row = [&](int y, T* p, T* hv) {
         if (active) pull2d<T, NC>(A, rs, vo, y, p);
-        if (ldl) hv[0] = pull2d_one<T>(A, hjl, xl, y);
-        if (ldr) hv[1] = pull2d_one<T>(A, hjr, xr, y);
+        if constexpr (one_held) {
+            if (ldl || ldr) hv[0] = pull2d_one<T>(A, ldl ? hjl : hjr, ldl ? xl : xr, y);
+        } else {
+            if (ldl) hv[0] = pull2d_one<T>(A, hjl, xl, y);
+            if (ldr) hv[HR] = pull2d_one<T>(A, hjr, xr, y);
+        }
     };
 
     // Fluid row into buffer q: own dC and the halo populations to LDS, a
@@ -179,8 +189,12 @@ __device__ __forceinline__ void sweep2d(const StepArgs<T>& A, int strip, int chu
 #pragma unroll
             for (int m = 0; m < NC; ++m) lds[q][m][t + 1] = c[m];
         }
-        if (ldl) hsc[hb][0][hjl] = hv[0];
-        if (ldr) hsc[hb][1][hjr] = hv[1];
+        if constexpr (one_held) {
+            if (ldl || ldr) hsc[hb][ldl ? 0 : 1][ldl ? hjl : hjr] = hv[0];
+        } else {
+            if (ldl) hsc[hb][0][hjl] = hv[0];
+            if (ldr) hsc[hb][1][hjr] = hv[HR];
+        }
         __syncthreads();
 #pragma unroll
         for (int side = 0; side < 2; ++side) {
@@ -271,35 +285,35 @@ __device__ __forceinline__ void sweep2d(const StepArgs<T>& A, int strip, int chu
         const int ya = row_of(-1);
         const int ga = ghost_of(ya);
         if (ga < 0) {
-            load_row(wrap_y(ya), P1, H1);
-            finish_fluid(P1, H1, 0, M1);
-            load_row(yfirst, P0, H0);
-            finish_fluid(P0, H0, 1, M0);
+            load_row(wrap_y(ya), P1, Hb1);
+            finish_fluid(P1, Hb1, 0, M1);
+            load_row(yfirst, P0, Hb0);
+            finish_fluid(P0, Hb0, 1, M0);
         } else {
-            load_row(yfirst, P0, H0);
-            finish_fluid(P0, H0, 1, M0);
+            load_row(yfirst, P0, Hb0);
+            finish_fluid(P0, Hb0, 1, M0);
             finish_ghost(ga, 1, 0);
         }
         const int yc = row_of(1);
-        if (ghost_of(yc) < 0) load_row(wrap_y(yc), P1, H1);
+        if (ghost_of(yc) < 0) load_row(wrap_y(yc), P1, Hb1);
     }
 
     if constexpr (DEPTH == 0) {
         int j = 0;
         for (; j + 1 < L; j += 2) {
-            row_step(j, P0, M0, P1, M1, H1, P2, H2);
-            row_step(j + 1, P1, M1, P0, M0, H0, P2, H2);
+            row_step(j, P0, M0, P1, M1, Hb1, P2, Hb2);
+            row_step(j + 1, P1, M1, P0, M0, Hb0, P2, Hb2);
         }
-        if (j < L) row_step(j, P0, M0, P1, M1, H1, P2, H2);
+        if (j < L) row_step(j, P0, M0, P1, M1, Hb1, P2, Hb2);
     } else {
         int j = 0;
         for (; j + 2 < L; j += 3) {
-            row_step(j, P0, M0, P1, M1, H1, P2, H2);
-            row_step(j + 1, P1, M1, P2, M2, H2, P0, H0);
-            row_step(j + 2, P2, M2, P0, M0, H0, P1, H1);
+            row_step(j, P0, M0, P1, M1, Hb1, P2, Hb2);
+            row_step(j + 1, P1, M1, P2, M2, Hb2, P0, Hb0);
+            row_step(j + 2, P2, M2, P0, M0, Hb0, P1, Hb1);
         }
-        if (j < L) row_step(j, P0, M0, P1, M1, H1, P2, H2);
-        if (j + 1 < L) row_step(j + 1, P1, M1, P2, M2, H2, P0, H0);
+        if (j < L) row_step(j, P0, M0, P1, M1, Hb1, P2, Hb2);
+        if (j + 1 < L) row_step(j + 1, P1, M1, P2, M2, Hb2, P0, Hb0);
     }
 }
 
