@@ -369,7 +369,8 @@ tlb_status tlb_device_copy(void* dst, const void* src, int64_t bytes, void* stre
  * own tlb_params (lattice TLB_D2Q9, nx, ny <= 65535, its own walls_y, kappa,
  * alpha, tau and Gamma); every domain must use the same prec.  One time step
  * of the batch is one persistent kernel launch whose workgroups take
- * (domain, strip, row-chunk) work items from per-XCD queues; with
+ * (domain, strip, row-chunk) or (domain, run of positions) work items from
+ * per-XCD queues; with
  * tlb_batch_set_graph the steps are replayed from a captured hipGraph.
  * A domain evolves exactly (bit for bit) as a tlb_sim with the same
  * parameters.  Domain indices run 0..ndom-1; host arrays follow the layouts
@@ -390,9 +391,14 @@ tlb_status tlb_batch_get_field(tlb_batch* batch, int32_t dom, int which, double*
 tlb_status tlb_batch_get_populations(tlb_batch* batch, int32_t dom, int species, double* out);
 tlb_status tlb_batch_diagnostics(tlb_batch* batch, int32_t dom, tlb_diag* out);
 /*
- * Launch shape of the batched step: width = strip width (64, 128, 256),
- * chunk = rows per work item (1..65535), variant as for a D2Q9 tlb_sim;
- * height is ignored.  Results do not depend on it.
+ * Launch shape of the batched step: width = workgroup width (64, 128, 256);
+ * variant 0 and 1 sweep every domain in strips of that many columns, chunk =
+ * rows per work item (1 adds a one-row prefetch, as for a D2Q9 tlb_sim);
+ * variant 2 sweeps each domain with nx + 3 <= width as one flat sequence of
+ * its rows (each padded with its two periodic halo columns), chunk = runs of
+ * `width` consecutive positions per work item, so that narrow domains leave
+ * no lanes idle, and the wider domains in strips as variant 0.  chunk is
+ * 1..65535; height is ignored.  Results do not depend on the shape.
  */
 tlb_status tlb_batch_set_launch(tlb_batch* batch, const tlb_launch* launch);
 tlb_status tlb_batch_get_launch(const tlb_batch* batch, tlb_launch* out);

@@ -8,8 +8,10 @@
 // once their own is empty.  The kernel boundary is the per-step barrier; the
 // queue counters of the next step are cleared inside the kernel, so a chain
 // of steps can be captured once in a hipGraph and replayed.  Each work item
-// runs the same strip sweep as the single-lattice kernel, so a domain's result
-// is bit-for-bit the one a single tlb_sim of that domain produces.
+// runs the same strip sweep as the single-lattice kernel, or (variant 2, for
+// domains no wider than a workgroup) a flat sweep over the row-major node
+// order with the same arithmetic, so a domain's result is bit-for-bit the one
+// a single tlb_sim of that domain produces.
 #include <math.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -31,6 +33,7 @@ struct DomDesc {
     int64_t off;      // element offset of the domain's state in a state buffer
     int64_t wet_off;  // element offset of its wetting array, or -1 (no walls)
     int32_t nx, ny, walls, chunk, ntx, nchunks;
+    int32_t flat;  // 0: strip sweep (chunk = rows per item); 1: flat sweep (chunk = segments per item)
     Phys<acc_t<T>> P;
 };
 
@@ -48,11 +51,183 @@ struct BatchArgs {
 
 constexpr int kQueues = 8;
 
-template <typename T, int W, int DEPTH>
-__global__ __launch_bounds__(W) __attribute__((amdgpu_waves_per_eu(step2d_waves<T, DEPTH>())))
+// Pull of node (x, y) addressed per lane: the loads of pull2d (same sources,
+// same half-way bounce-back) with the row folded into the lane's offset.  The
+// byte offsets of the three source rows and columns are formed once; a
+// direction adds one of each and its own array offset.
+template <typename T>
+__device__ __forceinline__ void pull_flat(Rsrc src, uint32_t N, int nx, int ny, bool walls, int x, int y, T* p)
+{
+    constexpr uint32_t ES = sizeof(T);
+    const uint32_t cx[3] = {(uint32_t)x * ES, (uint32_t)(x == 0 ? nx - 1 : x - 1) * ES,
+                            (uint32_t)(x == nx - 1 ? 0 : x + 1) * ES};  // columns x, x-1, x+1
+    const uint32_t r0 = (uint32_t)y * (uint32_t)nx * ES;
+    const uint32_t ry[3] = {r0, y == 0 ? (uint32_t)(ny - 1) * (uint32_t)nx * ES : r0 - (uint32_t)nx * ES,
+                            y == ny - 1 ? 0u : r0 + (uint32_t)nx * ES};  // rows y, y-1, y+1
+    const bool blo = walls && y == 0, bhi = walls && y == ny - 1;
+    const uint32_t own = r0 + cx[0];
+    const uint32_t NB = N * ES;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const int ex = L9::ex[i], ey = L9::ey[i];
+        const bool bb = (ey == 1) ? blo : (ey == -1) ? bhi : false;
+        const uint32_t from = ry[ey == 0 ? 0 : (ey == 1 ? 1 : 2)] + cx[ex == 0 ? 0 : (ex == 1 ? 1 : 2)];
+        const uint32_t vo = bb ? own + (uint32_t)L9::opp[i] * NB : from + (uint32_t)i * NB;
+#pragma unroll
+        for (int s = 0; s < 3; ++s) p[9 * s + i] = bload<T>(src, vo, (uint32_t)(9 * s) * NB);
+    }
+}
+
+template <typename T, int W>
+struct FlatLds {
+    acc_t<T> c[3][4 * W];  // C_m of virtual position v at [m][v mod 4W]
+};
+
+template <typename T, int W, bool FLAT>
+struct BatchLds {
+    Sweep2Lds<T, W> strip;
+};
+template <typename T, int W>
+struct BatchLds<T, W, true> {
+    union {
+        Sweep2Lds<T, W> strip;
+        FlatLds<T, W> flat;
+    };
+};
+
+// Flat sweep of one work item of a domain with nx + 3 <= W.  A strip of W
+// lanes would leave W - nx lanes of every row idle; here the rows, each padded
+// with its two periodic halo columns (P = nx + 2 positions: the copy of
+// column nx-1, columns 0 .. nx-1, the copy of column 0), are laid end to end
+// and lane t of segment s owns position v = s W + t.  The x neighbours of an
+// interior position are v -+ 1 and the rows below and above are v -+ P, so a
+// node's nine neighbours lie within the segments before and after its own.
+// The item runs over segments [seg0, seg1), upwards for even items and
+// downwards for odd ones (neighbouring items meet at shared segments, as the
+// strips do), in the strip sweep's pipeline: C_m of segment k+1 (pulled and
+// summed by every lane, halo lanes included) goes to a ring of four segments
+// in LDS and its populations stay in registers; one barrier; then the
+// interior nodes of segment k take their stencils from the ring and collide.
+// Positions beyond the ends are periodic images (y periodic) or never read
+// (walls: ghost rows are made from the node's own row).  Every value is formed
+// by the same operations in the same order as in the strip sweep (pull,
+// moments, concentrations, ghost rows, stencil9, collide), so the results are
+// bitwise those of the strip sweep.
+template <typename T, int W>
+__device__ __forceinline__ void flat2d(const StepArgs<T>& A, int item, FlatLds<T, W>& S)
+{
+    using C = acc_t<T>;
+    constexpr int RM = 4 * W - 1;
+    auto& ring = S.c;
+    const int t = threadIdx.x;
+    const int nx = A.nx, ny = A.ny, P = nx + 2, NP = ny * P;
+    const bool walls = A.walls != 0;
+    const int nseg = (NP + W - 1) / W;
+    const int seg0 = item * A.chunk, seg1 = min(seg0 + A.chunk, nseg);
+    const uint32_t NU = (uint32_t)A.N;
+    const uint32_t sbytes = (uint32_t)(27 * A.N * (int64_t)sizeof(T));
+    const Rsrc rs = make_rsrc(A.src, sbytes);
+    const Rsrc rd = make_rsrc(A.dst, sbytes);
+
+    // physical column of padded position xp
+    auto col_of = [&](int xp) { return xp == 0 ? nx - 1 : (xp == P - 1 ? 0 : xp - 1); };
+
+    // Segment s: every lane pulls its position's node into p, its moments
+    // into mo and C_m into the ring.
+    auto cpass = [&](int s, T* p, Moments<C, 3>& mo) {
+        const int v = s * W + t;
+        int u = v;
+        bool ok = v >= 0 && v < NP;
+        if (!walls) {
+            u = v % NP;
+            u = u < 0 ? u + NP : u;
+            ok = true;
+        }
+        if (ok) {
+            const int y = (int)((uint32_t)u / (uint32_t)P);
+            const int x = col_of(u - y * P);
+            pull_flat<T>(rs, NU, nx, ny, walls, x, y, p);
+            mo = moments<L9, 3>(p, p + 9, p + 18);
+            C c[3];
+            conc_dev<C, 3>(mo, c);
+#pragma unroll
+            for (int m = 0; m < 3; ++m) ring[m][v & RM] = c[m];
+        }
+    };
+    // Segment s: stencils, collision and store of its interior nodes.
+    auto bpass = [&](int s, T* p, const Moments<C, 3>& mo) {
+        const int v = s * W + t;
+        const int y = (int)((uint32_t)v / (uint32_t)P), xp = v - y * P;
+        if (v < NP && xp >= 1 && xp <= nx) {
+            const int x = xp - 1;
+            const int xl = col_of(xp - 1), xr = col_of(xp + 1);
+            const bool glo = walls && y == 0, ghi = walls && y == ny - 1;
+            C gC[3][3], lC[3], dc[3];
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                const C bl = ring[m][(v - 1) & RM], bc = ring[m][v & RM], br = ring[m][(v + 1) & RM];
+                C al = ring[m][(v - P - 1) & RM], ac = ring[m][(v - P) & RM], ar = ring[m][(v - P + 1) & RM];
+                C cl = ring[m][(v + P - 1) & RM], cc = ring[m][(v + P) & RM], cr = ring[m][(v + P + 1) & RM];
+                // ghost rows (reading R8): C_m(ghost) = C_m(adjacent fluid node) + h_m / (alpha^2 kappa_m)
+                if (glo) {
+                    const T* __restrict__ wt = A.wet + m * nx;
+                    al = bl + C(wt[xl]);
+                    ac = bc + C(wt[x]);
+                    ar = br + C(wt[xr]);
+                }
+                if (ghi) {
+                    const T* __restrict__ wt = A.wet + (3 + m) * nx;
+                    cl = bl + C(wt[xl]);
+                    cc = bc + C(wt[x]);
+                    cr = br + C(wt[xr]);
+                }
+                stencil9<C>(ac, al + ar, ar - al, bc, bl + br, br - bl, cc, cl + cr, cr - cl, 1, gC[m], lC[m]);
+                dc[m] = bc;
+            }
+            collide<L9, false, 3>(A.P, mo, dc, gC, lC, p, p + 9, p + 18);
+            const uint32_t vo = (uint32_t)(y * nx + x) * (uint32_t)sizeof(T);
+#pragma unroll
+            for (int q = 0; q < 27; ++q) bstore<T>(p[q], rd, vo, (uint32_t)q * NU * (uint32_t)sizeof(T));
+        }
+    };
+
+    // Two population buffers take turns; one barrier per segment (the ring
+    // slot written next is none of the three a lane may still be reading).
+    T P0[27], P1[27];
+#pragma unroll
+    for (int i = 0; i < 27; ++i) P0[i] = P1[i] = T(0);
+    Moments<C, 3> M0, M1;
+    const int d = (item & 1) ? -1 : 1;
+    const int kb = d > 0 ? seg0 : seg1 - 1;  // first segment collided
+    const int n = seg1 - seg0;
+    cpass(kb - d, P1, M1);
+    cpass(kb, P0, M0);
+    int j = 0;
+    for (; j + 1 < n; j += 2) {
+        const int k = kb + j * d;
+        cpass(k + d, P1, M1);
+        __syncthreads();
+        bpass(k, P0, M0);
+        cpass(k + 2 * d, P0, M0);
+        __syncthreads();
+        bpass(k + d, P1, M1);
+    }
+    if (j < n) {
+        const int k = kb + j * d;
+        cpass(k + d, P1, M1);
+        __syncthreads();
+        bpass(k, P0, M0);
+    }
+}
+
+// MODE 0: strip sweep; 1: strip sweep with a one-row prefetch; 2: flat sweep
+// for domains with nx + 3 <= W (flat in the descriptor), strips for the rest.
+template <typename T, int W, int MODE>
+__global__ __launch_bounds__(W) __attribute__((amdgpu_waves_per_eu(step2d_waves<T, MODE == 1 ? 1 : 0>())))
 void k_batch2d(BatchArgs<T> B)
 {
-    __shared__ Sweep2Lds<T, W> S;
+    constexpr int DEPTH = MODE == 1 ? 1 : 0;
+    __shared__ BatchLds<T, W, MODE == 2> S;
     __shared__ int s_item;
     if (blockIdx.x == 0 && threadIdx.x < kQueues) B.counters[(B.parity ^ 1) * kQueues + threadIdx.x] = 0;
     // Workgroups are dispatched round-robin over the XCDs: start on the
@@ -92,7 +267,14 @@ void k_batch2d(BatchArgs<T> B)
         A.nty = 1;
         A.nitems = D.ntx * D.nchunks;
         A.P = D.P;
-        sweep2d<T, W, DEPTH>(A, w.y >> 16, w.y & 0xffff, S);
+        if constexpr (MODE == 2) {
+            if (D.flat)
+                flat2d<T, W>(A, w.y & 0xffff, S.flat);
+            else
+                sweep2d<T, W, DEPTH>(A, w.y >> 16, w.y & 0xffff, S.strip);
+        } else {
+            sweep2d<T, W, DEPTH>(A, w.y >> 16, w.y & 0xffff, S.strip);
+        }
         __syncthreads();
     }
 }
@@ -111,6 +293,9 @@ static hipError_t launch_batch2d(const BatchArgs<T>& a, int width, int depth, in
     TLB_LB(64, 1)
     TLB_LB(128, 1)
     TLB_LB(256, 1)
+    TLB_LB(64, 2)
+    TLB_LB(128, 2)
+    TLB_LB(256, 2)
 #undef TLB_LB
     return hipErrorInvalidValue;
 }
@@ -127,6 +312,9 @@ static hipError_t occupancy_batch2d(int width, int depth, int* blocks_per_cu)
     TLB_OB(64, 1)
     TLB_OB(128, 1)
     TLB_OB(256, 1)
+    TLB_OB(64, 2)
+    TLB_OB(128, 2)
+    TLB_OB(256, 2)
 #undef TLB_OB
     return hipErrorInvalidValue;
 }
@@ -239,12 +427,23 @@ static tlb_status build_items(tlb_batch* b)
         D.nx = p.nx;
         D.ny = p.ny;
         D.walls = p.walls_y;
-        D.chunk = std::min(rows, p.ny);
-        D.ntx = (p.nx + W - 1) / W;
-        D.nchunks = (p.ny + D.chunk - 1) / D.chunk;
         D.P = phys_of<acc_t<T>>(p);
         const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-        load[k] += (int64_t)D.ntx * W * p.ny;
+        if (b->launch.variant == 2 && p.nx + 3 <= W) {
+            // flat sweep: items of `rows` segments of W positions of the padded rows
+            const int64_t nseg = ((int64_t)(p.nx + 2) * p.ny + W - 1) / W;
+            D.flat = 1;
+            D.chunk = (int)std::min<int64_t>(rows, nseg);
+            D.ntx = 1;
+            D.nchunks = (int)((nseg + D.chunk - 1) / D.chunk);
+            load[k] += nseg * W;
+        } else {
+            D.flat = 0;
+            D.chunk = std::min(rows, p.ny);
+            D.ntx = (p.nx + W - 1) / W;
+            D.nchunks = (p.ny + D.chunk - 1) / D.chunk;
+            load[k] += (int64_t)D.ntx * W * p.ny;
+        }
         for (int c = 0; c < D.nchunks; ++c)
             for (int s = 0; s < D.ntx; ++s) q[k].push_back(make_int2(d, (s << 16) | c));
     }
@@ -503,7 +702,7 @@ extern "C" tlb_status tlb_batch_set_launch(tlb_batch* b, const tlb_launch* l)
 {
     if (!b || !l) return TLB_EINVAL;
     if ((l->width != 64 && l->width != 128 && l->width != 256) || l->chunk < 1 || l->chunk > 65535 ||
-        (l->variant != 0 && l->variant != 1))
+        l->variant < 0 || l->variant > 2)
         return TLB_EINVAL;
     BHIP(hipStreamSynchronize(b->stream));
     b->launch = *l;
@@ -658,7 +857,7 @@ extern "C" tlb_status tlb_batch_autotune(tlb_batch* b, int32_t trial_steps, tlb_
     tlb_status st = TLB_OK;
     for (int wi = 0; wi < 3 && !st; ++wi)
         for (int ci = 0; ci < 4 && !st; ++ci)
-            for (int v = 0; v < 2 && !st; ++v) {
+            for (int v = 0; v < 3 && !st; ++v) {
                 tlb_launch l = {widths[wi], 1, chunks[ci], v};
                 st = tlb_batch_set_launch(b, &l);
                 if (st) break;

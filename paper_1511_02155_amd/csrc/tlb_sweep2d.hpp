@@ -90,6 +90,22 @@ __device__ __forceinline__ T pull2d_one(const StepArgs<T>& A, int j, int x, int 
     return A.src[(int64_t)s * 9 * A.N + off];
 }
 
+// The D2Q9 stencils of one node from three rows of C: a and c are the rows
+// before and after the node's row b in sweep order (dir > 0: a is row y-1),
+// each given as the node's column c, S = left + right and D = right - left.
+// Every sum is symmetric in a and c except the y differences, which take the
+// rows' true order, so both sweep directions round identically.
+template <typename C>
+__device__ __forceinline__ void stencil9(C ac, C aS, C aD, C bc, C bS, C bD, C cc, C cS, C cD, int dir, C* g, C& lap)
+{
+    const C up = dir > 0 ? cc : ac, dn = dir > 0 ? ac : cc;
+    const C Sup = dir > 0 ? cS : aS, Sdn = dir > 0 ? aS : cS;
+    g[0] = bD * C(1.0 / 3.0) + (aD + cD) * C(1.0 / 12.0);
+    g[1] = (up - dn) * C(1.0 / 3.0) + (Sup - Sdn) * C(1.0 / 12.0);
+    g[2] = C(0);
+    lap = (bS + (ac + cc)) * C(2.0 / 3.0) + (aS + cS) * C(1.0 / 6.0) - bc * C(10.0 / 3.0);
+}
+
 // Occupancy target (wavefronts per SIMD) the register allocation is held to
 // (the arithmetic is FP64 for both storage types).
 template <typename T, int DEPTH>
@@ -258,12 +274,7 @@ __device__ __forceinline__ void sweep2d(const StepArgs<T>& A, int strip, int chu
                         bD = lds[qb][m][t + 2] - lds[qb][m][t];
                 const C cc = lds[qc][m][t + 1], cS = lds[qc][m][t] + lds[qc][m][t + 2],
                         cD = lds[qc][m][t + 2] - lds[qc][m][t];
-                const C up = dir > 0 ? cc : ac, dn = dir > 0 ? ac : cc;
-                const C Sup = dir > 0 ? cS : aS, Sdn = dir > 0 ? aS : cS;
-                gC[m][0] = bD * C(1.0 / 3.0) + (aD + cD) * C(1.0 / 12.0);
-                gC[m][1] = (up - dn) * C(1.0 / 3.0) + (Sup - Sdn) * C(1.0 / 12.0);
-                gC[m][2] = C(0);
-                lC[m] = (bS + (ac + cc)) * C(2.0 / 3.0) + (aS + cS) * C(1.0 / 6.0) - bc * C(10.0 / 3.0);
+                stencil9<C>(ac, aS, aD, bc, bS, bD, cc, cS, cD, dir, gC[m], lC[m]);
             }
             C dc[NC];
 #pragma unroll

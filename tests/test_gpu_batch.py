@@ -72,7 +72,9 @@ def _single(tlb, d, prec, steps):
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("launch", [dict(width=64, chunk=8, variant=0), dict(width=128, chunk=16, variant=1),
-                                    dict(width=256, chunk=5, variant=1)])
+                                    dict(width=256, chunk=5, variant=1), dict(width=64, chunk=3, variant=2),
+                                    dict(width=128, chunk=1, variant=2), dict(width=256, chunk=4, variant=2),
+                                    dict(width=256, chunk=64, variant=2)])
 def test_batch_equals_single_lattices_bitwise(tlb, prec, launch):
     P = tlb.TLB_F64 if prec == "f64" else tlb.TLB_F32
     doms = _small_batch()
@@ -82,6 +84,50 @@ def test_batch_equals_single_lattices_bitwise(tlb, prec, launch):
     for i, d in enumerate(doms):
         ref = _single(tlb, d, P, 60)
         assert np.array_equal(b.all_populations(i), ref), i
+
+
+def _edge_domains(seed=25):
+    """Domains at the limits of the flat sweep: a few nodes only, fewer nodes than one segment, the widest
+    flat domain of each workgroup width (nx = W - 3), domains just too wide for it (strips), long thin
+    ones, walls and periodic rows."""
+    rng = np.random.default_rng(seed)
+    doms = []
+    for nx, ny, walls in [(3, 3, 0), (3, 5, 1), (5, 4, 0), (64, 3, 1), (64, 7, 0), (63, 10, 1), (33, 40, 0),
+                          (32, 9, 1), (65, 6, 1), (128, 5, 0), (130, 4, 1), (7, 70, 1), (61, 5, 1), (62, 4, 0),
+                          (125, 4, 0), (253, 3, 1), (254, 3, 0)]:
+        C = rng.random((3, nx * ny)) + 0.2
+        C /= C.sum(0)
+        h = rng.uniform(-0.01, 0.01, (2, 3, nx)) if walls else None
+        doms.append(dict(lattice=0, nx=nx, ny=ny, nz=1, walls_y=walls, kappa=tuple(0.005 + 0.02 * rng.random(3)),
+                         alpha=1.0, tau_f=0.9, tau_g=1.0, tau_k=0.8, gamma_phi=0.4, gamma_psi=0.3, C=C, h=h,
+                         no_advection=0))
+    return doms
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("width,chunk", [(64, 1), (64, 2), (128, 3), (256, 1)])
+def test_batch_flat_sweep_edge_domains_bitwise(tlb, prec, width, chunk):
+    """Variant 2 sweeps domains with nx <= width over the row-major node order; each must still equal
+    a single lattice bit for bit, also for tiny, periodic and exactly-workgroup-wide domains."""
+    P = tlb.TLB_F64 if prec == "f64" else tlb.TLB_F32
+    doms = _edge_domains()
+    _note(f"flat edge domains {prec} width {width} chunk {chunk}")
+    b = _make_batch(tlb, doms, P, dict(width=width, chunk=chunk, variant=2))
+    b.step(25)
+    for i, d in enumerate(doms):
+        ref = _single(tlb, d, P, 25)
+        assert np.array_equal(b.all_populations(i), ref), (i, d["nx"], d["ny"])
+
+
+def test_batch_launch_validation(tlb):
+    b = _make_batch(tlb, _small_batch(ndom=3, seed=26), tlb.TLB_F32)
+    for bad in (dict(width=96, chunk=8, variant=0), dict(width=64, chunk=0, variant=0),
+                dict(width=64, chunk=8, variant=3), dict(width=64, chunk=8, variant=-1)):
+        with pytest.raises(tlb.TLBError):
+            b.set_launch(**bad)
+    b.set_launch(width=256, chunk=8, variant=2)
+    assert b.launch() == dict(width=256, chunk=8, variant=2)
+    b.close()
 
 
 def test_batch_graph_replays_match_direct(tlb):
