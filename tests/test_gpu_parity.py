@@ -131,9 +131,9 @@ def test_d2q9_walls_wetting_ragged_fp64(tlb, orc, nx, ny, width, chunk):
 def test_d3q19_ragged_fp64(tlb, orc, dims, tile, walls):
     nx, ny, nz = dims
     w, C, h = _wet_case(nx, ny, nz, lattice=1, walls=walls)
-    for hold in (0, 1):
+    for variant in (0, 1):
         p, pop, s = _run_both(tlb, orc, w, C, h, 30, tlb.TLB_F64,
-                              dict(width=tile[0], height=tile[1], chunk=4, variant=hold))
+                              dict(width=tile[0], height=tile[1], chunk=4, variant=variant))
         _compare_f64(orc, p, pop, h, s)
 
 
@@ -183,6 +183,48 @@ def test_launch_shapes_bitwise_identical(tlb):
                     ref = got
                 else:
                     assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_d3q19_launch_shapes_bitwise_identical(tlb, prec):
+    """For each variant (plane z pulled again, or held from the previous plane) both tiles and every
+    chunk give the same bits.  The variants are separate kernels in which the compiler may fuse a
+    different set of multiply-adds, so across variants the results agree to rounding."""
+    w, C, h = _wet_case(70, 19, 11, lattice=1, walls=1)
+    P = tlb.TLB_F64 if prec == "f64" else tlb.TLB_F32
+    per_variant = {}
+    for variant in (0, 1):
+        for tile in ((32, 8), (64, 4)):
+            for chunk in (1, 4, 11):
+                _note(f"d3q19 {prec} tile {tile} chunk {chunk} variant {variant}")
+                s = _gsim(tlb, w, P, dict(width=tile[0], height=tile[1], chunk=chunk, variant=variant))
+                s.set_wetting_both(h)
+                s.init_equilibrium(C)
+                s.step(12)
+                got = s.all_populations()
+                s.close()
+                if variant not in per_variant:
+                    per_variant[variant] = got
+                else:
+                    assert np.array_equal(got, per_variant[variant]), (tile, chunk, variant)
+    ref = per_variant[0]
+    tol = 1e-13 * np.abs(ref).max() if prec == "f64" else 1e-6
+    assert np.abs(per_variant[1] - ref).max() <= tol
+
+
+def test_launch_validation(tlb):
+    w2, _, _ = _wet_case(40, 20)
+    w3, _, _ = _wet_case(20, 12, 8, lattice=1)
+    s2 = _gsim(tlb, w2, tlb.TLB_F64)
+    s3 = _gsim(tlb, w3, tlb.TLB_F32)
+    for s, bad in ((s2, dict(width=96, chunk=4, variant=0)), (s2, dict(width=64, chunk=-1, variant=0)),
+                   (s2, dict(width=64, chunk=4, variant=2)), (s3, dict(width=64, height=8, chunk=4, variant=0)),
+                   (s3, dict(width=32, height=8, chunk=4, variant=2))):
+        with pytest.raises(tlb.TLBError):
+            s.set_launch(**bad)
+    s3.set_launch(width=32, height=8, chunk=4, variant=1)
+    s2.close()
+    s3.close()
 
 
 def test_run_twice_is_deterministic_and_restart_continues(tlb):
