@@ -130,10 +130,11 @@ def test_batch_launch_validation(tlb):
     b.close()
 
 
-def test_batch_graph_replays_match_direct(tlb):
+@pytest.mark.parametrize("launch", [None, dict(width=256, chunk=8, variant=2)])
+def test_batch_graph_replays_match_direct(tlb, launch):
     doms = _small_batch(seed=22)
-    ref = _make_batch(tlb, doms, tlb.TLB_F32)
-    gb = _make_batch(tlb, doms, tlb.TLB_F32, graph=10)
+    ref = _make_batch(tlb, doms, tlb.TLB_F32, launch)
+    gb = _make_batch(tlb, doms, tlb.TLB_F32, launch, graph=10)
     total = 0
     for chunk in (25, 10, 31, 20):  # graph replays plus direct remainders, eager reads in between
         _note(f"graph replay chunk {chunk}")
