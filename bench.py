@@ -246,6 +246,87 @@ def cpu_baseline(w, steps):
                 sample=f"{w['name']} FP64, {steps} steps after 1 warm-up step, {dt:.1f} s")
 
 
+_PKEYS = ("lattice", "nx", "ny", "nz", "walls_y", "kappa", "alpha", "tau_f", "tau_g", "tau_k", "gamma_phi",
+          "gamma_psi")
+
+
+def _cpu_threads():
+    return int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+
+
+def cpu_single_thread(steps=4):
+    """The headline oracle sample on one thread (a child process started with OMP_NUM_THREADS=1)."""
+    import subprocess
+
+    code = ("import json, bench; from paper_1511_02155_amd import inputs; "
+            f"print(json.dumps(bench.cpu_baseline(inputs.spinodal_2d(1024, {steps}), {steps})))")
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True, text=True,
+                         timeout=600, check=True).stdout
+    return json.loads(out.strip().splitlines()[-1])
+
+
+def cpu_d3q19(n=128, steps=10):
+    """The D3Q19 oracle on a 128^3 sample of the 256^3 spinodal workload (same parameters)."""
+    import oracle
+    from paper_1511_02155_amd import inputs
+
+    w = inputs.spinodal_3d(n, steps)
+    p = oracle.Params(**{k: w[k] for k in _PKEYS})
+    pop = oracle.init_equilibrium(p, w["C"]())
+    oracle.step(p, pop, 1)
+    t0 = time.perf_counter()
+    oracle.step(p, pop, steps)
+    dt = time.perf_counter() - t0
+    return dict(value=p.N * steps / dt / 1e6, unit="MLUPS", cores=_cpu_threads(), kind="oracle",
+                sample=f"D3Q19 {n}^3 spinodal FP64, {steps} steps after 1 warm-up step, {dt:.1f} s")
+
+
+def cpu_batched(ndom=48, steps=40):
+    """The oracle stepping the first domains of the 512-domain batch one after another (walls, per-domain
+    kappa and h)."""
+    import oracle
+    from paper_1511_02155_amd import inputs
+
+    doms = inputs.batched_walls()[:ndom]
+    runs = []
+    for d in doms:
+        p = oracle.Params(**{k: d[k] for k in _PKEYS})
+        runs.append((p, oracle.init_equilibrium(p, d["C"], None, d["h"]), d["h"]))
+    t0 = time.perf_counter()
+    for p, pop, h in runs:
+        oracle.step(p, pop, steps, h)
+    dt = time.perf_counter() - t0
+    nodes = sum(p.N for p, _, _ in runs)
+    return dict(value=nodes * steps / dt / 1e6, unit="MLUPS", cores=_cpu_threads(), kind="oracle",
+                sample=f"domains 0-{ndom - 1} of the batch ({nodes} nodes), {steps} steps each, {dt:.1f} s")
+
+
+def cpu_gradient(steps=10):
+    """Reverse mode on the CPU: autograd through the PyTorch FP64 re-expression of the step (the reference
+    of the GPU adjoint) on the 512^2 walled drop; the rate counts nodes x steps of the whole gradient
+    (forward and backward)."""
+    import torch
+    import oracle
+    from oracle import torch_ref
+    from paper_1511_02155_amd import inputs
+
+    w = inputs.adjoint_drop_512()
+    p = oracle.Params(**{k: w[k] for k in _PKEYS})
+    pop0 = oracle.init_equilibrium(p, w["C"], None, w["h"])
+    t0 = torch.tensor(pop0.reshape(3, 9, w["ny"], w["nx"]))
+    hh = torch.tensor(w["h"].reshape(2, 3, w["nx"]))
+    args = (hh, torch.tensor(w["kappa"], dtype=torch.float64), w["alpha"], (w["tau_f"], w["tau_g"], w["tau_k"]),
+            (w["gamma_phi"], w["gamma_psi"]), True)
+    tgt = torch.tensor(w["target"].reshape(w["ny"], w["nx"]))
+    tic = time.perf_counter()
+    torch_ref.loss_and_grads(t0, *args, steps, tgt)
+    dt = time.perf_counter() - tic
+    return dict(value=p.N * steps / dt / 1e6, unit="MLUPS (gradient)", cores=torch.get_num_threads(),
+                kind="oracle (autograd through the PyTorch FP64 step)",
+                sample=f"512^2 walled drop, loss and gradients over {steps} step(s), {dt:.1f} s")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -349,7 +430,17 @@ def main():
     }
     if not args.no_cpu and hname == "d2q9_1024x1024_spinodal_f64":
         print(f"[bench] cpu oracle, {args.cpu_steps} steps", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(w2, args.cpu_steps)
+        cb = cpu_baseline(w2, args.cpu_steps)
+        if every:
+            # the other forms against the oracle on bounded samples, and the headline on one thread
+            print("[bench] cpu oracle: one thread, d3q19, batch, gradient", file=sys.stderr, flush=True)
+            forms = {"d2q9_1024x1024_spinodal_f64_one_thread": (cpu_single_thread(), head["mlups"]),
+                     "d3q19_256cube_spinodal": (cpu_d3q19(), res["d3q19_256cube_spinodal_f32"]["mlups"]),
+                     "batched_512_domains": (cpu_batched(), res["batched_512_domains_f32"]["mlups"]),
+                     "adjoint_512x512_wall_drop_gradient": (cpu_gradient(),
+                                                            res["adjoint_512x512_wall_drop_f64"]["gradient_mlups"])}
+            cb["forms"] = {k: dict(v, gpu_mlups=g, gpu_over_cpu=g / v["value"]) for k, (v, g) in forms.items()}
+        line["cpu_baseline"] = cb
     res["copy_kernel_GBps"] = copy_gbps
     line["extra"] = res
     print(json.dumps(line))

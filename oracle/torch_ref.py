@@ -8,7 +8,7 @@ parameters h_m and the bulk coefficients kappa_m.  It serves as the
 reference for the GPU adjoint; it is pinned to the C oracle (same forward
 map to rounding) and to central finite differences of the C oracle.
 
-Only the test suite may import it.  It shares no code with the C oracle or
+Only the test suite and the CPU baseline of bench.py may import it.  It shares no code with the C oracle or
 with the GPU library.  Readings of the paper are those of tlb_oracle.c
 (R1-R9, R18); the state is the post-propagation populations [species][q][ny][nx].
 """
