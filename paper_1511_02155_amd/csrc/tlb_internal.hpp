@@ -37,7 +37,7 @@ __device__ __forceinline__ int xcd_item(int b, int G)
 template <typename T>
 hipError_t launch_step2d(const StepArgs<T>& a, int width, int hold, bool mrt, int nc, hipStream_t s);
 template <typename T>
-hipError_t launch_step3d(const StepArgs<T>& a, int width, int height, int hold, bool mrt, hipStream_t s);
+hipError_t launch_step3d(const StepArgs<T>& a, int width, int height, int variant, bool mrt, hipStream_t s);
 
 // Auxiliary kernels (tlb_aux.hip).
 struct AuxGeom {

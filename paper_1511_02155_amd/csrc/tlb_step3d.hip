@@ -86,12 +86,18 @@ struct PlaneFull {
     T c[3], A[3], Dx[3], Dy[3], E[3], Fx[3], Fy[3];
 };
 
-// HOLD selects between keeping the pulled populations of plane z+1 in
-// registers and pulling plane z again (from cache) when it is collided.
-template <typename T, int BX, int BY, bool HOLD, bool MRT>
+// VAR 0 pulls plane z again (from cache) when it is collided; VAR 1 keeps
+// the pulled populations of plane z+1 in registers instead.  VAR 2 also
+// pipelines the sweep: the loads of plane z+2 (own column and ring node) are
+// issued before plane z is collided and reduced after it, so that their
+// latency overlaps the collision, and the populations of plane z+1 wait in
+// registers for its collision.  All three hold one wavefront per SIMD; VAR 2
+// needs about 490 registers (FP32 storage) and is meant for FP32 storage.
+template <typename T, int BX, int BY, int VAR, bool MRT>
 __global__ __launch_bounds__(BX* BY) void k_step3d(StepArgs<T> A)
 {
     using C = acc_t<T>;
+    constexpr bool HOLD = VAR == 1;
     __shared__ C lds[2][3][BY + 2][BX + 2];
 
     const int item = xcd_item(blockIdx.x, A.nitems);
@@ -202,6 +208,55 @@ __global__ __launch_bounds__(BX* BY) void k_step3d(StepArgs<T> A)
         buf ^= 1;
     };
 
+    // VAR 2: the loads of plane z (own column, and the ring node on ring lanes)
+    // into fc/gc/kc and rf/rg/rk, and their reduction to C_m and plane sums
+    // later (the same operations in the same order as plane()).
+    T rf[19], rg[19], rk[19];
+    auto issue = [&](int z) {
+        pull3d<T>(A, rs, col, z, wall_tile, blo, bhi, fc, gc, kc);
+        if (ring) pull3d<T>(A, rs, hcol, z, wall_tile, hblo, hbhi, rf, rg, rk);
+    };
+    auto finish = [&](int z, PlaneFull<C>& p) {
+        const Moments<C> mo = moments<L19>(fc, gc, kc);
+        conc_dev<C>(mo, p.c);
+        if (active) {
+#pragma unroll
+            for (int m = 0; m < 3; ++m) lds[buf][m][ty + 1][tx + 1] = p.c[m];
+        }
+        if (ring) {
+            Moments<C> hm = moments<L19>(rf, rg, rk);
+            C hc[3];
+            conc_dev<C>(hm, hc);
+            if (gwall >= 0) {
+                const T* __restrict__ wt = A.wet + (size_t)gwall * 3 * nxz + gx + (uint32_t)A.nx * z;
+#pragma unroll
+                for (int m = 0; m < 3; ++m) hc[m] += C(wt[m * nxz]);
+            }
+#pragma unroll
+            for (int m = 0; m < 3; ++m) lds[buf][m][hy + 1][hx + 1] = hc[m];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            const C l = lds[buf][m][ty + 1][tx];
+            const C r = lds[buf][m][ty + 1][tx + 2];
+            const C d = lds[buf][m][ty][tx + 1];
+            const C u = lds[buf][m][ty + 2][tx + 1];
+            const C ld = lds[buf][m][ty][tx];
+            const C rd = lds[buf][m][ty][tx + 2];
+            const C lu = lds[buf][m][ty + 2][tx];
+            const C ru = lds[buf][m][ty + 2][tx + 2];
+            p.A[m] = (l + r) + (d + u);
+            p.Dx[m] = r - l;
+            p.Dy[m] = u - d;
+            p.E[m] = (ld + rd) + (lu + ru);
+            p.Fx[m] = (rd + ru) - (ld + lu);
+            p.Fy[m] = (lu + ru) - (ld + rd);
+        }
+        buf ^= 1;
+    };
+    auto wrapz = [&](int z) { return z >= A.nz ? z - A.nz : z; };
+
     auto hold = [&]() {
         if constexpr (HOLD) {
 #pragma unroll
@@ -212,6 +267,77 @@ __global__ __launch_bounds__(BX* BY) void k_step3d(StepArgs<T> A)
             }
         }
     };
+
+    const uint32_t N = (uint32_t)A.N;
+    if constexpr (VAR == 2) {
+        T fh[19], gh[19], kh[19];  // populations of plane z+1, kept for its collision
+        // Prologue: planes z0 - 1 and z0 summed, the loads of z0 + 1 issued.
+        const int za = (z0 == 0) ? A.nz - 1 : z0 - 1;
+        issue(za);
+        finish(za, pc);
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            pa.c[m] = pc.c[m];
+            pa.A[m] = pc.A[m];
+            pa.Dx[m] = pc.Dx[m];
+            pa.Dy[m] = pc.Dy[m];
+        }
+        issue(z0);
+        finish(z0, pb);
+#pragma unroll
+        for (int i = 0; i < 19; ++i) {
+            fb[i] = fc[i];
+            gb[i] = gc[i];
+            kb[i] = kc[i];
+        }
+        issue(wrapz(z0 + 1));
+        for (int z = z0; z < z1; ++z) {
+            finish(wrapz(z + 1), pc);
+#pragma unroll
+            for (int i = 0; i < 19; ++i) {
+                fh[i] = fc[i];
+                gh[i] = gc[i];
+                kh[i] = kc[i];
+            }
+            if (z + 2 <= z1) issue(wrapz(z + 2));
+            C gC[3][3], lC[3];
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                gC[m][0] = pb.Dx[m] * C(1.0 / 6.0) + (pb.Fx[m] + pa.Dx[m] + pc.Dx[m]) * C(1.0 / 12.0);
+                gC[m][1] = pb.Dy[m] * C(1.0 / 6.0) + (pb.Fy[m] + pa.Dy[m] + pc.Dy[m]) * C(1.0 / 12.0);
+                gC[m][2] = (pc.c[m] - pa.c[m]) * C(1.0 / 6.0) + (pc.A[m] - pa.A[m]) * C(1.0 / 12.0);
+                lC[m] = (pb.A[m] + pa.c[m] + pc.c[m]) * C(1.0 / 3.0) +
+                        (pb.E[m] + pa.A[m] + pc.A[m]) * C(1.0 / 6.0) - pb.c[m] * C(4);
+            }
+            const Moments<C> mb = moments<L19>(fb, gb, kb);
+            collide<L19, MRT>(A.P, mb, pb.c, gC, lC, fb, gb, kb);
+            if (active) {
+                const uint32_t so = (uint32_t)z * (uint32_t)A.nx * (uint32_t)A.ny * (uint32_t)sizeof(T);
+                const uint32_t NB = N * (uint32_t)sizeof(T);
+#pragma unroll
+                for (int i = 0; i < 19; ++i) {
+                    bstore<T>(fb[i], rd[0], col[1][1], so + (uint32_t)i * NB);
+                    bstore<T>(gb[i], rd[1], col[1][1], so + (uint32_t)i * NB);
+                    bstore<T>(kb[i], rd[2], col[1][1], so + (uint32_t)i * NB);
+                }
+            }
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                pa.c[m] = pb.c[m];
+                pa.A[m] = pb.A[m];
+                pa.Dx[m] = pb.Dx[m];
+                pa.Dy[m] = pb.Dy[m];
+            }
+            pb = pc;
+#pragma unroll
+            for (int i = 0; i < 19; ++i) {
+                fb[i] = fh[i];
+                gb[i] = gh[i];
+                kb[i] = kh[i];
+            }
+        }
+        return;
+    }
 
     // Prologue: planes z0 - 1 and z0.
     {
@@ -228,7 +354,6 @@ __global__ __launch_bounds__(BX* BY) void k_step3d(StepArgs<T> A)
         hold();
     }
 
-    const uint32_t N = (uint32_t)A.N;
     for (int z = z0; z < z1; ++z) {
         const int zn = (z + 1 == A.nz) ? 0 : z + 1;
         plane(zn, pc);
@@ -270,22 +395,28 @@ __global__ __launch_bounds__(BX* BY) void k_step3d(StepArgs<T> A)
 }
 
 template <typename T>
-hipError_t launch_step3d(const StepArgs<T>& a, int width, int height, int hold, bool mrt, hipStream_t s)
+hipError_t launch_step3d(const StepArgs<T>& a, int width, int height, int variant, bool mrt, hipStream_t s)
 {
     dim3 grid(a.nitems);
-#define TLB_L3(BX, BY, H, M)                                                           \
-    if (width == BX && height == BY && (hold != 0) == H && mrt == M) {                 \
-        hipLaunchKernelGGL((k_step3d<T, BX, BY, H, M>), grid, dim3(BX * BY), 0, s, a); \
+#define TLB_L3(BX, BY, V, M)                                                           \
+    if (width == BX && height == BY && variant == V && mrt == M) {                     \
+        hipLaunchKernelGGL((k_step3d<T, BX, BY, V, M>), grid, dim3(BX * BY), 0, s, a); \
         return hipGetLastError();                                                      \
     }
-    TLB_L3(32, 8, false, false)
-    TLB_L3(64, 4, false, false)
-    TLB_L3(32, 8, true, false)
-    TLB_L3(64, 4, true, false)
-    TLB_L3(32, 8, false, true)
-    TLB_L3(64, 4, false, true)
-    TLB_L3(32, 8, true, true)
-    TLB_L3(64, 4, true, true)
+    TLB_L3(32, 8, 0, false)
+    TLB_L3(64, 4, 0, false)
+    TLB_L3(32, 8, 1, false)
+    TLB_L3(64, 4, 1, false)
+    TLB_L3(32, 8, 0, true)
+    TLB_L3(64, 4, 0, true)
+    TLB_L3(32, 8, 1, true)
+    TLB_L3(64, 4, 1, true)
+    if constexpr (sizeof(T) == 4) {  // VAR 2 is built for FP32 storage only
+        TLB_L3(32, 8, 2, false)
+        TLB_L3(64, 4, 2, false)
+        TLB_L3(32, 8, 2, true)
+        TLB_L3(64, 4, 2, true)
+    }
 #undef TLB_L3
     return hipErrorInvalidValue;
 }

@@ -155,7 +155,7 @@ def test_d2q9_walls_fp32(tlb, orc, width, hold):
     _compare_f32(orc, p, pop, h, s)
 
 
-@pytest.mark.parametrize("tile", [(32, 8, 0), (64, 4, 0), (32, 8, 1), (64, 4, 1)])
+@pytest.mark.parametrize("tile", [(32, 8, 0), (64, 4, 0), (32, 8, 1), (64, 4, 1), (32, 8, 2), (64, 4, 2)])
 def test_d3q19_fp32(tlb, orc, tile):
     w, C, h = _wet_case(40, 34, 12, lattice=1, walls=1)
     p, pop, s = _run_both(tlb, orc, w, C, h, 60, tlb.TLB_F32,
@@ -187,13 +187,13 @@ def test_launch_shapes_bitwise_identical(tlb):
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_d3q19_launch_shapes_bitwise_identical(tlb, prec):
-    """For each variant (plane z pulled again, or held from the previous plane) both tiles and every
-    chunk give the same bits.  The variants are separate kernels in which the compiler may fuse a
+    """For each variant (plane z pulled again, held from the previous plane, or held with the loads of
+    plane z+2 in flight; the last for FP32 storage) both tiles and every chunk give the same bits.  The variants are separate kernels in which the compiler may fuse a
     different set of multiply-adds, so across variants the results agree to rounding."""
     w, C, h = _wet_case(70, 19, 11, lattice=1, walls=1)
     P = tlb.TLB_F64 if prec == "f64" else tlb.TLB_F32
     per_variant = {}
-    for variant in (0, 1):
+    for variant in ((0, 1, 2) if prec == "f32" else (0, 1)):
         for tile in ((32, 8), (64, 4)):
             for chunk in (1, 4, 11):
                 _note(f"d3q19 {prec} tile {tile} chunk {chunk} variant {variant}")
@@ -209,7 +209,8 @@ def test_d3q19_launch_shapes_bitwise_identical(tlb, prec):
                     assert np.array_equal(got, per_variant[variant]), (tile, chunk, variant)
     ref = per_variant[0]
     tol = 1e-13 * np.abs(ref).max() if prec == "f64" else 1e-6
-    assert np.abs(per_variant[1] - ref).max() <= tol
+    for variant in per_variant:
+        assert np.abs(per_variant[variant] - ref).max() <= tol, variant
 
 
 def test_launch_validation(tlb):
@@ -217,14 +218,17 @@ def test_launch_validation(tlb):
     w3, _, _ = _wet_case(20, 12, 8, lattice=1)
     s2 = _gsim(tlb, w2, tlb.TLB_F64)
     s3 = _gsim(tlb, w3, tlb.TLB_F32)
+    s3d = _gsim(tlb, w3, tlb.TLB_F64)
     for s, bad in ((s2, dict(width=96, chunk=4, variant=0)), (s2, dict(width=64, chunk=-1, variant=0)),
-                   (s2, dict(width=64, chunk=4, variant=2)), (s3, dict(width=64, height=8, chunk=4, variant=0)),
-                   (s3, dict(width=32, height=8, chunk=4, variant=2))):
+                   (s2, dict(width=64, chunk=4, variant=2)),  # the pipelined sweep is a D3Q19 variant
+                   (s3, dict(width=64, height=8, chunk=4, variant=0)), (s3, dict(width=32, height=8, chunk=4, variant=3)),
+                   (s3d, dict(width=32, height=8, chunk=4, variant=2))):  # pipelined sweep: FP32 storage only
         with pytest.raises(tlb.TLBError):
             s.set_launch(**bad)
-    s3.set_launch(width=32, height=8, chunk=4, variant=1)
+    s3.set_launch(width=32, height=8, chunk=4, variant=2)
     s2.close()
     s3.close()
+    s3d.close()
 
 
 def test_run_twice_is_deterministic_and_restart_continues(tlb):
