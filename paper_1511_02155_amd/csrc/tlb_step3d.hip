@@ -210,7 +210,10 @@ __global__ __launch_bounds__(BX* BY) void k_step3d(StepArgs<T> A)
 
     // VAR 2: the loads of plane z (own column, and the ring node on ring lanes)
     // into fc/gc/kc and rf/rg/rk, and their reduction to C_m and plane sums
-    // later (the same operations in the same order as plane()).
+    // later (the same operations in the same order as plane()).  plane() keeps
+    // its own copy of the reduction: issuing the ring pull before the own
+    // column's moments, as issue() does, costs variants 0 and 1 about 60 more
+    // registers.
     T rf[19], rg[19], rk[19];
     auto issue = [&](int z) {
         pull3d<T>(A, rs, col, z, wall_tile, blo, bhi, fc, gc, kc);
