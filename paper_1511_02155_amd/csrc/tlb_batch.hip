@@ -45,6 +45,7 @@ struct BatchArgs {
     const DomDesc<T>* doms;
     const int2* items;  // {domain, strip << 16 | chunk}
     const int* qstart;  // [9]: queue k holds items [qstart[k], qstart[k+1])
+    // (flat items: {domain, first segment | count << 16 | downward << 31})
     int* counters;      // [2][8]
     int parity;
 };
@@ -95,16 +96,17 @@ struct BatchLds<T, W, true> {
     };
 };
 
-// Flat sweep of one work item of a domain with nx + 3 <= W.  A strip of W
+// Flat sweep of one work item of a domain with nx + 3 <= W: segments
+// [seg0, seg1), downwards if `down`.  A strip of W
 // lanes would leave W - nx lanes of every row idle; here the rows, each padded
 // with its two periodic halo columns (P = nx + 2 positions: the copy of
 // column nx-1, columns 0 .. nx-1, the copy of column 0), are laid end to end
 // and lane t of segment s owns position v = s W + t.  The x neighbours of an
 // interior position are v -+ 1 and the rows below and above are v -+ P, so a
 // node's nine neighbours lie within the segments before and after its own.
-// The item runs over segments [seg0, seg1), upwards for even items and
-// downwards for odd ones (neighbouring items meet at shared segments, as the
-// strips do), in the strip sweep's pipeline: C_m of segment k+1 (pulled and
+// Consecutive items of a domain alternate between upward and downward sweeps
+// (neighbouring items meet at shared segments, as the strips do).  The item
+// runs in the strip sweep's pipeline: C_m of segment k+1 (pulled and
 // summed by every lane, halo lanes included) goes to a ring of four segments
 // in LDS and its populations stay in registers; one barrier; then the
 // interior nodes of segment k take their stencils from the ring and collide.
@@ -114,7 +116,7 @@ struct BatchLds<T, W, true> {
 // moments, concentrations, ghost rows, stencil9, collide), so the results are
 // bitwise those of the strip sweep.
 template <typename T, int W>
-__device__ __forceinline__ void flat2d(const StepArgs<T>& A, int item, FlatLds<T, W>& S)
+__device__ __forceinline__ void flat2d(const StepArgs<T>& A, int seg0, int seg1, bool down, FlatLds<T, W>& S)
 {
     using C = acc_t<T>;
     constexpr int RM = 4 * W - 1;
@@ -122,8 +124,6 @@ __device__ __forceinline__ void flat2d(const StepArgs<T>& A, int item, FlatLds<T
     const int t = threadIdx.x;
     const int nx = A.nx, ny = A.ny, P = nx + 2, NP = ny * P;
     const bool walls = A.walls != 0;
-    const int nseg = (NP + W - 1) / W;
-    const int seg0 = item * A.chunk, seg1 = min(seg0 + A.chunk, nseg);
     const uint32_t NU = (uint32_t)A.N;
     const uint32_t sbytes = (uint32_t)(27 * A.N * (int64_t)sizeof(T));
     const Rsrc rs = make_rsrc(A.src, sbytes);
@@ -197,7 +197,7 @@ __device__ __forceinline__ void flat2d(const StepArgs<T>& A, int item, FlatLds<T
 #pragma unroll
     for (int i = 0; i < 27; ++i) P0[i] = P1[i] = T(0);
     Moments<C, 3> M0, M1;
-    const int d = (item & 1) ? -1 : 1;
+    const int d = down ? -1 : 1;
     const int kb = d > 0 ? seg0 : seg1 - 1;  // first segment collided
     const int n = seg1 - seg0;
     cpass(kb - d, P1, M1);
@@ -269,7 +269,7 @@ void k_batch2d(BatchArgs<T> B)
         A.P = D.P;
         if constexpr (MODE == 2) {
             if (D.flat)
-                flat2d<T, W>(A, w.y & 0xffff, S.flat);
+                flat2d<T, W>(A, w.y & 0xffff, (w.y & 0xffff) + ((w.y >> 16) & 0x7fff), w.y < 0, S.flat);
             else
                 sweep2d<T, W, DEPTH>(A, w.y >> 16, w.y & 0xffff, S.strip);
         } else {
@@ -406,7 +406,9 @@ static void drop_graph(tlb_batch* b)
 
 // Work items and queues for the current launch shape: domains go to the
 // least-loaded queue in decreasing size; within a queue, larger domains come
-// first and the strips of one chunk are adjacent.
+// first and the strips of one chunk are adjacent.  The flat items in the last
+// quarter of a queue's work are halved, so that the workgroups run out of
+// work at nearly the same time.
 template <typename T>
 static tlb_status build_items(tlb_batch* b)
 {
@@ -417,7 +419,11 @@ static tlb_status build_items(tlb_batch* b)
         return (int64_t)b->p[a].nx * b->p[a].ny > (int64_t)b->p[c].nx * b->p[c].ny;
     });
     std::vector<std::vector<int2>> q(kQueues);
+    std::vector<std::vector<int64_t>> qcost(kQueues);  // lane-rows of each item
     std::vector<int64_t> load(kQueues, 0);
+    auto flat_item = [](int d, int seg0, int cnt, bool down) {
+        return make_int2(d, (int)((uint32_t)seg0 | (uint32_t)cnt << 16 | (down ? 0x80000000u : 0u)));
+    };
     std::vector<DomDesc<T>> dd(b->ndom);
     for (int d : order) {
         const tlb_params& p = b->p[d];
@@ -433,10 +439,16 @@ static tlb_status build_items(tlb_batch* b)
             // flat sweep: items of `rows` segments of W positions of the padded rows
             const int64_t nseg = ((int64_t)(p.nx + 2) * p.ny + W - 1) / W;
             D.flat = 1;
-            D.chunk = (int)std::min<int64_t>(rows, nseg);
+            D.chunk = (int)std::min<int64_t>(std::min(rows, 0x7fff), nseg);
             D.ntx = 1;
             D.nchunks = (int)((nseg + D.chunk - 1) / D.chunk);
             load[k] += nseg * W;
+            for (int c = 0; c < D.nchunks; ++c) {
+                const int s0 = c * D.chunk, cnt = (int)std::min<int64_t>(D.chunk, nseg - s0);
+                q[k].push_back(flat_item(d, s0, cnt, c & 1));
+                qcost[k].push_back((int64_t)cnt * W);
+            }
+            continue;
         } else {
             D.flat = 0;
             D.chunk = std::min(rows, p.ny);
@@ -445,7 +457,29 @@ static tlb_status build_items(tlb_batch* b)
             load[k] += (int64_t)D.ntx * W * p.ny;
         }
         for (int c = 0; c < D.nchunks; ++c)
-            for (int s = 0; s < D.ntx; ++s) q[k].push_back(make_int2(d, (s << 16) | c));
+            for (int s = 0; s < D.ntx; ++s) {
+                q[k].push_back(make_int2(d, (s << 16) | c));
+                qcost[k].push_back((int64_t)W * std::min(D.chunk, p.ny - c * D.chunk));
+            }
+    }
+    for (int k = 0; k < kQueues; ++k) {
+        int64_t total = 0, cum = 0;
+        for (int64_t c : qcost[k]) total += c;
+        std::vector<int2> split;
+        for (size_t i = 0; i < q[k].size(); ++i) {
+            const int2 it = q[k][i];
+            const int cnt = (it.y >> 16) & 0x7fff;
+            if (dd[it.x].flat && cnt >= 2 && 4 * cum >= 3 * total) {
+                const int s0 = it.y & 0xffff, h = cnt / 2;
+                const bool down = it.y < 0;
+                split.push_back(flat_item(it.x, s0, h, down));
+                split.push_back(flat_item(it.x, s0 + h, cnt - h, !down));
+            } else {
+                split.push_back(it);
+            }
+            cum += qcost[k][i];
+        }
+        q[k].swap(split);
     }
     std::vector<int2> items;
     std::vector<int> qs(kQueues + 1, 0);
