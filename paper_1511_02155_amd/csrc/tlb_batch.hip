@@ -9,9 +9,9 @@
 // queue counters of the next step are cleared inside the kernel, so a chain
 // of steps can be captured once in a hipGraph and replayed.  Each work item
 // runs the same strip sweep as the single-lattice kernel, or (variant 2, for
-// domains no wider than a workgroup) a flat sweep over the row-major node
-// order with the same arithmetic, so a domain's result is bit-for-bit the one
-// a single tlb_sim of that domain produces.
+// domains with nx + 3 <= workgroup width) a flat sweep over the domain's
+// padded rows laid end to end, with the same arithmetic, so a domain's result
+// is bit-for-bit the one a single tlb_sim of that domain produces.
 #include <math.h>
 #include <stdio.h>
 #include <stdlib.h>
