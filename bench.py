@@ -340,7 +340,7 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print("bench.py measures one GPU: the fused step is single-device in this build "
+        print("bench.py measures one GPU: the fused step runs on a single device "
               f"(requested --gpus {args.gpus}).", file=sys.stderr)
         sys.exit(2)
 
