@@ -16,7 +16,7 @@
  *     half-way bounce-back, in that order;
  *   - node index n = x + nx*(y + ny*z); populations stored [species][q][n].
  *
- * Readings of the paper used here (each one is listed in the design doc):
+ * Readings of the paper used here:
  *   R1  mu_phi and mu_psi are written in the equivalent compact form
  *       mu_phi = (mu1 - mu2)/2, mu_psi = mu3 - (mu1 + mu2)/2 with
  *       mu_m = kappa_m C_m (1-C_m)(1-2C_m) - alpha^2 kappa_m lap C_m
