@@ -15,7 +15,7 @@ void k_step2d(StepArgs<T> A)
     sweep2d<T, W, DEPTH, MRT, NC>(A, strip, chunk, S);
 }
 
-// Instantiated: three components with both depths, four and five (Sec. II.E) with depth 0.
+// Instantiated: three, four and five components (Sec. II.E), both depths.
 template <typename T>
 hipError_t launch_step2d(const StepArgs<T>& a, int width, int depth, bool mrt, int nc, hipStream_t s)
 {
@@ -34,6 +34,10 @@ hipError_t launch_step2d(const StepArgs<T>& a, int width, int depth, bool mrt, i
     TLB_L2W(0, true, 4)
     TLB_L2W(0, false, 5)
     TLB_L2W(0, true, 5)
+    TLB_L2W(1, false, 4)
+    TLB_L2W(1, true, 4)
+    TLB_L2W(1, false, 5)
+    TLB_L2W(1, true, 5)
 #undef TLB_L2W
 #undef TLB_L2
     return hipErrorInvalidValue;

@@ -80,8 +80,10 @@ def _gpu(tlb, w, C, u, h, steps, prec, launch=None, **extra):
 @pytest.mark.parametrize("NC,nx,ny,walls,launch", [
     (4, 70, 23, 1, dict(width=64, chunk=5, variant=0)),
     (4, 131, 19, 0, dict(width=128, chunk=7, variant=0)),
+    (4, 70, 23, 1, dict(width=256, chunk=4, variant=1)),
     (5, 300, 11, 1, dict(width=256, chunk=3, variant=0)),
     (5, 45, 30, 0, dict(width=64, chunk=30, variant=0)),
+    (5, 131, 19, 1, dict(width=128, chunk=6, variant=1)),
 ])
 def test_ncomp_fp64_against_the_oracle(env, NC, nx, ny, walls, launch):
     torch, tlb = env
@@ -99,6 +101,24 @@ def test_ncomp_fp64_against_the_oracle(env, NC, nx, ny, walls, launch):
     for m in range(NC):
         assert np.abs(s.field(f"C{m + 1}") - Cref[m]).max() <= 1e-12, m
     s.close()
+
+
+@pytest.mark.parametrize("NC", [4, 5])
+def test_ncomp_launch_shapes_bitwise_identical(env, NC):
+    torch, tlb = env
+    w, C, u, h = _case(NC, 90, 26, 1, seed=NC + 40)
+    ref = None
+    for width in (64, 256):
+        for chunk in (3, 9):
+            for variant in (0, 1):
+                _note(f"ncomp {NC} shape width={width} chunk={chunk} variant={variant}")
+                s = _gpu(tlb, w, C, u, h, 15, tlb.TLB_F64, dict(width=width, chunk=chunk, variant=variant))
+                got = s.all_populations()
+                s.close()
+                if ref is None:
+                    ref = got
+                else:
+                    assert np.array_equal(got, ref), (width, chunk, variant)
 
 
 def test_ncomp_mrt_fp64(env):
@@ -155,7 +175,8 @@ def test_ncomp_limits_are_enforced(env):
     p = tlb.make_params(prec=tlb.TLB_F64, **w)
     s = tlb.Sim(p)
     with pytest.raises(tlb.TLBError):
-        s.set_launch(64, chunk=4, variant=1)  # no row prefetch with more than three components
+        s.set_launch(64, chunk=4, variant=2)  # D2Q9 has variants 0 and 1
+    s.set_launch(64, chunk=4, variant=1)
     with pytest.raises(tlb.TLBError):
         s.field(13)
     s.set_wetting_both(h)
