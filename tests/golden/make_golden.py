@@ -7,7 +7,7 @@ nodes, written with 17 significant digits.
 
     python tests/golden/make_golden.py [spinodal2d] [spinodal3d] [batched] [adjoint]
 
-Run times on 8 cores: spinodal2d ~10 min, spinodal3d ~1-2 h, batched and
+Run times on 8 shared cores: spinodal2d ~50 min, spinodal3d ~6.5 h, batched and
 adjoint ~1 min each.
 """
 from __future__ import annotations
