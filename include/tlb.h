@@ -168,7 +168,8 @@ const char* tlb_status_str(int status);
 int tlb_last_hip_error(void);
 /* ABI version (major * 100 + minor); 2xx: tlb_params.no_advection and tlb_diag.interface;
  * 3xx: tlb_params.collision, tau_bulk, tau_ghost; 4xx: tlb_params.ncomp, kappa_hi and
- * tlb_diag.mass_hi, interface_hi (N components). */
+ * tlb_diag.mass_hi, interface_hi (N components); 5xx: tlb_adjoint_step (in place) and the
+ * wetting range counts. */
 int tlb_version(void);
 
 /*
@@ -184,10 +185,19 @@ tlb_status tlb_get_params(const tlb_sim* sim, tlb_params* out);
 /*
  * Wetting parameters h_m of one wall (Sec. II.B, eq. Cahn): wall 0 = below
  * y = 0, wall 1 = above y = ny-1; h: host array [N][nx*nz] (N components,
- * 3 unless tlb_params.ncomp says more), finite values.
+ * 3 unless tlb_params.ncomp says more), finite values (TLB_EINVAL otherwise).
  * Requires walls_y == 1.  Takes effect from the next step (or initialisation).
+ * Values with |4 h_m / (alpha kappa_m)| > 1 lie outside the range in which the
+ * surface free energy of Sec. II.B gives closed-form wall concentrations and
+ * contact angles; they are accepted and applied as given (the ghost-row
+ * condition alpha^2 kappa_m d_perp C_m = -h_m does not need that range), the
+ * first such call of a simulation prints one warning line to stderr, and
+ * tlb_wetting_outside_range reports how many values of both walls are outside
+ * it (-1 if a wall was last set through tlb_set_wetting_dev, whose device
+ * values are not inspected).  tlb_set_kappa recounts.
  */
 tlb_status tlb_set_wetting(tlb_sim* sim, int wall, const double* h);
+tlb_status tlb_wetting_outside_range(const tlb_sim* sim, int64_t* count);
 
 /*
  * Initialise s_0 to the equilibria of the concentration fields C (host,
@@ -197,7 +207,14 @@ tlb_status tlb_set_wetting(tlb_sim* sim, int wall, const double* h);
  */
 tlb_status tlb_init_equilibrium(tlb_sim* sim, const double* C, const double* u);
 
-/* Advance the state by nsteps >= 0 time steps (asynchronous on the stream). */
+/* Advance the state by nsteps >= 0 time steps (asynchronous on the stream).
+ * One time step is the lattice Boltzmann update of Sec. IV: collision of f, g
+ * and k towards their equilibria (eq. latboltCollision, with the equilibria of
+ * eq. eqdistfbinary built from the chemical potentials and pressure tensor of
+ * Sec. III and the wetting condition of Sec. II.B) followed by propagation
+ * (eq. latboltPropagation) with half-way bounce-back at the walls.
+ * TLB_EINVAL for nsteps < 0, TLB_ESTATE before the state is initialised,
+ * TLB_ENAN from the periodic check of tlb_set_check_every. */
 tlb_status tlb_step(tlb_sim* sim, int64_t nsteps);
 
 /*
@@ -207,18 +224,28 @@ tlb_status tlb_step(tlb_sim* sim, int64_t nsteps);
  */
 tlb_status tlb_set_check_every(tlb_sim* sim, int64_t every);
 
-/* Macroscopic field `which` (TLB_FIELD_*) of the state s_t into host out[N]. */
+/* Macroscopic field `which` (TLB_FIELD_*) of the state s_t into host out[N]
+ * (TLB_EINVAL for an unknown selector, TLB_ESTATE before initialisation).
+ * rho, phi, psi and rho v are the moments of eq. lbconstraint (Sec. IV),
+ * v = (rho v) / rho; C1 = (rho + phi - psi)/2, C2 = (rho - phi - psi)/2,
+ * C3 = psi (Sec. II.C; C_l = psi_l for N > 3, Sec. II.E); mu_phi and mu_psi are
+ * the chemical potentials of Sec. III with the gradients of the step. */
 tlb_status tlb_get_field(tlb_sim* sim, int which, double* out);
 
 /* Post-propagation populations s_t of one species (0 f, 1 g, 2 .. ncomp-1 the
- * k sets of psi_3 ..) into host out[Q][N]. */
+ * k sets of psi_3 ..) into host out[Q][N]: the distributions of eq.
+ * latboltPropagation after the last step (TLB_EINVAL for an unknown species). */
 tlb_status tlb_get_populations(tlb_sim* sim, int species, double* out);
 
 /* Overwrite the populations s_t of one species from host in[Q][N]. */
 tlb_status tlb_set_populations(tlb_sim* sim, int species, const double* in);
 
-/* Mass, momentum, max |v| and a non-finite count of s_t.  Returns TLB_ENAN
- * (with *out filled) when non-finite values are present. */
+/* Mass, momentum, max |v| and a non-finite count of s_t, from the moments of
+ * eq. lbconstraint (Sec. IV): sum rho, sum phi and sum psi are conserved by the
+ * collision and by propagation with bounce-back, and sum rho v on fully periodic
+ * lattices; max |v| is the spurious-velocity measure of the equilibria of Sec.
+ * V.A.  Sums run over the fluid nodes in a fixed order (reproducible).  Returns
+ * TLB_ENAN (with *out filled) when non-finite values are present. */
 tlb_status tlb_diagnostics(tlb_sim* sim, tlb_diag* out);
 
 /* Time steps taken since initialisation. */
@@ -300,7 +327,17 @@ tlb_status tlb_wetting_from_angles(const double* kappa, double alpha, double the
  *   checkpoint into internal scratch (every states) and traversed backwards.
  *   The simulation's own state is not changed.
  */
+/*
+ * tlb_adjoint_step: the in-place form of tlb_adjoint_step_dev.  lambda_dev
+ *   holds lambda_{t+1} on entry and lambda_t on return; dh_dev is
+ *   [2][3][nx*nz] FP64 (nz = 1), dkappa_dev [3] FP64, both accumulated (either
+ *   may be NULL).  It runs the same kernel into an internal buffer and copies
+ *   the result back, so it moves one more state than the out-of-place form.
+ *   The first reverse-mode call of a simulation allocates its adjoint buffers.
+ */
 tlb_status tlb_adjoint_seed_dev(tlb_sim* sim, const void* dLdC_dev, void* lambda_dev);
+tlb_status tlb_adjoint_step(tlb_sim* sim, const void* state_dev, void* lambda_dev, double* dh_dev,
+                            double* dkappa_dev);
 tlb_status tlb_adjoint_step_dev(tlb_sim* sim, const void* state_dev, const void* lambda_in_dev,
                                 void* lambda_out_dev, double* dh_dev, double* dkappa_dev);
 int64_t tlb_checkpoint_slots(int64_t nsteps, int64_t every);
@@ -390,7 +427,13 @@ int32_t tlb_batch_size(const tlb_batch* batch);
 int64_t tlb_batch_nodes(const tlb_batch* batch);
 void* tlb_batch_get_stream(const tlb_batch* batch);
 tlb_status tlb_batch_synchronize(tlb_batch* batch);
+/* Wetting parameters of one wall of one domain (host [3][nx]); values outside
+ * |4 h_m / (alpha kappa_m)| <= 1 are applied as given and counted as for
+ * tlb_set_wetting (one stderr warning per batch);
+ * tlb_batch_wetting_outside_range gives the count of one domain, or of all
+ * domains for dom = -1. */
 tlb_status tlb_batch_set_wetting(tlb_batch* batch, int32_t dom, int wall, const double* h);
+tlb_status tlb_batch_wetting_outside_range(const tlb_batch* batch, int32_t dom, int64_t* count);
 tlb_status tlb_batch_init_equilibrium(tlb_batch* batch, int32_t dom, const double* C, const double* u);
 tlb_status tlb_batch_step(tlb_batch* batch, int64_t nsteps);
 tlb_status tlb_batch_get_field(tlb_batch* batch, int32_t dom, int which, double* out);

@@ -13,6 +13,11 @@ of C0 under the wetting parameters given then); the gradients are those of
 the run from that state, so they do not include the dependence of the
 initial populations on h_bottom or kappa.
 
+A runner holds one checkpoint store and one set of parameters, so only the
+most recent ``TernaryLB.apply`` on a runner can be differentiated: a backward
+pass of an earlier call raises ``RuntimeError`` instead of returning the
+gradients of the later one.
+
 The library works on a stream of the runner's own.  Every call orders it
 after torch's current stream on entry and orders torch's current stream
 after it on exit, so tensors handed over in either direction are safe to use
@@ -52,6 +57,8 @@ class Runner:
             self.ckpt = torch.empty(slots * self.sim.state_bytes(), dtype=torch.uint8, device="cuda")
         tlb.check(tlb.tlb_save_state_dev(self.sim.handle, self.state0.data_ptr()), "tlb_save_state_dev")
         self.sim.synchronize()
+        # forward calls made so far; the checkpoints and parameters are those of the last one
+        self.generation = 0
 
     def _enter(self, *tensors):
         """Order the runner's stream after torch's current one; keep ``tensors`` alive for it."""
@@ -71,6 +78,7 @@ class Runner:
             self._leave()
 
     def forward(self):
+        self.generation += 1
         C = torch.empty((3, self.ny, self.nx), dtype=self.dtype, device="cuda")
         self._enter(C)
         tlb.check(tlb.tlb_load_state_dev(self.sim.handle, self.state0.data_ptr(), 0), "tlb_load_state_dev")
@@ -99,12 +107,18 @@ class TernaryLB(torch.autograd.Function):
     def forward(ctx, h_bottom, kappa, runner):
         runner.set_parameters(h_bottom, kappa)
         ctx.runner = runner
+        out = runner.forward()
+        ctx.generation = runner.generation
         ctx.h_meta = (h_bottom.dtype, h_bottom.device)
         ctx.k_meta = (kappa.dtype, kappa.device)
-        return runner.forward()
+        return out
 
     @staticmethod
     def backward(ctx, dLdC):
+        if ctx.generation != ctx.runner.generation:
+            raise RuntimeError("TernaryLB: the runner's checkpoints belong to a later forward call "
+                               f"({ctx.runner.generation}, this call was {ctx.generation}); only the most "
+                               "recent call on a runner can be differentiated")
         dh, dk = ctx.runner.backward(dLdC)
         return (dh[0].to(dtype=ctx.h_meta[0], device=ctx.h_meta[1]),
                 dk.to(dtype=ctx.k_meta[0], device=ctx.k_meta[1]), None)

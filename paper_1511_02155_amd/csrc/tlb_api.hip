@@ -1,6 +1,7 @@
 // C ABI of libtlb (declared in include/tlb.h): simulation objects, host and
 // device I/O, the step loop and the conservation check.
 #include <math.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -42,6 +43,9 @@ struct tlb_sim {
     bool ready;
     int64_t check_every;
     tlb_launch launch;
+    double* hhost;            // [2][nc][nx*nz] h_m as last set from the host (range report)
+    int64_t wet_outside[2];   // per wall: values with |4 h_m / (alpha kappa_m)| > 1, -1 if set from device memory
+    bool wet_warned;
 };
 
 static thread_local int g_last_hip = 0;
@@ -72,7 +76,7 @@ extern "C" const char* tlb_status_str(int s)
 }
 
 extern "C" int tlb_last_hip_error(void) { return g_last_hip; }
-extern "C" int tlb_version(void) { return 400; }
+extern "C" int tlb_version(void) { return 500; }
 
 static int ncomp_of(const tlb_params* p) { return p->ncomp == 0 ? 3 : p->ncomp; }
 
@@ -306,6 +310,7 @@ extern "C" tlb_status tlb_destroy(tlb_sim* s)
     if (s->diag_partial) (void)hipFree(s->diag_partial);
     if (s->diag_out) (void)hipFree(s->diag_out);
     if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
+    free(s->hhost);
     delete s;
     return TLB_OK;
 }
@@ -382,12 +387,53 @@ static tlb_status set_wet_impl(tlb_sim* s, int wall, const TIn* h_dev)
     return rescale_wet(s, wall);
 }
 
+// Wetting parameters outside the range where the wall free energy of Sec. II.B has the closed-form
+// wall values (|4 h_m / (alpha kappa_m)| <= 1) are allowed; they are counted, and the first time a
+// simulation receives one a warning goes to stderr.
+static void count_outside(tlb_sim* s, int wall)
+{
+    if (!s->hhost) return;
+    const int64_t n = (int64_t)s->p.nx * s->p.nz;
+    const double* h = s->hhost + (size_t)wall * s->nc * n;
+    int64_t c = 0;
+    for (int m = 0; m < s->nc; ++m) {
+        const double lim = 0.25 * s->p.alpha * kappa_of(s->p, m);
+        for (int64_t j = 0; j < n; ++j) c += fabs(h[m * n + j]) > lim;
+    }
+    s->wet_outside[wall] = c;
+    if (c > 0 && !s->wet_warned) {
+        s->wet_warned = true;
+        fprintf(stderr,
+                "libtlb: warning: %lld wetting parameters of wall %d have |4 h_m / (alpha kappa_m)| > 1, outside the "
+                "range of the closed-form wall concentrations and contact angles (Sec. II.B); the boundary condition "
+                "is still applied as given\n",
+                (long long)c, wall);
+    }
+}
+
+extern "C" tlb_status tlb_wetting_outside_range(const tlb_sim* s, int64_t* count)
+{
+    if (!s || !count) return TLB_EINVAL;
+    if (s->wet_outside[0] < 0 || s->wet_outside[1] < 0) {
+        *count = -1;
+        return TLB_OK;
+    }
+    *count = s->wet_outside[0] + s->wet_outside[1];
+    return TLB_OK;
+}
+
 extern "C" tlb_status tlb_set_wetting(tlb_sim* s, int wall, const double* h)
 {
     if (!s || !h || (wall != 0 && wall != 1) || !s->p.walls_y) return TLB_EINVAL;
     const size_t n = (size_t)s->nc * s->p.nx * s->p.nz;
     for (size_t j = 0; j < n; ++j)
         if (!isfinite(h[j])) return TLB_EINVAL;
+    if (!s->hhost) {
+        s->hhost = (double*)calloc(2 * n, sizeof(double));
+        if (!s->hhost) return TLB_ENOMEM;
+    }
+    memcpy(s->hhost + (size_t)wall * n, h, n * sizeof(double));
+    count_outside(s, wall);
     tlb_status st = ensure_staging(s, n);
     if (st) return st;
     HIPCHK(hipMemcpyAsync(s->staging, h, n * sizeof(double), hipMemcpyHostToDevice, s->stream));
@@ -400,6 +446,7 @@ extern "C" tlb_status tlb_set_wetting(tlb_sim* s, int wall, const double* h)
 extern "C" tlb_status tlb_set_wetting_dev(tlb_sim* s, int wall, const void* h_dev)
 {
     if (!s || !h_dev || (wall != 0 && wall != 1) || !s->p.walls_y) return TLB_EINVAL;
+    s->wet_outside[wall] = -1;  // device values are not inspected on the host
     if (s->p.prec == TLB_F32) return set_wet_impl<float>(s, wall, (const float*)h_dev);
     return set_wet_impl<double>(s, wall, (const double*)h_dev);
 }
@@ -851,6 +898,8 @@ extern "C" tlb_status tlb_set_kappa(tlb_sim* s, const double* kappa)
         tlb_status st = rescale_wet(s, 0);
         if (!st) st = rescale_wet(s, 1);
         if (st) return st;
+        for (int w = 0; w < 2; ++w)
+            if (s->wet_outside[w] >= 0) count_outside(s, w);
     }
     return TLB_OK;
 }
@@ -966,6 +1015,19 @@ extern "C" tlb_status tlb_adjoint_step_dev(tlb_sim* s, const void* state, const 
     if (!st) st = adj_step_any(s, state, lam_in, lam_out, dh_target(s, dh));
     if (!st) st = kpart_reduce(s, dkappa);
     return st;
+}
+
+extern "C" tlb_status tlb_adjoint_step(tlb_sim* s, const void* state, void* lam, double* dh, double* dkappa)
+{
+    if (!s || !state || !lam) return TLB_EINVAL;
+    if (s->p.lattice != TLB_D2Q9 || s->p.collision != TLB_BGK || s->nc != 3) return TLB_EINVAL;
+    tlb_status st = adj_alloc(s, 0);
+    if (!st) st = kpart_clear(s);
+    if (!st) st = adj_step_any(s, state, lam, s->lam[0], dh_target(s, dh));
+    if (!st) st = kpart_reduce(s, dkappa);
+    if (st) return st;
+    HIPCHK(hipMemcpyAsync(lam, s->lam[0], (size_t)tlb_state_bytes(s), hipMemcpyDeviceToDevice, s->stream));
+    return TLB_OK;
 }
 
 extern "C" int64_t tlb_checkpoint_slots(int64_t nsteps, int64_t every)

@@ -352,6 +352,8 @@ struct tlb_batch {
     int graph_steps;
     hipGraphExec_t graph_exec;
     hipGraph_t graph;
+    std::vector<int64_t> wet_outside;  // [dom][wall]: wetting values with |4 h_m / (alpha kappa_m)| > 1
+    bool wet_warned;
 };
 
 static thread_local int g_batch_last_hip = 0;
@@ -542,6 +544,8 @@ extern "C" tlb_status tlb_batch_create(const tlb_params* per_dom, int32_t ndom, 
     b->p.assign(per_dom, per_dom + ndom);
     b->off.resize(ndom);
     b->wet_off.resize(ndom);
+    b->wet_outside.assign(2 * (size_t)ndom, 0);
+    b->wet_warned = false;
     b->state_elems = b->wet_elems = b->total_nodes = b->max_nodes = 0;
     for (int d = 0; d < ndom; ++d) {
         const int64_t N = (int64_t)per_dom[d].nx * per_dom[d].ny;
@@ -624,6 +628,21 @@ extern "C" tlb_status tlb_batch_set_wetting(tlb_batch* b, int32_t dom, int wall,
     const tlb_params& p = b->p[dom];
     for (int j = 0; j < 3 * p.nx; ++j)
         if (!isfinite(h[j])) return TLB_EINVAL;
+    // values outside the closed-form range of the wall free energy (Sec. II.B) are applied as
+    // given; they are counted and reported once per batch on stderr
+    int64_t outside = 0;
+    for (int m = 0; m < 3; ++m)
+        for (int j = 0; j < p.nx; ++j) outside += fabs(h[m * p.nx + j]) > 0.25 * p.alpha * p.kappa[m];
+    b->wet_outside[2 * (size_t)dom + wall] = outside;
+    if (outside > 0 && !b->wet_warned) {
+        b->wet_warned = true;
+        fprintf(stderr,
+                "libtlb: warning: domain %d, wall %d: %lld wetting parameters have |4 h_m / (alpha kappa_m)| > 1, "
+                "outside the range of the closed-form wall concentrations and contact angles (Sec. II.B); the "
+                "boundary condition is still applied as given (further domains are not reported; see "
+                "tlb_batch_wetting_outside_range)\n",
+                dom, wall, (long long)outside);
+    }
     tlb_status st = staging(b);
     if (st) return st;
     BHIP(hipMemcpyAsync(b->staging, h, sizeof(double) * 3 * p.nx, hipMemcpyHostToDevice, b->stream));
@@ -635,6 +654,16 @@ extern "C" tlb_status tlb_batch_set_wetting(tlb_batch* b, int32_t dom, int wall,
     else
         BHIP(launch_wet<double, double>(p.nx, 3, b->staging, inv, (double*)b->wet + o, b->stream));
     BHIP(hipStreamSynchronize(b->stream));
+    return TLB_OK;
+}
+
+extern "C" tlb_status tlb_batch_wetting_outside_range(const tlb_batch* b, int32_t dom, int64_t* count)
+{
+    if (!b || !count || dom < -1 || dom >= b->ndom) return TLB_EINVAL;
+    int64_t c = 0;
+    for (int d = (dom < 0 ? 0 : dom); d < (dom < 0 ? b->ndom : dom + 1); ++d)
+        c += b->wet_outside[2 * (size_t)d] + b->wet_outside[2 * (size_t)d + 1];
+    *count = c;
     return TLB_OK;
 }
 

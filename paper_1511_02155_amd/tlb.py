@@ -49,6 +49,7 @@ EXPORTS = (
     "tlb_batch_get_launch", "tlb_batch_autotune", "tlb_batch_set_graph",
     "tlb_set_kappa", "tlb_adjoint_seed_dev", "tlb_adjoint_step_dev", "tlb_checkpoint_slots",
     "tlb_forward_checkpointed", "tlb_adjoint_backward", "tlb_contact_angles", "tlb_wetting_from_angles",
+    "tlb_wetting_outside_range", "tlb_batch_wetting_outside_range", "tlb_adjoint_step",
 )
 
 
@@ -150,6 +151,10 @@ tlb_batch_set_graph = _sig("tlb_batch_set_graph", ctypes.c_int, [_vp, ctypes.c_i
 tlb_set_kappa = _sig("tlb_set_kappa", ctypes.c_int, [_vp, _dp])
 tlb_adjoint_seed_dev = _sig("tlb_adjoint_seed_dev", ctypes.c_int, [_vp, _vp, _vp])
 tlb_adjoint_step_dev = _sig("tlb_adjoint_step_dev", ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp])
+tlb_adjoint_step = _sig("tlb_adjoint_step", ctypes.c_int, [_vp, _vp, _vp, _vp, _vp])
+tlb_wetting_outside_range = _sig("tlb_wetting_outside_range", ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int64)])
+tlb_batch_wetting_outside_range = _sig("tlb_batch_wetting_outside_range", ctypes.c_int,
+                                       [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)])
 tlb_checkpoint_slots = _sig("tlb_checkpoint_slots", ctypes.c_int64, [ctypes.c_int64, ctypes.c_int64])
 tlb_forward_checkpointed = _sig("tlb_forward_checkpointed", ctypes.c_int, [_vp, ctypes.c_int64, ctypes.c_int64, _vp])
 tlb_adjoint_backward = _sig("tlb_adjoint_backward", ctypes.c_int,
@@ -263,6 +268,12 @@ class Sim:
         h = _arr(h).reshape(2, -1)
         self.set_wetting(0, h[0])
         self.set_wetting(1, h[1])
+
+    def wetting_outside_range(self):
+        """Wetting values of both walls with |4 h_m / (alpha kappa_m)| > 1 (-1: set from device memory)."""
+        c = ctypes.c_int64()
+        check(tlb_wetting_outside_range(self._h, ctypes.byref(c)), "tlb_wetting_outside_range")
+        return c.value
 
     def init_equilibrium(self, C, u=None):
         C = _arr(C, self.nc * self.N)
@@ -395,6 +406,12 @@ class Batch:
     def set_wetting(self, d, wall, h):
         h = _arr(h, 3 * self.params[d].nx)
         check(tlb_batch_set_wetting(self._h, d, wall, h.ctypes.data_as(_dp)), "tlb_batch_set_wetting")
+
+    def wetting_outside_range(self, d=-1):
+        """Wetting values with |4 h_m / (alpha kappa_m)| > 1 of domain d (all domains for d = -1)."""
+        c = ctypes.c_int64()
+        check(tlb_batch_wetting_outside_range(self._h, int(d), ctypes.byref(c)), "tlb_batch_wetting_outside_range")
+        return c.value
 
     def init_equilibrium(self, d, C, u=None):
         C = _arr(C, 3 * self._N(d))

@@ -238,6 +238,98 @@ def test_gradients_match_autodiff_reference(env, orc):
     assert np.allclose(dk, dkr.numpy(), rtol=1e-9, atol=1e-12 * np.abs(dkr.numpy()).max())
 
 
+# FP32 storage against the FP64 reference.  FP32 rounds every stored value of the forward state and of
+# lambda once per step (relative 2^-24 ~ 6e-8); to first order the gradient then differs from the FP64 one
+# by a sum of T such roundings per step through the map, about T 2^-24 ~ 2e-6 of its scale for T = 30,
+# times the conditioning of the map.  The bar is 1e-4 of the largest entry (a margin of about 50).
+F32_GRAD_REL = 1e-4
+
+
+def test_fp32_gradients_match_autodiff_reference(env, orc):
+    """FP32 storage: dL/dh and dL/dkappa after 30 steps against autograd through the PyTorch-CPU FP64
+    reference from the same initial state."""
+    torch, tlb = env
+    from oracle import torch_ref
+
+    w, C, h, target = _wall_case()
+    steps = 30
+    _note("fp32 gradients vs autodiff reference")
+    L, dh, dk = _gpu_grad(torch, tlb, w, C, h, target, steps, 6, tlb.TLB_F32)
+    p = orc.Params(**{k: w[k] for k in KEYS if k in w})
+    pop0 = orc.init_equilibrium(p, C, None, h)
+    t0 = torch.tensor(pop0.reshape(3, 9, w["ny"], w["nx"]))
+    hh = torch.tensor(h.reshape(2, 3, w["nx"]))
+    Lr, dhr, dkr = torch_ref.loss_and_grads(t0, hh, torch.tensor(w["kappa"], dtype=torch.float64), w["alpha"],
+                                            (w["tau_f"], w["tau_g"], w["tau_k"]), (w["gamma_phi"], w["gamma_psi"]),
+                                            True, steps, torch.tensor(target.reshape(w["ny"], w["nx"])))
+    dhr, dkr = dhr[0].numpy(), dkr.numpy()
+    e_h = np.abs(dh - dhr).max() / np.abs(dhr).max()
+    e_k = np.abs(dk - dkr).max() / np.abs(dkr).max()
+    print(f"fp32 gradient: relative error dL/dh {e_h:.3e}, dL/dkappa {e_k:.3e}, loss {abs(L - Lr) / Lr:.3e}")
+    assert e_h <= F32_GRAD_REL
+    assert e_k <= F32_GRAD_REL
+    assert L == pytest.approx(Lr, rel=F32_GRAD_REL)
+
+
+def test_stale_backward_is_refused(env):
+    """Two forward calls on one runner: the first call's backward raises (its checkpoints and parameters
+    were overwritten by the second), and the second call's backward equals a fresh single call."""
+    torch, tlb = env
+    from paper_1511_02155_amd.autograd import Runner, TernaryLB
+
+    w, C, h, target = _wall_case()
+    p = tlb.make_params(prec=tlb.TLB_F64, **{k: w[k] for k in KEYS if k in w})
+    r = Runner(p, C, 12, every=4, h=h)
+    tgt = torch.tensor(target.reshape(w["ny"], w["nx"]), dtype=torch.float64, device="cuda")
+
+    def call(scale):
+        hb = torch.tensor(h[0] * scale, dtype=torch.float64, device="cuda", requires_grad=True)
+        kap = torch.tensor(w["kappa"], dtype=torch.float64, device="cuda", requires_grad=True)
+        L = ((TernaryLB.apply(hb, kap, r)[0] - tgt) ** 2).sum()
+        return L, hb, kap
+
+    L1, hb1, _ = call(1.0)
+    L2, hb2, k2 = call(0.5)
+    with pytest.raises(RuntimeError, match="later forward call"):
+        L1.backward()
+    L2.backward()
+    L3, hb3, k3 = call(0.5)
+    L3.backward()
+    assert torch.equal(hb2.grad, hb3.grad) and torch.equal(k2.grad, k3.grad)
+
+
+def test_in_place_reverse_step_equals_out_of_place(env):
+    """tlb_adjoint_step (lambda in place) gives bitwise the lambda_t, dL/dh and dL/dkappa of
+    tlb_adjoint_step_dev."""
+    torch, tlb = env
+    w, C, h, _ = _wall_case(nx=70, ny=21)
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        s = _sim(torch, tlb, w, C, h, tlb.TLB_F64, st)
+        s.step(4)
+        u = _dev(torch, s)
+        tlb.check(tlb.tlb_save_state_dev(s.handle, u.data_ptr()), "save")
+        gen = torch.Generator(device="cuda").manual_seed(11)
+        lam = torch.randn(u.shape, dtype=torch.float64, device="cuda", generator=gen)
+        outs = []
+        for in_place in (False, True):
+            dh = torch.zeros((2, 3, w["nx"]), dtype=torch.float64, device="cuda")
+            dk = torch.zeros(3, dtype=torch.float64, device="cuda")
+            if in_place:
+                out = lam.clone()
+                tlb.check(tlb.tlb_adjoint_step(s.handle, u.data_ptr(), out.data_ptr(), dh.data_ptr(), dk.data_ptr()),
+                          "tlb_adjoint_step")
+            else:
+                out = torch.empty_like(u)
+                tlb.check(tlb.tlb_adjoint_step_dev(s.handle, u.data_ptr(), lam.data_ptr(), out.data_ptr(),
+                                                   dh.data_ptr(), dk.data_ptr()), "tlb_adjoint_step_dev")
+            s.synchronize()
+            outs.append((out.cpu(), dh.cpu(), dk.cpu()))
+    for a, b in zip(outs[0], outs[1]):
+        assert torch.equal(a, b)
+    assert outs[0][0].abs().max() > 0
+
+
 def test_checkpoint_interval_does_not_change_gradients(env):
     torch, tlb = env
     w, C, h, target = _wall_case(nx=30, ny=18)

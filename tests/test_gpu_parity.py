@@ -398,6 +398,41 @@ def test_interface_diagnostics_match_oracle_fields(tlb, orc, lattice):
         assert d["interface"][m] == pytest.approx(want, rel=1e-12)
 
 
+@pytest.mark.parametrize("lattice,walls", [(0, 0), (0, 1), (1, 0), (1, 1)])
+def test_mass_momentum_and_max_speed_match_oracle_fields(tlb, orc, lattice, walls):
+    """tlb_diag.mass, momentum and max_speed of the current state against sums of the oracle's moment
+    fields (Sec. IV, eq. lbconstraint): sum rho, sum phi, sum psi, sum rho v_a and max |v|, FP64, from a
+    state with a seeded velocity field so that every momentum component is non-trivial."""
+    dims = (50, 31, 1) if lattice == 0 else (18, 14, 11)
+    w, C, h = _wet_case(*dims, lattice=lattice, walls=walls, seed=13)
+    D = 2 if lattice == 0 else 3
+    N = dims[0] * dims[1] * dims[2]
+    u = 0.03 * np.random.default_rng(14).uniform(-1.0, 1.0, size=(D, N))
+    _note(f"diagnostics vs oracle lattice={lattice} walls={walls}")
+    p = _oparams(orc, w)
+    pop = orc.init_equilibrium(p, C, u, h)
+    orc.step(p, pop, 15, h)
+    s = _gsim(tlb, w, tlb.TLB_F64)
+    if h is not None:
+        s.set_wetting_both(h)
+    s.init_equilibrium(C, u)
+    s.step(15)
+    d = s.diagnostics()
+    F = orc.fields(p, pop, h)
+    for m, name in enumerate(("rho", "phi", "psi")):
+        want = float(F[name].sum())
+        assert abs(d["mass"][m] - want) <= 1e-12 * float(np.abs(F[name]).sum()), (name, d["mass"][m], want)
+    for a, name in enumerate(("ux", "uy", "uz")[:D]):
+        j = F["rho"] * F[name]
+        want = float(j.sum())
+        assert abs(d["momentum"][a] - want) <= 1e-12 * float(np.abs(j).sum()), (name, d["momentum"][a], want)
+    if D == 2:
+        assert d["momentum"][2] == 0.0
+    speed = np.sqrt(sum(F[name] ** 2 for name in ("ux", "uy", "uz")[:D]))
+    assert d["max_speed"] == pytest.approx(float(speed.max()), rel=1e-12)
+    assert d["nonfinite"] == 0
+
+
 # --------------------------------------------------------------------------
 # Multiple relaxation times for f (tlb_params.collision = TLB_MRT)
 # --------------------------------------------------------------------------

@@ -56,6 +56,37 @@ def test_laplace_pressure_gives_pair_surface_tensions(orc, m, n):
     assert slope == pytest.approx(g, rel=0.03)
 
 
+def test_drop_equilibrium_meets_the_spurious_velocity_stop_rule(orc):
+    """Sec. V.A stops its lens and emulsion runs once max |v| < 1e-5 (lattice units): the equilibrium of
+    a drop is at rest up to the discretisation's spurious currents.  A C1 drop (R = 16) in C2, kappa =
+    0.005, on a periodic 64^2 lattice falls below that bound within 4000 steps and stays below it; the
+    kinetic energy decays from the initial relaxation to the spurious level.  A pressure tensor that is
+    not the one of the free energy (a wrong gradient term of the equilibrium, a stencil that is not
+    isotropic) leaves a driven flow well above it."""
+    N, R = 64, 16.0
+    gp, gk = inputs.mobility_to_gamma(0.1, 1.0, 1.0)
+    p = orc.Params(lattice=0, nx=N, ny=N, walls_y=0, kappa=(0.005, 0.005, 0.005), alpha=1.0, tau_f=1.0, tau_g=1.0,
+                   tau_k=1.0, gamma_phi=gp, gamma_psi=gk)
+    x, y = np.meshgrid(np.arange(N) + 0.0, np.arange(N) + 0.0)
+    c1 = inputs.tanh_profile(np.hypot(x - N / 2, y - N / 2).ravel(), R, 1.0)
+    C = np.stack([c1, 1.0 - c1, np.zeros_like(c1)])
+    pop = orc.init_equilibrium(p, C)
+    speeds = []
+    for _ in range(4):
+        orc.step(p, pop, 1000)
+        F = orc.fields(p, pop)
+        speeds.append(float(np.sqrt(F["ux"] ** 2 + F["uy"] ** 2).max()))
+    extra = []
+    for _ in range(2):
+        orc.step(p, pop, 1000)
+        F = orc.fields(p, pop)
+        extra.append(float(np.sqrt(F["ux"] ** 2 + F["uy"] ** 2).max()))
+    assert speeds[0] > speeds[-1]
+    assert speeds[-1] < 1e-5 and max(extra) < 1e-5, (speeds, extra)
+    # the drop is intact: its area stays that of the initial disc
+    assert float(F["C1"].sum()) == pytest.approx(float(c1.sum()), rel=1e-10)
+
+
 def _cap_angle(orc, h, theta0, steps, nx=80, ny=40, R0=16.0, M=0.2):
     kappa = (0.01, 0.01, 0.01)
     gp, gk = inputs.mobility_to_gamma(M, 1.0, 1.0)
