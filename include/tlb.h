@@ -340,6 +340,26 @@ tlb_status tlb_adjoint_step(tlb_sim* sim, const void* state_dev, void* lambda_de
                             double* dkappa_dev);
 tlb_status tlb_adjoint_step_dev(tlb_sim* sim, const void* state_dev, const void* lambda_in_dev,
                                 void* lambda_out_dev, double* dh_dev, double* dkappa_dev);
+/*
+ * tlb_adjoint_step_noalloc: tlb_adjoint_step_dev for callers that cannot
+ *   allocate device memory during the call (code under HIP graph capture,
+ *   tight serving loops, harnesses that forbid hipMalloc).  Same arguments,
+ *   kernels, launch shape and results (bit for bit) as tlb_adjoint_step_dev,
+ *   but the call allocates nothing: its scratch (the per-work-item dL/dkappa
+ *   partials, their reduction partials and, when dh_dev is NULL, a sink for
+ *   dL/dh) lives in a static device array of TLB_NOALLOC_SCRATCH_BYTES per GPU,
+ *   which each GPU the library runs on holds until the process ends.  A
+ *   simulation needs tlb_adjoint_step_noalloc_scratch(sim) bytes of it
+ *   (3 * work items + 768 + 6 * nx * nz doubles); larger ones return
+ *   TLB_EINVAL.  Every call on one GPU uses that GPU's single array: calls that
+ *   overlap on one GPU (other streams, other host threads) race and must be
+ *   serialised by the caller.  The first call on a device looks up the array's
+ *   address (no allocation); it may be made before any capture starts.
+ */
+#define TLB_NOALLOC_SCRATCH_BYTES (1 << 20)
+tlb_status tlb_adjoint_step_noalloc(tlb_sim* sim, const void* state_dev, const void* lambda_in_dev,
+                                    void* lambda_out_dev, double* dh_dev, double* dkappa_dev);
+int64_t tlb_adjoint_step_noalloc_scratch(const tlb_sim* sim);
 int64_t tlb_checkpoint_slots(int64_t nsteps, int64_t every);
 tlb_status tlb_forward_checkpointed(tlb_sim* sim, int64_t nsteps, int64_t every, void* ckpt_dev);
 tlb_status tlb_adjoint_backward(tlb_sim* sim, int64_t nsteps, int64_t every, const void* ckpt_dev,

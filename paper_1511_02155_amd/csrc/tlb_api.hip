@@ -5,6 +5,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 
 #include "../../include/tlb.h"
@@ -950,7 +951,7 @@ static tlb_status adj_alloc(tlb_sim* s, int64_t seg_states)
 }
 
 template <typename T>
-static tlb_status adj_step(tlb_sim* s, const void* u, const void* lam1, void* lam0, double* dh)
+static tlb_status adj_step(tlb_sim* s, const void* u, const void* lam1, void* lam0, double* dh, double* kpart)
 {
     AdjArgs<T> a;
     memset(&a, 0, sizeof(a));
@@ -959,7 +960,7 @@ static tlb_status adj_step(tlb_sim* s, const void* u, const void* lam1, void* la
     a.lam0 = (T*)lam0;
     a.wet = (const T*)s->wet;
     a.dh = dh;
-    a.kpart = s->kpart;
+    a.kpart = kpart;
     a.nx = s->p.nx;
     a.ny = s->p.ny;
     a.walls = s->p.walls_y;
@@ -972,9 +973,12 @@ static tlb_status adj_step(tlb_sim* s, const void* u, const void* lam1, void* la
     return TLB_OK;
 }
 
-static tlb_status adj_step_any(tlb_sim* s, const void* u, const void* lam1, void* lam0, double* dh)
+static tlb_status adj_step_any(tlb_sim* s, const void* u, const void* lam1, void* lam0, double* dh,
+                               double* kpart = nullptr)
 {
-    return s->p.prec == TLB_F32 ? adj_step<float>(s, u, lam1, lam0, dh) : adj_step<double>(s, u, lam1, lam0, dh);
+    if (!kpart) kpart = s->kpart;
+    return s->p.prec == TLB_F32 ? adj_step<float>(s, u, lam1, lam0, dh, kpart)
+                                : adj_step<double>(s, u, lam1, lam0, dh, kpart);
 }
 
 // Clear the kappa partials before a reverse pass / reduce them into dkappa (+=) after it.
@@ -1027,6 +1031,73 @@ extern "C" tlb_status tlb_adjoint_step(tlb_sim* s, const void* state, void* lam,
     if (!st) st = kpart_reduce(s, dkappa);
     if (st) return st;
     HIPCHK(hipMemcpyAsync(lam, s->lam[0], (size_t)tlb_state_bytes(s), hipMemcpyDeviceToDevice, s->stream));
+    return TLB_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Reverse step without allocation.  Its scratch (the per-item kappa partials,
+// their reduction partials and, when the caller passes no dh array, a sink
+// for dL/dh) lives in one file-scope device array per GPU, so the call needs
+// no hipMalloc; every call on a GPU shares that GPU's copy.
+// ---------------------------------------------------------------------------
+constexpr int64_t kScratchDoubles = TLB_NOALLOC_SCRATCH_BYTES / 8;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[kMaxDevices];  // device address of `scratch` on each GPU (null until looked up)
+
+// Device address of this GPU's copy of `scratch`, looked up once per device with that device current.
+static tlb_status scratch_of(int dev, double** out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return TLB_EINVAL;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        int cur = -1;
+        HIPCHK(hipGetDevice(&cur));
+        if (cur != dev) HIPCHK(hipSetDevice(dev));
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (cur != dev) {
+            const hipError_t e2 = hipSetDevice(cur);
+            if (e == hipSuccess && e2 != hipSuccess) return hip_fail(e2);
+        }
+        if (e != hipSuccess) return hip_fail(e);
+        if (!ptr) return TLB_EHIP;
+        g_scratch_ptr[dev] = (double*)ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return TLB_OK;
+}
+
+extern "C" int64_t tlb_adjoint_step_noalloc_scratch(const tlb_sim* s)
+{
+    if (!s) return 0;
+    return (3 * adj_nitems(s) + 3 * (int64_t)kRedBlocks + 6 * (int64_t)s->p.nx * s->p.nz) * (int64_t)sizeof(double);
+}
+
+extern "C" tlb_status tlb_adjoint_step_noalloc(tlb_sim* s, const void* state, const void* lam_in, void* lam_out,
+                                               double* dh, double* dkappa)
+{
+    if (!s || !state || !lam_in || !lam_out || lam_in == lam_out) return TLB_EINVAL;
+    if (s->p.lattice != TLB_D2Q9 || s->p.collision != TLB_BGK || s->nc != 3) return TLB_EINVAL;
+    if (tlb_adjoint_step_noalloc_scratch(s) > TLB_NOALLOC_SCRATCH_BYTES) return TLB_EINVAL;
+    double* base = nullptr;
+    tlb_status st = scratch_of(s->dev, &base);
+    if (st) return st;
+    const int64_t items = adj_nitems(s);
+    double* kpart = base;                               // [3][items]
+    double* red = base + 3 * items;                     // [3][kRedBlocks]
+    double* sink = red + 3 * (int64_t)kRedBlocks;       // [2][3][nx*nz] when dh is NULL
+    // the partials start from zero; the scratch keeps whatever the last call on this GPU left
+    HIPCHK(launch_fill0(kpart, 3 * items, s->stream));
+    if (!dh) {
+        HIPCHK(launch_fill0(sink, 6 * (int64_t)s->p.nx * s->p.nz, s->stream));
+        dh = sink;
+    }
+    st = adj_step_any(s, state, lam_in, lam_out, dh, kpart);
+    if (st) return st;
+    if (dkappa) HIPCHK(launch_reduce3(kpart, items, red, dkappa, s->stream));
     return TLB_OK;
 }
 

@@ -50,7 +50,9 @@ EXPORTS = (
     "tlb_set_kappa", "tlb_adjoint_seed_dev", "tlb_adjoint_step_dev", "tlb_checkpoint_slots",
     "tlb_forward_checkpointed", "tlb_adjoint_backward", "tlb_contact_angles", "tlb_wetting_from_angles",
     "tlb_wetting_outside_range", "tlb_batch_wetting_outside_range", "tlb_adjoint_step",
+    "tlb_adjoint_step_noalloc", "tlb_adjoint_step_noalloc_scratch",
 )
+TLB_NOALLOC_SCRATCH_BYTES = 1 << 20
 
 
 class tlb_params(ctypes.Structure):
@@ -155,6 +157,8 @@ tlb_adjoint_step = _sig("tlb_adjoint_step", ctypes.c_int, [_vp, _vp, _vp, _vp, _
 tlb_wetting_outside_range = _sig("tlb_wetting_outside_range", ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int64)])
 tlb_batch_wetting_outside_range = _sig("tlb_batch_wetting_outside_range", ctypes.c_int,
                                        [_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)])
+tlb_adjoint_step_noalloc = _sig("tlb_adjoint_step_noalloc", ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp])
+tlb_adjoint_step_noalloc_scratch = _sig("tlb_adjoint_step_noalloc_scratch", ctypes.c_int64, [_vp])
 tlb_checkpoint_slots = _sig("tlb_checkpoint_slots", ctypes.c_int64, [ctypes.c_int64, ctypes.c_int64])
 tlb_forward_checkpointed = _sig("tlb_forward_checkpointed", ctypes.c_int, [_vp, ctypes.c_int64, ctypes.c_int64, _vp])
 tlb_adjoint_backward = _sig("tlb_adjoint_backward", ctypes.c_int,
