@@ -90,8 +90,9 @@ enum {
 /*
  * Simulation parameters.
  *   lattice   TLB_D2Q9 (requires nz == 1) or TLB_D3Q19 (requires nz >= 3).
- *   prec      TLB_F32 or TLB_F64: storage precision of the populations (the
- *             arithmetic is FP64 for both; FP32 rounds each population once per step).
+ *   prec      TLB_F32 or TLB_F64: storage precision of the populations.  D2Q9
+ *             computes in FP64 for both (FP32 storage then rounds each population
+ *             once per step); D3Q19 computes in the storage precision.
  *   nx, ny    lattice size, each >= 3; nz >= 1.
  *   walls_y   0: periodic in y; 1: half-way walls below y = 0 and above y = ny-1.
  *   kappa[m]  bulk coefficients kappa_1..3 > 0 (Sec. II.A); kappa'_m = alpha^2 kappa_m.

@@ -503,6 +503,7 @@ static StepArgs<T> step_args(const tlb_sim* s)
     a.walls = p.walls_y;
     a.N = s->N;
     a.P = make_phys<acc_t<T>>(p);
+    a.Pf = make_phys<float>(p);
     a.chunk = s->launch.chunk;
     if (p.lattice == TLB_D2Q9) {
         a.ntx = (p.nx + s->launch.width - 1) / s->launch.width;

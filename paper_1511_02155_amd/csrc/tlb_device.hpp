@@ -217,11 +217,10 @@ struct Moments {
     T dpsx[NC > 3 ? NC - 3 : 1];  // psi_l - psi_ref for l = 4 .. NC
 };
 
-// k points to the NC - 2 k population sets, Q values apart.
-template <class L, int NC = 3, typename T>
-__device__ __forceinline__ Moments<acc_t<T>, NC> moments(const T* f, const T* g, const T* k)
+// k points to the NC - 2 k population sets, Q values apart.  C: arithmetic type of the sums.
+template <typename C, class L, int NC = 3, typename T>
+__device__ __forceinline__ Moments<C, NC> moments_as(const T* f, const T* g, const T* k)
 {
-    using C = acc_t<T>;
     Moments<C, NC> m;
     C r = 0, jx = 0, jy = 0, jz = 0, ph = 0, ps[NC - 2];
 #pragma unroll
@@ -249,6 +248,12 @@ __device__ __forceinline__ Moments<acc_t<T>, NC> moments(const T* f, const T* g,
 #pragma unroll
     for (int l = 1; l < NC - 2; ++l) m.dpsx[l - 1] = ps[l];
     return m;
+}
+
+template <class L, int NC = 3, typename T>
+__device__ __forceinline__ Moments<acc_t<T>, NC> moments(const T* f, const T* g, const T* k)
+{
+    return moments_as<acc_t<T>, L, NC>(f, g, k);
 }
 
 // Concentration deviations dC_m = C_m - 1/NC from the moments:
@@ -294,14 +299,17 @@ __device__ __forceinline__ void chem_potentials(const Phys<T>& P, const T dc[NC]
 //   g_i^eq = w_i [ Gamma_phi mu_phi / c_s^2 + phi U_i ],  k_i^eq likewise (eq. eqdistfbinary)
 //   U_i    = e_i.v / c_s^2 + (e_i.v)^2 / (2 c_s^4) - v^2 / (2 c_s^2)
 //   rest populations from the mass constraints; BGK with 1/tau per species.
-template <class L, bool MRT = false, int NC = 3, typename T, typename S>
-__device__ __forceinline__ void collide(const Phys<T>& P, const Moments<T, NC>& mo, const T dc[NC],
-                                        const T gC[NC][3], const T lC[NC], S* f, S* g, S* k)
+//
+// collide_core reads the pre-collision populations through ld(s, i) and hands each post-collision
+// value to st(s, i, v) (species s: 0 f, 1 g, 2 + l the k set of psi_{3+l}; v in the arithmetic
+// type, rounded to the storage type by the caller); every value is read and written once, in the
+// same order for every caller, except that MRT reads f_i a second time.
+template <class L, bool MRT = false, int NC = 3, typename T, typename Ld, typename St>
+__device__ __forceinline__ void collide_core(const Phys<T>& P, const Moments<T, NC>& mo, const T dc[NC],
+                                             const T gC[NC][3], const T lC[NC], Ld ld, St st)
 {
-    // T: arithmetic type; S: storage type of the populations (rounded once, on the update).
-    // MRT: f relaxes with multiple relaxation times (g and k always with BGK).
-    // k: the NC - 2 k population sets, Q values apart; k_l relaxes with the k rate and
-    // mu_psi_l = mu_l - (mu_1 + mu_2)/2 (Sec. II.E).
+    // T: arithmetic type.  MRT: f relaxes with multiple relaxation times (g and k always with BGK).
+    // k_l relaxes with the k rate and mu_psi_l = mu_l - (mu_1 + mu_2)/2 (Sec. II.E).
     const T third = T(1.0 / 3.0);
     const T cref = T(psi_ref<NC>());
     T mu[NC];
@@ -375,9 +383,9 @@ __device__ __forceinline__ void collide(const Phys<T>& P, const Moments<T, NC>& 
         sg += geq;
 #pragma unroll
         for (int l = 0; l < NK; ++l) sk[l] += keq[l];
-        const T fi = T(f[i]), gi = T(g[i]);
+        const T fi = ld(0, i), gi = ld(1, i);
 #pragma unroll
-        for (int l = 0; l < NK; ++l) ki[l] = T(k[l * L::Q + i]);
+        for (int l = 0; l < NK; ++l) ki[l] = ld(2 + l, i);
         if constexpr (MRT) {
             const T di = fi - feq;
             dq[i] = di;
@@ -385,13 +393,13 @@ __device__ __forceinline__ void collide(const Phys<T>& P, const Moments<T, NC>& 
 #pragma unroll
             for (int q = 0; q < NS; ++q) ms[q] += T(mrt_stress<L>(q, i)) * di;
         } else {
-            f[i] = S(fi + wf * (feq - fi));
+            st(0, i, fi + wf * (feq - fi));
         }
-        g[i] = S(gi + wg * (geq - gi));
+        st(1, i, gi + wg * (geq - gi));
 #pragma unroll
-        for (int l = 0; l < NK; ++l) k[l * L::Q + i] = S(ki[l] + wk * (keq[l] - ki[l]));
+        for (int l = 0; l < NK; ++l) st(2 + l, i, ki[l] + wk * (keq[l] - ki[l]));
     }
-    const T f0 = T(f[0]), g0 = T(g[0]);
+    const T f0 = ld(0, 0), g0 = ld(1, 0);
     if constexpr (MRT) {
         // the rest population has no stress moment; it enters the energy moment
         dq[0] = f0 - (mo.drho - sf);
@@ -401,22 +409,40 @@ __device__ __forceinline__ void collide(const Phys<T>& P, const Moments<T, NC>& 
         for (int q = 0; q < NS; ++q) ms[q] *= P.mrt_dv * T(1.0 / mrt_stress_norm<L>(q));
 #pragma unroll
         for (int i = 0; i < L::Q; ++i) {
-            T r = T(f[i]) - P.mrt_sg * dq[i] - T(mrt_energy<L>(i)) * me;
+            T r = (i == 0 ? f0 : ld(0, i)) - P.mrt_sg * dq[i] - T(mrt_energy<L>(i)) * me;
 #pragma unroll
             for (int q = 0; q < NS; ++q)
                 if (mrt_stress<L>(q, i) != 0.0) r -= T(mrt_stress<L>(q, i)) * ms[q];
-            f[i] = S(r);
+            st(0, i, r);
         }
     } else {
-        f[0] = S(f0 + wf * ((mo.drho - sf) - f0));
+        st(0, 0, f0 + wf * ((mo.drho - sf) - f0));
     }
-    g[0] = S(g0 + wg * ((mo.phi - sg) - g0));
+    st(1, 0, g0 + wg * ((mo.phi - sg) - g0));
 #pragma unroll
     for (int l = 0; l < NK; ++l) {
-        const T k0 = T(k[l * L::Q]);
+        const T k0 = ld(2 + l, 0);
         const T dps = l == 0 ? mo.dpsi : mo.dpsx[l > 0 ? l - 1 : 0];
-        k[l * L::Q] = S(k0 + wk * ((dps - sk[l]) - k0));
+        st(2 + l, 0, k0 + wk * ((dps - sk[l]) - k0));
     }
+}
+
+// collide_core on arrays, in place: f, g and the NC - 2 k sets (Q values apart) in storage type S,
+// each rounded once on the update.
+template <class L, bool MRT = false, int NC = 3, typename T, typename S>
+__device__ __forceinline__ void collide(const Phys<T>& P, const Moments<T, NC>& mo, const T dc[NC],
+                                        const T gC[NC][3], const T lC[NC], S* f, S* g, S* k)
+{
+    auto ld = [&](int s, int i) -> T { return T(s == 0 ? f[i] : s == 1 ? g[i] : k[(s - 2) * L::Q + i]); };
+    auto st = [&](int s, int i, T v) {
+        if (s == 0)
+            f[i] = S(v);
+        else if (s == 1)
+            g[i] = S(v);
+        else
+            k[(s - 2) * L::Q + i] = S(v);
+    };
+    collide_core<L, MRT, NC>(P, mo, dc, gC, lC, ld, st);
 }
 
 // Equilibrium populations (shifted) of given fields; used by initialisation.

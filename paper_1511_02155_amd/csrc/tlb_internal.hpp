@@ -22,6 +22,7 @@ struct StepArgs {
     int ntx, nty; // strips (D2Q9: ntx) / tiles (D3Q19: ntx * nty) across the sweep
     int nitems;   // ntx * nty * nchunks
     Phys<acc_t<T>> P;
+    Phys<float> Pf;  // the same parameters for kernels whose arithmetic is FP32
 };
 
 // Map a hardware workgroup id onto a logical work item so that each XCD

@@ -93,10 +93,25 @@ struct PlaneFull {
 // latency overlaps the collision, and the populations of plane z+1 wait in
 // registers for its collision.  All three hold one wavefront per SIMD; VAR 2
 // needs about 490 registers (FP32 storage) and is meant for FP32 storage.
+// Arithmetic type of the D3Q19 step: the storage type.
+template <typename T>
+__device__ __forceinline__ const Phys<T>& phys3d(const StepArgs<T>& A);
+template <>
+__device__ __forceinline__ const Phys<float>& phys3d<float>(const StepArgs<float>& A)
+{
+    return A.Pf;
+}
+template <>
+__device__ __forceinline__ const Phys<double>& phys3d<double>(const StepArgs<double>& A)
+{
+    return A.P;
+}
+
 template <typename T, int BX, int BY, int VAR, bool MRT>
 __global__ __launch_bounds__(BX* BY) void k_step3d(StepArgs<T> A)
 {
-    using C = acc_t<T>;
+    using C = T;
+    const Phys<C>& PH = phys3d<T>(A);
     constexpr bool HOLD = VAR == 1;
     __shared__ C lds[2][3][BY + 2][BX + 2];
 
@@ -167,7 +182,7 @@ __global__ __launch_bounds__(BX* BY) void k_step3d(StepArgs<T> A)
 
     auto plane = [&](int z, PlaneFull<C>& p) {
         pull3d<T>(A, rs, col, z, wall_tile, blo, bhi, fc, gc, kc);
-        const Moments<C> mo = moments<L19>(fc, gc, kc);
+        const Moments<C> mo = moments_as<C, L19>(fc, gc, kc);
         conc_dev<C>(mo, p.c);
         if (active) {
 #pragma unroll
@@ -176,7 +191,7 @@ __global__ __launch_bounds__(BX* BY) void k_step3d(StepArgs<T> A)
         if (ring) {
             T hf[19], hg[19], hk[19];
             pull3d<T>(A, rs, hcol, z, wall_tile, hblo, hbhi, hf, hg, hk);
-            Moments<C> hm = moments<L19>(hf, hg, hk);
+            Moments<C> hm = moments_as<C, L19>(hf, hg, hk);
             C hc[3];
             conc_dev<C>(hm, hc);
             if (gwall >= 0) {
@@ -220,14 +235,14 @@ __global__ __launch_bounds__(BX* BY) void k_step3d(StepArgs<T> A)
         if (ring) pull3d<T>(A, rs, hcol, z, wall_tile, hblo, hbhi, rf, rg, rk);
     };
     auto finish = [&](int z, PlaneFull<C>& p) {
-        const Moments<C> mo = moments<L19>(fc, gc, kc);
+        const Moments<C> mo = moments_as<C, L19>(fc, gc, kc);
         conc_dev<C>(mo, p.c);
         if (active) {
 #pragma unroll
             for (int m = 0; m < 3; ++m) lds[buf][m][ty + 1][tx + 1] = p.c[m];
         }
         if (ring) {
-            Moments<C> hm = moments<L19>(rf, rg, rk);
+            Moments<C> hm = moments_as<C, L19>(rf, rg, rk);
             C hc[3];
             conc_dev<C>(hm, hc);
             if (gwall >= 0) {
@@ -312,8 +327,8 @@ __global__ __launch_bounds__(BX* BY) void k_step3d(StepArgs<T> A)
                 lC[m] = (pb.A[m] + pa.c[m] + pc.c[m]) * C(1.0 / 3.0) +
                         (pb.E[m] + pa.A[m] + pc.A[m]) * C(1.0 / 6.0) - pb.c[m] * C(4);
             }
-            const Moments<C> mb = moments<L19>(fb, gb, kb);
-            collide<L19, MRT>(A.P, mb, pb.c, gC, lC, fb, gb, kb);
+            const Moments<C> mb = moments_as<C, L19>(fb, gb, kb);
+            collide<L19, MRT>(PH, mb, pb.c, gC, lC, fb, gb, kb);
             if (active) {
                 const uint32_t so = (uint32_t)z * (uint32_t)A.nx * (uint32_t)A.ny * (uint32_t)sizeof(T);
                 const uint32_t NB = N * (uint32_t)sizeof(T);
@@ -371,8 +386,8 @@ __global__ __launch_bounds__(BX* BY) void k_step3d(StepArgs<T> A)
                     pb.c[m] * C(4);
         }
         if constexpr (!HOLD) pull3d<T>(A, rs, col, z, wall_tile, blo, bhi, fb, gb, kb);
-        const Moments<C> mb = moments<L19>(fb, gb, kb);
-        collide<L19, MRT>(A.P, mb, pb.c, gC, lC, fb, gb, kb);
+        const Moments<C> mb = moments_as<C, L19>(fb, gb, kb);
+        collide<L19, MRT>(PH, mb, pb.c, gC, lC, fb, gb, kb);
 
         if (active) {
             const uint32_t so = (uint32_t)z * (uint32_t)A.nx * (uint32_t)A.ny * (uint32_t)sizeof(T);
