@@ -113,11 +113,14 @@ static bool params_valid(const tlb_params* p)
     }
     const int64_t N = (int64_t)p->nx * p->ny * p->nz;
     const int Q = p->lattice == TLB_D2Q9 ? 9 : 19;
-    // one species array must stay addressable by 32-bit byte offsets
     const int64_t esize = p->prec == TLB_F32 ? 4 : 8;
-    if ((int64_t)Q * N * esize > (int64_t)0xFFFFFF00) return false;
-    // the D2Q9 kernels address all population sets of a state through one descriptor
-    if (p->lattice == TLB_D2Q9 && (int64_t)nc * Q * N * esize > (int64_t)0xFFFFFF00) return false;
+    if (p->lattice == TLB_D2Q9) {
+        // the D2Q9 kernels address all population sets of a state through one descriptor
+        if ((int64_t)nc * Q * N * esize > (int64_t)0xFFFFFF00) return false;
+    } else {
+        // the D3Q19 kernels address each z plane through a descriptor of its own
+        if (plane3d_elems(p->nx, p->ny, nc * Q) * esize > (int64_t)0xFFFFFF00) return false;
+    }
     return true;
 }
 
@@ -267,9 +270,12 @@ extern "C" tlb_status tlb_create(const tlb_params* params, void* stream, tlb_sim
         }
         s->own_stream = true;
     }
-    const size_t bytes = (size_t)s->nc * s->Q * s->N * s->esize;
+    const size_t bytes = (size_t)tlb_state_bytes(s);
     for (int b = 0; b < 2; ++b) {
         e = hipMalloc(&s->state[b], bytes);
+        // the padding of the D3Q19 blocks is never written by the kernels; zero it once so that raw
+        // states compare and checkpoint bit for bit
+        if (e == hipSuccess) e = hipMemsetAsync(s->state[b], 0, bytes, s->stream);
         if (e != hipSuccess) {
             tlb_destroy(s);
             return hip_fail(e);
@@ -752,7 +758,10 @@ extern "C" tlb_status tlb_diagnostics(tlb_sim* s, tlb_diag* out)
 // ---------------------------------------------------------------------------
 extern "C" int64_t tlb_state_bytes(const tlb_sim* s)
 {
-    return s ? (int64_t)s->nc * s->Q * s->N * (int64_t)s->esize : 0;
+    if (!s) return 0;
+    if (s->p.lattice == TLB_D3Q19)
+        return (int64_t)s->p.nz * plane3d_elems(s->p.nx, s->p.ny, s->nc * s->Q) * (int64_t)s->esize;
+    return (int64_t)s->nc * s->Q * s->N * (int64_t)s->esize;
 }
 
 extern "C" tlb_status tlb_save_state(tlb_sim* s, void* dst, int64_t* step)

@@ -28,32 +28,43 @@ __device__ __forceinline__ int64_t node_id(const AuxGeom& g, int x, int y, int z
     return (int64_t)x + (int64_t)g.nx * ((int64_t)y + (int64_t)g.ny * z);
 }
 
+// Element of population j = s*Q + i of node (x, y, z) in a state: species-major [NC][Q][N] for D2Q9,
+// plane-major blocks for D3Q19 (tlb_device.hpp).
+template <class L, int NC>
+__device__ __forceinline__ int64_t sidx(const AuxGeom& g, int j, int x, int y, int z)
+{
+    if constexpr (L::D == 2) {
+        return (int64_t)j * g.N + node_id(g, x, y, z);
+    } else {
+        constexpr int NQ = NC * L::Q;
+        return (int64_t)z * plane3d_elems(g.nx, g.ny, NQ) + plane3d_index(x + (int64_t)g.nx * y, NQ, j);
+    }
+}
+
 // Pull of s_t at node (x, y, z) (generic lattice): p[NC][Q].
 template <class L, int NC, typename T>
 __device__ void pull_node(const AuxGeom& g, const T* __restrict__ st, int x, int y, int z, T* p)
 {
-    const int64_t n0 = node_id(g, x, y, z);
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
         const int ys = y - L::ey[i];
-        int64_t off;
-        if (g.walls && (ys < 0 || ys >= g.ny)) {
-            off = (int64_t)L::opp[i] * g.N + n0;
-        } else {
-            off = (int64_t)i * g.N + node_id(g, wrapi(x - L::ex[i], g.nx), wrapi(ys, g.ny), wrapi(z - L::ez[i], g.nz));
-        }
+        const bool bb = g.walls && (ys < 0 || ys >= g.ny);
+        const int ii = bb ? L::opp[i] : i;
+        const int xs = bb ? x : wrapi(x - L::ex[i], g.nx);
+        const int yy = bb ? y : wrapi(ys, g.ny);
+        const int zs = bb ? z : wrapi(z - L::ez[i], g.nz);
 #pragma unroll
-        for (int s = 0; s < NC; ++s) p[s * L::Q + i] = st[(int64_t)s * L::Q * g.N + off];
+        for (int s = 0; s < NC; ++s) p[s * L::Q + i] = st[sidx<L, NC>(g, s * L::Q + ii, xs, yy, zs)];
     }
 }
 
-// Inverse propagation target of direction i from node (x, y, z).
-template <class L>
-__device__ __forceinline__ int64_t unstream_off(const AuxGeom& g, int i, int x, int y, int z)
+// Element that receives s_i (species s) of node (x, y, z) under inverse propagation.
+template <class L, int NC>
+__device__ __forceinline__ int64_t unstream_idx(const AuxGeom& g, int s, int i, int x, int y, int z)
 {
     const int ys = y - L::ey[i];
-    if (g.walls && (ys < 0 || ys >= g.ny)) return (int64_t)L::opp[i] * g.N + node_id(g, x, y, z);
-    return (int64_t)i * g.N + node_id(g, wrapi(x - L::ex[i], g.nx), wrapi(ys, g.ny), wrapi(z - L::ez[i], g.nz));
+    if (g.walls && (ys < 0 || ys >= g.ny)) return sidx<L, NC>(g, s * L::Q + L::opp[i], x, y, z);
+    return sidx<L, NC>(g, s * L::Q + i, wrapi(x - L::ex[i], g.nx), wrapi(ys, g.ny), wrapi(z - L::ez[i], g.nz));
 }
 
 // dC_m at a (possibly ghost) neighbour, read from an [nc][N] array of
@@ -130,9 +141,8 @@ __global__ void k_init(AuxGeom g, Phys<acc_t<T>> P, const TIn* __restrict__ C, c
     equilibrium<L, NC>(P, mo, dc, gC, lC, p, p + L::Q, p + 2 * L::Q);
 #pragma unroll
     for (int i = 0; i < L::Q; ++i) {
-        const int64_t off = unstream_off<L>(g, i, x, y, z);
 #pragma unroll
-        for (int s = 0; s < NC; ++s) st[(int64_t)s * L::Q * g.N + off] = p[s * L::Q + i];
+        for (int s = 0; s < NC; ++s) st[unstream_idx<L, NC>(g, s, i, x, y, z)] = p[s * L::Q + i];
     }
 }
 
@@ -207,10 +217,9 @@ __global__ void k_set_pops(AuxGeom g, const TIn* __restrict__ in, int s, T* __re
     if (n >= g.N) return;
     int x, y, z;
     node_xyz(g, n, x, y, z);
-    T* base = st + (int64_t)s * L::Q * g.N;
 #pragma unroll
     for (int i = 0; i < L::Q; ++i)
-        base[unstream_off<L>(g, i, x, y, z)] = T(in[(int64_t)i * g.N + n]) - T(ref<L, NC>(s, i));
+        st[unstream_idx<L, NC>(g, s, i, x, y, z)] = T(in[(int64_t)i * g.N + n]) - T(ref<L, NC>(s, i));
 }
 
 // Diagnostic slots (diag_slots(NC) of them): mass of rho, phi, psi_3 (0-2), momentum (3-5), max |v|

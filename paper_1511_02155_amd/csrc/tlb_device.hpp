@@ -139,6 +139,29 @@ __host__ __device__ constexpr double ref(int s, int i)
 }
 
 // ---------------------------------------------------------------------------
+// D3Q19 state layout: plane-major blocks.  The nodes of one z plane are
+// numbered m = x + nx*y and grouped into blocks of 64 consecutive m; a block
+// stores the NQ = NC*Q populations of its nodes population-major ([NQ][64]),
+// the blocks of a plane follow one another (the last one padded), and so do
+// the planes.  A wavefront pulling one row of a tile then reads a few
+// contiguous runs of NQ*64 values instead of NQ separate arrays (measured on
+// MI355X with the step's traversal: 5.2 TB/s against 4.5 TB/s for the
+// species-major layout), and each plane is addressed through a buffer
+// descriptor of its own, so byte offsets stay below 2^32 for any nz.  (D2Q9
+// states are species-major [NC][Q][N].)
+// ---------------------------------------------------------------------------
+constexpr int kBlock3d = 64;
+__host__ __device__ constexpr int64_t plane3d_elems(int nx, int ny, int nq)
+{
+    return ((int64_t)nx * ny + kBlock3d - 1) / kBlock3d * nq * kBlock3d;
+}
+// Element of population j (= s*Q + i) of in-plane node m within its plane.
+__host__ __device__ constexpr int64_t plane3d_index(int64_t m, int nq, int j)
+{
+    return ((m / kBlock3d) * nq + j) * kBlock3d + (m % kBlock3d);
+}
+
+// ---------------------------------------------------------------------------
 // Raw buffer access.  A buffer resource covers one species array; loads and
 // stores take a per-lane 32-bit byte offset (voffset) and a wavefront-uniform
 // byte offset (soffset), so the address arithmetic of the lattice pull runs

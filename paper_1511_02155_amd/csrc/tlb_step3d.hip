@@ -15,38 +15,36 @@
 //   d_z C = (C_{z+1} - C_{z-1})/6 + (A_{z+1} - A_{z-1})/12
 //   lap C = (A_z + C_{z-1} + C_{z+1})/3 + (E_z + A_{z-1} + A_{z+1})/6 - 4 C_z.
 // HBM traffic per node and step: 57 values read + 57 written; the ring and
-// the chunk-end planes are re-read from L2.
+// the chunk-end planes are re-read from L2.  The state is stored in
+// plane-major blocks of 64 nodes (tlb_device.hpp), one buffer descriptor per
+// z plane.
 #include "tlb_internal.hpp"
 
 namespace tlb {
 
 using L19 = D3Q19;
 
-// Pull of node (x, y, z) through buffer accesses: one descriptor per species
-// array, a per-lane byte offset of the in-plane source column and a
-// wavefront-uniform byte offset of direction and z plane.  col[dy + 1][dx + 1]
-// holds the offset of column (x + dx, y + dy) (periodic wrap), so direction i
-// reads col[1 - e_y][1 - e_x].  Where r - e_i lies beyond a y wall the lane
-// reads opp(i) at its own node instead (half-way bounce-back); only lanes on
-// a wall row of a tile touching a wall (wall_tile) take that branch.
+// Pull of node (x, y, z) through buffer accesses.  The state is stored in
+// plane-major blocks of 64 nodes (tlb_device.hpp); rp[0..2] are the buffer
+// descriptors of planes z-1, z, z+1 (periodic), col[dy + 1][dx + 1] the
+// per-lane byte offset of in-plane column (x + dx, y + dy) within a plane,
+// and population j = s*19 + i sits j*64 values further (wavefront-uniform),
+// so direction i reads col[1 - e_y][1 - e_x] in plane z - e_z.  Where r - e_i
+// lies beyond a y wall the lane reads opp(i) at its own node instead
+// (half-way bounce-back); only lanes on a wall row of a tile touching a wall
+// (wall_tile) take that branch.
 template <typename T>
-__device__ __forceinline__ void pull3d(const StepArgs<T>& A, const Rsrc* rs, const uint32_t (&col)[3][3], int z,
-                                       bool wall_tile, bool blo, bool bhi, T* f, T* g, T* k)
+__device__ __forceinline__ void pull3d(const Rsrc (&rp)[3], const uint32_t (&col)[3][3], bool wall_tile, bool blo,
+                                       bool bhi, T* f, T* g, T* k)
 {
     constexpr uint32_t ES = sizeof(T);
-    const int nz = A.nz;
-    const uint32_t PB = (uint32_t)A.nx * (uint32_t)A.ny * ES;  // bytes of one z plane
-    const uint32_t NB = (uint32_t)A.N * ES;                    // bytes of one direction array
-    const uint32_t zm = (z == 0) ? nz - 1 : z - 1;
-    const uint32_t zp = (z == nz - 1) ? 0 : z + 1;
 #pragma unroll
     for (int s = 0; s < 3; ++s) {
         T* out = (s == 0) ? f : (s == 1) ? g : k;
 #pragma unroll
         for (int i = 0; i < 19; ++i) {
             const int ex = L19::ex[i], ey = L19::ey[i], ez = L19::ez[i];
-            const uint32_t zs = ez == 0 ? (uint32_t)z : (ez == 1 ? zm : zp);
-            out[i] = bload<T>(rs[s], col[1 - ey][1 - ex], (uint32_t)i * NB + zs * PB);
+            out[i] = bload<T>(rp[1 - ez], col[1 - ey][1 - ex], (uint32_t)((s * 19 + i) * kBlock3d) * ES);
         }
         if (wall_tile) {
 #pragma unroll
@@ -54,13 +52,13 @@ __device__ __forceinline__ void pull3d(const StepArgs<T>& A, const Rsrc* rs, con
                 const int ey = L19::ey[i];
                 if (ey == 0) continue;
                 if ((ey == 1 && blo) || (ey == -1 && bhi))
-                    out[i] = bload<T>(rs[s], col[1][1], (uint32_t)L19::opp[i] * NB + (uint32_t)z * PB);
+                    out[i] = bload<T>(rp[1], col[1][1], (uint32_t)((s * 19 + L19::opp[i]) * kBlock3d) * ES);
             }
         }
     }
 }
 
-// Byte offsets of the nine in-plane columns around (x, y), periodic in x and y.
+// Byte offsets within a plane of the nine in-plane columns around (x, y), periodic in x and y.
 template <typename T>
 __device__ __forceinline__ void columns(int x, int y, int nx, int ny, uint32_t (&col)[3][3])
 {
@@ -72,7 +70,8 @@ __device__ __forceinline__ void columns(int x, int y, int nx, int ny, uint32_t (
         for (int dx = -1; dx <= 1; ++dx) {
             int xx = x + dx;
             xx = xx < 0 ? xx + nx : (xx >= nx ? xx - nx : xx);
-            col[dy + 1][dx + 1] = ((uint32_t)xx + (uint32_t)nx * (uint32_t)yy) * (uint32_t)sizeof(T);
+            const uint32_t m = (uint32_t)xx + (uint32_t)nx * (uint32_t)yy;
+            col[dy + 1][dx + 1] = (uint32_t)plane3d_index(m, 57, 0) * (uint32_t)sizeof(T);
         }
     }
 }
@@ -162,10 +161,17 @@ __global__ __launch_bounds__(BX* BY) void k_step3d(StepArgs<T> A)
     }
     const uint32_t nxz = (uint32_t)A.nx * A.nz;
 
-    // buffer descriptors of the three species arrays of the source and destination states
-    const uint32_t SB = 19u * (uint32_t)A.N * (uint32_t)sizeof(T);
-    const Rsrc rs[3] = {make_rsrc(A.src, SB), make_rsrc(A.src + 19 * A.N, SB), make_rsrc(A.src + 38 * A.N, SB)};
-    const Rsrc rd[3] = {make_rsrc(A.dst, SB), make_rsrc(A.dst + 19 * A.N, SB), make_rsrc(A.dst + 38 * A.N, SB)};
+    // one buffer descriptor per z plane (the three source planes of a pull, the destination plane)
+    const int64_t PE = plane3d_elems(A.nx, A.ny, 57);
+    const uint32_t PBYTES = (uint32_t)(PE * (int64_t)sizeof(T));
+    auto src_planes = [&](int z, Rsrc (&rp)[3]) {
+        const int zm = (z == 0) ? A.nz - 1 : z - 1;
+        const int zp = (z == A.nz - 1) ? 0 : z + 1;
+        rp[0] = make_rsrc(A.src + (int64_t)zm * PE, PBYTES);
+        rp[1] = make_rsrc(A.src + (int64_t)z * PE, PBYTES);
+        rp[2] = make_rsrc(A.src + (int64_t)zp * PE, PBYTES);
+    };
+    auto dst_plane = [&](int z) { return make_rsrc(A.dst + (int64_t)z * PE, PBYTES); };
     uint32_t col[3][3], hcol[3][3];
     columns<T>(x, y, A.nx, A.ny, col);
     columns<T>(gx, gy, A.nx, A.ny, hcol);
@@ -181,7 +187,9 @@ __global__ __launch_bounds__(BX* BY) void k_step3d(StepArgs<T> A)
     int buf = 0;
 
     auto plane = [&](int z, PlaneFull<C>& p) {
-        pull3d<T>(A, rs, col, z, wall_tile, blo, bhi, fc, gc, kc);
+        Rsrc rp[3];
+        src_planes(z, rp);
+        pull3d<T>(rp, col, wall_tile, blo, bhi, fc, gc, kc);
         const Moments<C> mo = moments_as<C, L19>(fc, gc, kc);
         conc_dev<C>(mo, p.c);
         if (active) {
@@ -190,7 +198,7 @@ __global__ __launch_bounds__(BX* BY) void k_step3d(StepArgs<T> A)
         }
         if (ring) {
             T hf[19], hg[19], hk[19];
-            pull3d<T>(A, rs, hcol, z, wall_tile, hblo, hbhi, hf, hg, hk);
+            pull3d<T>(rp, hcol, wall_tile, hblo, hbhi, hf, hg, hk);
             Moments<C> hm = moments_as<C, L19>(hf, hg, hk);
             C hc[3];
             conc_dev<C>(hm, hc);
@@ -231,8 +239,10 @@ __global__ __launch_bounds__(BX* BY) void k_step3d(StepArgs<T> A)
     // registers.
     T rf[19], rg[19], rk[19];
     auto issue = [&](int z) {
-        pull3d<T>(A, rs, col, z, wall_tile, blo, bhi, fc, gc, kc);
-        if (ring) pull3d<T>(A, rs, hcol, z, wall_tile, hblo, hbhi, rf, rg, rk);
+        Rsrc rp[3];
+        src_planes(z, rp);
+        pull3d<T>(rp, col, wall_tile, blo, bhi, fc, gc, kc);
+        if (ring) pull3d<T>(rp, hcol, wall_tile, hblo, hbhi, rf, rg, rk);
     };
     auto finish = [&](int z, PlaneFull<C>& p) {
         const Moments<C> mo = moments_as<C, L19>(fc, gc, kc);
@@ -286,7 +296,6 @@ __global__ __launch_bounds__(BX* BY) void k_step3d(StepArgs<T> A)
         }
     };
 
-    const uint32_t N = (uint32_t)A.N;
     if constexpr (VAR == 2) {
         T fh[19], gh[19], kh[19];  // populations of plane z+1, kept for its collision
         // Prologue: planes z0 - 1 and z0 summed, the loads of z0 + 1 issued.
@@ -330,13 +339,12 @@ __global__ __launch_bounds__(BX* BY) void k_step3d(StepArgs<T> A)
             const Moments<C> mb = moments_as<C, L19>(fb, gb, kb);
             collide<L19, MRT>(PH, mb, pb.c, gC, lC, fb, gb, kb);
             if (active) {
-                const uint32_t so = (uint32_t)z * (uint32_t)A.nx * (uint32_t)A.ny * (uint32_t)sizeof(T);
-                const uint32_t NB = N * (uint32_t)sizeof(T);
+                const Rsrc rd = dst_plane(z);
 #pragma unroll
                 for (int i = 0; i < 19; ++i) {
-                    bstore<T>(fb[i], rd[0], col[1][1], so + (uint32_t)i * NB);
-                    bstore<T>(gb[i], rd[1], col[1][1], so + (uint32_t)i * NB);
-                    bstore<T>(kb[i], rd[2], col[1][1], so + (uint32_t)i * NB);
+                    bstore<T>(fb[i], rd, col[1][1], (uint32_t)(i * kBlock3d) * (uint32_t)sizeof(T));
+                    bstore<T>(gb[i], rd, col[1][1], (uint32_t)((19 + i) * kBlock3d) * (uint32_t)sizeof(T));
+                    bstore<T>(kb[i], rd, col[1][1], (uint32_t)((38 + i) * kBlock3d) * (uint32_t)sizeof(T));
                 }
             }
 #pragma unroll
@@ -385,18 +393,21 @@ __global__ __launch_bounds__(BX* BY) void k_step3d(StepArgs<T> A)
             lC[m] = (pb.A[m] + pa.c[m] + pc.c[m]) * C(1.0 / 3.0) + (pb.E[m] + pa.A[m] + pc.A[m]) * C(1.0 / 6.0) -
                     pb.c[m] * C(4);
         }
-        if constexpr (!HOLD) pull3d<T>(A, rs, col, z, wall_tile, blo, bhi, fb, gb, kb);
+        if constexpr (!HOLD) {
+            Rsrc rp[3];
+            src_planes(z, rp);
+            pull3d<T>(rp, col, wall_tile, blo, bhi, fb, gb, kb);
+        }
         const Moments<C> mb = moments_as<C, L19>(fb, gb, kb);
         collide<L19, MRT>(PH, mb, pb.c, gC, lC, fb, gb, kb);
 
         if (active) {
-            const uint32_t so = (uint32_t)z * (uint32_t)A.nx * (uint32_t)A.ny * (uint32_t)sizeof(T);
-            const uint32_t NB = N * (uint32_t)sizeof(T);
+            const Rsrc rd = dst_plane(z);
 #pragma unroll
             for (int i = 0; i < 19; ++i) {
-                bstore<T>(fb[i], rd[0], col[1][1], so + (uint32_t)i * NB);
-                bstore<T>(gb[i], rd[1], col[1][1], so + (uint32_t)i * NB);
-                bstore<T>(kb[i], rd[2], col[1][1], so + (uint32_t)i * NB);
+                bstore<T>(fb[i], rd, col[1][1], (uint32_t)(i * kBlock3d) * (uint32_t)sizeof(T));
+                bstore<T>(gb[i], rd, col[1][1], (uint32_t)((19 + i) * kBlock3d) * (uint32_t)sizeof(T));
+                bstore<T>(kb[i], rd, col[1][1], (uint32_t)((38 + i) * kBlock3d) * (uint32_t)sizeof(T));
             }
         }
 
