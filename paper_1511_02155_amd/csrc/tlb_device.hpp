@@ -144,11 +144,11 @@ __host__ __device__ constexpr double ref(int s, int i)
 // stores the NQ = NC*Q populations of its nodes population-major ([NQ][64]),
 // the blocks of a plane follow one another (the last one padded), and so do
 // the planes.  A wavefront pulling one row of a tile then reads a few
-// contiguous runs of NQ*64 values instead of NQ separate arrays (measured on
-// MI355X with the step's traversal: 5.2 TB/s against 4.5 TB/s for the
-// species-major layout), and each plane is addressed through a buffer
-// descriptor of its own, so byte offsets stay below 2^32 for any nz.  (D2Q9
-// states are species-major [NC][Q][N].)
+// contiguous runs of NQ*64 values instead of NQ separate arrays (on MI355X
+// the 256^3 FP32 step went from 1.85 to 1.62 ms; runs of one species per
+// plane instead of all NQ populations per block measured 1.66 ms), and each
+// plane is addressed through a buffer descriptor of its own, so byte offsets
+// stay below 2^32 for any nz.  (D2Q9 states are species-major [NC][Q][N].)
 // ---------------------------------------------------------------------------
 constexpr int kBlock3d = 64;
 __host__ __device__ constexpr int64_t plane3d_elems(int nx, int ny, int nq)
