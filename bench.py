@@ -1,13 +1,16 @@
 """Throughput of the fused ternary LB step on one MI355X.
 
-Headline: the 1024x1024 D2Q9 spinodal workload (C1, C2 = 1/3 + U(-0.01, 0.01),
-kappa = (0.01, 0.015, 0.02), alpha = 1, tau = 1, M = 0.1) in FP64, MLUPS over
-K timed steps with the state resident in HBM.  The same line carries the
-roofline of the fused step kernel, the CPU oracle timed on a bounded sample,
-and further measurements (FP32 of the same workload, D3Q19 256^3 FP32, a
-device copy ceiling) under "extra".
+Headline: the 256^3 D3Q19 spinodal workload (C1, C2 = 1/3 + U(-0.01, 0.01),
+kappa = 0.01, alpha = 1, tau = 0.8, M = 0.05) with FP32 populations, MLUPS
+over K timed steps with the state resident in HBM; it is the largest of the
+single-GPU workloads.  The same line carries the roofline of the fused step
+kernel, the CPU oracle timed on a bounded sample of the same workload, and
+the other forms under "extra": the 1024^2 D2Q9 spinodal in FP64 and FP32, the
+512-domain batch, the multiple-relaxation-time and four-component variants,
+the reverse step with a whole checkpointed gradient, and a device copy
+ceiling.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--quick]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--quick] [--only NAME]
 """
 from __future__ import annotations
 
@@ -254,6 +257,20 @@ def _cpu_threads():
     return int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
 
 
+def cpu_model():
+    """The host CPU's model name (first processor of /proc/cpuinfo) and its logical processor count."""
+    name = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    name = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return f"{name} ({os.cpu_count()} logical processors visible)"
+
+
 def cpu_single_thread(steps=4):
     """The headline oracle sample on one thread (a child process started with OMP_NUM_THREADS=1)."""
     import subprocess
@@ -266,8 +283,8 @@ def cpu_single_thread(steps=4):
     return json.loads(out.strip().splitlines()[-1])
 
 
-def cpu_d3q19(n=128, steps=10):
-    """The D3Q19 oracle on a 128^3 sample of the 256^3 spinodal workload (same parameters)."""
+def cpu_d3q19(n=256, steps=10):
+    """The D3Q19 oracle on the 256^3 spinodal workload (a bounded number of steps)."""
     import oracle
     from paper_1511_02155_amd import inputs
 
@@ -330,13 +347,13 @@ def cpu_gradient(steps=10):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10000)
-    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle timing")
-    ap.add_argument("--cpu-steps", type=int, default=300)
+    ap.add_argument("--cpu-steps", type=int, default=10)
     ap.add_argument("--quick", action="store_true", help="headline only (no extra workloads)")
     ap.add_argument("--only", default=None,
-                    help="run a single workload: f64, f32, d3q19, batched, mrt, ncomp, adjoint64, adjoint32")
+                    help="run a single workload: d3q19, f64, f32, batched, mrt, ncomp, adjoint64, adjoint32")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -350,9 +367,11 @@ def main():
     torch.cuda.set_device(0)
     from paper_1511_02155_amd import inputs, tlb
 
-    w2 = inputs.spinodal_2d(1024, args.steps)
     sel = args.only
     every = sel is None and not args.quick
+    # the 2D workloads run a tenth of the steps of the headline by default (about 0.1 ms per step)
+    s2 = args.steps if sel else max(1000, min(10000, 5 * args.steps))
+    w2 = inputs.spinodal_2d(1024, s2)
     res = {}  # workload name -> measurements, the headline first
 
     def add(name, r):
@@ -363,42 +382,42 @@ def main():
             r["traffic_over_algorithmic"] = t / r["bytes_per_launch"]
         res[name] = r
 
-    if sel in (None, "f64"):
-        print(f"[bench] d2q9 1024^2 f64: {args.warmup} warm-up + {args.steps} timed steps", file=sys.stderr,
+    if sel in (None, "d3q19"):
+        print(f"[bench] d3q19 256^3 f32: {args.warmup} warm-up + {args.steps} timed steps", file=sys.stderr,
               flush=True)
-        add("d2q9_1024x1024_spinodal_f64", run_plain(tlb, torch, w2, tlb.TLB_F64, args.steps, args.warmup))
+        add("d3q19_256cube_spinodal_f32", run_plain(tlb, torch, inputs.spinodal_3d(256, args.steps), tlb.TLB_F32,
+                                                    args.steps, args.warmup))
+    if sel == "f64" or every:
+        print(f"[bench] d2q9 1024^2 f64: {s2} steps", file=sys.stderr, flush=True)
+        add("d2q9_1024x1024_spinodal_f64", run_plain(tlb, torch, w2, tlb.TLB_F64, s2, 100))
     if sel == "f32" or every:
-        print(f"[bench] d2q9 1024^2 f32: {args.steps} steps", file=sys.stderr, flush=True)
-        r = run_plain(tlb, torch, w2, tlb.TLB_F32, args.steps, args.warmup)
+        print(f"[bench] d2q9 1024^2 f32: {s2} steps", file=sys.stderr, flush=True)
+        r = run_plain(tlb, torch, w2, tlb.TLB_F32, s2, 100)
         r["note"] = "working set 226 MB fits the 256 MB Infinity Cache (cache-assisted)"
         add("d2q9_1024x1024_spinodal_f32", r)
-    if sel == "d3q19" or every:
-        s3 = args.steps if sel else max(50, min(2000, args.steps // 20))
-        print(f"[bench] d3q19 256^3 f32: {s3} steps", file=sys.stderr, flush=True)
-        add("d3q19_256cube_spinodal_f32", run_plain(tlb, torch, inputs.spinodal_3d(256, s3), tlb.TLB_F32, s3, 10))
     if sel == "batched" or every:
-        sb = args.steps if sel else max(100, min(5000, args.steps // 2))
+        sb = args.steps if sel else max(100, min(5000, args.steps // 4))
         print(f"[bench] batched 512 domains f32: {sb} steps", file=sys.stderr, flush=True)
         add("batched_512_domains_f32", run_batched(tlb, torch, sb))
     if sel == "mrt" or every:
         # multiple relaxation times for f: same workloads, distinct bulk and ghost rates
         mrt = dict(collision=1, tau_bulk=0.8, tau_ghost=1.2)
-        sm = args.steps if sel else max(200, min(2000, args.steps // 5))
+        sm = args.steps if sel else max(200, min(2000, s2 // 5))
         print(f"[bench] d2q9 1024^2 f64 MRT: {sm} steps", file=sys.stderr, flush=True)
         add("d2q9_1024x1024_spinodal_f64_mrt", run_plain(tlb, torch, dict(w2, **mrt), tlb.TLB_F64, sm, 10))
-        s3 = args.steps if sel else max(50, min(2000, args.steps // 20))
+        s3 = args.steps if sel else max(50, min(2000, args.steps // 10))
         print(f"[bench] d3q19 256^3 f32 MRT: {s3} steps", file=sys.stderr, flush=True)
         add("d3q19_256cube_spinodal_f32_mrt",
             run_plain(tlb, torch, dict(inputs.spinodal_3d(256, s3), **mrt), tlb.TLB_F32, s3, 10))
     if sel == "ncomp" or every:
         # more than three components (Sec. II.E): four-component spinodal, FP64
-        sn = args.steps if sel else max(200, min(2000, args.steps // 5))
+        sn = args.steps if sel else max(200, min(2000, s2 // 5))
         print(f"[bench] d2q9 1024^2 f64 four components: {sn} steps", file=sys.stderr, flush=True)
         add("d2q9_1024x1024_spinodal_n4_f64", run_plain(tlb, torch, inputs.spinodal_2d_nc(1024, sn, 4), tlb.TLB_F64,
                                                         sn, 10))
     for name, prec in (("f64", tlb.TLB_F64), ("f32", tlb.TLB_F32)):
         if sel == "adjoint" + name[1:] or every:
-            sa = args.steps if sel else max(100, min(2000, args.steps // 5))
+            sa = args.steps if sel else max(100, min(2000, s2 // 5))
             print(f"[bench] adjoint 512^2 {name}: {sa} reverse steps + one 2000-step gradient", file=sys.stderr,
                   flush=True)
             add(f"adjoint_512x512_wall_drop_{name}", run_adjoint(tlb, torch, prec, sa))
@@ -428,18 +447,21 @@ def main():
                      "frac_of_copy_kernel": head["achieved_GBps"] / copy_gbps},
         "check": {"nonfinite": head.get("nonfinite"), "mass": head.get("mass")},
     }
-    if not args.no_cpu and hname == "d2q9_1024x1024_spinodal_f64":
-        print(f"[bench] cpu oracle, {args.cpu_steps} steps", file=sys.stderr, flush=True)
-        cb = cpu_baseline(w2, args.cpu_steps)
+    if not args.no_cpu and hname == "d3q19_256cube_spinodal_f32":
+        print(f"[bench] cpu oracle: d3q19 256^3, {args.cpu_steps} steps", file=sys.stderr, flush=True)
+        cb = cpu_d3q19(256, args.cpu_steps)
         if every:
-            # the other forms against the oracle on bounded samples, and the headline on one thread
-            print("[bench] cpu oracle: one thread, d3q19, batch, gradient", file=sys.stderr, flush=True)
-            forms = {"d2q9_1024x1024_spinodal_f64_one_thread": (cpu_single_thread(), head["mlups"]),
-                     "d3q19_256cube_spinodal": (cpu_d3q19(), res["d3q19_256cube_spinodal_f32"]["mlups"]),
+            # the other forms against the oracle on bounded samples
+            print("[bench] cpu oracle: d2q9 (all threads and one thread), batch, gradient", file=sys.stderr,
+                  flush=True)
+            g2 = res["d2q9_1024x1024_spinodal_f64"]["mlups"]
+            forms = {"d2q9_1024x1024_spinodal_f64": (cpu_baseline(inputs.spinodal_2d(1024, 300), 300), g2),
+                     "d2q9_1024x1024_spinodal_f64_one_thread": (cpu_single_thread(), g2),
                      "batched_512_domains": (cpu_batched(), res["batched_512_domains_f32"]["mlups"]),
                      "adjoint_512x512_wall_drop_gradient": (cpu_gradient(),
                                                             res["adjoint_512x512_wall_drop_f64"]["gradient_mlups"])}
             cb["forms"] = {k: dict(v, gpu_mlups=g, gpu_over_cpu=g / v["value"]) for k, (v, g) in forms.items()}
+        cb["cpu_model"] = cpu_model()
         line["cpu_baseline"] = cb
     res["copy_kernel_GBps"] = copy_gbps
     line["extra"] = res

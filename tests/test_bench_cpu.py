@@ -39,3 +39,11 @@ def test_traffic_records_name_their_kernel_sources():
         assert rec["kind"] in bench.KERNEL_SOURCES, name
         assert rec["read_bytes_per_launch"] > 0 and rec["write_bytes_per_launch"] > 0, name
         assert len(rec["source_sha"]) == 16, name
+
+
+def test_cpu_model_names_the_host():
+    sys.path.insert(0, ROOT)
+    import bench
+
+    m = bench.cpu_model()
+    assert "logical processors visible" in m and len(m) > 30
