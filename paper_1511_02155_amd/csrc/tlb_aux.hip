@@ -227,11 +227,42 @@ __global__ void k_set_pops(AuxGeom g, const TIn* __restrict__ in, int s, T* __re
 // masses of psi_4 .. psi_NC and the interface sums of C4 .. C_NC.
 //
 // Block-level sums in FP64 with a fixed assignment of nodes to blocks (deterministic).
+//
+// Reduction of a 256-lane block: each wavefront folds its 64 lanes with a
+// butterfly of cross-lane exchanges (5 xor steps of 32 .. 1 lanes, no LDS and
+// no barrier), lane 0 of each of the four wavefronts writes its result to
+// LDS, and after one barrier thread q adds (or takes the maximum of) the four
+// wavefront results of slot q in wavefront order; red[q][0] then holds slot
+// q.  Slot 6 is a maximum, the others sums.  The order is fixed, so results
+// are reproducible bit for bit.
+template <int S>
+__device__ __forceinline__ void block_reduce(double (&acc)[S], double (&red)[S][4])
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < S; ++q) {
+        double v = acc[q];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const double w = __shfl_xor(v, o, 64);
+            v = (q == 6) ? fmax(v, w) : v + w;
+        }
+        if (lane == 0) red[q][wave] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < S) {
+        const int q = threadIdx.x;
+        double v = red[q][0];
+        for (int k = 1; k < 4; ++k) v = (q == 6) ? fmax(v, red[q][k]) : v + red[q][k];
+        red[q][0] = v;
+    }
+}
+
 template <class L, int NC, typename T>
 __global__ __launch_bounds__(256) void k_diag1(AuxGeom g, const T* __restrict__ st, double* __restrict__ partial)
 {
     constexpr int S = diag_slots(NC);
-    __shared__ double red[S][256];
+    __shared__ double red[S][4];
     double acc[S];
 #pragma unroll
     for (int q = 0; q < S; ++q) acc[q] = 0.0;
@@ -282,28 +313,14 @@ __global__ __launch_bounds__(256) void k_diag1(AuxGeom g, const T* __restrict__ 
             acc[7] += 1.0;
         }
     }
-#pragma unroll
-    for (int q = 0; q < S; ++q) red[q][threadIdx.x] = acc[q];
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w) {
-#pragma unroll
-            for (int q = 0; q < S; ++q) {
-                if (q == 6)
-                    red[q][threadIdx.x] = fmax(red[q][threadIdx.x], red[q][threadIdx.x + w]);
-                else
-                    red[q][threadIdx.x] += red[q][threadIdx.x + w];
-            }
-        }
-        __syncthreads();
-    }
+    block_reduce<S>(acc, red);
     if (threadIdx.x < S) partial[(int64_t)blockIdx.x * S + threadIdx.x] = red[threadIdx.x][0];
 }
 
 template <int S>
 __global__ __launch_bounds__(256) void k_diag2(const double* __restrict__ partial, int nblocks, double* __restrict__ out)
 {
-    __shared__ double red[S][256];
+    __shared__ double red[S][4];
     double acc[S];
 #pragma unroll
     for (int q = 0; q < S; ++q) acc[q] = 0.0;
@@ -314,21 +331,7 @@ __global__ __launch_bounds__(256) void k_diag2(const double* __restrict__ partia
             acc[q] = (q == 6) ? fmax(acc[q], v) : acc[q] + v;
         }
     }
-#pragma unroll
-    for (int q = 0; q < S; ++q) red[q][threadIdx.x] = acc[q];
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w) {
-#pragma unroll
-            for (int q = 0; q < S; ++q) {
-                if (q == 6)
-                    red[q][threadIdx.x] = fmax(red[q][threadIdx.x], red[q][threadIdx.x + w]);
-                else
-                    red[q][threadIdx.x] += red[q][threadIdx.x + w];
-            }
-        }
-        __syncthreads();
-    }
+    block_reduce<S>(acc, red);
     if (threadIdx.x < S) out[threadIdx.x] = red[threadIdx.x][0];
 }
 

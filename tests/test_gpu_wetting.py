@@ -1,9 +1,12 @@
 """Contact angles on the GPU from wetting parameters given by tlb_wetting_from_angles (Sec. II.B,
 II.D, V.B): a sweep of target angles in the spirit of the paper's sessile-drop benchmark.
 
-A C1 cap in C2 (C3 absent) starts at 90 degrees on the wall below y = 0 with h from the requested
-theta_12 (theta_23 = 90 degrees, sum h/kappa = 0) and relaxes; the fitted angle must come within
-4 degrees of the request.
+A C1 cap in C2 (C3 absent) starts on the wall below y = 0 with h from the requested theta_12
+(theta_23 = 90 degrees, sum h/kappa = 0) and relaxes; the fitted angle must come within 4 degrees of
+the request over 14 .. 145 degrees (the paper reports that accuracy over 14 .. 166 degrees; the
+non-wetting end is discussed below).  Caps of the
+middle angles start at 90 degrees; those near the ends of the range start 10-15 degrees from the
+target on a lattice sized for the final cap (a 14-degree cap of height ~15 is ~250 nodes wide).
 """
 from __future__ import annotations
 
@@ -32,20 +35,30 @@ def tlb():
     return t
 
 
-@pytest.mark.parametrize("theta", [45.0, 70.0, 110.0, 135.0])
-def test_sessile_cap_reaches_requested_angle(tlb, theta):
+# (target angle, start angle, nx, ny, start radius, steps)
+# The caps near the ends of the range have the area of a final cap of height ~15 (14, 30 degrees) or of
+# radius 50 (145 degrees), so that the lattice resolves the fitted circle near the wall.  Beyond 145
+# degrees the caps of this discretisation leave the bar: 150 degrees relaxes to 154.3 (radius 27 or 50
+# alike) and a 166-degree cap lifts off the wall onto a film of C2.
+CAPS = [(45.0, 90.0, 200, 100, 32.0, 150000), (70.0, 90.0, 200, 100, 32.0, 150000),
+        (110.0, 90.0, 200, 100, 32.0, 150000), (135.0, 90.0, 200, 100, 32.0, 150000),
+        (14.0, 17.0, 420, 60, 380.0, 400000), (30.0, 36.0, 320, 70, 150.0, 300000),
+        (145.0, 135.0, 200, 150, 51.0, 300000)]
+
+
+@pytest.mark.parametrize("theta,theta0,nx,ny,R0,steps", CAPS)
+def test_sessile_cap_reaches_requested_angle(tlb, theta, theta0, nx, ny, R0, steps):
     kappa, alpha = (0.01, 0.01, 0.01), 1.0
     h = tlb.wetting_from_angles(kappa, alpha, theta, 90.0)
-    nx, ny, R0 = 200, 100, 32.0
     gp, gk = inputs.mobility_to_gamma(0.2, 1.0, 1.0)
     w = dict(lattice=0, nx=nx, ny=ny, nz=1, walls_y=1, kappa=kappa, alpha=alpha, tau_f=1.0, tau_g=1.0, tau_k=1.0,
              gamma_phi=gp, gamma_psi=gk)
-    print(f"[case] sessile cap theta={theta} h={h}", flush=True)
+    print(f"[case] sessile cap theta={theta} from {theta0} {nx}x{ny} h={h}", flush=True)
     sys.stdout.flush()
     s = tlb.Sim(tlb.make_params(prec=tlb.TLB_F64, **{k: w[k] for k in KEYS}))
     s.set_wetting_both(inputs.uniform_h(nx, h))
-    s.init_equilibrium(inputs.cap(nx, ny, R0, 90.0))
-    s.step(150000)
+    s.init_equilibrium(inputs.cap(nx, ny, R0, theta0))
+    s.step(steps)
     d = s.diagnostics()
     assert d["nonfinite"] == 0
     got = shapes.fit_contact_angle(s.field("C1").reshape(ny, nx), nx, ny)
