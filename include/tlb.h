@@ -118,7 +118,7 @@ enum {
  *             BGK only (TLB_EINVAL otherwise).
  *   tau_bulk, tau_ghost  MRT relaxation times, each > 1/2 (ignored for BGK).
  *   ncomp     number of fluid components N, 3 .. TLB_MAX_COMP (0 means 3).
- *             N > 3 (Sec. II.E, D2Q9 only) uses rho = sum_m C_m, phi = C1 - C2
+ *             N > 3 (Sec. II.E, both lattices) uses rho = sum_m C_m, phi = C1 - C2
  *             and psi_l = C_l for l >= 3, with one k population set per psi_l
  *             (species 2 .. N-1, all relaxing with tau_k and using gamma_psi)
  *             and mu_psi_l = mu_l - (mu_1 + mu_2)/2.  Every per-component

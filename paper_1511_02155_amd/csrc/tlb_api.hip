@@ -101,10 +101,9 @@ static bool params_valid(const tlb_params* p)
     if (!isfinite(p->gamma_phi) || !isfinite(p->gamma_psi)) return false;
     if (p->no_advection != 0 && p->no_advection != 1) return false;
     if (p->collision != TLB_BGK && p->collision != TLB_MRT) return false;
-    // more than three components (Sec. II.E): D2Q9 only
+    // more than three components (Sec. II.E)
     if (p->ncomp != 0 && (p->ncomp < 3 || p->ncomp > TLB_MAX_COMP)) return false;
     const int nc = ncomp_of(p);
-    if (nc > 3 && p->lattice != TLB_D2Q9) return false;
     for (int m = 3; m < nc; ++m)
         if (!(p->kappa_hi[m - 3] > 0.0) || !isfinite(p->kappa_hi[m - 3])) return false;
     if (p->collision == TLB_MRT) {
@@ -224,7 +223,9 @@ static void default_launch(tlb_sim* s)
         s->launch.width = bx;
         s->launch.height = by;
         s->launch.chunk = chunk;
-        s->launch.variant = p.prec == TLB_F32 ? 2 : 1;
+        // the pipelined sweep is built for FP32 storage of three components; with more components
+        // the populations a lane holds in variant 1 spill in FP64, so they pull plane z twice
+        s->launch.variant = s->nc > 3 ? 0 : (p.prec == TLB_F32 ? 2 : 1);
     }
 }
 
@@ -233,7 +234,8 @@ static bool launch_valid(const tlb_sim* s, const tlb_launch* l)
     if (l->chunk < 1 || l->variant < 0 || l->variant > 2) return false;
     if (s->p.lattice == TLB_D2Q9)
         return l->variant < 2 && (l->width == 64 || l->width == 128 || l->width == 256);
-    if (l->variant == 2 && s->p.prec != TLB_F32) return false;  // the pipelined sweep is built for FP32 storage
+    // the pipelined sweep is built for FP32 storage of three components
+    if (l->variant == 2 && (s->p.prec != TLB_F32 || s->nc != 3)) return false;
     const int w = l->width, h = l->height;
     if (w == 32 && h == 8) return true;
     if (w == 64 && h == 4) return true;
@@ -531,7 +533,7 @@ static hipError_t launch_one(const tlb_sim* s, const StepArgs<T>& a)
                ? launch_step2d<T>(a, s->launch.width, s->launch.variant, s->p.collision == TLB_MRT, s->nc,
                                   s->stream)
                : launch_step3d<T>(a, s->launch.width, s->launch.height, s->launch.variant,
-                                  s->p.collision == TLB_MRT, s->stream);
+                                  s->p.collision == TLB_MRT, s->nc, s->stream);
 }
 
 template <typename T>

@@ -381,12 +381,15 @@ hipError_t launch_copy16(const void* src, void* dst, int64_t n16, hipStream_t s)
     return hipGetLastError();
 }
 
-// Dispatch on the lattice and the number of components (3, 4 or 5; more than
-// three on D2Q9 only).
+// Dispatch on the lattice and the number of components (3, 4 or 5).
 #define TLB_AUX_DISPATCH(KERNEL, GRID, BLOCK, S, ...)                                                       \
     do {                                                                                                  \
-        if (g.lattice == 1)                                                                               \
+        if (g.lattice == 1 && g.nc == 3)                                                                  \
             hipLaunchKernelGGL((KERNEL<D3Q19, 3, __VA_ARGS__>), GRID, BLOCK, 0, S, ARGS);                  \
+        else if (g.lattice == 1 && g.nc == 4)                                                             \
+            hipLaunchKernelGGL((KERNEL<D3Q19, 4, __VA_ARGS__>), GRID, BLOCK, 0, S, ARGS);                  \
+        else if (g.lattice == 1)                                                                          \
+            hipLaunchKernelGGL((KERNEL<D3Q19, 5, __VA_ARGS__>), GRID, BLOCK, 0, S, ARGS);                  \
         else if (g.nc == 3)                                                                               \
             hipLaunchKernelGGL((KERNEL<D2Q9, 3, __VA_ARGS__>), GRID, BLOCK, 0, S, ARGS);                   \
         else if (g.nc == 4)                                                                               \

@@ -38,14 +38,18 @@ __device__ __forceinline__ int xcd_item(int b, int G)
 template <typename T>
 hipError_t launch_step2d(const StepArgs<T>& a, int width, int hold, bool mrt, int nc, hipStream_t s);
 template <typename T>
-hipError_t launch_step3d(const StepArgs<T>& a, int width, int height, int variant, bool mrt, hipStream_t s);
+hipError_t launch_step3d(const StepArgs<T>& a, int width, int height, int variant, bool mrt, int nc, hipStream_t s);
+template <typename T>
+hipError_t launch_step3d_n4(const StepArgs<T>& a, int width, int height, int variant, bool mrt, hipStream_t s);
+template <typename T>
+hipError_t launch_step3d_n5(const StepArgs<T>& a, int width, int height, int variant, bool mrt, hipStream_t s);
 
 // Auxiliary kernels (tlb_aux.hip).
 struct AuxGeom {
     int lattice;  // 0 D2Q9, 1 D3Q19
     int nx, ny, nz, walls;
     int64_t N;
-    int nc = 3;   // components (3 .. kMaxComp; more than 3 on D2Q9 only)
+    int nc = 3;   // components (3 .. kMaxComp)
 };
 
 // 1 / (alpha^2 kappa_m) per component, for the wetting ghost offsets.

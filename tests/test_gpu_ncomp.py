@@ -191,3 +191,87 @@ def test_ncomp_limits_are_enforced(env):
     ps = (tlb.tlb_params * 1)(p)
     hb = ctypes.c_void_p()
     assert tlb.tlb_batch_create(ps, 1, None, ctypes.byref(hb)) == tlb.TLB_EINVAL
+
+
+# --------------------------------------------------------------------------
+# D3Q19 with N components, against torch_ref.step3 (FP64 1e-12, FP32 storage 1e-5)
+# --------------------------------------------------------------------------
+def _case3(NC, nx, ny, nz, walls, seed, tau=(0.9, 0.8, 0.7)):
+    rng = np.random.default_rng(seed)
+    C = rng.random((NC, nz, ny, nx)) + 0.1
+    C[1] += 1.0  # a majority component with noisy minorities
+    C /= C.sum(0)
+    u = 0.02 * rng.standard_normal((3, nz, ny, nx))
+    h = rng.uniform(-0.003, 0.003, (2, NC, nz, nx)) if walls else None
+    kappa = list(0.01 + 0.01 * rng.random(NC))
+    gp, gk = inputs.mobility_to_gamma(0.1, tau[1], tau[2])
+    w = dict(lattice=1, nx=nx, ny=ny, nz=nz, walls_y=walls, kappa=kappa, alpha=1.1, tau_f=tau[0], tau_g=tau[1],
+             tau_k=tau[2], gamma_phi=gp, gamma_psi=gk)
+    return w, C, u, h
+
+
+def _oracle3(torch, w, C, u, h, steps):
+    from oracle import torch_ref
+
+    hh = None if h is None else torch.tensor(h)
+    kap = torch.tensor(w["kappa"], dtype=torch.float64)
+    g = (w["gamma_phi"], w["gamma_psi"])
+    pop = torch_ref.equilibrium_state3(torch.tensor(C), hh, kap, w["alpha"], g, bool(w["walls_y"]), torch.tensor(u))
+    pop = torch_ref.run3(pop, hh, kap, w["alpha"], (w["tau_f"], w["tau_g"], w["tau_k"]), g, bool(w["walls_y"]), steps)
+    return pop.numpy()
+
+
+def _gpu3(tlb, w, C, u, h, steps, prec, launch=None):
+    s = tlb.Sim(tlb.make_params(prec=prec, **w))
+    if launch:
+        s.set_launch(**launch)
+    if h is not None:
+        s.set_wetting_both(h.reshape(2, -1))
+    s.init_equilibrium(C.reshape(C.shape[0], -1), u.reshape(3, -1))
+    s.step(steps)
+    return s
+
+
+@pytest.mark.parametrize("NC,dims,walls,launch", [
+    (4, (20, 13, 7), 1, dict(width=32, height=8, chunk=3, variant=0)),
+    (4, (20, 13, 7), 1, dict(width=64, height=4, chunk=7, variant=1)),
+    (4, (9, 70, 5), 0, dict(width=64, height=4, chunk=2, variant=0)),
+    (5, (20, 13, 7), 1, dict(width=32, height=8, chunk=4, variant=1)),
+    (5, (3, 3, 3), 0, dict(width=32, height=8, chunk=1, variant=0)),
+])
+def test_ncomp_d3q19_fp64_against_the_oracle(env, NC, dims, walls, launch):
+    torch, tlb = env
+    nx, ny, nz = dims
+    w, C, u, h = _case3(NC, nx, ny, nz, walls, seed=NC * 10 + nx)
+    _note(f"ncomp d3q19 {NC} {dims} walls={walls} {launch}")
+    ref = _oracle3(torch, w, C, u, h, 12)
+    s = _gpu3(tlb, w, C, u, h, 12, tlb.TLB_F64, launch)
+    got = s.all_populations().reshape(ref.shape)
+    for sp in range(NC):
+        err = np.abs(got[sp] - ref[sp]).max()
+        assert err <= 1e-12 * np.abs(ref[sp]).max(), (sp, err)
+    from oracle import torch_ref
+
+    Cref = torch_ref.concentrations(torch.tensor(ref)).numpy().reshape(NC, -1)
+    for m in range(NC):
+        assert np.abs(s.field(f"C{m + 1}") - Cref[m]).max() <= 1e-12, m
+    d = s.diagnostics()
+    for l in range(NC - 2):
+        assert d["mass"][2 + l] == pytest.approx(ref[2 + l].sum(), rel=1e-12)
+    s.close()
+
+
+@pytest.mark.parametrize("NC", [4, 5])
+def test_ncomp_d3q19_fp32_storage(env, NC):
+    torch, tlb = env
+    w, C, u, h = _case3(NC, 24, 17, 9, 1, seed=NC + 3)
+    _note(f"ncomp d3q19 {NC} fp32")
+    from oracle import torch_ref
+
+    ref = torch_ref.concentrations(torch.tensor(_oracle3(torch, w, C, u, h, 40))).numpy().reshape(NC, -1)
+    s = _gpu3(tlb, w, C, u, h, 40, tlb.TLB_F32)
+    for m in range(NC):
+        assert np.abs(s.field(f"C{m + 1}") - ref[m]).max() <= 1e-5, m
+    with pytest.raises(tlb.TLBError):
+        s.set_launch(64, height=4, chunk=4, variant=2)  # the pipelined sweep holds three components only
+    s.close()

@@ -134,3 +134,64 @@ def test_laplace_pressure_of_pairs_with_a_fourth_component(m, n):
     pb = Cf.sum(0) / 3 + sum(kappa[k] / 2 * Cf[k] ** 2 * (1 - Cf[k]) * (1 - 3 * Cf[k]) for k in range(NC))
     g = analytic.surface_tension(kappa[m], kappa[n], 1.0)
     assert 0.95 <= (pb[N // 2, N // 2] - pb[0, 0]) * R / g <= 1.03
+
+
+# --------------------------------------------------------------------------
+# D3Q19 with N components: torch_ref.step3, the oracle of the 3D GPU step for N > 3 (N = 3 is pinned
+# to the C oracle in test_oracle_torch_ref.py)
+# --------------------------------------------------------------------------
+def _args3(kappa, h=None, walls=False):
+    return _args(kappa, h, walls)
+
+
+def _init3(C, a, u=None):
+    from oracle import torch_ref
+
+    return torch_ref.equilibrium_state3(torch.tensor(C), a["h"], a["kappa"], a["alpha"], a["gamma"], a["walls"],
+                                        None if u is None else torch.tensor(u))
+
+
+def _run3(pop, a, steps):
+    from oracle import torch_ref
+
+    return torch_ref.run3(pop, a["h"], a["kappa"], a["alpha"], a["tau"], a["gamma"], a["walls"], steps)
+
+
+@pytest.mark.parametrize("NC,swap", [(4, (2, 3)), (5, (0, 1))])
+def test_d3q19_relabelling_components_permutes_the_run(NC, swap):
+    nx, ny, nz = 7, 6, 5
+    rng = np.random.default_rng(14)
+    C = _random_fields(NC, ny * nz, nx, 15).reshape(NC, nz, ny, nx)
+    u = 0.02 * rng.standard_normal((3, nz, ny, nx))
+    h = rng.uniform(-0.003, 0.003, (2, NC, nz, nx))
+    kappa = list(0.01 + 0.01 * rng.random(NC))
+    i, j = swap
+    perm = list(range(NC))
+    perm[i], perm[j] = j, i
+    a = _args3(kappa, h, True)
+    b = _args3([kappa[k] for k in perm], h[:, perm], True)
+    r1 = torch_ref_concentrations(_run3(_init3(C, a, u), a, 12))
+    r2 = torch_ref_concentrations(_run3(_init3(C[perm], b, u), b, 12))
+    assert np.abs(r1[perm] - r2).max() < 1e-14
+
+
+@pytest.mark.parametrize("NC", [4, 5])
+def test_d3q19_each_population_set_is_conserved(NC):
+    nx, ny, nz = 8, 6, 5
+    C = _random_fields(NC, ny * nz, nx, 16).reshape(NC, nz, ny, nx)
+    u = 0.02 * np.random.default_rng(17).standard_normal((3, nz, ny, nx))
+    a = _args3([0.01 + 0.002 * m for m in range(NC)])
+    pop0 = _init3(C, a, u)
+    pop = _run3(pop0, a, 25)
+    s0, s1 = pop0.sum(dim=(1, 2, 3, 4)), pop.sum(dim=(1, 2, 3, 4))
+    assert torch.abs(s1 - s0).max().item() < 1e-12 * nx * ny * nz
+    assert torch.abs(pop - pop0).max().item() > 1e-4
+
+
+def test_d3q19_uniform_state_at_rest_is_a_fixed_point():
+    NC, nx, ny, nz = 5, 6, 5, 4
+    C = np.ones((NC, nz, ny, nx)) * np.array([0.3, 0.25, 0.2, 0.15, 0.1]).reshape(NC, 1, 1, 1)
+    a = _args3([0.01, 0.012, 0.014, 0.016, 0.018], np.zeros((2, NC, nz, nx)), True)
+    pop0 = _init3(C, a)
+    pop = _run3(pop0, a, 10)
+    assert torch.abs(pop - pop0).max().item() < 1e-14
