@@ -114,8 +114,8 @@ static bool params_valid(const tlb_params* p)
     const int Q = p->lattice == TLB_D2Q9 ? 9 : 19;
     const int64_t esize = p->prec == TLB_F32 ? 4 : 8;
     if (p->lattice == TLB_D2Q9) {
-        // the D2Q9 kernels address all population sets of a state through one descriptor
-        if ((int64_t)nc * Q * N * esize > (int64_t)0xFFFFFF00) return false;
+        // the D2Q9 step addresses each population array through a descriptor of its own
+        if (N * esize > (int64_t)0xFFFFFF00) return false;
     } else {
         // the D3Q19 kernels address each z plane through a descriptor of its own
         if (plane3d_elems(p->nx, p->ny, nc * Q) * esize > (int64_t)0xFFFFFF00) return false;
@@ -1007,13 +1007,16 @@ static tlb_status kpart_reduce(tlb_sim* s, double* dkappa)
     return TLB_OK;
 }
 
+// The reverse sweep addresses a whole state through one buffer descriptor (32-bit byte offsets).
+static bool adj_fits(const tlb_sim* s) { return tlb_state_bytes(s) <= (int64_t)0xFFFFFF00; }
+
 // dh accumulation target [2][3][nx]: the caller's array, or a scratch sink.
 static double* dh_target(tlb_sim* s, double* dh) { return dh ? dh : s->dhs; }
 
 extern "C" tlb_status tlb_adjoint_seed_dev(tlb_sim* s, const void* dLdC, void* lam)
 {
     if (!s || !lam) return TLB_EINVAL;
-    if (s->p.lattice != TLB_D2Q9 || s->p.collision != TLB_BGK || s->nc != 3) return TLB_EINVAL;
+    if (s->p.lattice != TLB_D2Q9 || s->p.collision != TLB_BGK || s->nc != 3 || !adj_fits(s)) return TLB_EINVAL;
     const AuxGeom g = geom(s);
     hipError_t e = (s->p.prec == TLB_F32) ? launch_adjoint_seed<float>(g, (const float*)dLdC, (float*)lam, s->stream)
                                           : launch_adjoint_seed<double>(g, (const double*)dLdC, (double*)lam, s->stream);
@@ -1025,7 +1028,7 @@ extern "C" tlb_status tlb_adjoint_step_dev(tlb_sim* s, const void* state, const 
                                            double* dh, double* dkappa)
 {
     if (!s || !state || !lam_in || !lam_out || lam_in == lam_out) return TLB_EINVAL;
-    if (s->p.lattice != TLB_D2Q9 || s->p.collision != TLB_BGK || s->nc != 3) return TLB_EINVAL;
+    if (s->p.lattice != TLB_D2Q9 || s->p.collision != TLB_BGK || s->nc != 3 || !adj_fits(s)) return TLB_EINVAL;
     tlb_status st = adj_alloc(s, 0);
     if (!st) st = kpart_clear(s);
     if (!st) st = adj_step_any(s, state, lam_in, lam_out, dh_target(s, dh));
@@ -1036,7 +1039,7 @@ extern "C" tlb_status tlb_adjoint_step_dev(tlb_sim* s, const void* state, const 
 extern "C" tlb_status tlb_adjoint_step(tlb_sim* s, const void* state, void* lam, double* dh, double* dkappa)
 {
     if (!s || !state || !lam) return TLB_EINVAL;
-    if (s->p.lattice != TLB_D2Q9 || s->p.collision != TLB_BGK || s->nc != 3) return TLB_EINVAL;
+    if (s->p.lattice != TLB_D2Q9 || s->p.collision != TLB_BGK || s->nc != 3 || !adj_fits(s)) return TLB_EINVAL;
     tlb_status st = adj_alloc(s, 0);
     if (!st) st = kpart_clear(s);
     if (!st) st = adj_step_any(s, state, lam, s->lam[0], dh_target(s, dh));
@@ -1092,7 +1095,7 @@ extern "C" tlb_status tlb_adjoint_step_noalloc(tlb_sim* s, const void* state, co
                                                double* dh, double* dkappa)
 {
     if (!s || !state || !lam_in || !lam_out || lam_in == lam_out) return TLB_EINVAL;
-    if (s->p.lattice != TLB_D2Q9 || s->p.collision != TLB_BGK || s->nc != 3) return TLB_EINVAL;
+    if (s->p.lattice != TLB_D2Q9 || s->p.collision != TLB_BGK || s->nc != 3 || !adj_fits(s)) return TLB_EINVAL;
     if (tlb_adjoint_step_noalloc_scratch(s) > TLB_NOALLOC_SCRATCH_BYTES) return TLB_EINVAL;
     double* base = nullptr;
     tlb_status st = scratch_of(s->dev, &base);
@@ -1153,7 +1156,7 @@ extern "C" tlb_status tlb_adjoint_backward(tlb_sim* s, int64_t nsteps, int64_t e
                                            const void* dLdC, double* dh, double* dkappa)
 {
     if (!s || !ckpt || nsteps < 1 || every < 1) return TLB_EINVAL;
-    if (s->p.lattice != TLB_D2Q9 || s->p.collision != TLB_BGK || s->nc != 3) return TLB_EINVAL;
+    if (s->p.lattice != TLB_D2Q9 || s->p.collision != TLB_BGK || s->nc != 3 || !adj_fits(s)) return TLB_EINVAL;
     tlb_status st = adj_alloc(s, every);
     if (st) return st;
     const size_t sb = (size_t)tlb_state_bytes(s);

@@ -1,28 +1,21 @@
 // Plain D2Q9 step: one workgroup per (strip, chunk) item of one lattice.
 // The sweep itself (tlb_sweep2d.hpp) is shared with the batched kernel.
-#include "tlb_sweep2d.hpp"
+#include "tlb_step2d.hpp"
 
 namespace tlb {
 
-template <typename T, int W, int DEPTH, bool MRT, int NC>
-__global__ __launch_bounds__(W) __attribute__((amdgpu_waves_per_eu(step2d_waves<T, DEPTH>(NC))))
-void k_step2d(StepArgs<T> A)
-{
-    __shared__ Sweep2Lds<T, W, NC> S;
-    const int item = xcd_item(blockIdx.x, A.nitems);
-    const int chunk = item / A.ntx;  // chunk-major: an XCD's range covers whole bands
-    const int strip = item - chunk * A.ntx;
-    sweep2d<T, W, DEPTH, MRT, NC>(A, strip, chunk, S);
-}
 
 // Instantiated: three, four and five components (Sec. II.E), both depths.
 template <typename T>
 hipError_t launch_step2d(const StepArgs<T>& a, int width, int depth, bool mrt, int nc, hipStream_t s)
 {
+    // states past 4 GiB take the kernels with one buffer descriptor per population array
+    if ((int64_t)9 * nc * a.N * (int64_t)sizeof(T) > (int64_t)0xFFFFFF00)
+        return launch_step2d_big<T>(a, width, depth, mrt, nc, s);
     dim3 grid(a.nitems);
 #define TLB_L2(W, D, M, NC)                                                        \
     if (width == W && depth == D && mrt == M && nc == NC) {                        \
-        hipLaunchKernelGGL((k_step2d<T, W, D, M, NC>), grid, dim3(W), 0, s, a);    \
+        hipLaunchKernelGGL((k_step2d<T, W, D, M, NC, false>), grid, dim3(W), 0, s, a); \
         return hipGetLastError();                                                  \
     }
 #define TLB_L2W(D, M, NC) TLB_L2(64, D, M, NC) TLB_L2(128, D, M, NC) TLB_L2(256, D, M, NC)

@@ -38,15 +38,41 @@ namespace tlb {
 
 using L9 = D2Q9;
 
+// Addressing of population array j (= 9 s + i) of a species-major state [NC][9][N].  A state of at
+// most 4 GiB is covered by one buffer descriptor and a wavefront-uniform byte offset
+// (j N + row) sizeof(T).  A larger state (BIG) takes one descriptor per array, so that byte offsets
+// within an array (row y * nx + column) stay below 2^32 whatever the size of the whole state; the
+// extra scalar work of building them costs about 2% at 1024^2, hence the two forms.
+template <typename T, bool BIG>
+struct StateAddr {
+    const T* base;
+    int64_t N;
+    Rsrc whole;
+    __device__ __forceinline__ StateAddr(const T* b, int64_t n, int nc) : base(b), N(n)
+    {
+        whole = make_rsrc(b, BIG ? 0u : (uint32_t)((int64_t)9 * nc * n * (int64_t)sizeof(T)));
+    }
+    __device__ __forceinline__ Rsrc rsrc(int j) const
+    {
+        return BIG ? make_rsrc(base + (int64_t)j * N, (uint32_t)(N * (int64_t)sizeof(T))) : whole;
+    }
+    // byte offset of row element `row` (= y nx) of array j
+    __device__ __forceinline__ uint32_t soff(int j, uint32_t row) const
+    {
+        return (uint32_t)((BIG ? row : (uint32_t)j * (uint32_t)N + row) * (uint32_t)sizeof(T));
+    }
+};
+
 // Pull of the post-propagation populations of row y at the lane's column:
 // f_i(r) = u_i(r - e_i), or u_opp(i)(r) when r - e_i lies beyond a wall
 // (half-way bounce-back).  vo[0..2]: byte offsets of columns x, x-1, x+1;
 // every row-dependent part of the address is wavefront-uniform.
-template <typename T, int NC = 3>
-__device__ __forceinline__ void pull2d(const StepArgs<T>& A, Rsrc src, const uint32_t* vo, int y, T* p)
+template <typename T, int NC = 3, bool BIG = false>
+__device__ __forceinline__ void pull2d(const StepArgs<T>& A, const StateAddr<T, BIG>& src, const uint32_t* vo, int y,
+                                       T* p)
 {
     const int ny = A.ny;
-    const uint32_t nx = (uint32_t)A.nx, N = (uint32_t)A.N;
+    const uint32_t nx = (uint32_t)A.nx;
     const uint32_t ym = (y == 0) ? ny - 1 : y - 1;
     const uint32_t yp = (y == ny - 1) ? 0 : y + 1;
     const bool blo = A.walls && y == 0;
@@ -56,10 +82,12 @@ __device__ __forceinline__ void pull2d(const StepArgs<T>& A, Rsrc src, const uin
         const int ex = L9::ex[i], ey = L9::ey[i];
         const bool bb = (ey == 1) ? blo : (ey == -1) ? bhi : false;
         const uint32_t ys = ey == 0 ? (uint32_t)y : (ey == 1 ? ym : yp);
-        const uint32_t so = (bb ? (uint32_t)L9::opp[i] * N + (uint32_t)y * nx : (uint32_t)i * N + ys * nx) * sizeof(T);
+        const int ia = bb ? L9::opp[i] : i;
+        const uint32_t row = bb ? (uint32_t)y * nx : ys * nx;
         const uint32_t v = bb ? vo[0] : vo[ex == 0 ? 0 : (ex == 1 ? 1 : 2)];
 #pragma unroll
-        for (int s = 0; s < NC; ++s) p[9 * s + i] = bload<T>(src, v, so + (uint32_t)(9 * s) * N * sizeof(T));
+        for (int s = 0; s < NC; ++s)
+            p[9 * s + i] = bload<T>(src.rsrc(9 * s + ia), v, src.soff(9 * s + ia, row));
     }
 }
 
@@ -123,7 +151,7 @@ struct Sweep2Lds {
 // One work item: strip `strip` (W columns) of rows [chunk*A.chunk, ...) of
 // the lattice described by A, swept in the direction given by the chunk's
 // parity.  Every lane of the workgroup must call it.
-template <typename T, int W, int DEPTH, bool MRT = false, int NC = 3>
+template <typename T, int W, int DEPTH, bool MRT = false, int NC = 3, bool BIG = false>
 __device__ __forceinline__ void sweep2d(const StepArgs<T>& A, int strip, int chunk, Sweep2Lds<T, W, NC>& S)
 {
     auto& lds = S.row;
@@ -155,17 +183,14 @@ __device__ __forceinline__ void sweep2d(const StepArgs<T>& A, int strip, int chu
     const bool ldr = one_held ? ((t >= W - 64) && lane >= 32 && lane < 32 + J) : ((t >= W - 64) && lane >= 64 - J);
     const int hjl = lane, hjr = one_held ? lane - 32 : lane - (64 - J);
     const uint32_t nxz = (uint32_t)A.nx;  // nz == 1
-    const uint32_t N = (uint32_t)A.N;
+
+    const StateAddr<T, BIG> src(A.src, A.N, NC), dst(A.dst, A.N, NC);
 
     // Row r_j of the sweep (j = -1 .. L) lives in LDS buffer (j + 1) & 3.
     auto row_of = [&](int j) { return yfirst + j * dir; };
     auto ghost_of = [&](int y) { return (A.walls && y < 0) ? 0 : ((A.walls && y >= A.ny) ? 1 : -1); };
     auto wrap_y = [&](int y) { return y < 0 ? y + A.ny : (y >= A.ny ? y - A.ny : y); };
 
-    // buffer resources of the source and destination states (9 NC N values each)
-    const uint32_t sbytes = (uint32_t)(J * A.N * (int64_t)sizeof(T));
-    const Rsrc rs = make_rsrc(A.src, sbytes);
-    const Rsrc rd = make_rsrc(A.dst, sbytes);
     const uint32_t vo[3] = {(uint32_t)x * (uint32_t)sizeof(T),
                             (uint32_t)(x == 0 ? A.nx - 1 : x - 1) * (uint32_t)sizeof(T),
                             (uint32_t)(x == A.nx - 1 ? 0 : x + 1) * (uint32_t)sizeof(T)};
@@ -185,7 +210,7 @@ __device__ __forceinline__ void sweep2d(const StepArgs<T>& A, int strip, int chu
     int hb = 0;
 
     auto load_row = [&](int y, T* p, T* hv) {
-        if (active) pull2d<T, NC>(A, rs, vo, y, p);
+        if (active) pull2d<T, NC, BIG>(A, src, vo, y, p);
         if constexpr (one_held) {
             if (ldl || ldr) hv[0] = pull2d_one<T>(A, ldl ? hjl : hjr, ldl ? xl : xr, y);
         } else {
@@ -280,12 +305,12 @@ __device__ __forceinline__ void sweep2d(const StepArgs<T>& A, int strip, int chu
 #pragma unroll
             for (int m = 0; m < NC; ++m) dc[m] = lds[qb][m][t + 1];
             collide<L9, MRT, NC>(A.P, Mc, dc, gC, lC, Pc, Pc + 9, Pc + 18);
-            const uint32_t rowo = (uint32_t)y * (uint32_t)A.nx;
+            const uint32_t row = (uint32_t)y * (uint32_t)A.nx;
 #pragma unroll
             for (int i = 0; i < 9; ++i) {
-                const uint32_t so = ((uint32_t)i * N + rowo) * (uint32_t)sizeof(T);
 #pragma unroll
-                for (int s = 0; s < NC; ++s) bstore<T>(Pc[9 * s + i], rd, vo[0], so + (uint32_t)(9 * s) * N * sizeof(T));
+                for (int s = 0; s < NC; ++s)
+                    bstore<T>(Pc[9 * s + i], dst.rsrc(9 * s + i), vo[0], dst.soff(9 * s + i, row));
             }
         }
     };

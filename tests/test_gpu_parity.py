@@ -360,6 +360,62 @@ def test_spinodal_256cube_full_size_sampled(tlb, orc):
             assert np.abs(gpu_pops[sp][:, n] - pop[sp][:, ic]).max() < 2e-7, (c, sp)
 
 
+def _window2(C, nx, ny, centre, W):
+    xs = (np.arange(W) + centre[0] - W // 2) % nx
+    ys = (np.arange(W) + centre[1] - W // 2) % ny
+    return C.reshape(3, ny, nx)[:, ys][:, :, xs].reshape(3, -1)
+
+
+def test_d2q9_state_beyond_32bit_offsets_sampled(tlb, orc):
+    """6144^2 D2Q9 FP64 (8.2 GB per state, past the 4 GiB one buffer descriptor can address): C_m at
+    seeded nodes after 3 steps against the oracle on a periodic 24^2 window around each (the update
+    reaches 2 nodes per step plus 1 for the initial stencil, less than the half-width 12)."""
+    n, steps, W = 6144, 3, 24
+    w = inputs.spinodal_2d(n, steps)
+    C = w["C"]()
+    _note("6144^2 fp64 beyond 32-bit offsets")
+    s = _gsim(tlb, w, tlb.TLB_F64)
+    assert s.state_bytes() > 2 ** 32
+    s.init_equilibrium(C)
+    s.step(steps)
+    got = np.stack([s.field(f) for f in ("C1", "C2", "C3")])
+    s.close()
+    pw = _oparams(orc, w).replace(nx=W, ny=W)
+    rng = np.random.default_rng(78)
+    ic = W // 2 + W * (W // 2)
+    for c in [(0, 0), (n - 1, n - 1)] + [tuple(rng.integers(0, n, 2)) for _ in range(6)]:
+        pop = orc.init_equilibrium(pw, _window2(C, n, n, c, W))
+        orc.step(pw, pop, steps)
+        F = orc.fields(pw, pop)
+        node = c[0] + n * c[1]
+        for m, f in enumerate(("C1", "C2", "C3")):
+            assert abs(got[m][node] - F[f][ic]) <= 1e-12, (c, f)
+
+
+def test_d3q19_state_beyond_32bit_offsets_sampled(tlb, orc):
+    """448^3 D3Q19 FP32 (20.5 GB per state; a species-major state stopped at 383^3): C_m at seeded nodes
+    after 2 steps against the oracle on periodic 16^3 windows."""
+    n, steps, W = 448, 2, 16
+    w = inputs.spinodal_3d(n, steps)
+    C = w["C"]()
+    _note("448^3 fp32 beyond 32-bit offsets")
+    s = _gsim(tlb, w, tlb.TLB_F32)
+    s.init_equilibrium(C)
+    s.step(steps)
+    got = np.stack([s.field(f) for f in ("C1", "C2", "C3")])
+    s.close()
+    pw = _oparams(orc, w).replace(nx=W, ny=W, nz=W)
+    rng = np.random.default_rng(79)
+    ic = W // 2 + W * (W // 2 + W * (W // 2))
+    for c in [(0, 0, 0), (n - 1, n - 1, n - 1)] + [tuple(rng.integers(0, n, 3)) for _ in range(4)]:
+        pop = orc.init_equilibrium(pw, _window(C, (n, n, n), c, W))
+        orc.step(pw, pop, steps)
+        F = orc.fields(pw, pop)
+        node = c[0] + n * (c[1] + n * c[2])
+        for m, f in enumerate(("C1", "C2", "C3")):
+            assert abs(got[m][node] - F[f][ic]) <= 1e-6, (c, f)
+
+
 # --------------------------------------------------------------------------
 # Diffusive Cahn-Hilliard (no advection) and the interface diagnostics
 # --------------------------------------------------------------------------
