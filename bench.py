@@ -92,6 +92,11 @@ def run_plain(tlb, torch, w, prec, steps, warmup, launch=None):
     N = w["nx"] * w["ny"] * w["nz"]
     per_launch_ms = ms / steps
     bytes_per_launch = sim.bytes_per_node() * N
+    # the same bytes in the same pattern and launch shape without the arithmetic (propagation alone),
+    # timed after the step's state was read out
+    ns = min(steps, 200)
+    sim.stream_only(2)
+    ms_stream = _events_time(torch, stream, lambda: sim.stream_only(ns)) / ns
     out = dict(
         ms_total=ms,
         ms_per_step=per_launch_ms,
@@ -103,6 +108,7 @@ def run_plain(tlb, torch, w, prec, steps, warmup, launch=None):
         launch=sim.launch(),
         steps=steps,
         kernel="k_step2d" if w["lattice"] == 0 else "k_step3d",
+        pattern_ceiling_GBps=bytes_per_launch / (ms_stream * 1e-3) / 1e9,
         mass=d["mass"],
         max_speed=d["max_speed"],
         nonfinite=d["nonfinite"],
@@ -376,6 +382,8 @@ def main():
 
     def add(name, r):
         r["frac_of_hbm"] = r["achieved_GBps"] / HBM_PEAK_GBS
+        if r.get("pattern_ceiling_GBps"):
+            r["frac_of_pattern_ceiling"] = r["achieved_GBps"] / r["pattern_ceiling_GBps"]
         t = measured_traffic(name, r.get("launch"))
         r["traffic"] = t
         if t is not None:
@@ -444,7 +452,10 @@ def main():
         "roofline": {"bound": "hbm", "achieved": head["achieved_GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": head["frac_of_hbm"], "traffic": head["traffic"],
                      "kernel": head.get("kernel"), "bytes_per_launch": head["bytes_per_launch"],
-                     "frac_of_copy_kernel": head["achieved_GBps"] / copy_gbps},
+                     "frac_of_copy_kernel": head["achieved_GBps"] / copy_gbps,
+                     "pattern_ceiling": head.get("pattern_ceiling_GBps"),
+                     "frac_of_pattern_ceiling": (head["achieved_GBps"] / head["pattern_ceiling_GBps"]
+                                                 if head.get("pattern_ceiling_GBps") else None)},
         "check": {"nonfinite": head.get("nonfinite"), "mass": head.get("mass")},
     }
     if not args.no_cpu and hname == "d3q19_256cube_spinodal_f32":

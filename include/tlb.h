@@ -381,7 +381,7 @@ tlb_status tlb_set_wetting_dev(tlb_sim* sim, int wall, const void* h_dev);
  *   D3Q19: each workgroup sweeps a tile of width x height columns (32x8 or
  *     64x4) over `chunk` planes; variant 1 keeps the next plane's populations in registers
  *     between their two uses, variant 0 reads them a second time from cache;
- *     variant 2 (FP32 storage only) also issues the loads of the plane after
+ *     variant 2 (FP32 storage, three components) also issues the loads of the plane after
  *     next before the current plane is collided.
  *   chunk >= 1; chunk = 0 picks a default.  The default shape depends on the
  *   lattice size and precision.  For a given variant, results are bitwise
@@ -414,6 +414,17 @@ tlb_status tlb_get_adjoint_launch(const tlb_sim* sim, tlb_launch* out);
 
 /* Algorithmic HBM bytes one fused step moves per fluid node (read + write). */
 double tlb_bytes_per_node(const tlb_sim* sim);
+
+/*
+ * Propagation alone: nsteps >= 0 times the pull of the fused step (with
+ * half-way bounce-back, eq. latboltPropagation) and its store, with no
+ * collision, in the step's work decomposition and current launch shape (the
+ * D3Q19 tiles without their ring).  It moves exactly the bytes of a step in
+ * exactly its access pattern, so its bandwidth is the ceiling that pattern
+ * leaves the fused step.  It changes the state (to the free-streamed one) but
+ * not the step counter; a measurement call.  Asynchronous on the stream.
+ */
+tlb_status tlb_stream_only(tlb_sim* sim, int64_t nsteps);
 
 /*
  * Plain device-to-device copy kernel (16-byte vector loads and stores) of

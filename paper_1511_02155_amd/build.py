@@ -17,7 +17,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libtlb.so")
 
 SOURCES = ["tlb_api.hip", "tlb_step2d.hip", "tlb_step2d_big.hip", "tlb_step3d.hip", "tlb_step3d_nc.hip",
-           "tlb_aux.hip", "tlb_batch.hip", "tlb_adjoint.hip"]
+           "tlb_aux.hip", "tlb_batch.hip", "tlb_adjoint.hip", "tlb_stream.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

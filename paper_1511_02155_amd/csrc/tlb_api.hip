@@ -562,6 +562,26 @@ extern "C" tlb_status tlb_step(tlb_sim* s, int64_t nsteps)
     return s->p.prec == TLB_F32 ? step_impl<float>(s, nsteps) : step_impl<double>(s, nsteps);
 }
 
+template <typename T>
+static tlb_status stream_impl(tlb_sim* s, int64_t nsteps)
+{
+    StepArgs<T> a = step_args<T>(s);
+    for (int64_t t = 0; t < nsteps; ++t) {
+        a.src = (const T*)s->state[s->cur];
+        a.dst = (T*)s->state[s->cur ^ 1];
+        HIPCHK(launch_stream_only<T>(a, s->p.lattice, s->launch.width, s->launch.height, s->nc, s->stream));
+        s->cur ^= 1;
+    }
+    return TLB_OK;
+}
+
+extern "C" tlb_status tlb_stream_only(tlb_sim* s, int64_t nsteps)
+{
+    if (!s || nsteps < 0) return TLB_EINVAL;
+    if (!s->ready) return TLB_ESTATE;
+    return s->p.prec == TLB_F32 ? stream_impl<float>(s, nsteps) : stream_impl<double>(s, nsteps);
+}
+
 extern "C" tlb_status tlb_set_check_every(tlb_sim* s, int64_t every)
 {
     if (!s || every < 0) return TLB_EINVAL;

@@ -44,6 +44,10 @@ hipError_t launch_step3d_n4(const StepArgs<T>& a, int width, int height, int var
 template <typename T>
 hipError_t launch_step3d_n5(const StepArgs<T>& a, int width, int height, int variant, bool mrt, hipStream_t s);
 
+// Propagation alone in the fused step's pattern and launch shape (tlb_stream.hip).
+template <typename T>
+hipError_t launch_stream_only(const StepArgs<T>& a, int lattice, int width, int height, int nc, hipStream_t s);
+
 // Auxiliary kernels (tlb_aux.hip).
 struct AuxGeom {
     int lattice;  // 0 D2Q9, 1 D3Q19

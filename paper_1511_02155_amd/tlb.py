@@ -50,7 +50,7 @@ EXPORTS = (
     "tlb_set_kappa", "tlb_adjoint_seed_dev", "tlb_adjoint_step_dev", "tlb_checkpoint_slots",
     "tlb_forward_checkpointed", "tlb_adjoint_backward", "tlb_contact_angles", "tlb_wetting_from_angles",
     "tlb_wetting_outside_range", "tlb_batch_wetting_outside_range", "tlb_adjoint_step",
-    "tlb_adjoint_step_noalloc", "tlb_adjoint_step_noalloc_scratch",
+    "tlb_adjoint_step_noalloc", "tlb_adjoint_step_noalloc_scratch", "tlb_stream_only",
 )
 TLB_NOALLOC_SCRATCH_BYTES = 1 << 20
 
@@ -133,6 +133,7 @@ tlb_save_state = _sig("tlb_save_state", ctypes.c_int, [_vp, _vp, ctypes.POINTER(
 tlb_load_state = _sig("tlb_load_state", ctypes.c_int, [_vp, _vp, ctypes.c_int64])
 tlb_save_state_dev = _sig("tlb_save_state_dev", ctypes.c_int, [_vp, _vp])
 tlb_load_state_dev = _sig("tlb_load_state_dev", ctypes.c_int, [_vp, _vp, ctypes.c_int64])
+tlb_stream_only = _sig("tlb_stream_only", ctypes.c_int, [_vp, ctypes.c_int64])
 tlb_device_copy = _sig("tlb_device_copy", ctypes.c_int, [_vp, _vp, ctypes.c_int64, _vp])
 tlb_batch_create = _sig("tlb_batch_create", ctypes.c_int, [_P, ctypes.c_int32, _vp, ctypes.POINTER(_vp)])
 tlb_batch_destroy = _sig("tlb_batch_destroy", ctypes.c_int, [_vp])
@@ -292,6 +293,10 @@ class Sim:
 
     def synchronize(self):
         check(tlb_synchronize(self._h), "tlb_synchronize")
+
+    def stream_only(self, n):
+        """Propagation alone (no collision) n times, in the step's pattern: a bandwidth reference."""
+        check(tlb_stream_only(self._h, int(n)), "tlb_stream_only")
 
     def field(self, which):
         idx = FIELD_INDEX[which] if isinstance(which, str) else int(which)

@@ -416,6 +416,46 @@ def test_d3q19_state_beyond_32bit_offsets_sampled(tlb, orc):
             assert abs(got[m][node] - F[f][ic]) <= 1e-6, (c, f)
 
 
+def _pull_np(pop, lattice, dims, walls):
+    """Propagation of s [NC][Q][N] with half-way bounce-back in y, in numpy: s'_i(r) = s_i(r - e_i), or
+    s_opp(i)(r) where r - e_i is beyond a wall."""
+    from oracle import torch_ref
+
+    nx, ny, nz = dims
+    E = torch_ref.E3 if lattice == 1 else [(e[0], e[1], 0) for e in torch_ref.E]
+    opp = torch_ref.OPP3 if lattice == 1 else torch_ref.OPP
+    a = pop.reshape(pop.shape[0], len(E), nz, ny, nx)
+    out = np.empty_like(a)
+    for i, (ex, ey, ez) in enumerate(E):
+        out[:, i] = np.roll(a[:, i], shift=(ez, ey, ex), axis=(1, 2, 3))
+        if walls and ey == 1:
+            out[:, i, :, 0, :] = a[:, opp[i], :, 0, :]
+        if walls and ey == -1:
+            out[:, i, :, ny - 1, :] = a[:, opp[i], :, ny - 1, :]
+    return out.reshape(pop.shape)
+
+
+@pytest.mark.parametrize("lattice,dims,walls,launch", [
+    (0, (70, 23, 1), 1, dict(width=64, chunk=5)), (0, (300, 9, 1), 0, dict(width=256, chunk=4)),
+    (1, (37, 21, 13), 1, dict(width=32, height=8, chunk=4)), (1, (9, 70, 5), 0, dict(width=64, height=4, chunk=3))])
+def test_stream_only_is_propagation(tlb, lattice, dims, walls, launch):
+    """tlb_stream_only moves the populations exactly as propagation with half-way bounce-back does
+    (bit for bit), without touching the step counter."""
+    w, C, h = _wet_case(*dims, lattice=lattice, walls=walls, seed=4)
+    s = _gsim(tlb, w, tlb.TLB_F64, dict(launch, variant=0))
+    if h is not None:
+        s.set_wetting_both(h)
+    s.init_equilibrium(C)
+    s.step(3)
+    before = s.all_populations()
+    s.stream_only(2)
+    after = s.all_populations()
+    want = _pull_np(_pull_np(before, lattice, dims, walls), lattice, dims, walls)
+    assert np.array_equal(after, want)
+    assert s.diagnostics()["step"] == 3
+    s.close()
+
+
 # --------------------------------------------------------------------------
 # Diffusive Cahn-Hilliard (no advection) and the interface diagnostics
 # --------------------------------------------------------------------------
