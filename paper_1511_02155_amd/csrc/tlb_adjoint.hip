@@ -148,10 +148,23 @@ __device__ __forceinline__ void adj_local(const Phys<T>& P, const Moments<T>& mo
 // transposes (stage 2 -> 3) of a row are made by one group and used by the next, so they go through
 // LDS rings too; with K = 1 they stay in registers.  Every node runs the same arithmetic for every
 // W and K.
+template <typename T>
+__device__ __forceinline__ Phys<T> adj_phys(const AdjArgs<T>& A);
+template <>
+__device__ __forceinline__ Phys<float> adj_phys<float>(const AdjArgs<float>& A)
+{
+    return A.Pf;
+}
+template <>
+__device__ __forceinline__ Phys<double> adj_phys<double>(const AdjArgs<double>& A)
+{
+    return A.P;
+}
+
 template <typename T, int W, int K, int HOIST>
 __global__ __launch_bounds__(W * K) void k_adj2d(AdjArgs<T> A)
 {
-    using C = acc_t<T>;  // arithmetic type (T is the storage type)
+    using C = T;  // arithmetic type: the storage type
     constexpr int R = K + 2;              // ring rows
     constexpr int RX = K > 1 ? R : 1;     // rings of moments and local transposes (K > 1 only)
     __shared__ C sC[R][3][W];  // dC_m of stage-1 rows
@@ -174,7 +187,7 @@ __global__ __launch_bounds__(W * K) void k_adj2d(AdjArgs<T> A)
     const int y0 = chunk * A.chunk;
     const int y1 = (y0 + A.chunk < ny) ? y0 + A.chunk : ny;
     const bool walls = A.walls != 0;
-    const Phys<C> P = A.P;
+    const Phys<C> P = adj_phys<T>(A);
     const C w0 = C(weight<L9>(0));
 
     Moments<C> mom_prev = {};
@@ -270,7 +283,7 @@ __global__ __launch_bounds__(W * K) void k_adj2d(AdjArgs<T> A)
         // ---- stage 1: moments and dC of row a ----
         Moments<C> mom_new = {};
         if (act1) {
-            mom_new = moments<L9>(pu, pu + 9, pu + 18);
+            mom_new = moments_as<C, L9>(pu, pu + 9, pu + 18);
             C dc[3];
             conc_dev<C>(mom_new, dc);
             const int sa = slot(a);

@@ -176,7 +176,9 @@ static tlb_launch default_adj_launch(const tlb_params& p, int cus)
     l.height = 4;
     l.variant = 2;
     const int nstrips = (p.nx + 57) / 58;
-    int nch = (cus > 0 ? cus : 256) / nstrips;
+    // FP32 storage computes in FP32: about 205 registers and 52 KB of LDS, two workgroups per compute unit
+    const int per_cu = p.prec == TLB_F32 ? 2 : 1;
+    int nch = per_cu * (cus > 0 ? cus : 256) / nstrips;
     if (nch < 1) nch = 1;
     int chunk = (p.ny + nch - 1) / nch;
     chunk += (4 - (chunk + 6) % 4) % 4;
@@ -1001,6 +1003,7 @@ static tlb_status adj_step(tlb_sim* s, const void* u, const void* lam1, void* la
     adj_items(s, a.nstrips, a.nchunks);
     a.nitems = a.nstrips * a.nchunks;
     a.P = make_phys<acc_t<T>>(s->p);
+    a.Pf = make_phys<float>(s->p);
     HIPCHK(launch_adjoint_sweep<T>(a, s->adj_launch.width, s->adj_launch.height, s->adj_launch.variant, s->stream));
     return TLB_OK;
 }

@@ -99,6 +99,7 @@ struct AdjArgs {
     int64_t N;
     int chunk, nchunks, nstrips, nitems;  // strips of (width - 6) output columns
     Phys<acc_t<T>> P;
+    Phys<float> Pf;  // the same parameters for FP32 arithmetic
 };
 template <typename T>
 hipError_t launch_adjoint_sweep(const AdjArgs<T>& a, int width, int rows, int hoist, hipStream_t s);
