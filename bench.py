@@ -31,8 +31,8 @@ _CSRC = "paper_1511_02155_amd/csrc/"
 _COMMON = [_CSRC + "tlb_device.hpp", _CSRC + "tlb_internal.hpp", "paper_1511_02155_amd/build.py"]
 # sources that decide each measured kernel's code; its counter readings are used only while they are unchanged
 KERNEL_SOURCES = {
-    "step2d": _COMMON + [_CSRC + "tlb_sweep2d.hpp", _CSRC + "tlb_step2d.hip"],
-    "step3d": _COMMON + [_CSRC + "tlb_step3d.hip"],
+    "step2d": _COMMON + [_CSRC + "tlb_sweep2d.hpp", _CSRC + "tlb_step2d.hpp", _CSRC + "tlb_step2d.hip"],
+    "step3d": _COMMON + [_CSRC + "tlb_step3d.hpp", _CSRC + "tlb_step3d.hip"],
     "batch2d": _COMMON + [_CSRC + "tlb_sweep2d.hpp", _CSRC + "tlb_batch.hip"],
     "adjoint": _COMMON + [_CSRC + "tlb_adjoint.hip"],
 }
