@@ -189,18 +189,26 @@ __device__ __forceinline__ double bload<double>(Rsrc r, uint32_t voff, uint32_t 
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
 }
 
-template <typename T>
-__device__ __forceinline__ void bstore(T v, Rsrc r, uint32_t voff, uint32_t soff);
-template <>
-__device__ __forceinline__ void bstore<float>(float v, Rsrc r, uint32_t voff, uint32_t soff)
+// Stores take a cache-policy operand: 0 is the default; kStoreStream sets the
+// non-temporal bit (gfx950: "nt"), which writes the line toward memory without
+// keeping it in the caches.  That pays where the stored state is far larger
+// than the 256 MB Infinity Cache, so that the next step cannot find it there
+// anyway, and costs where the state fits (the next step then reads it from
+// memory instead of the cache).
+constexpr int kStoreStream = 2;
+// A state buffer beyond this size is stored with kStoreStream by the kernels that opt in.
+constexpr int64_t kStreamStoreBytes = (int64_t)256 << 20;
+
+template <typename T, int POL = 0>
+__device__ __forceinline__ void bstore(T v, Rsrc r, uint32_t voff, uint32_t soff)
 {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)voff, (int)soff, 0);
-}
-template <>
-__device__ __forceinline__ void bstore<double>(double v, Rsrc r, uint32_t voff, uint32_t soff)
-{
-    typedef uint32_t u2 __attribute__((ext_vector_type(2)));
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, (int)voff, (int)soff, 0);
+    static_assert(sizeof(T) == 4 || sizeof(T) == 8, "FP32 or FP64 values");
+    if constexpr (sizeof(T) == 4) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)voff, (int)soff, POL);
+    } else {
+        typedef uint32_t u2 __attribute__((ext_vector_type(2)));
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, (int)voff, (int)soff, POL);
+    }
 }
 
 // ---------------------------------------------------------------------------

@@ -110,7 +110,7 @@ __device__ __forceinline__ const Phys<double>& phys3d<double>(const StepArgs<dou
     return A.P;
 }
 
-template <typename T, int BX, int BY, int VAR, bool MRT, int NC>
+template <typename T, int BX, int BY, int VAR, bool MRT, int NC, bool NT>
 __global__ __launch_bounds__(BX* BY) void k_step3d(StepArgs<T> A)
 {
     using C = T;
@@ -337,7 +337,8 @@ __global__ __launch_bounds__(BX* BY) void k_step3d(StepArgs<T> A)
                 for (int i = 0; i < 19; ++i)
 #pragma unroll
                     for (int s = 0; s < NC; ++s)
-                        bstore<T>(fb[19 * s + i], rd, col[1][1], (uint32_t)((19 * s + i) * kBlock3d) * (uint32_t)sizeof(T));
+                        bstore<T, NT ? kStoreStream : 0>(fb[19 * s + i], rd, col[1][1],
+                                                     (uint32_t)((19 * s + i) * kBlock3d) * (uint32_t)sizeof(T));
             }
 #pragma unroll
             for (int m = 0; m < NC; ++m) {
@@ -395,7 +396,8 @@ __global__ __launch_bounds__(BX* BY) void k_step3d(StepArgs<T> A)
             for (int i = 0; i < 19; ++i)
 #pragma unroll
                 for (int s = 0; s < NC; ++s)
-                    bstore<T>(fb[19 * s + i], rd, col[1][1], (uint32_t)((19 * s + i) * kBlock3d) * (uint32_t)sizeof(T));
+                    bstore<T, NT ? kStoreStream : 0>(fb[19 * s + i], rd, col[1][1],
+                                                     (uint32_t)((19 * s + i) * kBlock3d) * (uint32_t)sizeof(T));
         }
 
 #pragma unroll
@@ -410,15 +412,27 @@ __global__ __launch_bounds__(BX* BY) void k_step3d(StepArgs<T> A)
     }
 }
 
+// Whether a D3Q19 state of these sizes is stored with the streaming (non-temporal) policy: it is
+// when one state buffer exceeds the Infinity Cache, where it measured 4.5% faster at 256^3 FP32.
+template <typename T, int NC>
+inline bool stream_stores3d(const StepArgs<T>& a)
+{
+    return (int64_t)a.nz * plane3d_elems(a.nx, a.ny, 19 * NC) * (int64_t)sizeof(T) > kStreamStoreBytes;
+}
+
 // Launch of the NC-component kernels (one translation unit per set of NC).
 template <typename T, int NC>
 hipError_t launch_step3d_n(const StepArgs<T>& a, int width, int height, int variant, bool mrt, hipStream_t s)
 {
     dim3 grid(a.nitems);
-#define TLB_L3(BX, BY, V, M)                                                               \
-    if (width == BX && height == BY && variant == V && mrt == M) {                         \
-        hipLaunchKernelGGL((k_step3d<T, BX, BY, V, M, NC>), grid, dim3(BX * BY), 0, s, a); \
-        return hipGetLastError();                                                          \
+    const bool nt = stream_stores3d<T, NC>(a);
+#define TLB_L3(BX, BY, V, M)                                                                         \
+    if (width == BX && height == BY && variant == V && mrt == M) {                                   \
+        if (nt)                                                                                      \
+            hipLaunchKernelGGL((k_step3d<T, BX, BY, V, M, NC, true>), grid, dim3(BX * BY), 0, s, a); \
+        else                                                                                         \
+            hipLaunchKernelGGL((k_step3d<T, BX, BY, V, M, NC, false>), grid, dim3(BX * BY), 0, s, a);\
+        return hipGetLastError();                                                                    \
     }
     TLB_L3(32, 8, 0, false)
     TLB_L3(64, 4, 0, false)

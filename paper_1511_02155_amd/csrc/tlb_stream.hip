@@ -42,8 +42,9 @@ __global__ __launch_bounds__(W) void k_stream2d(StepArgs<T> A)
     }
 }
 
-// D3Q19: a BX x BY tile of columns over a chunk of z planes, as in k_step3d, without the ring.
-template <typename T, int BX, int BY, int NC>
+// D3Q19: a BX x BY tile of columns over a chunk of z planes, as in k_step3d, without the ring, with the
+// store policy k_step3d uses for the same state.
+template <typename T, int BX, int BY, int NC, bool NT>
 __global__ __launch_bounds__(BX* BY) void k_stream3d(StepArgs<T> A)
 {
     constexpr int J = 19 * NC;
@@ -77,7 +78,8 @@ __global__ __launch_bounds__(BX* BY) void k_stream3d(StepArgs<T> A)
         for (int i = 0; i < 19; ++i)
 #pragma unroll
             for (int s = 0; s < NC; ++s)
-                bstore<T>(p[19 * s + i], rd, col[1][1], (uint32_t)((19 * s + i) * kBlock3d) * (uint32_t)sizeof(T));
+                bstore<T, NT ? kStoreStream : 0>(p[19 * s + i], rd, col[1][1],
+                                                 (uint32_t)((19 * s + i) * kBlock3d) * (uint32_t)sizeof(T));
     }
 }
 
@@ -105,7 +107,10 @@ hipError_t launch_stream_only(const StepArgs<T>& a, int lattice, int width, int 
     }
 #define TLB_S3(BX, BY, NC)                                                                         \
     if (width == BX && height == BY && nc == NC) {                                                 \
-        hipLaunchKernelGGL((k_stream3d<T, BX, BY, NC>), grid, dim3(BX * BY), 0, s, a);             \
+        if (stream_stores3d<T, NC>(a))                                                             \
+            hipLaunchKernelGGL((k_stream3d<T, BX, BY, NC, true>), grid, dim3(BX * BY), 0, s, a);   \
+        else                                                                                       \
+            hipLaunchKernelGGL((k_stream3d<T, BX, BY, NC, false>), grid, dim3(BX * BY), 0, s, a);  \
         return hipGetLastError();                                                                  \
     }
     TLB_S3(32, 8, 3) TLB_S3(64, 4, 3)
