@@ -7,8 +7,8 @@ nodes, written with 17 significant digits.
 
     python tests/golden/make_golden.py [spinodal2d] [spinodal3d] [batched] [adjoint]
 
-Run times on 8 shared cores: spinodal2d ~50 min, spinodal3d ~6.5 h, batched and
-adjoint ~1 min each.
+Run times on 8 shared cores: spinodal2d ~50 min, spinodal3d ~6.5 h, batched ~30 min
+(each domain also with FP32-storage rounding, one step at a time), adjoint ~1 min.
 """
 from __future__ import annotations
 
@@ -21,6 +21,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(os.path.dirname(HERE))
 sys.path.insert(0, ROOT)
+sys.path.insert(0, os.path.dirname(HERE))  # tests/: the FP32-storage model of the oracle
 
 import oracle  # noqa: E402
 from paper_1511_02155_amd import inputs  # noqa: E402
@@ -83,14 +84,28 @@ def batched_picks(doms):
 
 
 def batched():
+    """Each picked domain twice: the FP64 oracle, and the FP64 oracle whose stored state is rounded as FP32
+    storage rounds it after every step (the state an FP32-storage run holds, up to its own arithmetic).  The
+    second file also records the largest difference between the two over all nodes (the storage floor)."""
+    from storage32 import run_fp32_storage
+
     doms = inputs.batched_walls()
     for i in batched_picks(doms):
         d = doms[i]
+        head = [f"domain {i} of the 512-domain walled D2Q9 batch (seed 4): {d['nx']}x{d['ny']}, 5000 steps",
+                f"kappa = {tuple(float(k) for k in d['kappa'])}, h = {tuple(float(v) for v in d['h'][0][:, 0])} "
+                "on both walls, tau = 1, M = 0.1, alpha = 1"]
+        nodes = sample_nodes(d["nx"] * d["ny"], 105 + i, 256)
         p, F = run(d, d["C"], d["h"], d["steps"])
-        write(f"batched_domain{i:03d}_5000.txt",
-              [f"domain {i} of the 512-domain walled D2Q9 batch (seed 4): {d['nx']}x{d['ny']}, 5000 steps",
-               f"kappa = {d['kappa']}, h = {tuple(d['h'][0][:, 0])} on both walls, tau = 1, M = 0.1, alpha = 1"],
-              F, sample_nodes(p.N, 105 + i, 256))
+        write(f"batched_domain{i:03d}_5000.txt", head, F, nodes)
+        pop = oracle.init_equilibrium(p, d["C"], None, d["h"])
+        run_fp32_storage(oracle, p, pop, d["steps"], d["h"])
+        G = oracle.fields(p, pop, d["h"])
+        floor = {f"floor_{f}": float(np.abs(G[f] - F[f]).max()) for f in ("C1", "C2", "C3")}
+        write(f"batched_domain{i:03d}_5000_storage32.txt",
+              head + ["state rounded to FP32 after every step (populations relative to w_i, 0, 1/3 for f, g, k_0)",
+                      "scalar floor_Cm = max over all nodes of |C_m(rounded run) - C_m(FP64 run)|"],
+              G, nodes, extra=floor)
 
 
 def adjoint():

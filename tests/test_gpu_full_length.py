@@ -110,10 +110,20 @@ def test_spinodal_256cube_full_2000_steps_fp32(tlb):
         assert C[m].sum() == pytest.approx(sums[f], rel=1e-6)
 
 
+# FP32 populations against the oracle run that rounds its state to FP32 after every step, as FP32
+# storage does: what is left is the kernel's own FP64 arithmetic (rounding order), far below the floor.
+BATCH_VS_STORAGE32 = 1e-6
+
+
 def test_batched_512_domains_full_5000_steps(tlb):
+    """The 512-domain batch (h_m ~ U[-0.01, 0.01] unclipped), FP32 storage, 5000 steps, on four
+    domains: against the FP64 oracle at 1e-5 wherever FP32 storage itself allows it, and against the
+    oracle with FP32 storage rounding (the floor model) at 1e-6 everywhere.  The stored floor is the
+    largest difference between the two oracle runs over all nodes; on three of the four domains it
+    exceeds 1e-5 (up to 2.1e-5, domain 359), so there the FP64 bar is the floor plus the 1e-6."""
     doms = inputs.batched_walls()
-    picks = sorted(int(f[len("batched_domain"):len("batched_domain") + 3]) for f in os.listdir(GOLDEN)
-                   if f.startswith("batched_domain"))
+    picks = sorted({int(f[len("batched_domain"):len("batched_domain") + 3]) for f in os.listdir(GOLDEN)
+                    if f.startswith("batched_domain")})
     if not picks:
         pytest.skip("stored oracle values of the batch not generated")
     b = tlb.Batch([tlb.make_params(prec=tlb.TLB_F32, **{k: d[k] for k in KEYS}) for d in doms])
@@ -124,11 +134,22 @@ def test_batched_512_domains_full_5000_steps(tlb):
         b.init_equilibrium(i, d["C"])
     _note("batch 512 domains f32 5000 steps")
     b.step(5000)
+    failures = []
     for i in picks:
         nodes, ref, _, _ = load_golden(f"batched_domain{i:03d}_5000.txt")
-        C = np.stack([b.field(i, f) for f in ("C1", "C2", "C3")])
-        _check(C[:, nodes], ref, "f32", f"domain {i}", f32_bar=3e-5)
+        nodes32, ref32, _, sc = load_golden(f"batched_domain{i:03d}_5000_storage32.txt")
+        assert np.array_equal(nodes, nodes32)
+        C = np.stack([b.field(i, f) for f in ("C1", "C2", "C3")])[:, nodes]
         assert b.diagnostics(i)["nonfinite"] == 0
+        e64 = np.abs(C - ref).max(axis=1)
+        e32 = np.abs(C - ref32).max(axis=1)
+        floor = np.array([sc[f"floor_C{m + 1}"] for m in range(3)])
+        bar64 = np.maximum(1e-5, floor + BATCH_VS_STORAGE32)
+        print(f"domain {i:3d}: |GPU - FP64 oracle| {e64}, |GPU - FP32-storage oracle| {e32}, "
+              f"storage floor {floor}, FP64 bar {bar64}", flush=True)
+        if (e32 > BATCH_VS_STORAGE32).any() or (e64 > bar64).any():
+            failures.append((i, e64, e32, bar64))
+    assert not failures, failures
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
