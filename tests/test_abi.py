@@ -16,6 +16,11 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "tlb.h")
 
 
+def _has_gpu():
+    """A valid create would reach the device; without one it fails there (not at validation)."""
+    return os.path.exists("/dev/kfd")
+
+
 def _declared():
     txt = open(HEADER).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
@@ -78,11 +83,26 @@ def test_create_rejects_invalid_parameters(bad):
 
 
 def test_create_rejects_lattices_beyond_32bit_offsets():
+    """Every buffer descriptor covers at most 4 GiB - 256 B: one population array on D2Q9, one z plane of
+    all populations on D3Q19.  Shapes beyond that are rejected before any device call; shapes within it
+    pass validation (on a machine without a GPU the call then fails at the device, not with EINVAL)."""
     from paper_1511_02155_amd import tlb
 
-    p = tlb.make_params(tlb.TLB_D3Q19, 1024, 1024, 256, prec=tlb.TLB_F32)  # 19 * 2^28 > 2^32
-    h = ctypes.c_void_p()
-    assert tlb.tlb_create(ctypes.byref(p), None, ctypes.byref(h)) == tlb.TLB_EINVAL
+    def rc(*a, **k):
+        p = tlb.make_params(*a, **k)
+        h = ctypes.c_void_p()
+        return tlb.tlb_create(ctypes.byref(p), None, ctypes.byref(h))
+
+    # one D2Q9 FP64 array of 32768 x 16385 nodes is 4 GiB + 256 KiB; 23170^2 is the largest square
+    assert rc(tlb.TLB_D2Q9, 32768, 16385, prec=tlb.TLB_F64) == tlb.TLB_EINVAL
+    assert rc(tlb.TLB_D2Q9, 32768, 32768, prec=tlb.TLB_F32) == tlb.TLB_EINVAL
+    # one D3Q19 FP32 plane of 8192 x 4096 nodes holds 57 x 2^25 values = 7.1 GiB
+    assert rc(tlb.TLB_D3Q19, 8192, 4096, 3, prec=tlb.TLB_F32) == tlb.TLB_EINVAL
+    assert rc(tlb.TLB_D3Q19, 4096, 4096, 3, prec=tlb.TLB_F64) == tlb.TLB_EINVAL
+    if not _has_gpu():
+        # beyond the former whole-state limit of 4 GiB, within the per-array / per-plane one
+        assert rc(tlb.TLB_D2Q9, 6144, 6144, prec=tlb.TLB_F64) != tlb.TLB_EINVAL
+        assert rc(tlb.TLB_D3Q19, 448, 448, 448, prec=tlb.TLB_F32) != tlb.TLB_EINVAL
 
 
 def test_null_handles_are_rejected():
@@ -95,7 +115,7 @@ def test_null_handles_are_rejected():
 
 
 def test_create_rejects_invalid_component_counts():
-    """ncomp in 3 .. TLB_MAX_COMP (0 = 3), more than three on D2Q9 only, every kappa_m > 0."""
+    """ncomp in 3 .. TLB_MAX_COMP (0 = 3) on either lattice, every kappa_m > 0."""
     from paper_1511_02155_amd import tlb
 
     def rc(p):
@@ -104,13 +124,15 @@ def test_create_rejects_invalid_component_counts():
         assert r != tlb.TLB_OK or h.value  # a successful create would need a GPU; only errors are expected here
         return r
 
-    p = tlb.make_params(lattice=tlb.TLB_D3Q19, nx=8, ny=8, nz=8, kappa=(0.01,) * 4)
-    assert rc(p) == tlb.TLB_EINVAL
-    for n, bad in ((6, None), (2, None), (4, 0.0), (5, float("nan"))):
-        p = tlb.make_params(lattice=tlb.TLB_D2Q9, nx=8, ny=8, kappa=(0.01,) * 5)
-        p.ncomp = n
-        if bad is not None:
-            p.kappa_hi[n - 4] = bad
-        assert rc(p) == tlb.TLB_EINVAL, (n, bad)
+    for lat, nz in ((tlb.TLB_D2Q9, 1), (tlb.TLB_D3Q19, 8)):
+        for n, bad in ((6, None), (2, None), (4, 0.0), (5, float("nan"))):
+            p = tlb.make_params(lattice=lat, nx=8, ny=8, nz=nz, kappa=(0.01,) * 5)
+            p.ncomp = n
+            if bad is not None:
+                p.kappa_hi[n - 4] = bad
+            assert rc(p) == tlb.TLB_EINVAL, (lat, n, bad)
+        if not _has_gpu():
+            p = tlb.make_params(lattice=lat, nx=8, ny=8, nz=nz, kappa=(0.01,) * 4)
+            assert rc(p) != tlb.TLB_EINVAL
     with pytest.raises(ValueError):
         tlb.make_params(lattice=tlb.TLB_D2Q9, nx=8, ny=8, kappa=(0.01,) * 6)
