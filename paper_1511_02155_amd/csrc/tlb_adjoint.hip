@@ -211,8 +211,23 @@ __global__ __launch_bounds__(W * K) void k_adj2d(AdjArgs<T> A)
     };
     // pull of row a_: direction i from r - e_i, or opp(i) at r where r - e_i lies beyond a wall
     auto load_pull = [&](int a_, T* pu) {
-        const int row = walls ? a_ : modi(a_, ny);
+        const int row = (walls || (a_ >= 0 && a_ < ny)) ? a_ : modi(a_, ny);
         const uint32_t ym = row == 0 ? ny - 1 : row - 1, yp = row == ny - 1 ? 0 : row + 1;
+        if (!walls || (row > 0 && row < ny - 1)) {
+            // no wall next to the row: every direction pulls from r - e_i
+            // source row offset by 1 - e_y: r - e_i lies in row ym for e_y = 1, row for 0, yp for -1
+            const uint32_t ro[3] = {ym * nxu * ES, (uint32_t)row * nxu * ES, yp * nxu * ES};
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                const int ex = L9::ex[i], ey = L9::ey[i];
+                const uint32_t so = (uint32_t)i * NB + ro[1 - ey];
+                const uint32_t v = ex == 0 ? vx0 : (ex == 1 ? vxm : vxp);
+                pu[i] = bload<T>(ru, v, so);
+                pu[9 + i] = bload<T>(ru, v, so + 9u * NB);
+                pu[18 + i] = bload<T>(ru, v, so + 18u * NB);
+            }
+            return;
+        }
         const bool blo = walls && row == 0, bhi = walls && row == ny - 1;
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
@@ -228,7 +243,7 @@ __global__ __launch_bounds__(W * K) void k_adj2d(AdjArgs<T> A)
     };
     // lambda_{t+1} of row b_
     auto load_lam = [&](int b_, T* la) {
-        const uint32_t so = (uint32_t)(walls ? b_ : modi(b_, ny)) * nxu * ES;
+        const uint32_t so = (uint32_t)((walls || (b_ >= 0 && b_ < ny)) ? b_ : modi(b_, ny)) * nxu * ES;
 #pragma unroll
         for (int q = 0; q < 27; ++q) la[q] = bload<T>(rl1, vx0, so + (uint32_t)q * NB);
     };
@@ -254,8 +269,23 @@ __global__ __launch_bounds__(W * K) void k_adj2d(AdjArgs<T> A)
         T pu[27], la[27], lg[27];
         // lambda_{t+1} around row d (d is a fluid row): direction j from r + e_j, or opp(j) at r where
         // r + e_j lies beyond a wall
+        const bool d_in = !walls || (d > 0 && d < ny - 1);  // no wall next to row d
         auto gather = [&]() {
             const uint32_t dm = d == 0 ? ny - 1 : d - 1, dp = d == ny - 1 ? 0 : d + 1;
+            if (d_in) {
+                // source row offset by 1 + e_y: r + e_j lies in row dm for e_y = -1, d for 0, dp for 1
+                const uint32_t ro[3] = {dm * nxu * ES, (uint32_t)d * nxu * ES, dp * nxu * ES};
+#pragma unroll
+                for (int j = 0; j < 9; ++j) {
+                    const int ex = L9::ex[j], ey = L9::ey[j];
+                    const uint32_t so = (uint32_t)j * NB + ro[1 + ey];
+                    const uint32_t v = ex == 0 ? vx0 : (ex == 1 ? vxp : vxm);
+                    lg[j] = bload<T>(rl1, v, so);
+                    lg[9 + j] = bload<T>(rl1, v, so + 9u * NB);
+                    lg[18 + j] = bload<T>(rl1, v, so + 18u * NB);
+                }
+                return;
+            }
             const bool blo = walls && d == 0, bhi = walls && d == ny - 1;
 #pragma unroll
             for (int j = 0; j < 9; ++j) {
@@ -312,33 +342,8 @@ __global__ __launch_bounds__(W * K) void k_adj2d(AdjArgs<T> A)
             }
             const bool glo = walls && b == 0, ghi = walls && b == ny - 1;
             C dc[3], gx[3], gy[3], lC[3];
-#pragma unroll
-            for (int m = 0; m < 3; ++m) {
-                // 3x3 neighbourhood v[dy+1][dx+1]
-                C v[3][3];
-                v[1][0] = sC[s0][m][l - 1];
-                v[1][1] = sC[s0][m][l];
-                v[1][2] = sC[s0][m][l + 1];
-                if (glo) {
-                    const T* wl = A.wet + m * nx;
-                    v[0][0] = v[1][0] + C(wl[xm]);
-                    v[0][1] = v[1][1] + C(wl[x]);
-                    v[0][2] = v[1][2] + C(wl[xp]);
-                } else {
-                    v[0][0] = sC[sm][m][l - 1];
-                    v[0][1] = sC[sm][m][l];
-                    v[0][2] = sC[sm][m][l + 1];
-                }
-                if (ghi) {
-                    const T* wh = A.wet + (3 + m) * nx;
-                    v[2][0] = v[1][0] + C(wh[xm]);
-                    v[2][1] = v[1][1] + C(wh[x]);
-                    v[2][2] = v[1][2] + C(wh[xp]);
-                } else {
-                    v[2][0] = sC[sp][m][l - 1];
-                    v[2][1] = sC[sp][m][l];
-                    v[2][2] = sC[sp][m][l + 1];
-                }
+            // gradients and Laplacian of C_m from its 3x3 neighbourhood v[dy+1][dx+1]
+            auto stencil = [&](int m, const C (&v)[3][3]) {
                 dc[m] = v[1][1];
                 C sx = 0, sy = 0, lp = 0;
 #pragma unroll
@@ -352,6 +357,49 @@ __global__ __launch_bounds__(W * K) void k_adj2d(AdjArgs<T> A)
                 gx[m] = C(3) * sx;
                 gy[m] = C(3) * sy;
                 lC[m] = C(6) * lp;
+            };
+            if (!glo && !ghi) {
+#pragma unroll
+                for (int m = 0; m < 3; ++m) {
+                    C v[3][3];
+#pragma unroll
+                    for (int dy = 0; dy < 3; ++dy) {
+                        const int sr = dy == 0 ? sm : (dy == 1 ? s0 : sp);
+                        v[dy][0] = sC[sr][m][l - 1];
+                        v[dy][1] = sC[sr][m][l];
+                        v[dy][2] = sC[sr][m][l + 1];
+                    }
+                    stencil(m, v);
+                }
+            } else {
+#pragma unroll
+                for (int m = 0; m < 3; ++m) {
+                    C v[3][3];
+                    v[1][0] = sC[s0][m][l - 1];
+                    v[1][1] = sC[s0][m][l];
+                    v[1][2] = sC[s0][m][l + 1];
+                    if (glo) {  // ghost row below a lower wall
+                        const T* wl = A.wet + m * nx;
+                        v[0][0] = v[1][0] + C(wl[xm]);
+                        v[0][1] = v[1][1] + C(wl[x]);
+                        v[0][2] = v[1][2] + C(wl[xp]);
+                    } else {
+                        v[0][0] = sC[sm][m][l - 1];
+                        v[0][1] = sC[sm][m][l];
+                        v[0][2] = sC[sm][m][l + 1];
+                    }
+                    if (ghi) {  // ghost row above an upper wall
+                        const T* wh = A.wet + (3 + m) * nx;
+                        v[2][0] = v[1][0] + C(wh[xm]);
+                        v[2][1] = v[1][1] + C(wh[x]);
+                        v[2][2] = v[1][2] + C(wh[xp]);
+                    } else {
+                        v[2][0] = sC[sp][m][l - 1];
+                        v[2][1] = sC[sp][m][l];
+                        v[2][2] = sC[sp][m][l + 1];
+                    }
+                    stencil(m, v);
+                }
             }
             C bG[3][2], bL[3], kb[3];
             adj_local<C, T>(P, mom_prev, dc, gx, gy, lC, la, lb_new, bG, bL, kb);
@@ -388,10 +436,9 @@ __global__ __launch_bounds__(W * K) void k_adj2d(AdjArgs<T> A)
             C Cb[3];
 #pragma unroll
             for (int m = 0; m < 3; ++m) Cb[m] = lb_prev[5 + m] - C(6) * (C(1) - w0) * sA[q0][6 + m][l];
-#pragma unroll
-            for (int i = 1; i < 9; ++i) {
+            // neighbour r - e_i of row c, skipped where it lies beyond a wall (a ghost, transposed below)
+            auto tstencil = [&](int i) {
                 const int ey = L9::ey[i], ex = L9::ex[i];
-                if (walls && ((ey == 1 && c == 0) || (ey == -1 && c == ny - 1))) continue;
                 const int sl = ey == 0 ? q0 : (ey == 1 ? qm : qp);  // row c - ey
                 const int ln = l - ex;
                 const C w = C(weight<L9>(i));
@@ -399,6 +446,17 @@ __global__ __launch_bounds__(W * K) void k_adj2d(AdjArgs<T> A)
                 for (int m = 0; m < 3; ++m)
                     Cb[m] += C(3) * w * (C(ex) * sA[sl][2 * m][ln] + C(ey) * sA[sl][2 * m + 1][ln]) +
                              C(6) * w * sA[sl][6 + m][ln];
+            };
+            if (!walls || (c > 0 && c < ny - 1)) {
+#pragma unroll
+                for (int i = 1; i < 9; ++i) tstencil(i);
+            } else {
+#pragma unroll
+                for (int i = 1; i < 9; ++i) {
+                    const int ey = L9::ey[i];
+                    if ((ey == 1 && c == 0) || (ey == -1 && c == ny - 1)) continue;
+                    tstencil(i);
+                }
             }
             if (walls && (c == 0 || c == ny - 1)) {
                 const int wall = (c == 0) ? 0 : 1;
@@ -439,6 +497,19 @@ __global__ __launch_bounds__(W * K) void k_adj2d(AdjArgs<T> A)
             if (HOIST != 1) gather();  // all 27 loads before the first store
             const int p0 = slot(d), pm = slot(d - 1), pp = slot(c);
             const uint32_t so = (uint32_t)d * nxu * ES;
+            if (d_in) {
+#pragma unroll
+                for (int j = 0; j < 9; ++j) {
+                    const int ln = l + L9::ex[j];
+                    const int sl = L9::ey[j] == 0 ? p0 : (L9::ey[j] == 1 ? pp : pm);
+                    const C Sf = sS[sl][0][ln], Jx = sS[sl][1][ln], Jy = sS[sl][2][ln];
+                    const C Sg = sS[sl][3][ln], Sk = sS[sl][4][ln];
+                    bstore<T>(T((C(1) - P.omega[0]) * C(lg[j]) + Sf + (C(L9::ex[j]) * Jx + C(L9::ey[j]) * Jy)), rl0,
+                              vx0, so + (uint32_t)j * NB);
+                    bstore<T>(T((C(1) - P.omega[1]) * C(lg[9 + j]) + Sg), rl0, vx0, so + (uint32_t)(9 + j) * NB);
+                    bstore<T>(T((C(1) - P.omega[2]) * C(lg[18 + j]) + Sk), rl0, vx0, so + (uint32_t)(18 + j) * NB);
+                }
+            } else {
 #pragma unroll
             for (int j = 0; j < 9; ++j) {
                 const int yy = d + L9::ey[j];
@@ -452,6 +523,7 @@ __global__ __launch_bounds__(W * K) void k_adj2d(AdjArgs<T> A)
                           vx0, so + (uint32_t)j * NB);
                 bstore<T>(T((C(1) - P.omega[1]) * C(lg[9 + j]) + Sg), rl0, vx0, so + (uint32_t)(9 + j) * NB);
                 bstore<T>(T((C(1) - P.omega[2]) * C(lg[18 + j]) + Sk), rl0, vx0, so + (uint32_t)(18 + j) * NB);
+            }
             }
         }
         if constexpr (K == 1) {
