@@ -347,11 +347,12 @@ tlb_status tlb_adjoint_step_dev(tlb_sim* sim, const void* state_dev, const void*
  *   tight serving loops, harnesses that forbid hipMalloc).  Same arguments,
  *   kernels, launch shape and results (bit for bit) as tlb_adjoint_step_dev,
  *   but the call allocates nothing: its scratch (the per-work-item dL/dkappa
- *   partials, their reduction partials and, when dh_dev is NULL, a sink for
- *   dL/dh) lives in a static device array of TLB_NOALLOC_SCRATCH_BYTES per GPU,
- *   which each GPU the library runs on holds until the process ends.  A
- *   simulation needs tlb_adjoint_step_noalloc_scratch(sim) bytes of it
- *   (3 * work items + 768 + 6 * nx * nz doubles); larger ones return
+ *   partials, which the call writes before it reduces them, and, when dh_dev is
+ *   NULL, a sink for dL/dh, which it clears) lives in a static device array of
+ *   TLB_NOALLOC_SCRATCH_BYTES per GPU, which each GPU the library runs on holds
+ *   until the process ends.  A simulation needs
+ *   tlb_adjoint_step_noalloc_scratch(sim) bytes of it
+ *   (3 * work items + 6 * nx * nz doubles); larger ones return
  *   TLB_EINVAL.  Every call on one GPU uses that GPU's single array: calls that
  *   overlap on one GPU (other streams, other host threads) race and must be
  *   serialised by the caller.  The first call on a device looks up the array's

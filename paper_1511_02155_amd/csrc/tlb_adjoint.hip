@@ -33,8 +33,9 @@
 // halo rows and columns are re-read from L2.
 //
 // The kappa gradient is summed per work item in a fixed order (lanes, then a
-// tree) into its own slot kpart[m][item], which the caller reduces in a
-// fixed order, so results do not depend on scheduling.
+// tree) into its own slot kpart[m][item] (added to it over a reverse pass, or
+// written by a single step), which the caller reduces in a fixed order, so
+// results do not depend on scheduling.
 #include <stdint.h>
 
 #include "../../include/tlb.h"
@@ -544,7 +545,10 @@ __global__ __launch_bounds__(W * K) void k_adj2d(AdjArgs<T> A)
         }
         __syncthreads();
     }
-    if (t < 3) A.kpart[t * A.nitems + item] += sred[t][0];
+    if (t < 3) {
+        double* kp = A.kpart + t * A.nitems + item;
+        *kp = A.kassign ? sred[t][0] : *kp + sred[t][0];
+    }
 }
 
 // Inverse of the pull: position in u of the value that the pull of node (x, y) reads for direction i.
@@ -580,37 +584,22 @@ __global__ void k_fill0(double* p, int64_t n)
     if (i < n) p[i] = 0.0;
 }
 
-// Fixed-order reduction of the kappa field [3][N] into out[3] (+=) in two passes: kRedBlocks blocks per
-// component sum fixed contiguous ranges into part[3][kRedBlocks], then one block per component sums those.
-__device__ __forceinline__ double block_sum256(double v, double* red)
+// Fixed-order reduction of the per-item kappa partials [3][n] into out[3] (+=): block m sums part[m][.]
+// with each of its 256 threads taking a fixed strided subset in order, then a fixed tree.
+__global__ __launch_bounds__(256) void k_reduce_items(const double* __restrict__ part, int64_t n,
+                                                      double* __restrict__ out)
 {
-    red[threadIdx.x] = v;
+    __shared__ double red[256];
+    const int m = blockIdx.x;
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) acc += part[m * n + i];
+    red[threadIdx.x] = acc;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
         if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
-    return red[0];
-}
-
-__global__ __launch_bounds__(256) void k_reduce3a(const double* __restrict__ f, int64_t N, double* __restrict__ part)
-{
-    __shared__ double red[256];
-    const int m = blockIdx.x / kRedBlocks, j = blockIdx.x % kRedBlocks;
-    const int64_t per = (N + kRedBlocks - 1) / kRedBlocks;
-    const int64_t lo = j * per, hi = lo + per < N ? lo + per : N;
-    double acc = 0.0;
-    for (int64_t i = lo + threadIdx.x; i < hi; i += 256) acc += f[m * N + i];
-    const double t = block_sum256(acc, red);
-    if (threadIdx.x == 0) part[m * kRedBlocks + j] = t;
-}
-
-__global__ __launch_bounds__(256) void k_reduce3b(const double* __restrict__ part, double* __restrict__ out)
-{
-    __shared__ double red[256];
-    static_assert(kRedBlocks == 256, "one partial per lane");
-    const double t = block_sum256(part[blockIdx.x * kRedBlocks + threadIdx.x], red);
-    if (threadIdx.x == 0) out[blockIdx.x] += t;
+    if (threadIdx.x == 0) out[m] += red[0];
 }
 
 inline dim3 gridN(int64_t N) { return dim3((unsigned)((N + 255) / 256)); }
@@ -654,10 +643,9 @@ hipError_t launch_fill0(double* p, int64_t n, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_reduce3(const double* f, int64_t N, double* part, double* out, hipStream_t s)
+hipError_t launch_reduce_items(const double* part, int64_t n, double* out, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_reduce3a, dim3(3 * kRedBlocks), dim3(256), 0, s, f, N, part);
-    hipLaunchKernelGGL(k_reduce3b, dim3(3), dim3(256), 0, s, part, out);
+    hipLaunchKernelGGL(k_reduce_items, dim3(3), dim3(256), 0, s, part, n, out);
     return hipGetLastError();
 }
 

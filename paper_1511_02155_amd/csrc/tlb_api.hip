@@ -27,7 +27,7 @@ struct tlb_sim {
     double* hbuf;       // [2][nc][nx*nz] h_m as set (to rescale when kappa changes)
     // adjoint scratch (lazy)
     void* lam[2];
-    double* kpart;      // [3][items] kappa-gradient partials + [3][kRedBlocks] reduction scratch
+    double* kpart;      // [3][items] kappa-gradient partials
     int64_t kpart_cap;  // items the allocation holds
     tlb_launch adj_launch;
     int cus;            // compute units of the device
@@ -967,7 +967,7 @@ static tlb_status adj_alloc(tlb_sim* s, int64_t seg_states)
             s->kpart = nullptr;
             s->kpart_cap = 0;
         }
-        HIPCHK(hipMalloc((void**)&s->kpart, ((size_t)3 * items + 3 * kRedBlocks) * sizeof(double)));
+        HIPCHK(hipMalloc((void**)&s->kpart, (size_t)3 * items * sizeof(double)));
         s->kpart_cap = items;
     }
     if (!s->dhs) HIPCHK(hipMalloc((void**)&s->dhs, (size_t)6 * s->p.nx * s->p.nz * sizeof(double)));
@@ -984,8 +984,11 @@ static tlb_status adj_alloc(tlb_sim* s, int64_t seg_states)
     return TLB_OK;
 }
 
+// One reverse step.  kassign: write the kappa partials of this step (a single step, or the first of a
+// pass) instead of adding to them, so that they need no clearing.
 template <typename T>
-static tlb_status adj_step(tlb_sim* s, const void* u, const void* lam1, void* lam0, double* dh, double* kpart)
+static tlb_status adj_step(tlb_sim* s, const void* u, const void* lam1, void* lam0, double* dh, double* kpart,
+                           bool kassign)
 {
     AdjArgs<T> a;
     memset(&a, 0, sizeof(a));
@@ -995,6 +998,7 @@ static tlb_status adj_step(tlb_sim* s, const void* u, const void* lam1, void* la
     a.wet = (const T*)s->wet;
     a.dh = dh;
     a.kpart = kpart;
+    a.kassign = kassign ? 1 : 0;
     a.nx = s->p.nx;
     a.ny = s->p.ny;
     a.walls = s->p.walls_y;
@@ -1008,25 +1012,18 @@ static tlb_status adj_step(tlb_sim* s, const void* u, const void* lam1, void* la
     return TLB_OK;
 }
 
-static tlb_status adj_step_any(tlb_sim* s, const void* u, const void* lam1, void* lam0, double* dh,
+static tlb_status adj_step_any(tlb_sim* s, const void* u, const void* lam1, void* lam0, double* dh, bool kassign,
                                double* kpart = nullptr)
 {
     if (!kpart) kpart = s->kpart;
-    return s->p.prec == TLB_F32 ? adj_step<float>(s, u, lam1, lam0, dh, kpart)
-                                : adj_step<double>(s, u, lam1, lam0, dh, kpart);
+    return s->p.prec == TLB_F32 ? adj_step<float>(s, u, lam1, lam0, dh, kpart, kassign)
+                                : adj_step<double>(s, u, lam1, lam0, dh, kpart, kassign);
 }
 
-// Clear the kappa partials before a reverse pass / reduce them into dkappa (+=) after it.
-static tlb_status kpart_clear(tlb_sim* s)
-{
-    HIPCHK(launch_fill0(s->kpart, 3 * adj_nitems(s), s->stream));
-    return TLB_OK;
-}
-
+// Reduce the kappa partials into dkappa (+=) after a reverse step or pass.
 static tlb_status kpart_reduce(tlb_sim* s, double* dkappa)
 {
-    const int64_t items = adj_nitems(s);
-    if (dkappa) HIPCHK(launch_reduce3(s->kpart, items, s->kpart + 3 * items, dkappa, s->stream));
+    if (dkappa) HIPCHK(launch_reduce_items(s->kpart, adj_nitems(s), dkappa, s->stream));
     return TLB_OK;
 }
 
@@ -1053,8 +1050,7 @@ extern "C" tlb_status tlb_adjoint_step_dev(tlb_sim* s, const void* state, const 
     if (!s || !state || !lam_in || !lam_out || lam_in == lam_out) return TLB_EINVAL;
     if (s->p.lattice != TLB_D2Q9 || s->p.collision != TLB_BGK || s->nc != 3 || !adj_fits(s)) return TLB_EINVAL;
     tlb_status st = adj_alloc(s, 0);
-    if (!st) st = kpart_clear(s);
-    if (!st) st = adj_step_any(s, state, lam_in, lam_out, dh_target(s, dh));
+    if (!st) st = adj_step_any(s, state, lam_in, lam_out, dh_target(s, dh), true);
     if (!st) st = kpart_reduce(s, dkappa);
     return st;
 }
@@ -1064,8 +1060,7 @@ extern "C" tlb_status tlb_adjoint_step(tlb_sim* s, const void* state, void* lam,
     if (!s || !state || !lam) return TLB_EINVAL;
     if (s->p.lattice != TLB_D2Q9 || s->p.collision != TLB_BGK || s->nc != 3 || !adj_fits(s)) return TLB_EINVAL;
     tlb_status st = adj_alloc(s, 0);
-    if (!st) st = kpart_clear(s);
-    if (!st) st = adj_step_any(s, state, lam, s->lam[0], dh_target(s, dh));
+    if (!st) st = adj_step_any(s, state, lam, s->lam[0], dh_target(s, dh), true);
     if (!st) st = kpart_reduce(s, dkappa);
     if (st) return st;
     HIPCHK(hipMemcpyAsync(lam, s->lam[0], (size_t)tlb_state_bytes(s), hipMemcpyDeviceToDevice, s->stream));
@@ -1111,7 +1106,7 @@ static tlb_status scratch_of(int dev, double** out)
 extern "C" int64_t tlb_adjoint_step_noalloc_scratch(const tlb_sim* s)
 {
     if (!s) return 0;
-    return (3 * adj_nitems(s) + 3 * (int64_t)kRedBlocks + 6 * (int64_t)s->p.nx * s->p.nz) * (int64_t)sizeof(double);
+    return (3 * adj_nitems(s) + 6 * (int64_t)s->p.nx * s->p.nz) * (int64_t)sizeof(double);
 }
 
 extern "C" tlb_status tlb_adjoint_step_noalloc(tlb_sim* s, const void* state, const void* lam_in, void* lam_out,
@@ -1124,18 +1119,15 @@ extern "C" tlb_status tlb_adjoint_step_noalloc(tlb_sim* s, const void* state, co
     tlb_status st = scratch_of(s->dev, &base);
     if (st) return st;
     const int64_t items = adj_nitems(s);
-    double* kpart = base;                               // [3][items]
-    double* red = base + 3 * items;                     // [3][kRedBlocks]
-    double* sink = red + 3 * (int64_t)kRedBlocks;       // [2][3][nx*nz] when dh is NULL
-    // the partials start from zero; the scratch keeps whatever the last call on this GPU left
-    HIPCHK(launch_fill0(kpart, 3 * items, s->stream));
+    double* kpart = base;             // [3][items], written by the step (whatever the last call left)
+    double* sink = base + 3 * items;  // [2][3][nx*nz] when dh is NULL
     if (!dh) {
         HIPCHK(launch_fill0(sink, 6 * (int64_t)s->p.nx * s->p.nz, s->stream));
         dh = sink;
     }
-    st = adj_step_any(s, state, lam_in, lam_out, dh, kpart);
+    st = adj_step_any(s, state, lam_in, lam_out, dh, true, kpart);
     if (st) return st;
-    if (dkappa) HIPCHK(launch_reduce3(kpart, items, red, dkappa, s->stream));
+    if (dkappa) HIPCHK(launch_reduce_items(kpart, items, dkappa, s->stream));
     return TLB_OK;
 }
 
@@ -1183,11 +1175,10 @@ extern "C" tlb_status tlb_adjoint_backward(tlb_sim* s, int64_t nsteps, int64_t e
     tlb_status st = adj_alloc(s, every);
     if (st) return st;
     const size_t sb = (size_t)tlb_state_bytes(s);
-    st = kpart_clear(s);
-    if (st) return st;
     st = tlb_adjoint_seed_dev(s, dLdC, s->lam[0]);
     if (st) return st;
     int cur = 0;
+    bool first = true;  // the first reverse step writes the kappa partials, the others add to them
     const int64_t nseg = tlb_checkpoint_slots(nsteps, every);
     for (int64_t seg = nseg - 1; seg >= 0; --seg) {
         const int64_t t0 = seg * every;
@@ -1197,8 +1188,9 @@ extern "C" tlb_status tlb_adjoint_backward(tlb_sim* s, int64_t nsteps, int64_t e
         if (st) return st;
         for (int64_t t = t1 - 1; t >= t0; --t) {
             const void* u = (const char*)s->seg + sb * (size_t)(t - t0);
-            st = adj_step_any(s, u, s->lam[cur], s->lam[cur ^ 1], dh_target(s, dh));
+            st = adj_step_any(s, u, s->lam[cur], s->lam[cur ^ 1], dh_target(s, dh), first);
             if (st) return st;
+            first = false;
             cur ^= 1;
         }
     }

@@ -94,7 +94,8 @@ struct AdjArgs {
     T* __restrict__ lam0;        // lambda_t [27][N]
     const T* __restrict__ wet;   // [2][3][nx] h_m / (alpha^2 kappa_m), or nullptr
     double* __restrict__ dh;     // [2][3][nx], accumulated
-    double* __restrict__ kpart;  // [3][nitems], accumulated per work item
+    double* __restrict__ kpart;  // [3][nitems], per work item: accumulated, or written when kassign != 0
+    int kassign;                 // nonzero: write the item's kappa partials instead of adding them
     int nx, ny, walls;
     int64_t N;
     int chunk, nchunks, nstrips, nitems;  // strips of (width - 6) output columns
@@ -106,9 +107,8 @@ hipError_t launch_adjoint_sweep(const AdjArgs<T>& a, int width, int rows, int ho
 template <typename T>
 hipError_t launch_adjoint_seed(const AuxGeom& g, const T* dC, T* lam, hipStream_t s);
 hipError_t launch_fill0(double* p, int64_t n, hipStream_t s);
-// reduction of a [3][N] field into out[3] (+=); part holds 3 * kRedBlocks doubles of scratch
-constexpr int kRedBlocks = 256;
-hipError_t launch_reduce3(const double* f, int64_t N, double* part, double* out, hipStream_t s);
+// out[m] += sum of part[m][0 .. n) for m < 3, in a fixed order (one launch)
+hipError_t launch_reduce_items(const double* part, int64_t n, double* out, hipStream_t s);
 template <typename TIn, typename TOut>
 hipError_t launch_convert(const TIn* in, TOut* out, int64_t n, hipStream_t s);
 

@@ -94,8 +94,9 @@ struct PlaneFull {
 // pipelines the sweep: the loads of plane z+2 (own column and ring node) are
 // issued before plane z is collided and reduced after it, so that their
 // latency overlaps the collision, and the populations of plane z+1 wait in
-// registers for its collision.  All three hold one wavefront per SIMD; VAR 2
-// needs about 490 registers (FP32 storage) and is meant for FP32 storage.
+// registers for its collision.  With FP32 storage VAR 0 holds two wavefronts
+// per SIMD (about 190 registers), VAR 1 and VAR 2 one (about 260 and 380);
+// VAR 2 is built for FP32 storage of three components only.
 // Arithmetic type of the D3Q19 step: the storage type.
 template <typename T>
 __device__ __forceinline__ const Phys<T>& phys3d(const StepArgs<T>& A);

@@ -1,8 +1,9 @@
 """The reverse step that allocates nothing (tlb_adjoint_step_noalloc) against tlb_adjoint_step_dev.
 
 Both run the same kernels with the same launch shape, so lambda_t, dL/dh and dL/dkappa must agree bit for
-bit.  Two calls in a row on one GPU, the second on a smaller lattice, check that the shared scratch array
-is cleared where it must start from zero; a lattice whose scratch would exceed the array is refused.
+bit.  Two calls in a row on one GPU, the second on a smaller lattice, check that nothing the first call
+left in the shared scratch array reaches the second; a lattice whose scratch would exceed the array is
+refused.
 """
 from __future__ import annotations
 
