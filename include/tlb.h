@@ -178,6 +178,12 @@ int tlb_version(void);
  * enqueue all work on, or NULL to let the simulation create (and own) one.
  * The state is undefined until tlb_init_equilibrium or tlb_set_populations.
  * Wetting parameters start at zero (neutral walls).
+ * TLB_EINVAL for parameters outside the ranges documented with tlb_params, and
+ * for lattices beyond the 32-bit offsets of the buffer instructions: each
+ * descriptor covers at most 4 GiB - 256 bytes, which is one population array
+ * on D2Q9 (nx * ny * sizeof) and one z plane of all populations on D3Q19
+ * (ceil(nx * ny / 64) * 64 * 19 * N * sizeof).  TLB_ENOMEM when the two state
+ * buffers do not fit on the device.
  */
 tlb_status tlb_create(const tlb_params* params, void* stream, tlb_sim** out);
 tlb_status tlb_destroy(tlb_sim* sim);
