@@ -33,6 +33,7 @@ _COMMON = [_CSRC + "tlb_device.hpp", _CSRC + "tlb_internal.hpp", "paper_1511_021
 KERNEL_SOURCES = {
     "step2d": _COMMON + [_CSRC + "tlb_sweep2d.hpp", _CSRC + "tlb_step2d.hpp", _CSRC + "tlb_step2d.hip"],
     "step3d": _COMMON + [_CSRC + "tlb_step3d.hpp", _CSRC + "tlb_step3d.hip"],
+    "step3d_nc": _COMMON + [_CSRC + "tlb_step3d.hpp", _CSRC + "tlb_step3d_nc.hip"],
     "batch2d": _COMMON + [_CSRC + "tlb_sweep2d.hpp", _CSRC + "tlb_batch.hip"],
     "adjoint": _COMMON + [_CSRC + "tlb_adjoint.hip"],
 }
@@ -423,6 +424,10 @@ def main():
         print(f"[bench] d2q9 1024^2 f64 four components: {sn} steps", file=sys.stderr, flush=True)
         add("d2q9_1024x1024_spinodal_n4_f64", run_plain(tlb, torch, inputs.spinodal_2d_nc(1024, sn, 4), tlb.TLB_F64,
                                                         sn, 10))
+        s3n = args.steps if sel else max(20, min(200, args.steps // 10))
+        print(f"[bench] d3q19 256^3 f32 four components: {s3n} steps", file=sys.stderr, flush=True)
+        add("d3q19_256cube_spinodal_n4_f32", run_plain(tlb, torch, inputs.spinodal_3d_nc(256, s3n, 4), tlb.TLB_F32,
+                                                       s3n, 5))
     for name, prec in (("f64", tlb.TLB_F64), ("f32", tlb.TLB_F32)):
         if sel == "adjoint" + name[1:] or every:
             sa = args.steps if sel else max(100, min(2000, s2 // 5))
@@ -492,6 +497,8 @@ WORKLOAD_CONFIG = {
     "d3q19_256cube_spinodal_f32_mrt": dict(lattice="D3Q19", nx=256, ny=256, nz=256, boundary="periodic",
                                            kappa=[0.01, 0.01, 0.01], alpha=1.0, tau=0.8, mobility=0.05,
                                            collision="MRT", tau_bulk=0.8, tau_ghost=1.2),
+    "d3q19_256cube_spinodal_n4_f32": dict(lattice="D3Q19", nx=256, ny=256, nz=256, boundary="periodic", components=4,
+                                          kappa=[0.01, 0.015, 0.02, 0.025], alpha=1.0, tau=0.8, mobility=0.05),
     "d2q9_1024x1024_spinodal_n4_f64": dict(lattice="D2Q9", nx=1024, ny=1024, boundary="periodic", components=4,
                                            kappa=[0.01, 0.015, 0.02, 0.025], alpha=1.0, tau=1.0, mobility=0.1),
     "batched_512_domains_f32": dict(lattice="D2Q9", domains=512, side=[32, 256], boundary="walls_y"),

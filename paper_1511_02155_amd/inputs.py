@@ -181,6 +181,15 @@ def spinodal_3d(n=256, steps=2000, seed=3):
     return w
 
 
+def spinodal_3d_nc(n=256, steps=2000, nc=4, seed=8):
+    """D3Q19 n^3 periodic spinodal of nc components (Sec. II.E); kappa_m = 0.01 + 0.005 m, tau=0.8, M=0.05."""
+    w = _params(1, n, n, n, 0, tuple(0.01 + 0.005 * m for m in range(nc)), 1.0, 0.8, 0.05, steps)
+    w["name"] = f"d3q19_{n}^3_spinodal_n{nc}"
+    w["C"] = lambda: spinodal_nc(n, n * n, nc, seed=seed)
+    w["h"] = None
+    return w
+
+
 # Domains of the 512-domain batch (seed 4) whose wetting parameters are clamped to
 # |h_m| <= alpha kappa_m / 4.  The stated range h_m ~ U[-0.01, 0.01] is kept for every other
 # domain; a domain would be listed only if the FP64 oracle, run for 5000 steps with the stated
