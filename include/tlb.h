@@ -231,6 +231,20 @@ tlb_status tlb_step(tlb_sim* sim, int64_t nsteps);
  */
 tlb_status tlb_set_check_every(tlb_sim* sim, int64_t every);
 
+/*
+ * Replay the steps of tlb_step from a captured hipGraph in chains of
+ * steps_per_graph launches (an even number; 0, the default, launches every step
+ * directly).  For small lattices, where a step takes about as long as its
+ * launch, this removes most of the launch overhead.  The chain is captured on
+ * the simulation's stream at the first tlb_step that needs it and replayed
+ * after that; tlb_set_launch and tlb_set_kappa drop it (the launches hold the
+ * shape and the coefficients), wetting parameters and states are read from
+ * device memory and need no new capture.  Results are bit for bit those of
+ * direct launches.  The capture must not overlap other work enqueued on the
+ * same stream from another thread.  TLB_EINVAL for an odd or negative count.
+ */
+tlb_status tlb_set_graph(tlb_sim* sim, int64_t steps_per_graph);
+
 /* Macroscopic field `which` (TLB_FIELD_*) of the state s_t into host out[N]
  * (TLB_EINVAL for an unknown selector, TLB_ESTATE before initialisation).
  * rho, phi, psi and rho v are the moments of eq. lbconstraint (Sec. IV),

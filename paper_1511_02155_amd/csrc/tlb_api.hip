@@ -5,6 +5,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <new>
 
@@ -47,7 +48,19 @@ struct tlb_sim {
     double* hhost;            // [2][nc][nx*nz] h_m as last set from the host (range report)
     int64_t wet_outside[2];   // per wall: values with |4 h_m / (alpha kappa_m)| > 1, -1 if set from device memory
     bool wet_warned;
+    int64_t graph_steps;      // steps per captured chain (even), 0: every step launched directly
+    hipGraph_t graph;         // the chain from buffer 0, captured on first use
+    hipGraphExec_t graph_exec;
 };
+
+// Drop the captured chain of steps (its launches hold the parameters and launch shape of capture time).
+static void drop_graph(tlb_sim* s)
+{
+    if (s->graph_exec) (void)hipGraphExecDestroy(s->graph_exec);
+    if (s->graph) (void)hipGraphDestroy(s->graph);
+    s->graph_exec = nullptr;
+    s->graph = nullptr;
+}
 
 static thread_local int g_last_hip = 0;
 
@@ -194,13 +207,17 @@ static void default_launch(tlb_sim* s)
         // (about 2000 wavefronts in flight), no prefetch of the next row (its
         // buffer would cost occupancy; the arithmetic is FP64 in both
         // storage precisions).
+        // Smaller lattices get shorter chunks rather than fewer workgroups: an item's time is its rows
+        // times a row's latency, so a lattice too small to fill the chip runs fastest with one or two
+        // rows per item (64^2 FP64: 7.1 us per step at one row against 16.5 at four; 200^2: 9.1
+        // against 18.4; 384^2: 19.4 at two against 21.0 at four).
         int w = p.nx >= 256 ? 256 : (p.nx >= 128 ? 128 : 64);
         const int ntx = (p.nx + w - 1) / w;
         const int64_t waves_per_item = w / 64;
         int64_t want_items = 2048 / waves_per_item;
         int64_t nch = (want_items + ntx - 1) / ntx;
         int chunk = (int)((p.ny + nch - 1) / nch);
-        if (chunk < 4) chunk = 4;
+        if (chunk < 1) chunk = 1;
         s->launch.width = w;
         s->launch.height = 1;
         s->launch.chunk = chunk;
@@ -312,6 +329,7 @@ extern "C" tlb_status tlb_destroy(tlb_sim* s)
 {
     if (!s) return TLB_EINVAL;
     if (s->stream) (void)hipStreamSynchronize(s->stream);
+    drop_graph(s);
     for (int b = 0; b < 2; ++b)
         if (s->state[b]) (void)hipFree(s->state[b]);
     if (s->wet) (void)hipFree(s->wet);
@@ -539,22 +557,76 @@ static hipError_t launch_one(const tlb_sim* s, const StepArgs<T>& a)
                                   s->p.collision == TLB_MRT, s->nc, s->stream);
 }
 
+// n steps, each launched directly.
 template <typename T>
-static tlb_status step_impl(tlb_sim* s, int64_t nsteps)
+static tlb_status launch_steps(tlb_sim* s, int64_t n)
 {
     StepArgs<T> a = step_args<T>(s);
-    for (int64_t t = 0; t < nsteps; ++t) {
+    for (int64_t t = 0; t < n; ++t) {
         a.src = (const T*)s->state[s->cur];
         a.dst = (T*)s->state[s->cur ^ 1];
         HIPCHK(launch_one<T>(s, a));
         s->cur ^= 1;
-        s->step += 1;
+    }
+    return TLB_OK;
+}
+
+// n steps: whole chains of graph_steps replayed from the captured graph (which starts from buffer 0
+// and, being even, ends there), the rest launched directly.
+template <typename T>
+static tlb_status run_steps(tlb_sim* s, int64_t n)
+{
+    const int64_t G = s->graph_steps;
+    if (G > 0 && n >= G + (s->cur != 0 ? 1 : 0)) {
+        if (s->cur != 0) {
+            tlb_status st = launch_steps<T>(s, 1);
+            if (st) return st;
+            --n;
+        }
+        if (!s->graph_exec) {
+            HIPCHK(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
+            tlb_status st = launch_steps<T>(s, G);  // recorded, not run: cur is back at 0
+            hipGraph_t g = nullptr;
+            const hipError_t e = hipStreamEndCapture(s->stream, &g);
+            if (st) {
+                if (g) (void)hipGraphDestroy(g);
+                return st;
+            }
+            HIPCHK(e);
+            s->graph = g;
+            HIPCHK(hipGraphInstantiate(&s->graph_exec, g, nullptr, nullptr, 0));
+        }
+        for (; n >= G; n -= G) HIPCHK(hipGraphLaunch(s->graph_exec, s->stream));
+    }
+    return launch_steps<T>(s, n);
+}
+
+template <typename T>
+static tlb_status step_impl(tlb_sim* s, int64_t nsteps)
+{
+    while (nsteps > 0) {
+        // up to the next conservation check
+        int64_t n = nsteps;
+        if (s->check_every > 0) n = std::min<int64_t>(n, s->check_every - s->step % s->check_every);
+        tlb_status st = run_steps<T>(s, n);
+        if (st) return st;
+        s->step += n;
+        nsteps -= n;
         if (s->check_every > 0 && s->step % s->check_every == 0) {
             tlb_diag d;
-            tlb_status st = tlb_diagnostics(s, &d);
+            st = tlb_diagnostics(s, &d);
             if (st) return st;
         }
     }
+    return TLB_OK;
+}
+
+extern "C" tlb_status tlb_set_graph(tlb_sim* s, int64_t steps_per_graph)
+{
+    if (!s || steps_per_graph < 0 || (steps_per_graph & 1)) return TLB_EINVAL;
+    HIPCHK(hipStreamSynchronize(s->stream));
+    drop_graph(s);
+    s->graph_steps = steps_per_graph;
     return TLB_OK;
 }
 
@@ -604,6 +676,10 @@ extern "C" tlb_status tlb_set_launch(tlb_sim* s, const tlb_launch* l)
         s->launch = d;
     }
     if (!launch_valid(s, &v)) return TLB_EINVAL;
+    if (memcmp(&v, &s->launch, sizeof(v)) != 0) {
+        HIPCHK(hipStreamSynchronize(s->stream));
+        drop_graph(s);  // the captured launches have the old shape
+    }
     s->launch = v;
     return TLB_OK;
 }
@@ -929,6 +1005,8 @@ extern "C" tlb_status tlb_set_kappa(tlb_sim* s, const double* kappa)
     if (!s || !kappa) return TLB_EINVAL;
     for (int m = 0; m < s->nc; ++m)
         if (!(kappa[m] > 0.0) || !isfinite(kappa[m])) return TLB_EINVAL;
+    HIPCHK(hipStreamSynchronize(s->stream));
+    drop_graph(s);  // the captured launches hold the old coefficients
     for (int m = 0; m < s->nc; ++m) (m < 3 ? s->p.kappa[m] : s->p.kappa_hi[m - 3]) = kappa[m];
     if (s->p.walls_y) {
         tlb_status st = rescale_wet(s, 0);

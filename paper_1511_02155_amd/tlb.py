@@ -36,7 +36,7 @@ FIELD_INDEX.update(C4=11, C5=12)  # simulations with more than three components
 # Every symbol declared in include/tlb.h.
 EXPORTS = (
     "tlb_status_str", "tlb_last_hip_error", "tlb_version", "tlb_create", "tlb_destroy",
-    "tlb_get_params", "tlb_set_wetting", "tlb_init_equilibrium", "tlb_step", "tlb_set_check_every",
+    "tlb_get_params", "tlb_set_wetting", "tlb_init_equilibrium", "tlb_step", "tlb_set_check_every", "tlb_set_graph",
     "tlb_get_field", "tlb_get_populations", "tlb_set_populations", "tlb_diagnostics", "tlb_get_step",
     "tlb_synchronize", "tlb_get_stream", "tlb_init_equilibrium_dev", "tlb_get_field_dev",
     "tlb_get_populations_dev", "tlb_set_populations_dev", "tlb_set_wetting_dev", "tlb_set_launch",
@@ -108,6 +108,7 @@ tlb_set_wetting = _sig("tlb_set_wetting", ctypes.c_int, [_vp, ctypes.c_int, _dp]
 tlb_init_equilibrium = _sig("tlb_init_equilibrium", ctypes.c_int, [_vp, _dp, _dp])
 tlb_step = _sig("tlb_step", ctypes.c_int, [_vp, ctypes.c_int64])
 tlb_set_check_every = _sig("tlb_set_check_every", ctypes.c_int, [_vp, ctypes.c_int64])
+tlb_set_graph = _sig("tlb_set_graph", ctypes.c_int, [_vp, ctypes.c_int64])
 tlb_get_field = _sig("tlb_get_field", ctypes.c_int, [_vp, ctypes.c_int, _dp])
 tlb_get_populations = _sig("tlb_get_populations", ctypes.c_int, [_vp, ctypes.c_int, _dp])
 tlb_set_populations = _sig("tlb_set_populations", ctypes.c_int, [_vp, ctypes.c_int, _dp])
@@ -290,6 +291,13 @@ class Sim:
 
     def step(self, n):
         check(tlb_step(self._h, int(n)), "tlb_step")
+
+    def set_graph(self, steps_per_graph):
+        """Replay steps from a captured hipGraph in chains of this many (even; 0 = direct launches)."""
+        check(tlb_set_graph(self._h, int(steps_per_graph)), "tlb_set_graph")
+
+    def set_check_every(self, every):
+        check(tlb_set_check_every(self._h, int(every)), "tlb_set_check_every")
 
     def synchronize(self):
         check(tlb_synchronize(self._h), "tlb_synchronize")
