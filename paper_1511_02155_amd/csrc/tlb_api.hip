@@ -588,6 +588,7 @@ static tlb_status run_steps(tlb_sim* s, int64_t n)
             --n;
         }
         if (!s->graph_exec) {
+            drop_graph(s);  // a graph left by a failed instantiation
             HIPCHK(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
             tlb_status st = launch_steps<T>(s, G);  // recorded, not run: cur is back at 0
             hipGraph_t g = nullptr;
