@@ -24,13 +24,15 @@
 //        lambda_{t,i}(r) = sbar_i(r + e_i), or sbar_opp(i)(r) where r + e_i lies
 //      beyond a wall.
 // The dependency radius is 3 nodes.  k_adj2d runs all four stages in one
-// sweep: a workgroup of W lanes covers W columns and produces the middle
-// W - 6 of them, sweeping a chunk of rows with the stages three rows apart
-// (stage 1 at row a, stage 2 at a-1, stage 3 at a-2, stage 4 at a-3).  The
-// per-row quantities that neighbours need (dC_m; Gbar, Lbar; S, J) live in
-// three-row LDS rings, the rest in registers.  HBM traffic per node and step:
-// u_t and lambda_{t+1} read, lambda_t written (81 values); the overlapping
-// halo rows and columns are re-read from L2.
+// sweep: a workgroup of K row groups of W lanes covers W columns and produces
+// the middle W - 6 of them, sweeping a chunk of rows with the stages one row
+// apart (stage 1 at row a, stage 2 at a-1, stage 3 at a-2, stage 4 at a-3),
+// K rows per iteration.  The per-row quantities that neighbours need (dC_m;
+// Gbar, Lbar; S, J; with K > 1 also the moments and local transposes) live in
+// (K + 2)-row LDS rings, the rest in registers.  HBM traffic per node and
+// step: u_t and lambda_{t+1} read, lambda_t written (81 values); the
+// overlapping halo rows and columns are re-read, from L2 when they are still
+// there.
 //
 // The kappa gradient is summed per work item in a fixed order (lanes, then a
 // tree) into its own slot kpart[m][item] (added to it over a reverse pass, or
