@@ -278,12 +278,13 @@ def cpu_model():
     return f"{name} ({os.cpu_count()} logical processors visible)"
 
 
-def cpu_single_thread(steps=4):
-    """The headline oracle sample on one thread (a child process started with OMP_NUM_THREADS=1)."""
+def cpu_single_thread(steps=4, call=None):
+    """An oracle sample on one thread (a child process started with OMP_NUM_THREADS=1); by default the
+    1024^2 D2Q9 spinodal, else the bench function call given as text."""
     import subprocess
 
-    code = ("import json, bench; from paper_1511_02155_amd import inputs; "
-            f"print(json.dumps(bench.cpu_baseline(inputs.spinodal_2d(1024, {steps}), {steps})))")
+    call = call or f"bench.cpu_baseline(inputs.spinodal_2d(1024, {steps}), {steps})"
+    code = f"import json, bench; from paper_1511_02155_amd import inputs; print(json.dumps({call}))"
     env = dict(os.environ, OMP_NUM_THREADS="1")
     out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True, text=True,
                          timeout=600, check=True).stdout
@@ -473,6 +474,8 @@ def main():
             g2 = res["d2q9_1024x1024_spinodal_f64"]["mlups"]
             forms = {"d2q9_1024x1024_spinodal_f64": (cpu_baseline(inputs.spinodal_2d(1024, 300), 300), g2),
                      "d2q9_1024x1024_spinodal_f64_one_thread": (cpu_single_thread(), g2),
+                     "d3q19_96cube_spinodal_f64_one_thread": (cpu_single_thread(call="bench.cpu_d3q19(96, 3)"),
+                                                              head["mlups"]),
                      "batched_512_domains": (cpu_batched(), res["batched_512_domains_f32"]["mlups"]),
                      "adjoint_512x512_wall_drop_gradient": (cpu_gradient(),
                                                             res["adjoint_512x512_wall_drop_f64"]["gradient_mlups"])}
