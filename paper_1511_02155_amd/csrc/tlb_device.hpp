@@ -394,41 +394,57 @@ __device__ __forceinline__ void collide_core(const Phys<T>& P, const Moments<T, 
 #pragma unroll
         for (int q = 0; q < NS; ++q) ms[q] = 0;
     }
+    // Directions come in pairs e_j = -e_i with the same weights (w_i and the second-order w_i^ab are
+    // even in e), so an equilibrium splits into a part even in e, shared by the pair, and an odd part
+    // of opposite signs: U_i = Ue + Uo, U_j = Ue - Uo with Uo = 3 e_i.v, Ue = 9/2 (e_i.v)^2 - 3/2 v^2.
 #pragma unroll
     for (int i = 1; i < L::Q; ++i) {
+        const int j = L::opp[i];
+        if (j < i) continue;  // each pair once, from its lower index
         const T w = T(weight<L>(i));
         const T ev = T(L::ex[i]) * vx + T(L::ey[i]) * vy + T(L::ez[i]) * vz;
-        const T U = T(3) * ev + T(4.5) * ev * ev - T(1.5) * vv;
+        const T Ue = T(4.5) * ev * ev - T(1.5) * vv, Uo = T(3) * ev;
         T G = T(3 * wdiag<L>(i, 0)) * Txx + T(3 * wdiag<L>(i, 1)) * Tyy +
               T(3 * woff<L>(i, 0, 1)) * Txy;
         if (L::D == 3)
             G += T(3 * wdiag<L>(i, 2)) * Tzz + T(3 * woff<L>(i, 1, 2)) * Tyz +
                  T(3 * woff<L>(i, 2, 0)) * Tzx;
-        const T feq = w * (A + rho * U) + G;
-        const T Ua = P.adv * U;  // velocity terms of g^eq, k^eq (absent without advection)
-        const T geq = w * (Bp + mo.phi * Ua);
-        T keq[NK], ki[NK];
+        const T fe = w * (A + rho * Ue) + G, fo = w * rho * Uo;
+        // velocity terms of g^eq, k^eq (absent without advection)
+        const T Uae = P.adv * Ue, Uao = P.adv * Uo;
+        const T ge = w * (Bp + mo.phi * Uae), go = w * mo.phi * Uao;
+        T ke[NK], ko[NK];
 #pragma unroll
-        for (int l = 0; l < NK; ++l) keq[l] = w * (Bk[l] + psi[l] * Ua);
-        sf += feq;
-        sg += geq;
-#pragma unroll
-        for (int l = 0; l < NK; ++l) sk[l] += keq[l];
-        const T fi = ld(0, i), gi = ld(1, i);
-#pragma unroll
-        for (int l = 0; l < NK; ++l) ki[l] = ld(2 + l, i);
-        if constexpr (MRT) {
-            const T di = fi - feq;
-            dq[i] = di;
-            me += T(mrt_energy<L>(i)) * di;
-#pragma unroll
-            for (int q = 0; q < NS; ++q) ms[q] += T(mrt_stress<L>(q, i)) * di;
-        } else {
-            st(0, i, fi + wf * (feq - fi));
+        for (int l = 0; l < NK; ++l) {
+            ke[l] = w * (Bk[l] + psi[l] * Uae);
+            ko[l] = w * psi[l] * Uao;
         }
-        st(1, i, gi + wg * (geq - gi));
+        sf += T(2) * fe;
+        sg += T(2) * ge;
 #pragma unroll
-        for (int l = 0; l < NK; ++l) st(2 + l, i, ki[l] + wk * (keq[l] - ki[l]));
+        for (int l = 0; l < NK; ++l) sk[l] += T(2) * ke[l];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int d = h == 0 ? i : j;
+            const T sgn = h == 0 ? T(1) : T(-1);
+            const T feq = fe + sgn * fo, geq = ge + sgn * go;
+            const T fi = ld(0, d), gi = ld(1, d);
+            T ki[NK];
+#pragma unroll
+            for (int l = 0; l < NK; ++l) ki[l] = ld(2 + l, d);
+            if constexpr (MRT) {
+                const T di = fi - feq;
+                dq[d] = di;
+                me += T(mrt_energy<L>(d)) * di;
+#pragma unroll
+                for (int q = 0; q < NS; ++q) ms[q] += T(mrt_stress<L>(q, d)) * di;
+            } else {
+                st(0, d, fi + wf * (feq - fi));
+            }
+            st(1, d, gi + wg * (geq - gi));
+#pragma unroll
+            for (int l = 0; l < NK; ++l) st(2 + l, d, ki[l] + wk * ((ke[l] + sgn * ko[l]) - ki[l]));
+        }
     }
     const T f0 = ld(0, 0), g0 = ld(1, 0);
     if constexpr (MRT) {
