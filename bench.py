@@ -120,7 +120,10 @@ def run_plain(tlb, torch, w, prec, steps, warmup, launch=None):
 
 def run_batched(tlb, torch, steps, warmup=10, graph_steps=50):
     """The 512-domain batched workload (FP32, walls, per-domain kappa and h): autotuned launch
-    shape (outside the timed region), steps replayed from a captured hipGraph."""
+    shape (outside the timed region), steps replayed from captured hipGraphs.  With the domains split
+    over G stream groups a step is G concurrent launches, one per group; the events on the batch's
+    stream bracket all of them (the groups join it at the end of every step call), and the bytes
+    are those of a whole step."""
     doms = inputs_mod().batched_walls()
     keys = ("lattice", "nx", "ny", "nz", "walls_y", "kappa", "alpha", "tau_f", "tau_g", "tau_k", "gamma_phi",
             "gamma_psi")
@@ -141,7 +144,7 @@ def run_batched(tlb, torch, steps, warmup=10, graph_steps=50):
     out = dict(mlups=nodes * steps / (ms * 1e-3) / 1e6, ms_per_step=ms / steps,
                achieved_GBps=bytes_per_step / (ms / steps * 1e-3) / 1e9, domains=len(doms), nodes=nodes,
                steps=steps, launch=chosen, graph_steps=graph_steps, bytes_per_launch=bytes_per_step,
-               kernel="k_batch2d")
+               launches_per_step=chosen["groups"], kernel="k_batch2d")
     b.close()
     return out
 

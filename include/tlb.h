@@ -464,10 +464,11 @@ tlb_status tlb_device_copy(void* dst, const void* src, int64_t bytes, void* stre
  * of Sec. V, e.g. sweeps over kappa_m and h_m) together.  Each domain has its
  * own tlb_params (lattice TLB_D2Q9, nx, ny <= 65535, its own walls_y, kappa,
  * alpha, tau and Gamma); every domain must use the same prec.  One time step
- * of the batch is one persistent kernel launch whose workgroups take
+ * of the batch is one persistent kernel launch per stream group (one group
+ * unless tlb_batch_set_launch asks for more) whose workgroups take
  * (domain, strip, row-chunk) or (domain, run of positions) work items from
- * per-XCD queues; with
- * tlb_batch_set_graph the steps are replayed from a captured hipGraph.
+ * per-XCD queues; with tlb_batch_set_graph the steps are replayed from
+ * captured hipGraphs (one per group).
  * A domain evolves exactly (bit for bit) as a tlb_sim with the same
  * parameters.  Domain indices run 0..ndom-1; host arrays follow the layouts
  * of the single-lattice calls for that domain's nx, ny.
@@ -500,13 +501,20 @@ tlb_status tlb_batch_diagnostics(tlb_batch* batch, int32_t dom, tlb_diag* out);
  * its rows (each padded with its two periodic halo columns), chunk = runs of
  * `width` consecutive positions per work item, so that narrow domains leave
  * no lanes idle, and the wider domains in strips as variant 0.  chunk is
- * 1..65535; height is ignored.  Results do not depend on the shape.
+ * 1..65535.  height (1..4, 0 means 1) splits the domains into that many
+ * stream groups of nearly equal work (at most one per domain); each group
+ * runs its own chain of launches on its own stream, forked from and joined
+ * back into the batch's stream inside tlb_batch_step, so that one group's
+ * launch fills the compute units another group's launch leaves idle as it
+ * drains.  Streams other than the batch's are created by the library, at
+ * the default priority.  Results do not depend on the shape.
  */
 tlb_status tlb_batch_set_launch(tlb_batch* batch, const tlb_launch* launch);
 tlb_status tlb_batch_get_launch(const tlb_batch* batch, tlb_launch* out);
 /*
  * Time every launch shape for trial_steps steps from the current state
- * (which is restored) and keep the fastest; writes it to *chosen if not NULL.
+ * (which is restored) in one stream group, then the fastest of them in 2, 3
+ * and 4 groups, and keep the fastest; writes it to *chosen if not NULL.
  * If the environment variable TLB_TUNE_CACHE names a file, a previous result
  * for the same domain sizes is taken from it, and new results are appended.
  */

@@ -1,7 +1,10 @@
 // Batched D2Q9 ternary LB: many independent lattices of uneven size and
 // parameters advanced together.
 //
-// One time step of the whole batch is one persistent launch: a grid sized to
+// One time step of the whole batch is one persistent launch per stream group
+// (the domains split into up to four groups of nearly equal work, each on its
+// own stream, so that one group's launch fills the compute units another's
+// leaves idle as it drains): a grid sized to
 // the number of workgroups the GPU holds at once, whose workgroups take
 // (domain, strip, chunk) work items from eight queues (one per XCD, filled
 // largest domain first and balanced by load) and steal from the other queues
@@ -51,6 +54,7 @@ struct BatchArgs {
 };
 
 constexpr int kQueues = 8;
+constexpr int kMaxGroups = 4;  // stream groups a batch's domains can be split over
 
 // Pull of node (x, y) addressed per lane: the loads of pull2d (same sources,
 // same half-way bounce-back) with the row folded into the lane's offset.  The
@@ -338,8 +342,8 @@ struct tlb_batch {
     void* wet;
     void* doms;  // DomDesc<T>[ndom]
     int2* items;
-    int* qstart;
-    int* counters;
+    int* qstart;    // [kMaxGroups][kQueues + 1]
+    int* counters;  // [kMaxGroups][2][kQueues]
     int nitems;
     void* fields;
     double* staging;
@@ -347,11 +351,18 @@ struct tlb_batch {
     double* diag_out;
     int64_t step;
     bool ready;
-    tlb_launch launch;  // width, height (unused), chunk = rows per work item, variant
-    int grid;
+    tlb_launch launch;  // width, height = stream groups, chunk = rows per work item, variant
+    // Stream groups: the domains are split over `groups` sets of nearly equal work, each stepped by
+    // its own chain of launches on its own stream (group 0 on `stream`), forked from and joined back
+    // into `stream` by events, so that one group's launch fills the compute units another's leaves
+    // idle while it drains.
+    int groups;
+    int grid[kMaxGroups];
+    hipStream_t group_stream[kMaxGroups];
+    hipEvent_t fork, join[kMaxGroups];
     int graph_steps;
-    hipGraphExec_t graph_exec;
-    hipGraph_t graph;
+    hipGraphExec_t graph_exec[kMaxGroups];
+    hipGraph_t graph[kMaxGroups];
     std::vector<int64_t> wet_outside;  // [dom][wall]: wetting values with |4 h_m / (alpha kappa_m)| > 1
     bool wet_warned;
 };
@@ -400,13 +411,29 @@ static AuxGeom dom_geom(const tlb_batch* b, int d)
 
 static void drop_graph(tlb_batch* b)
 {
-    if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
-    if (b->graph) (void)hipGraphDestroy(b->graph);
-    b->graph_exec = nullptr;
-    b->graph = nullptr;
+    for (int L = 0; L < kMaxGroups; ++L) {
+        if (b->graph_exec[L]) (void)hipGraphExecDestroy(b->graph_exec[L]);
+        if (b->graph[L]) (void)hipGraphDestroy(b->graph[L]);
+        b->graph_exec[L] = nullptr;
+        b->graph[L] = nullptr;
+    }
+}
+
+// Waits for the work of every group's stream (the groups are joined into `stream` only at the end of
+// tlb_batch_step, so a failed step can leave them running).
+static hipError_t sync_groups(tlb_batch* b)
+{
+    hipError_t e = hipSuccess;
+    for (int L = 0; L < kMaxGroups; ++L)
+        if (b->group_stream[L]) {
+            const hipError_t f = hipStreamSynchronize(b->group_stream[L]);
+            if (e == hipSuccess) e = f;
+        }
+    return e;
 }
 
 // Work items and queues for the current launch shape: domains go to the
+// least-loaded stream group in decreasing size, then, within a group, to its
 // least-loaded queue in decreasing size; within a queue, larger domains come
 // first and the strips of one chunk are adjacent.  The flat items in the last
 // quarter of a queue's work are halved, so that the workgroups run out of
@@ -420,83 +447,99 @@ static tlb_status build_items(tlb_batch* b)
     std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
         return (int64_t)b->p[a].nx * b->p[a].ny > (int64_t)b->p[c].nx * b->p[c].ny;
     });
-    std::vector<std::vector<int2>> q(kQueues);
-    std::vector<std::vector<int64_t>> qcost(kQueues);  // lane-rows of each item
-    std::vector<int64_t> load(kQueues, 0);
+    const int S = b->groups;
+    std::vector<int> group_of(b->ndom);
+    {
+        std::vector<int64_t> gload(S, 0);
+        for (int d : order) {
+            const int L = (int)(std::min_element(gload.begin(), gload.end()) - gload.begin());
+            group_of[d] = L;
+            gload[L] += (int64_t)(b->p[d].nx + 2) * b->p[d].ny;
+        }
+    }
     auto flat_item = [](int d, int seg0, int cnt, bool down) {
         return make_int2(d, (int)((uint32_t)seg0 | (uint32_t)cnt << 16 | (down ? 0x80000000u : 0u)));
     };
     std::vector<DomDesc<T>> dd(b->ndom);
-    for (int d : order) {
-        const tlb_params& p = b->p[d];
-        DomDesc<T>& D = dd[d];
-        D.off = b->off[d];
-        D.wet_off = b->wet_off[d];
-        D.nx = p.nx;
-        D.ny = p.ny;
-        D.walls = p.walls_y;
-        D.P = phys_of<acc_t<T>>(p);
-        const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-        if (b->launch.variant == 2 && p.nx + 3 <= W) {
-            // flat sweep: items of `rows` segments of W positions of the padded rows
-            const int64_t nseg = ((int64_t)(p.nx + 2) * p.ny + W - 1) / W;
-            D.flat = 1;
-            D.chunk = (int)std::min<int64_t>(std::min(rows, 0x7fff), nseg);
-            D.ntx = 1;
-            D.nchunks = (int)((nseg + D.chunk - 1) / D.chunk);
-            load[k] += nseg * W;
-            for (int c = 0; c < D.nchunks; ++c) {
-                const int s0 = c * D.chunk, cnt = (int)std::min<int64_t>(D.chunk, nseg - s0);
-                q[k].push_back(flat_item(d, s0, cnt, c & 1));
-                qcost[k].push_back((int64_t)cnt * W);
-            }
-            continue;
-        } else {
-            D.flat = 0;
-            D.chunk = std::min(rows, p.ny);
-            D.ntx = (p.nx + W - 1) / W;
-            D.nchunks = (p.ny + D.chunk - 1) / D.chunk;
-            load[k] += (int64_t)D.ntx * W * p.ny;
-        }
-        for (int c = 0; c < D.nchunks; ++c)
-            for (int s = 0; s < D.ntx; ++s) {
-                q[k].push_back(make_int2(d, (s << 16) | c));
-                qcost[k].push_back((int64_t)W * std::min(D.chunk, p.ny - c * D.chunk));
-            }
-    }
-    for (int k = 0; k < kQueues; ++k) {
-        int64_t total = 0, cum = 0;
-        for (int64_t c : qcost[k]) total += c;
-        std::vector<int2> split;
-        for (size_t i = 0; i < q[k].size(); ++i) {
-            const int2 it = q[k][i];
-            const int cnt = (it.y >> 16) & 0x7fff;
-            if (dd[it.x].flat && cnt >= 2 && 4 * cum >= 3 * total) {
-                const int s0 = it.y & 0xffff, h = cnt / 2;
-                const bool down = it.y < 0;
-                split.push_back(flat_item(it.x, s0, h, down));
-                split.push_back(flat_item(it.x, s0 + h, cnt - h, !down));
-            } else {
-                split.push_back(it);
-            }
-            cum += qcost[k][i];
-        }
-        q[k].swap(split);
-    }
     std::vector<int2> items;
-    std::vector<int> qs(kQueues + 1, 0);
-    for (int k = 0; k < kQueues; ++k) {
-        qs[k] = (int)items.size();
-        items.insert(items.end(), q[k].begin(), q[k].end());
+    std::vector<int> qs((size_t)kMaxGroups * (kQueues + 1), 0);
+    std::vector<int> group_items(kMaxGroups, 0);
+    for (int L = 0; L < S; ++L) {
+        std::vector<std::vector<int2>> q(kQueues);
+        std::vector<std::vector<int64_t>> qcost(kQueues);  // lane-rows of each item
+        std::vector<int64_t> load(kQueues, 0);
+        for (int d : order) {
+            if (group_of[d] != L) continue;
+            const tlb_params& p = b->p[d];
+            DomDesc<T>& D = dd[d];
+            D.off = b->off[d];
+            D.wet_off = b->wet_off[d];
+            D.nx = p.nx;
+            D.ny = p.ny;
+            D.walls = p.walls_y;
+            D.P = phys_of<acc_t<T>>(p);
+            const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+            if (b->launch.variant == 2 && p.nx + 3 <= W) {
+                // flat sweep: items of `rows` segments of W positions of the padded rows
+                const int64_t nseg = ((int64_t)(p.nx + 2) * p.ny + W - 1) / W;
+                D.flat = 1;
+                D.chunk = (int)std::min<int64_t>(std::min(rows, 0x7fff), nseg);
+                D.ntx = 1;
+                D.nchunks = (int)((nseg + D.chunk - 1) / D.chunk);
+                load[k] += nseg * W;
+                for (int c = 0; c < D.nchunks; ++c) {
+                    const int s0 = c * D.chunk, cnt = (int)std::min<int64_t>(D.chunk, nseg - s0);
+                    q[k].push_back(flat_item(d, s0, cnt, c & 1));
+                    qcost[k].push_back((int64_t)cnt * W);
+                }
+                continue;
+            } else {
+                D.flat = 0;
+                D.chunk = std::min(rows, p.ny);
+                D.ntx = (p.nx + W - 1) / W;
+                D.nchunks = (p.ny + D.chunk - 1) / D.chunk;
+                load[k] += (int64_t)D.ntx * W * p.ny;
+            }
+            for (int c = 0; c < D.nchunks; ++c)
+                for (int s = 0; s < D.ntx; ++s) {
+                    q[k].push_back(make_int2(d, (s << 16) | c));
+                    qcost[k].push_back((int64_t)W * std::min(D.chunk, p.ny - c * D.chunk));
+                }
+        }
+        for (int k = 0; k < kQueues; ++k) {
+            int64_t total = 0, cum = 0;
+            for (int64_t c : qcost[k]) total += c;
+            std::vector<int2> split;
+            for (size_t i = 0; i < q[k].size(); ++i) {
+                const int2 it = q[k][i];
+                const int cnt = (it.y >> 16) & 0x7fff;
+                if (dd[it.x].flat && cnt >= 2 && 4 * cum >= 3 * total) {
+                    const int s0 = it.y & 0xffff, h = cnt / 2;
+                    const bool down = it.y < 0;
+                    split.push_back(flat_item(it.x, s0, h, down));
+                    split.push_back(flat_item(it.x, s0 + h, cnt - h, !down));
+                } else {
+                    split.push_back(it);
+                }
+                cum += qcost[k][i];
+            }
+            q[k].swap(split);
+        }
+        const int first = (int)items.size();
+        for (int k = 0; k < kQueues; ++k) {
+            qs[(size_t)L * (kQueues + 1) + k] = (int)items.size();
+            items.insert(items.end(), q[k].begin(), q[k].end());
+        }
+        qs[(size_t)L * (kQueues + 1) + kQueues] = (int)items.size();
+        group_items[L] = (int)items.size() - first;
     }
-    qs[kQueues] = (int)items.size();
     if (b->items) BHIP(hipFree(b->items));
     b->items = nullptr;
     BHIP(hipMalloc((void**)&b->items, sizeof(int2) * items.size()));
     BHIP(hipMemcpyAsync(b->items, items.data(), sizeof(int2) * items.size(), hipMemcpyHostToDevice, b->stream));
     BHIP(hipMemcpyAsync(b->qstart, qs.data(), sizeof(int) * qs.size(), hipMemcpyHostToDevice, b->stream));
     BHIP(hipMemcpyAsync(b->doms, dd.data(), sizeof(DomDesc<T>) * dd.size(), hipMemcpyHostToDevice, b->stream));
-    BHIP(hipMemsetAsync(b->counters, 0, sizeof(int) * 2 * kQueues, b->stream));
+    BHIP(hipMemsetAsync(b->counters, 0, sizeof(int) * 2 * kQueues * kMaxGroups, b->stream));
     BHIP(hipStreamSynchronize(b->stream));
     b->nitems = (int)items.size();
     int dev = 0, ncu = 0, per_cu = 0;
@@ -504,7 +547,9 @@ static tlb_status build_items(tlb_batch* b)
     BHIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
     BHIP(occupancy_batch2d<T>(W, b->launch.variant, &per_cu));
     if (per_cu < 1) per_cu = 1;
-    b->grid = std::max(1, std::min(ncu * per_cu, b->nitems));
+    for (int L = 0; L < kMaxGroups; ++L) b->grid[L] = std::min(ncu * per_cu, group_items[L]);
+    for (int L = 1; L < S; ++L)
+        if (!b->group_stream[L]) BHIP(hipStreamCreateWithFlags(&b->group_stream[L], hipStreamNonBlocking));
     drop_graph(b);
     return TLB_OK;
 }
@@ -560,6 +605,7 @@ extern "C" tlb_status tlb_batch_create(const tlb_params* per_dom, int32_t ndom, 
     b->launch.height = 1;
     b->launch.chunk = 16;
     b->launch.variant = prec == TLB_F32 ? 1 : 0;
+    b->groups = 1;
     hipError_t e = hipSuccess;
     if (stream) {
         b->stream = (hipStream_t)stream;
@@ -567,14 +613,17 @@ extern "C" tlb_status tlb_batch_create(const tlb_params* per_dom, int32_t ndom, 
         e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
         b->own_stream = true;
     }
+    b->group_stream[0] = b->stream;
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+    for (int L = 1; L < kMaxGroups && e == hipSuccess; ++L) e = hipEventCreateWithFlags(&b->join[L], hipEventDisableTiming);
     const size_t dsz = prec == TLB_F32 ? sizeof(DomDesc<float>) : sizeof(DomDesc<double>);
     if (e == hipSuccess) e = hipMalloc(&b->state[0], b->state_elems * b->esize);
     if (e == hipSuccess) e = hipMalloc(&b->state[1], b->state_elems * b->esize);
     if (e == hipSuccess) e = hipMalloc(&b->wet, std::max<int64_t>(b->wet_elems, 1) * b->esize);
     if (e == hipSuccess) e = hipMemsetAsync(b->wet, 0, std::max<int64_t>(b->wet_elems, 1) * b->esize, b->stream);
     if (e == hipSuccess) e = hipMalloc(&b->doms, dsz * ndom);
-    if (e == hipSuccess) e = hipMalloc((void**)&b->qstart, sizeof(int) * (kQueues + 1));
-    if (e == hipSuccess) e = hipMalloc((void**)&b->counters, sizeof(int) * 2 * kQueues);
+    if (e == hipSuccess) e = hipMalloc((void**)&b->qstart, sizeof(int) * kMaxGroups * (kQueues + 1));
+    if (e == hipSuccess) e = hipMalloc((void**)&b->counters, sizeof(int) * kMaxGroups * 2 * kQueues);
     if (e == hipSuccess) e = hipMalloc((void**)&b->diag_partial, sizeof(double) * kDiagBlocks * kDiagSlots);
     if (e == hipSuccess) e = hipMalloc((void**)&b->diag_out, sizeof(double) * kDiagSlots);
     if (e != hipSuccess) {
@@ -594,11 +643,16 @@ extern "C" tlb_status tlb_batch_create(const tlb_params* per_dom, int32_t ndom, 
 extern "C" tlb_status tlb_batch_destroy(tlb_batch* b)
 {
     if (!b) return TLB_EINVAL;
-    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    (void)sync_groups(b);
     drop_graph(b);
     for (void* ptr : {b->state[0], b->state[1], b->wet, b->doms, (void*)b->items, (void*)b->qstart, (void*)b->counters,
                       b->fields, (void*)b->staging, (void*)b->diag_partial, (void*)b->diag_out})
         if (ptr) (void)hipFree(ptr);
+    for (int L = 1; L < kMaxGroups; ++L) {
+        if (b->group_stream[L]) (void)hipStreamDestroy(b->group_stream[L]);
+        if (b->join[L]) (void)hipEventDestroy(b->join[L]);
+    }
+    if (b->fork) (void)hipEventDestroy(b->fork);
     if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
     delete b;
     return TLB_OK;
@@ -693,30 +747,66 @@ extern "C" tlb_status tlb_batch_init_equilibrium(tlb_batch* b, int32_t dom, cons
     return TLB_OK;
 }
 
+// One step of stream group L from buffer `cur` on the group's stream.
 template <typename T>
-static tlb_status batch_launch_one(tlb_batch* b)
+static tlb_status batch_launch_one(tlb_batch* b, int L, int cur)
 {
     BatchArgs<T> a;
-    a.src = (const T*)b->state[b->cur];
-    a.dst = (T*)b->state[b->cur ^ 1];
+    a.src = (const T*)b->state[cur];
+    a.dst = (T*)b->state[cur ^ 1];
     a.wet = (const T*)b->wet;
     a.doms = (const DomDesc<T>*)b->doms;
     a.items = b->items;
-    a.qstart = b->qstart;
-    a.counters = b->counters;
-    a.parity = b->cur;
-    BHIP(launch_batch2d<T>(a, b->launch.width, b->launch.variant, b->grid, b->stream));
-    b->cur ^= 1;
+    a.qstart = b->qstart + L * (kQueues + 1);
+    a.counters = b->counters + L * 2 * kQueues;
+    a.parity = cur;
+    BHIP(launch_batch2d<T>(a, b->launch.width, b->launch.variant, b->grid[L], b->group_stream[L]));
+    return TLB_OK;
+}
+
+static tlb_status launch_one(tlb_batch* b, int L, int cur)
+{
+    return b->prec == TLB_F32 ? batch_launch_one<float>(b, L, cur) : batch_launch_one<double>(b, L, cur);
+}
+
+// The other groups' streams wait for the work queued on `stream` so far.
+static tlb_status fork_groups(tlb_batch* b)
+{
+    if (b->groups < 2) return TLB_OK;
+    BHIP(hipEventRecord(b->fork, b->stream));
+    for (int L = 1; L < b->groups; ++L) BHIP(hipStreamWaitEvent(b->group_stream[L], b->fork, 0));
+    return TLB_OK;
+}
+
+// Work queued on `stream` from now on waits for the other groups' streams.
+static tlb_status join_groups(tlb_batch* b)
+{
+    for (int L = 1; L < b->groups; ++L) {
+        BHIP(hipEventRecord(b->join[L], b->group_stream[L]));
+        BHIP(hipStreamWaitEvent(b->stream, b->join[L], 0));
+    }
+    return TLB_OK;
+}
+
+// n steps of every group, step by step across the groups so that all streams are fed.
+static tlb_status launch_steps(tlb_batch* b, int64_t n)
+{
+    for (int64_t t = 0; t < n; ++t) {
+        for (int L = 0; L < b->groups; ++L) {
+            tlb_status st = launch_one(b, L, b->cur);
+            if (st) return st;
+        }
+        b->cur ^= 1;
+    }
     return TLB_OK;
 }
 
 static tlb_status batch_direct(tlb_batch* b, int64_t n)
 {
-    for (int64_t t = 0; t < n; ++t) {
-        tlb_status st = b->prec == TLB_F32 ? batch_launch_one<float>(b) : batch_launch_one<double>(b);
-        if (st) return st;
-    }
-    return TLB_OK;
+    tlb_status st = fork_groups(b);
+    if (!st) st = launch_steps(b, n);
+    if (!st) st = join_groups(b);
+    return st;
 }
 
 extern "C" tlb_status tlb_batch_step(tlb_batch* b, int64_t nsteps)
@@ -724,29 +814,34 @@ extern "C" tlb_status tlb_batch_step(tlb_batch* b, int64_t nsteps)
     if (!b || nsteps < 0) return TLB_EINVAL;
     if (!b->ready) return TLB_ESTATE;
     int64_t left = nsteps;
+    tlb_status st = fork_groups(b);
+    if (st) return st;
     if (b->graph_steps > 0 && left >= b->graph_steps) {
-        if (b->cur != 0) {  // the captured chain starts from buffer 0
-            tlb_status st = batch_direct(b, 1);
+        if (b->cur != 0) {  // the captured chains start from buffer 0
+            st = launch_steps(b, 1);
             if (st) return st;
             --left;
         }
-        if (!b->graph_exec) {
-            BHIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-            tlb_status st = batch_direct(b, b->graph_steps);
+        // one captured chain per group, on the group's stream
+        for (int L = 0; L < b->groups; ++L) {
+            if (b->graph_exec[L]) continue;
+            hipStream_t s = b->group_stream[L];
+            BHIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            for (int t = 0; t < b->graph_steps && !st; ++t) st = launch_one(b, L, t & 1);
             hipGraph_t g = nullptr;
-            hipError_t e = hipStreamEndCapture(b->stream, &g);
+            hipError_t e = hipStreamEndCapture(s, &g);
             if (st) return st;
             BHIP(e);
-            b->graph = g;
-            BHIP(hipGraphInstantiate(&b->graph_exec, g, nullptr, nullptr, 0));
-            b->cur = 0;  // capture recorded the launches without running them
+            b->graph[L] = g;
+            BHIP(hipGraphInstantiate(&b->graph_exec[L], g, nullptr, nullptr, 0));
         }
         while (left >= b->graph_steps) {
-            BHIP(hipGraphLaunch(b->graph_exec, b->stream));
+            for (int L = 0; L < b->groups; ++L) BHIP(hipGraphLaunch(b->graph_exec[L], b->group_stream[L]));
             left -= b->graph_steps;
         }
     }
-    tlb_status st = batch_direct(b, left);
+    st = launch_steps(b, left);
+    if (!st) st = join_groups(b);
     if (st) return st;
     b->step += nsteps;
     return TLB_OK;
@@ -755,7 +850,7 @@ extern "C" tlb_status tlb_batch_step(tlb_batch* b, int64_t nsteps)
 extern "C" tlb_status tlb_batch_set_graph(tlb_batch* b, int32_t steps_per_graph)
 {
     if (!b || steps_per_graph < 0 || (steps_per_graph & 1)) return TLB_EINVAL;
-    BHIP(hipStreamSynchronize(b->stream));
+    BHIP(sync_groups(b));
     drop_graph(b);
     b->graph_steps = steps_per_graph;
     return TLB_OK;
@@ -765,11 +860,12 @@ extern "C" tlb_status tlb_batch_set_launch(tlb_batch* b, const tlb_launch* l)
 {
     if (!b || !l) return TLB_EINVAL;
     if ((l->width != 64 && l->width != 128 && l->width != 256) || l->chunk < 1 || l->chunk > 65535 ||
-        l->variant < 0 || l->variant > 2)
+        l->variant < 0 || l->variant > 2 || l->height < 0 || l->height > kMaxGroups)
         return TLB_EINVAL;
-    BHIP(hipStreamSynchronize(b->stream));
+    BHIP(sync_groups(b));
     b->launch = *l;
-    b->launch.height = 1;
+    b->groups = std::max(1, std::min(l->height, b->ndom));
+    b->launch.height = b->groups;
     return rebuild(b);
 }
 
@@ -870,17 +966,18 @@ static std::string batch_signature(const tlb_batch* b)
     return buf;
 }
 
+// Cache lines: key width chunk variant groups (lines with fewer fields are skipped).
 static bool cache_lookup(const char* path, const std::string& key, tlb_launch* l)
 {
     FILE* f = fopen(path, "r");
     if (!f) return false;
-    char k[128];
-    int w, c, v;
+    char line[256], k[128];
+    int w, c, v, g;
     bool found = false;
-    while (fscanf(f, "%127s %d %d %d", k, &w, &c, &v) == 4)
-        if (key == k) {
+    while (fgets(line, sizeof(line), f))
+        if (sscanf(line, "%127s %d %d %d %d", k, &w, &c, &v, &g) == 5 && key == k) {
             l->width = w;
-            l->height = 1;
+            l->height = g;
             l->chunk = c;
             l->variant = v;
             found = true;
@@ -918,25 +1015,27 @@ extern "C" tlb_status tlb_batch_autotune(tlb_batch* b, int32_t trial_steps, tlb_
     const int widths[3] = {64, 128, 256};
     const int chunks[4] = {8, 16, 32, 64};
     tlb_status st = TLB_OK;
+    auto trial = [&](const tlb_launch& l) {
+        st = tlb_batch_set_launch(b, &l);
+        if (!st) st = batch_direct(b, 1);  // warm-up
+        if (st) return;
+        (void)hipEventRecord(e0, b->stream);
+        st = batch_direct(b, trial_steps);
+        (void)hipEventRecord(e1, b->stream);
+        (void)hipEventSynchronize(e1);
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (!st && ms < best_ms) {
+            best_ms = ms;
+            best = l;
+        }
+    };
+    // every shape in one stream group, then the fastest split over more groups
     for (int wi = 0; wi < 3 && !st; ++wi)
         for (int ci = 0; ci < 4 && !st; ++ci)
-            for (int v = 0; v < 3 && !st; ++v) {
-                tlb_launch l = {widths[wi], 1, chunks[ci], v};
-                st = tlb_batch_set_launch(b, &l);
-                if (st) break;
-                st = batch_direct(b, 1);  // warm-up
-                if (st) break;
-                (void)hipEventRecord(e0, b->stream);
-                st = batch_direct(b, trial_steps);
-                (void)hipEventRecord(e1, b->stream);
-                (void)hipEventSynchronize(e1);
-                float ms = 0;
-                (void)hipEventElapsedTime(&ms, e0, e1);
-                if (!st && ms < best_ms) {
-                    best_ms = ms;
-                    best = l;
-                }
-            }
+            for (int v = 0; v < 3 && !st; ++v) trial(tlb_launch{widths[wi], 1, chunks[ci], v});
+    const tlb_launch one = best;
+    for (int g = 2; g <= std::min(kMaxGroups, b->ndom) && !st; ++g) trial(tlb_launch{one.width, g, one.chunk, one.variant});
     (void)hipMemcpyAsync(b->state[cur0], save, bytes, hipMemcpyDeviceToDevice, b->stream);
     (void)hipStreamSynchronize(b->stream);
     (void)hipFree(save);
@@ -950,7 +1049,7 @@ extern "C" tlb_status tlb_batch_autotune(tlb_batch* b, int32_t trial_steps, tlb_
     if (cache) {
         FILE* f = fopen(cache, "a");
         if (f) {
-            fprintf(f, "%s %d %d %d\n", key.c_str(), best.width, best.chunk, best.variant);
+            fprintf(f, "%s %d %d %d %d\n", key.c_str(), best.width, best.chunk, best.variant, best.height);
             fclose(f);
         }
     }

@@ -464,19 +464,19 @@ class Batch:
         return dict(mass=list(dg.mass), momentum=list(dg.momentum), max_speed=dg.max_speed,
                     nonfinite=dg.nonfinite, step=dg.step, interface=list(dg.interface))
 
-    def set_launch(self, width, chunk, variant=1):
-        l = tlb_launch(width, 1, chunk, variant)
+    def set_launch(self, width, chunk, variant=1, groups=1):
+        l = tlb_launch(width, groups, chunk, variant)
         check(tlb_batch_set_launch(self._h, ctypes.byref(l)), "tlb_batch_set_launch")
 
     def launch(self):
         l = tlb_launch()
         check(tlb_batch_get_launch(self._h, ctypes.byref(l)), "tlb_batch_get_launch")
-        return dict(width=l.width, chunk=l.chunk, variant=l.variant)
+        return dict(width=l.width, chunk=l.chunk, variant=l.variant, groups=l.height)
 
     def autotune(self, trial_steps=10):
         l = tlb_launch()
         check(tlb_batch_autotune(self._h, int(trial_steps), ctypes.byref(l)), "tlb_batch_autotune")
-        return dict(width=l.width, chunk=l.chunk, variant=l.variant)
+        return dict(width=l.width, chunk=l.chunk, variant=l.variant, groups=l.height)
 
     def set_graph(self, steps_per_graph):
         check(tlb_batch_set_graph(self._h, int(steps_per_graph)), "tlb_batch_set_graph")

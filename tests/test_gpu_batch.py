@@ -74,7 +74,9 @@ def _single(tlb, d, prec, steps):
 @pytest.mark.parametrize("launch", [dict(width=64, chunk=8, variant=0), dict(width=128, chunk=16, variant=1),
                                     dict(width=256, chunk=5, variant=1), dict(width=64, chunk=3, variant=2),
                                     dict(width=128, chunk=1, variant=2), dict(width=256, chunk=4, variant=2),
-                                    dict(width=256, chunk=64, variant=2)])
+                                    dict(width=256, chunk=64, variant=2), dict(width=128, chunk=16, variant=1, groups=2),
+                                    dict(width=64, chunk=3, variant=2, groups=3),
+                                    dict(width=256, chunk=4, variant=2, groups=4)])
 def test_batch_equals_single_lattices_bitwise(tlb, prec, launch):
     P = tlb.TLB_F64 if prec == "f64" else tlb.TLB_F32
     doms = _small_batch()
@@ -122,15 +124,22 @@ def test_batch_flat_sweep_edge_domains_bitwise(tlb, prec, width, chunk):
 def test_batch_launch_validation(tlb):
     b = _make_batch(tlb, _small_batch(ndom=3, seed=26), tlb.TLB_F32)
     for bad in (dict(width=96, chunk=8, variant=0), dict(width=64, chunk=0, variant=0),
-                dict(width=64, chunk=8, variant=3), dict(width=64, chunk=8, variant=-1)):
+                dict(width=64, chunk=8, variant=3), dict(width=64, chunk=8, variant=-1),
+                dict(width=64, chunk=8, variant=0, groups=5), dict(width=64, chunk=8, variant=0, groups=-1)):
         with pytest.raises(tlb.TLBError):
             b.set_launch(**bad)
     b.set_launch(width=256, chunk=8, variant=2)
-    assert b.launch() == dict(width=256, chunk=8, variant=2)
+    assert b.launch() == dict(width=256, chunk=8, variant=2, groups=1)
+    # at most one stream group per domain; 0 means one group
+    b.set_launch(width=128, chunk=4, variant=2, groups=4)
+    assert b.launch() == dict(width=128, chunk=4, variant=2, groups=3)
+    b.set_launch(width=128, chunk=4, variant=2, groups=0)
+    assert b.launch()["groups"] == 1
     b.close()
 
 
-@pytest.mark.parametrize("launch", [None, dict(width=256, chunk=8, variant=2)])
+@pytest.mark.parametrize("launch", [None, dict(width=256, chunk=8, variant=2),
+                                    dict(width=256, chunk=8, variant=2, groups=4)])
 def test_batch_graph_replays_match_direct(tlb, launch):
     doms = _small_batch(seed=22)
     ref = _make_batch(tlb, doms, tlb.TLB_F32, launch)
