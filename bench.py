@@ -134,7 +134,7 @@ def run_batched(tlb, torch, steps, warmup=10, graph_steps=50):
         b.set_wetting(i, 0, d["h"][0])
         b.set_wetting(i, 1, d["h"][1])
         b.init_equilibrium(i, d["C"])
-    chosen = b.autotune(5)
+    chosen = b.autotune(10)
     b.set_graph(graph_steps)
     b.step(warmup)
     b.synchronize()

@@ -1015,12 +1015,13 @@ extern "C" tlb_status tlb_batch_autotune(tlb_batch* b, int32_t trial_steps, tlb_
     const int widths[3] = {64, 128, 256};
     const int chunks[4] = {8, 16, 32, 64};
     tlb_status st = TLB_OK;
-    auto trial = [&](const tlb_launch& l) {
+    auto trial = [&](const tlb_launch& l, int steps) {
         st = tlb_batch_set_launch(b, &l);
-        if (!st) st = batch_direct(b, 1);  // warm-up
+        // warm-up as long as the trial: a group's first launches on a new stream are slower
+        if (!st) st = batch_direct(b, steps);
         if (st) return;
         (void)hipEventRecord(e0, b->stream);
-        st = batch_direct(b, trial_steps);
+        st = batch_direct(b, steps);
         (void)hipEventRecord(e1, b->stream);
         (void)hipEventSynchronize(e1);
         float ms = 0;
@@ -1030,12 +1031,15 @@ extern "C" tlb_status tlb_batch_autotune(tlb_batch* b, int32_t trial_steps, tlb_
             best = l;
         }
     };
-    // every shape in one stream group, then the fastest split over more groups
+    // every shape in one stream group; then the fastest of them again and split over 2..4 groups,
+    // with four times the steps (the groups differ by a few percent)
     for (int wi = 0; wi < 3 && !st; ++wi)
         for (int ci = 0; ci < 4 && !st; ++ci)
-            for (int v = 0; v < 3 && !st; ++v) trial(tlb_launch{widths[wi], 1, chunks[ci], v});
+            for (int v = 0; v < 3 && !st; ++v) trial(tlb_launch{widths[wi], 1, chunks[ci], v}, trial_steps);
     const tlb_launch one = best;
-    for (int g = 2; g <= std::min(kMaxGroups, b->ndom) && !st; ++g) trial(tlb_launch{one.width, g, one.chunk, one.variant});
+    best_ms = 1e30f;
+    for (int g = 1; g <= std::min(kMaxGroups, b->ndom) && !st; ++g)
+        trial(tlb_launch{one.width, g, one.chunk, one.variant}, 4 * trial_steps);
     (void)hipMemcpyAsync(b->state[cur0], save, bytes, hipMemcpyDeviceToDevice, b->stream);
     (void)hipStreamSynchronize(b->stream);
     (void)hipFree(save);
