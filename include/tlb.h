@@ -402,8 +402,8 @@ tlb_status tlb_set_wetting_dev(tlb_sim* sim, int wall, const void* h_dev);
  *   D3Q19: each workgroup sweeps a tile of width x height columns (32x8 or
  *     64x4) over `chunk` planes; variant 1 keeps the next plane's populations in registers
  *     between their two uses, variant 0 reads them a second time from cache;
- *     variant 2 (FP32 storage, three components) also issues the loads of the plane after
- *     next before the current plane is collided.
+ *     variant 2 (FP32 storage, three or four components) also issues the loads of the plane
+ *     after next before the current plane is collided.
  *   chunk >= 1; chunk = 0 picks a default.  The default shape depends on the
  *   lattice size and precision.  For a given variant, results are bitwise
  *   identical for every shape.  The D2Q9 variants are bitwise identical to each

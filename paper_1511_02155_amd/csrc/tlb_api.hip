@@ -249,7 +249,7 @@ static void default_launch(tlb_sim* s)
         // the pipelined sweep is built for FP32 storage of three components.  With more components
         // FP32 keeps plane z's populations (variant 1: 256^3, four components 2.42 against 2.60 ms,
         // five 3.09 against 3.31 ms); in FP64 those would spill, so it pulls plane z twice
-        s->launch.variant = s->nc > 3 ? (p.prec == TLB_F32 ? 1 : 0) : (p.prec == TLB_F32 ? 2 : 1);
+        s->launch.variant = p.prec == TLB_F32 ? (s->nc <= 4 ? 2 : 1) : (s->nc > 3 ? 0 : 1);
     }
 }
 
@@ -259,7 +259,7 @@ static bool launch_valid(const tlb_sim* s, const tlb_launch* l)
     if (s->p.lattice == TLB_D2Q9)
         return l->variant < 2 && (l->width == 64 || l->width == 128 || l->width == 256);
     // the pipelined sweep is built for FP32 storage of three components
-    if (l->variant == 2 && (s->p.prec != TLB_F32 || s->nc != 3)) return false;
+    if (l->variant == 2 && (s->p.prec != TLB_F32 || s->nc > 4)) return false;
     const int w = l->width, h = l->height;
     if (w == 32 && h == 8) return true;
     if (w == 64 && h == 4) return true;

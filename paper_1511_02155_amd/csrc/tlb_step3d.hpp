@@ -96,7 +96,8 @@ struct PlaneFull {
 // latency overlaps the collision, and the populations of plane z+1 wait in
 // registers for its collision.  With FP32 storage VAR 0 holds two wavefronts
 // per SIMD (about 190 registers), VAR 1 and VAR 2 one (about 260 and 380);
-// VAR 2 is built for FP32 storage of three components only.
+// VAR 2 is built for FP32 storage of three or four components (about 460
+// registers at four; five would spill).
 // Arithmetic type of the D3Q19 step: the storage type.
 template <typename T>
 __device__ __forceinline__ const Phys<T>& phys3d(const StepArgs<T>& A);
@@ -443,7 +444,7 @@ hipError_t launch_step3d_n(const StepArgs<T>& a, int width, int height, int vari
     TLB_L3(64, 4, 0, true)
     TLB_L3(32, 8, 1, true)
     TLB_L3(64, 4, 1, true)
-    if constexpr (sizeof(T) == 4 && NC == 3) {  // VAR 2 is built for FP32 storage of three components
+    if constexpr (sizeof(T) == 4 && NC <= 4) {  // VAR 2: FP32 storage of three or four components
         TLB_L3(32, 8, 2, false)
         TLB_L3(64, 4, 2, false)
         TLB_L3(32, 8, 2, true)

@@ -261,17 +261,23 @@ def test_ncomp_d3q19_fp64_against_the_oracle(env, NC, dims, walls, launch):
     s.close()
 
 
-@pytest.mark.parametrize("NC", [4, 5])
-def test_ncomp_d3q19_fp32_storage(env, NC):
+@pytest.mark.parametrize("NC,launch", [(4, None), (4, dict(width=64, height=4, chunk=4, variant=1)),
+                                       (4, dict(width=32, height=8, chunk=3, variant=2)), (5, None)])
+def test_ncomp_d3q19_fp32_storage(env, NC, launch):
+    """FP32 storage (FP32 arithmetic) against the FP64 oracle; four components default to the pipelined
+    sweep (variant 2), five to variant 1."""
     torch, tlb = env
     w, C, u, h = _case3(NC, 24, 17, 9, 1, seed=NC + 3)
-    _note(f"ncomp d3q19 {NC} fp32")
+    _note(f"ncomp d3q19 {NC} fp32 {launch}")
     from oracle import torch_ref
 
     ref = torch_ref.concentrations(torch.tensor(_oracle3(torch, w, C, u, h, 40))).numpy().reshape(NC, -1)
-    s = _gpu3(tlb, w, C, u, h, 40, tlb.TLB_F32)
+    s = _gpu3(tlb, w, C, u, h, 40, tlb.TLB_F32, launch)
+    if launch is None:
+        assert s.launch()["variant"] == (2 if NC == 4 else 1)
     for m in range(NC):
         assert np.abs(s.field(f"C{m + 1}") - ref[m]).max() <= 1e-5, m
-    with pytest.raises(tlb.TLBError):
-        s.set_launch(64, height=4, chunk=4, variant=2)  # the pipelined sweep holds three components only
+    if NC == 5:
+        with pytest.raises(tlb.TLBError):
+            s.set_launch(64, height=4, chunk=4, variant=2)  # the pipelined sweep holds up to four components
     s.close()
