@@ -569,6 +569,7 @@ static tlb_status launch_steps(tlb_sim* s, int64_t n)
     for (int64_t t = 0; t < n; ++t) {
         a.src = (const T*)s->state[s->cur];
         a.dst = (T*)s->state[s->cur ^ 1];
+        a.flip = s->cur;  // every other step sweeps each chunk the other way
         HIPCHK(launch_one<T>(s, a));
         s->cur ^= 1;
     }
@@ -649,6 +650,7 @@ static tlb_status stream_impl(tlb_sim* s, int64_t nsteps)
     for (int64_t t = 0; t < nsteps; ++t) {
         a.src = (const T*)s->state[s->cur];
         a.dst = (T*)s->state[s->cur ^ 1];
+        a.flip = s->cur;
         HIPCHK(launch_stream_only<T>(a, s->p.lattice, s->launch.width, s->launch.height, s->nc, s->stream));
         s->cur ^= 1;
     }
@@ -1246,6 +1248,7 @@ static tlb_status recompute(tlb_sim* s, const void* from, int64_t count)
     for (int64_t k = 1; k < count; ++k) {
         a.src = (const T*)((const char*)s->seg + sb * (size_t)(k - 1));
         a.dst = (T*)((char*)s->seg + sb * (size_t)k);
+        a.flip = (int)(k & 1);
         HIPCHK(launch_one<T>(s, a));
     }
     return TLB_OK;

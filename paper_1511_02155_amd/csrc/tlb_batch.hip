@@ -270,10 +270,12 @@ void k_batch2d(BatchArgs<T> B)
         A.ntx = D.ntx;
         A.nty = 1;
         A.nitems = D.ntx * D.nchunks;
+        A.flip = B.parity;  // every other step sweeps each item the other way
         A.P = D.P;
         if constexpr (MODE == 2) {
             if (D.flat)
-                flat2d<T, W>(A, w.y & 0xffff, (w.y & 0xffff) + ((w.y >> 16) & 0x7fff), w.y < 0, S.flat);
+                flat2d<T, W>(A, w.y & 0xffff, (w.y & 0xffff) + ((w.y >> 16) & 0x7fff), (w.y < 0) != (B.parity != 0),
+                             S.flat);
             else
                 sweep2d<T, W, DEPTH>(A, w.y >> 16, w.y & 0xffff, S.strip);
         } else {

@@ -21,6 +21,7 @@ struct StepArgs {
     int nchunks;  // chunks along the sweep axis
     int ntx, nty; // strips (D2Q9: ntx) / tiles (D3Q19: ntx * nty) across the sweep
     int nitems;   // ntx * nty * nchunks
+    int flip;     // D2Q9 strips: 1 reverses the sweep direction of every chunk (alternates per step)
     Phys<acc_t<T>> P;
     Phys<float> Pf;  // the same parameters for kernels whose arithmetic is FP32
 };

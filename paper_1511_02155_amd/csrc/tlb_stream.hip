@@ -12,7 +12,8 @@ namespace tlb {
 namespace {
 
 // D2Q9: a strip of W columns over a chunk of rows, swept upwards for even chunks and downwards for odd
-// ones, as in sweep2d; each lane pulls its node's 9 NC populations and stores them unchanged.
+// ones (the other way round on steps with A.flip), as in sweep2d; each lane pulls its node's 9 NC
+// populations and stores them unchanged.
 template <typename T, int W, int NC, bool BIG>
 __global__ __launch_bounds__(W) void k_stream2d(StepArgs<T> A)
 {
@@ -25,7 +26,7 @@ __global__ __launch_bounds__(W) void k_stream2d(StepArgs<T> A)
     const int x = x0 + t;
     const int y0 = chunk * A.chunk;
     const int y1 = min(y0 + A.chunk, A.ny);
-    const int dir = (chunk & 1) ? -1 : 1;
+    const int dir = ((chunk ^ A.flip) & 1) ? -1 : 1;
     const StateAddr<T, BIG> src(A.src, A.N, NC), dst(A.dst, A.N, NC);
     const uint32_t vo[3] = {(uint32_t)x * (uint32_t)sizeof(T),
                             (uint32_t)(x == 0 ? A.nx - 1 : x - 1) * (uint32_t)sizeof(T),

@@ -10,6 +10,9 @@
 // strip of W columns and sweeps a chunk of rows, upwards for even chunks and
 // downwards for odd ones, so that two neighbouring chunks reach their shared
 // boundary rows at the same time and the second read of those rows hits L2.
+// Every other step (A.flip) reverses all directions, so that a chunk first
+// reads the rows it wrote last in the previous step, which are the likeliest
+// to be still in the Infinity Cache.
 // The concentration deviations dC_m of the last four rows of the sweep sit in
 // LDS (W+2 entries per row: the strip and one halo column on each side).  Per
 // row the lane needs S = C(x-1) + C(x+1) and D = C(x+1) - C(x-1), which fold
@@ -164,7 +167,7 @@ __device__ __forceinline__ void sweep2d(const StepArgs<T>& A, int strip, int chu
     const int y0 = chunk * A.chunk;
     const int y1 = min(y0 + A.chunk, A.ny);
     const int L = y1 - y0;
-    const int dir = (chunk & 1) ? -1 : 1;
+    const int dir = ((chunk ^ A.flip) & 1) ? -1 : 1;
     const int yfirst = dir > 0 ? y0 : y1 - 1;
     const bool hl = (t == 0);
     const bool hr = (t == nact - 1);
