@@ -203,10 +203,14 @@ static void default_launch(tlb_sim* s)
 {
     const tlb_params& p = s->p;
     if (p.lattice == TLB_D2Q9) {
-        // Measured on MI355X (1024^2): 256-wide strips, 8 rows per workgroup
-        // (about 2000 wavefronts in flight), no prefetch of the next row (its
-        // buffer would cost occupancy; the arithmetic is FP64 in both
-        // storage precisions).
+        // Measured on MI355X (1024^2): 256-wide strips.  FP64 storage: the
+        // prefetch of the next row for three and four components and
+        // 16-row items, about 1000 wavefronts in flight, one per SIMD (three
+        // components 89.7 against 93.9 us at 8 rows without the prefetch,
+        // four 123 against 133 us at 8 rows; five, which spill with the
+        // prefetch, 165 against 179 us at 16 rows; 512^2 23.7 against 26.7,
+        // 2048^2 353 against 361).  FP32 storage: 8-row items without the
+        // prefetch, about 2000 wavefronts in flight (43.0 against 48.5 us).
         // Smaller lattices get shorter chunks rather than fewer workgroups: an item's time is its rows
         // times a row's latency, so a lattice too small to fill the chip runs fastest with one or two
         // rows per item (64^2 FP64: 7.1 us per step at one row against 16.5 at four; 200^2: 9.1
@@ -214,17 +218,17 @@ static void default_launch(tlb_sim* s)
         int w = p.nx >= 256 ? 256 : (p.nx >= 128 ? 128 : 64);
         const int ntx = (p.nx + w - 1) / w;
         const int64_t waves_per_item = w / 64;
-        int64_t want_items = 2048 / waves_per_item;
+        const bool f64 = p.prec == TLB_F64;
+        int64_t want_items = (f64 ? 1024 : 2048) / waves_per_item;
         int64_t nch = (want_items + ntx - 1) / ntx;
         int chunk = (int)((p.ny + nch - 1) / nch);
         if (chunk < 1) chunk = 1;
         s->launch.width = w;
         s->launch.height = 1;
         s->launch.chunk = chunk;
-        // four components already hold one wavefront per SIMD, where the
-        // prefetch of the next row pays (7,900 against 7,370 MLUPS, FP64
-        // 1024^2); with five it spills
-        s->launch.variant = s->nc == 4 ? 1 : 0;
+        // four components hold one wavefront per SIMD in either storage, where the prefetch of the
+        // next row pays; with five it spills
+        s->launch.variant = (s->nc == 4 || (f64 && s->nc == 3)) ? 1 : 0;
         s->adj_launch = default_adj_launch(p, s->cus);
     } else {
         // Measured on MI355X (256^3 FP32): 64x4 tiles holding the next plane,
@@ -246,9 +250,9 @@ static void default_launch(tlb_sim* s)
         s->launch.width = bx;
         s->launch.height = by;
         s->launch.chunk = chunk;
-        // the pipelined sweep is built for FP32 storage of three components.  With more components
-        // FP32 keeps plane z's populations (variant 1: 256^3, four components 2.42 against 2.60 ms,
-        // five 3.09 against 3.31 ms); in FP64 those would spill, so it pulls plane z twice
+        // the pipelined sweep is built for FP32 storage of three or four components (four: 2.11
+        // against 2.34 ms with variant 1 at 256^3).  With five FP32 keeps plane z's populations
+        // (variant 1: 3.09 against 3.31 ms); in FP64 those would spill, so it pulls plane z twice
         s->launch.variant = p.prec == TLB_F32 ? (s->nc <= 4 ? 2 : 1) : (s->nc > 3 ? 0 : 1);
     }
 }
