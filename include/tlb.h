@@ -506,8 +506,9 @@ tlb_status tlb_batch_diagnostics(tlb_batch* batch, int32_t dom, tlb_diag* out);
  * runs its own chain of launches on its own stream, forked from and joined
  * back into the batch's stream inside tlb_batch_step, so that one group's
  * launch fills the compute units another group's launch leaves idle as it
- * drains.  Streams other than the batch's are created by the library, at
- * the default priority.  Results do not depend on the shape.
+ * drains.  With more than one group every group runs on a stream the
+ * library creates (four, together, at the default priority).  Results do
+ * not depend on the shape.
  */
 tlb_status tlb_batch_set_launch(tlb_batch* batch, const tlb_launch* launch);
 tlb_status tlb_batch_get_launch(const tlb_batch* batch, tlb_launch* out);

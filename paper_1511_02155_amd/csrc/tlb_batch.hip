@@ -355,9 +355,11 @@ struct tlb_batch {
     bool ready;
     tlb_launch launch;  // width, height = stream groups, chunk = rows per work item, variant
     // Stream groups: the domains are split over `groups` sets of nearly equal work, each stepped by
-    // its own chain of launches on its own stream (group 0 on `stream`), forked from and joined back
-    // into `stream` by events, so that one group's launch fills the compute units another's leaves
-    // idle while it drains.
+    // its own chain of launches on its own stream, forked from and joined back into `stream` by
+    // events, so that one group's launch fills the compute units another's leaves idle while it
+    // drains.  One group runs on `stream` itself.  The group streams are created together, the
+    // first time more than one group is asked for, so that the runtime spreads them over distinct
+    // hardware queues (streams that share a queue run one after the other).
     int groups;
     int grid[kMaxGroups];
     hipStream_t group_stream[kMaxGroups];
@@ -425,7 +427,7 @@ static void drop_graph(tlb_batch* b)
 // tlb_batch_step, so a failed step can leave them running).
 static hipError_t sync_groups(tlb_batch* b)
 {
-    hipError_t e = hipSuccess;
+    hipError_t e = hipStreamSynchronize(b->stream);
     for (int L = 0; L < kMaxGroups; ++L)
         if (b->group_stream[L]) {
             const hipError_t f = hipStreamSynchronize(b->group_stream[L]);
@@ -550,8 +552,8 @@ static tlb_status build_items(tlb_batch* b)
     BHIP(occupancy_batch2d<T>(W, b->launch.variant, &per_cu));
     if (per_cu < 1) per_cu = 1;
     for (int L = 0; L < kMaxGroups; ++L) b->grid[L] = std::min(ncu * per_cu, group_items[L]);
-    for (int L = 1; L < S; ++L)
-        if (!b->group_stream[L]) BHIP(hipStreamCreateWithFlags(&b->group_stream[L], hipStreamNonBlocking));
+    if (S > 1 && !b->group_stream[0])
+        for (int L = 0; L < kMaxGroups; ++L) BHIP(hipStreamCreateWithFlags(&b->group_stream[L], hipStreamNonBlocking));
     drop_graph(b);
     return TLB_OK;
 }
@@ -615,9 +617,8 @@ extern "C" tlb_status tlb_batch_create(const tlb_params* per_dom, int32_t ndom, 
         e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
         b->own_stream = true;
     }
-    b->group_stream[0] = b->stream;
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
-    for (int L = 1; L < kMaxGroups && e == hipSuccess; ++L) e = hipEventCreateWithFlags(&b->join[L], hipEventDisableTiming);
+    for (int L = 0; L < kMaxGroups && e == hipSuccess; ++L) e = hipEventCreateWithFlags(&b->join[L], hipEventDisableTiming);
     const size_t dsz = prec == TLB_F32 ? sizeof(DomDesc<float>) : sizeof(DomDesc<double>);
     if (e == hipSuccess) e = hipMalloc(&b->state[0], b->state_elems * b->esize);
     if (e == hipSuccess) e = hipMalloc(&b->state[1], b->state_elems * b->esize);
@@ -650,7 +651,7 @@ extern "C" tlb_status tlb_batch_destroy(tlb_batch* b)
     for (void* ptr : {b->state[0], b->state[1], b->wet, b->doms, (void*)b->items, (void*)b->qstart, (void*)b->counters,
                       b->fields, (void*)b->staging, (void*)b->diag_partial, (void*)b->diag_out})
         if (ptr) (void)hipFree(ptr);
-    for (int L = 1; L < kMaxGroups; ++L) {
+    for (int L = 0; L < kMaxGroups; ++L) {
         if (b->group_stream[L]) (void)hipStreamDestroy(b->group_stream[L]);
         if (b->join[L]) (void)hipEventDestroy(b->join[L]);
     }
@@ -749,6 +750,9 @@ extern "C" tlb_status tlb_batch_init_equilibrium(tlb_batch* b, int32_t dom, cons
     return TLB_OK;
 }
 
+// The stream group L runs on: `stream` itself when there is one group.
+static hipStream_t gstream(const tlb_batch* b, int L) { return b->groups > 1 ? b->group_stream[L] : b->stream; }
+
 // One step of stream group L from buffer `cur` on the group's stream.
 template <typename T>
 static tlb_status batch_launch_one(tlb_batch* b, int L, int cur)
@@ -762,7 +766,7 @@ static tlb_status batch_launch_one(tlb_batch* b, int L, int cur)
     a.qstart = b->qstart + L * (kQueues + 1);
     a.counters = b->counters + L * 2 * kQueues;
     a.parity = cur;
-    BHIP(launch_batch2d<T>(a, b->launch.width, b->launch.variant, b->grid[L], b->group_stream[L]));
+    BHIP(launch_batch2d<T>(a, b->launch.width, b->launch.variant, b->grid[L], gstream(b, L)));
     return TLB_OK;
 }
 
@@ -771,19 +775,20 @@ static tlb_status launch_one(tlb_batch* b, int L, int cur)
     return b->prec == TLB_F32 ? batch_launch_one<float>(b, L, cur) : batch_launch_one<double>(b, L, cur);
 }
 
-// The other groups' streams wait for the work queued on `stream` so far.
+// The groups' streams wait for the work queued on `stream` so far.
 static tlb_status fork_groups(tlb_batch* b)
 {
     if (b->groups < 2) return TLB_OK;
     BHIP(hipEventRecord(b->fork, b->stream));
-    for (int L = 1; L < b->groups; ++L) BHIP(hipStreamWaitEvent(b->group_stream[L], b->fork, 0));
+    for (int L = 0; L < b->groups; ++L) BHIP(hipStreamWaitEvent(b->group_stream[L], b->fork, 0));
     return TLB_OK;
 }
 
-// Work queued on `stream` from now on waits for the other groups' streams.
+// Work queued on `stream` from now on waits for the groups' streams.
 static tlb_status join_groups(tlb_batch* b)
 {
-    for (int L = 1; L < b->groups; ++L) {
+    if (b->groups < 2) return TLB_OK;
+    for (int L = 0; L < b->groups; ++L) {
         BHIP(hipEventRecord(b->join[L], b->group_stream[L]));
         BHIP(hipStreamWaitEvent(b->stream, b->join[L], 0));
     }
@@ -827,7 +832,7 @@ extern "C" tlb_status tlb_batch_step(tlb_batch* b, int64_t nsteps)
         // one captured chain per group, on the group's stream
         for (int L = 0; L < b->groups; ++L) {
             if (b->graph_exec[L]) continue;
-            hipStream_t s = b->group_stream[L];
+            hipStream_t s = gstream(b, L);
             BHIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
             for (int t = 0; t < b->graph_steps && !st; ++t) st = launch_one(b, L, t & 1);
             hipGraph_t g = nullptr;
@@ -838,7 +843,7 @@ extern "C" tlb_status tlb_batch_step(tlb_batch* b, int64_t nsteps)
             BHIP(hipGraphInstantiate(&b->graph_exec[L], g, nullptr, nullptr, 0));
         }
         while (left >= b->graph_steps) {
-            for (int L = 0; L < b->groups; ++L) BHIP(hipGraphLaunch(b->graph_exec[L], b->group_stream[L]));
+            for (int L = 0; L < b->groups; ++L) BHIP(hipGraphLaunch(b->graph_exec[L], gstream(b, L)));
             left -= b->graph_steps;
         }
     }
