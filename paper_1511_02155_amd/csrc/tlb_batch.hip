@@ -552,8 +552,17 @@ static tlb_status build_items(tlb_batch* b)
     BHIP(occupancy_batch2d<T>(W, b->launch.variant, &per_cu));
     if (per_cu < 1) per_cu = 1;
     for (int L = 0; L < kMaxGroups; ++L) b->grid[L] = std::min(ncu * per_cu, group_items[L]);
-    if (S > 1 && !b->group_stream[0])
-        for (int L = 0; L < kMaxGroups; ++L) BHIP(hipStreamCreateWithFlags(&b->group_stream[L], hipStreamNonBlocking));
+    if (S > 1 && !b->group_stream[0]) {
+        hipStream_t gs[kMaxGroups] = {};
+        hipError_t e = hipSuccess;
+        for (int L = 0; L < kMaxGroups && e == hipSuccess; ++L) e = hipStreamCreateWithFlags(&gs[L], hipStreamNonBlocking);
+        if (e != hipSuccess) {  // all four or none
+            for (hipStream_t x : gs)
+                if (x) (void)hipStreamDestroy(x);
+            BHIP(e);
+        }
+        for (int L = 0; L < kMaxGroups; ++L) b->group_stream[L] = gs[L];
+    }
     drop_graph(b);
     return TLB_OK;
 }
@@ -870,10 +879,18 @@ extern "C" tlb_status tlb_batch_set_launch(tlb_batch* b, const tlb_launch* l)
         l->variant < 0 || l->variant > 2 || l->height < 0 || l->height > kMaxGroups)
         return TLB_EINVAL;
     BHIP(sync_groups(b));
+    const tlb_launch old = b->launch;
+    const int old_groups = b->groups;
     b->launch = *l;
     b->groups = std::max(1, std::min(l->height, b->ndom));
     b->launch.height = b->groups;
-    return rebuild(b);
+    const tlb_status st = rebuild(b);
+    if (st) {  // keep the batch steppable in its previous shape
+        b->launch = old;
+        b->groups = old_groups;
+        (void)rebuild(b);
+    }
+    return st;
 }
 
 extern "C" tlb_status tlb_batch_get_launch(const tlb_batch* b, tlb_launch* out)
