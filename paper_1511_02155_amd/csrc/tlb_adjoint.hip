@@ -91,27 +91,37 @@ __device__ __forceinline__ void adj_local(const Phys<T>& P, const Moments<T>& mo
     }
     T b_drho = af[0], b_phi = ag[0], b_dpsi = ak[0];
     T bA = 0, b_rho = 0, bBp = 0, bBk = 0, b_psi = 0, bTxx = 0, bTyy = 0, bTxy = 0, bvx = 0, bvy = 0, bvv = 0;
+    // Opposite directions i and j = opp(i) share the weights w, w^{ab} and the even part
+    // Ue = 4.5 (e.v)^2 - 1.5 v^2 of U_i = Ue + Uo, U_j = Ue - Uo (Uo = 3 e_i.v), so each pair enters
+    // through the sums and differences of its two adjoints.
 #pragma unroll
     for (int i = 1; i < 9; ++i) {
+        const int j = L9::opp[i];
+        if (j < i) continue;
         const T w = T(weight<L9>(i));
-        const T fb = af[i] - af[0], gb = ag[i] - ag[0], kb_ = ak[i] - ak[0];
+        const T fbi = af[i] - af[0], gbi = ag[i] - ag[0], kbi = ak[i] - ak[0];
+        const T fbj = af[j] - af[0], gbj = ag[j] - ag[0], kbj = ak[j] - ak[0];
+        const T fs = fbi + fbj, fd = fbi - fbj, gs = gbi + gbj, gd = gbi - gbj, ks = kbi + kbj, kd = kbi - kbj;
         const T ev = T(L9::ex[i]) * vx + T(L9::ey[i]) * vy;
-        const T U = T(3) * ev + T(4.5) * ev * ev - T(1.5) * vv;
-        const T Ua = P.adv * U;  // velocity terms of g^eq, k^eq (absent without advection)
-        bA += w * fb;
-        b_rho += w * U * fb;
-        bTxx += T(3 * wdiag<L9>(i, 0)) * fb;
-        bTyy += T(3 * wdiag<L9>(i, 1)) * fb;
-        bTxy += T(3 * woff<L9>(i, 0, 1)) * fb;
-        bBp += w * gb;
-        b_phi += w * Ua * gb;
-        bBk += w * kb_;
-        b_psi += w * Ua * kb_;
-        const T bU = w * (rho * fb + P.adv * (phi * gb + psi * kb_));
-        const T bev = bU * (T(3) + T(9) * ev);
-        bvv += T(-1.5) * bU;
-        bvx += T(L9::ex[i]) * bev;
-        bvy += T(L9::ey[i]) * bev;
+        const T Ue = T(4.5) * ev * ev - T(1.5) * vv, Uo = T(3) * ev;
+        const T wa = w * P.adv;  // velocity terms of g^eq, k^eq (absent without advection)
+        bA += w * fs;
+        b_rho += w * (Ue * fs + Uo * fd);
+        bTxx += T(3 * wdiag<L9>(i, 0)) * fs;
+        bTyy += T(3 * wdiag<L9>(i, 1)) * fs;
+        bTxy += T(3 * woff<L9>(i, 0, 1)) * fs;
+        bBp += w * gs;
+        b_phi += wa * (Ue * gs + Uo * gd);
+        bBk += w * ks;
+        b_psi += wa * (Ue * ks + Uo * kd);
+        // bU = w (rho fb + adv (phi gb + psi kb)) per direction; its pair sum and difference
+        const T bUs = w * (rho * fs + P.adv * (phi * gs + psi * ks));
+        const T bUd = w * (rho * fd + P.adv * (phi * gd + psi * kd));
+        // e_i bU_i (3 + 9 e_i.v) + e_j bU_j (3 + 9 e_j.v) = e_i (3 bUd + 9 (e_i.v) bUs)
+        const T bo = T(3) * bUd + T(9) * ev * bUs;
+        bvv += T(-1.5) * bUs;
+        bvx += T(L9::ex[i]) * bo;
+        bvy += T(L9::ey[i]) * bo;
     }
     bvx += T(2) * vx * bvv;
     bvy += T(2) * vy * bvv;
