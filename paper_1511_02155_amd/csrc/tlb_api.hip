@@ -262,7 +262,7 @@ static bool launch_valid(const tlb_sim* s, const tlb_launch* l)
     if (l->chunk < 1 || l->variant < 0 || l->variant > 2) return false;
     if (s->p.lattice == TLB_D2Q9)
         return l->variant < 2 && (l->width == 64 || l->width == 128 || l->width == 256);
-    // the pipelined sweep is built for FP32 storage of three components
+    // the pipelined sweep is built for FP32 storage of three or four components
     if (l->variant == 2 && (s->p.prec != TLB_F32 || s->nc > 4)) return false;
     const int w = l->width, h = l->height;
     if (w == 32 && h == 8) return true;
