@@ -345,8 +345,11 @@ tlb_status tlb_wetting_from_angles(const double* kappa, double alpha, double the
  *   tlb_checkpoint_slots(nsteps, every) states (every ~ sqrt(nsteps)).
  * tlb_adjoint_backward: with those checkpoints, run the whole reverse pass
  *   for dL/dC of the state after nsteps: each segment is recomputed from its
- *   checkpoint into internal scratch (every states) and traversed backwards.
- *   The simulation's own state is not changed.
+ *   checkpoint into internal scratch and traversed backwards.  The scratch is
+ *   two buffers of `every` states: the recompute of the next segment runs on a
+ *   stream of the library's own (default priority) while the current segment
+ *   is reversed on the simulation's stream, which waits for it before the
+ *   call's work ends.  The simulation's own state is not changed.
  */
 /*
  * tlb_adjoint_step: the in-place form of tlb_adjoint_step_dev.  lambda_dev

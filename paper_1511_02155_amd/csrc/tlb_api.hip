@@ -34,8 +34,10 @@ struct tlb_sim {
     int cus;            // compute units of the device
     int nc;             // components (3 .. kMaxComp)
     double* dhs;        // [2][3][nx*nz] sink for dL/dh when the caller passes none
-    void* seg;
+    void* seg[2];       // two segment buffers of seg_cap states: one reversed, the next recomputed
     int64_t seg_cap;
+    hipStream_t aux;    // recomputes the next segment while the current one is reversed
+    hipEvent_t seg_ready[2], main_mark;
     void* fields;       // [11][N] (lazy)
     double* staging;    // device doubles for host I/O (lazy)
     size_t staging_elems;
@@ -341,8 +343,12 @@ extern "C" tlb_status tlb_destroy(tlb_sim* s)
     for (int b = 0; b < 2; ++b)
         if (s->state[b]) (void)hipFree(s->state[b]);
     if (s->wet) (void)hipFree(s->wet);
-    for (void* q : {(void*)s->hbuf, s->lam[0], s->lam[1], (void*)s->kpart, (void*)s->dhs, s->seg})
+    if (s->aux) (void)hipStreamSynchronize(s->aux);
+    for (void* q : {(void*)s->hbuf, s->lam[0], s->lam[1], (void*)s->kpart, (void*)s->dhs, s->seg[0], s->seg[1]})
         if (q) (void)hipFree(q);
+    for (hipEvent_t e : {s->seg_ready[0], s->seg_ready[1], s->main_mark})
+        if (e) (void)hipEventDestroy(e);
+    if (s->aux) (void)hipStreamDestroy(s->aux);
     if (s->fields) (void)hipFree(s->fields);
     if (s->staging) (void)hipFree(s->staging);
     if (s->diag_partial) (void)hipFree(s->diag_partial);
@@ -1062,14 +1068,21 @@ static tlb_status adj_alloc(tlb_sim* s, int64_t seg_states)
     }
     if (!s->dhs) HIPCHK(hipMalloc((void**)&s->dhs, (size_t)6 * s->p.nx * s->p.nz * sizeof(double)));
     if (seg_states > s->seg_cap) {
-        if (s->seg) {
-            HIPCHK(hipStreamSynchronize(s->stream));
-            HIPCHK(hipFree(s->seg));
-            s->seg = nullptr;
-            s->seg_cap = 0;
-        }
-        HIPCHK(hipMalloc(&s->seg, sb * (size_t)seg_states));
+        HIPCHK(hipStreamSynchronize(s->stream));
+        if (s->aux) HIPCHK(hipStreamSynchronize(s->aux));
+        for (int b = 0; b < 2; ++b)
+            if (s->seg[b]) {
+                HIPCHK(hipFree(s->seg[b]));
+                s->seg[b] = nullptr;
+            }
+        s->seg_cap = 0;
+        for (int b = 0; b < 2; ++b) HIPCHK(hipMalloc(&s->seg[b], sb * (size_t)seg_states));
         s->seg_cap = seg_states;
+    }
+    if (seg_states > 0 && !s->aux) {
+        for (int b = 0; b < 2; ++b) HIPCHK(hipEventCreateWithFlags(&s->seg_ready[b], hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&s->main_mark, hipEventDisableTiming));
+        HIPCHK(hipStreamCreateWithFlags(&s->aux, hipStreamNonBlocking));
     }
     return TLB_OK;
 }
@@ -1243,19 +1256,28 @@ extern "C" tlb_status tlb_forward_checkpointed(tlb_sim* s, int64_t nsteps, int64
 }
 
 template <typename T>
-static tlb_status recompute(tlb_sim* s, const void* from, int64_t count)
+static tlb_status recompute(tlb_sim* s, const void* from, int64_t count, void* seg, hipStream_t stream)
 {
     // seg[0] = from; seg[k] = step(seg[k-1]) for k < count
     const size_t sb = (size_t)tlb_state_bytes(s);
-    HIPCHK(hipMemcpyAsync(s->seg, from, sb, hipMemcpyDeviceToDevice, s->stream));
+    HIPCHK(hipMemcpyAsync(seg, from, sb, hipMemcpyDeviceToDevice, stream));
     StepArgs<T> a = step_args<T>(s);
     for (int64_t k = 1; k < count; ++k) {
-        a.src = (const T*)((const char*)s->seg + sb * (size_t)(k - 1));
-        a.dst = (T*)((char*)s->seg + sb * (size_t)k);
+        a.src = (const T*)((const char*)seg + sb * (size_t)(k - 1));
+        a.dst = (T*)((char*)seg + sb * (size_t)k);
         a.flip = (int)(k & 1);
-        HIPCHK(launch_one<T>(s, a));
+        HIPCHK((s->p.lattice == TLB_D2Q9)
+                   ? launch_step2d<T>(a, s->launch.width, s->launch.variant, s->p.collision == TLB_MRT, s->nc, stream)
+                   : launch_step3d<T>(a, s->launch.width, s->launch.height, s->launch.variant,
+                                      s->p.collision == TLB_MRT, s->nc, stream));
     }
     return TLB_OK;
+}
+
+static tlb_status recompute_any(tlb_sim* s, const void* from, int64_t count, void* seg, hipStream_t stream)
+{
+    return s->p.prec == TLB_F32 ? recompute<float>(s, from, count, seg, stream)
+                                : recompute<double>(s, from, count, seg, stream);
 }
 
 extern "C" tlb_status tlb_adjoint_backward(tlb_sim* s, int64_t nsteps, int64_t every, const void* ckpt,
@@ -1271,14 +1293,31 @@ extern "C" tlb_status tlb_adjoint_backward(tlb_sim* s, int64_t nsteps, int64_t e
     int cur = 0;
     bool first = true;  // the first reverse step writes the kappa partials, the others add to them
     const int64_t nseg = tlb_checkpoint_slots(nsteps, every);
-    for (int64_t seg = nseg - 1; seg >= 0; --seg) {
-        const int64_t t0 = seg * every;
-        const int64_t t1 = (t0 + every <= nsteps) ? t0 + every : nsteps;
-        const void* from = (const char*)ckpt + sb * (size_t)seg;
-        st = (s->p.prec == TLB_F32) ? recompute<float>(s, from, t1 - t0) : recompute<double>(s, from, t1 - t0);
-        if (st) return st;
+    auto seg_t0 = [&](int64_t seg) { return seg * every; };
+    auto seg_len = [&](int64_t seg) { return ((seg_t0(seg) + every <= nsteps) ? every : nsteps - seg_t0(seg)); };
+    auto seg_from = [&](int64_t seg) { return (const void*)((const char*)ckpt + sb * (size_t)seg); };
+    // Segments are reversed from the last to the first, in two buffers that take turns: while the
+    // reverse steps of segment `seg` run on the simulation's stream from one buffer, the forward
+    // recompute of segment seg - 1 runs on the auxiliary stream into the other one.  The auxiliary
+    // stream starts each recompute after all work queued on the simulation's stream so far (which
+    // includes the reverse steps that last read that buffer, and the caller's checkpoints), and the
+    // reverse steps of a segment start after its recompute.
+    st = recompute_any(s, seg_from(nseg - 1), seg_len(nseg - 1), s->seg[0], s->stream);
+    if (st) return st;
+    for (int64_t i = 0; i < nseg; ++i) {
+        const int64_t seg = nseg - 1 - i;
+        const int b = (int)(i & 1);
+        if (seg > 0) {
+            HIPCHK(hipEventRecord(s->main_mark, s->stream));
+            HIPCHK(hipStreamWaitEvent(s->aux, s->main_mark, 0));
+            st = recompute_any(s, seg_from(seg - 1), seg_len(seg - 1), s->seg[b ^ 1], s->aux);
+            if (st) return st;
+            HIPCHK(hipEventRecord(s->seg_ready[b ^ 1], s->aux));
+        }
+        if (i > 0) HIPCHK(hipStreamWaitEvent(s->stream, s->seg_ready[b], 0));
+        const int64_t t0 = seg_t0(seg), t1 = t0 + seg_len(seg);
         for (int64_t t = t1 - 1; t >= t0; --t) {
-            const void* u = (const char*)s->seg + sb * (size_t)(t - t0);
+            const void* u = (const char*)s->seg[b] + sb * (size_t)(t - t0);
             st = adj_step_any(s, u, s->lam[cur], s->lam[cur ^ 1], dh_target(s, dh), first);
             if (st) return st;
             first = false;
