@@ -115,24 +115,28 @@ def test_spinodal_256cube_full_2000_steps_fp32(tlb):
 BATCH_VS_STORAGE32 = 1e-6
 
 
-def test_batched_512_domains_full_5000_steps(tlb):
+@pytest.mark.parametrize("launch", [None, dict(width=256, chunk=16, variant=2, groups=2)])
+def test_batched_512_domains_full_5000_steps(tlb, launch):
     """The 512-domain batch (h_m ~ U[-0.01, 0.01] unclipped), FP32 storage, 5000 steps, on four
     domains: against the FP64 oracle at 1e-5 wherever FP32 storage itself allows it, and against the
     oracle with FP32 storage rounding (the floor model) at 1e-6 everywhere.  The stored floor is the
     largest difference between the two oracle runs over all nodes; on three of the four domains it
-    exceeds 1e-5 (up to 2.1e-5, domain 359), so there the FP64 bar is the floor plus the 1e-6."""
+    exceeds 1e-5 (up to 2.1e-5, domain 359), so there the FP64 bar is the floor plus the 1e-6.  Run in
+    the default launch shape and in the one the bench's tuner picks (flat sweep, two stream groups)."""
     doms = inputs.batched_walls()
     picks = sorted({int(f[len("batched_domain"):len("batched_domain") + 3]) for f in os.listdir(GOLDEN)
                     if f.startswith("batched_domain")})
     if not picks:
         pytest.skip("stored oracle values of the batch not generated")
     b = tlb.Batch([tlb.make_params(prec=tlb.TLB_F32, **{k: d[k] for k in KEYS}) for d in doms])
+    if launch:
+        b.set_launch(**launch)
     b.set_graph(50)
     for i, d in enumerate(doms):
         b.set_wetting(i, 0, d["h"][0])
         b.set_wetting(i, 1, d["h"][1])
         b.init_equilibrium(i, d["C"])
-    _note("batch 512 domains f32 5000 steps")
+    _note(f"batch 512 domains f32 5000 steps {launch}")
     b.step(5000)
     failures = []
     for i in picks:
