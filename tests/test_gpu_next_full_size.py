@@ -1,0 +1,166 @@
+"""Full-size parity of the bench's workloads for more than three components (Sec. II.E) and for multiple
+relaxation times (Sec. IV), in the launch shapes the bench times (the defaults).
+
+The D2Q9 1024^2 forms are compared node by node with the oracle run on the whole lattice for 20 steps.
+At 256^3 the oracle cannot run the whole lattice, but the populations of a node after k steps depend only
+on the initial state within 2k nodes (the pull reaches one node, the concentration stencils one more).
+So the oracle runs a 24^3 periodic box cut out around each sampled point: the box's periodic faces are
+wrong from the start on their outer layer, that error moves at most two nodes inwards per step, and the
+nodes at 1 + 2k or more from the faces are compared with the GPU's run of the full lattice.
+"""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1511_02155_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("lattice", "nx", "ny", "nz", "walls_y", "kappa", "alpha", "tau_f", "tau_g", "tau_k", "gamma_phi", "gamma_psi")
+MRT = dict(collision=1, tau_bulk=0.8, tau_ghost=1.2)  # the bench's MRT rates
+BOX, STEPS3 = 24, 3
+CORE = slice(1 + 2 * STEPS3, BOX - 1 - 2 * STEPS3)  # nodes the box's faces cannot reach in STEPS3 steps
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.init()
+    from paper_1511_02155_amd import tlb
+
+    return torch, tlb
+
+
+def _note(msg):
+    print(f"[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def _sim(tlb, w, prec, **extra):
+    return tlb.Sim(tlb.make_params(prec=prec, **{k: w[k] for k in KEYS}, **extra))
+
+
+def test_d2q9_1024_four_components_fp64_whole_lattice(env):
+    """The four-component 1024^2 spinodal (FP64, default launch) against the PyTorch oracle, every node and
+    population, after 20 steps, at the FP64 bar 1e-12 relative per species."""
+    torch, tlb = env
+    from oracle import torch_ref
+
+    w = inputs.spinodal_2d_nc(1024, 20, 4)
+    C = w["C"]()
+    _note("d2q9 1024^2 four components fp64, 20 steps")
+    s = _sim(tlb, w, tlb.TLB_F64)
+    s.init_equilibrium(C)
+    s.step(20)
+    got = s.all_populations()
+    s.close()
+    kap = torch.tensor(w["kappa"], dtype=torch.float64)
+    g = (w["gamma_phi"], w["gamma_psi"])
+    pop = torch_ref.equilibrium_state(torch.tensor(C.reshape(4, 1024, 1024)), None, kap, w["alpha"], g, False,
+                                      torch.zeros((2, 1024, 1024), dtype=torch.float64))
+    ref = torch_ref.run(pop, None, kap, w["alpha"], (w["tau_f"], w["tau_g"], w["tau_k"]), g, False, 20).numpy()
+    got = got.reshape(ref.shape)
+    for sp in range(4):
+        err = np.abs(got[sp] - ref[sp]).max()
+        assert err <= 1e-12 * np.abs(ref[sp]).max(), (sp, err)
+
+
+def test_d2q9_1024_mrt_fp64_whole_lattice(env, orc):
+    """The 1024^2 spinodal with multiple relaxation times (FP64, default launch) against the C oracle, every
+    node and population, after 20 steps, at 1e-12 relative per species."""
+    torch, tlb = env
+    w = inputs.spinodal_2d(1024, 20)
+    C = w["C"]() if callable(w["C"]) else w["C"]
+    _note("d2q9 1024^2 mrt fp64, 20 steps")
+    s = _sim(tlb, w, tlb.TLB_F64, **MRT)
+    s.init_equilibrium(C)
+    s.step(20)
+    got = s.all_populations()
+    s.close()
+    p = orc.Params(**{k: w[k] for k in KEYS}, **MRT)
+    pop = orc.init_equilibrium(p, C)
+    orc.step(p, pop, 20)
+    got = got.reshape(pop.shape)
+    for sp in range(3):
+        err = np.abs(got[sp] - pop[sp]).max()
+        assert err <= 1e-12 * np.abs(pop[sp]).max(), (sp, err)
+
+
+def _centres(n, seed):
+    rng = np.random.default_rng(seed)
+    pts = [(0, 0, 0), (n - 1, n // 2, 3)]  # across the periodic faces of the full lattice too
+    pts += [tuple(int(v) for v in rng.integers(0, n, 3)) for _ in range(2)]
+    return pts
+
+
+def _box(a, centre, n):
+    """a[..., z, y, x] of the full lattice, cut as a BOX^3 periodic box centred on centre = (x, y, z)."""
+    x, y, z = centre
+    ix = (x - BOX // 2 + np.arange(BOX)) % n
+    iy = (y - BOX // 2 + np.arange(BOX)) % n
+    iz = (z - BOX // 2 + np.arange(BOX)) % n
+    return a[..., iz[:, None, None], iy[None, :, None], ix[None, None, :]]
+
+
+def _gpu_fields(s, nc, n):
+    return np.stack([s.field(f"C{m + 1}").reshape(n, n, n) for m in range(nc)])
+
+
+def test_d3q19_256_four_components_fp32_sampled(env):
+    """The four-component 256^3 spinodal (FP32 storage, default launch: the pipelined sweep) after 3
+    steps: C_m at the cores of four oracle boxes, at the FP32 bar 1e-5."""
+    torch, tlb = env
+    from oracle import torch_ref
+
+    n, nc = 256, 4
+    w = inputs.spinodal_3d_nc(n, STEPS3, nc)
+    C = w["C"]().reshape(nc, n, n, n)
+    _note("d3q19 256^3 four components fp32, 3 steps")
+    s = _sim(tlb, w, tlb.TLB_F32)
+    assert s.launch()["variant"] == 2
+    s.init_equilibrium(C.reshape(nc, -1))
+    s.step(STEPS3)
+    G = _gpu_fields(s, nc, n)
+    s.close()
+    kap = torch.tensor(w["kappa"], dtype=torch.float64)
+    g = (w["gamma_phi"], w["gamma_psi"])
+    for c in _centres(n, 31):
+        pop = torch_ref.equilibrium_state3(torch.tensor(_box(C, c, n)), None, kap, w["alpha"], g, False,
+                                           torch.zeros((3, BOX, BOX, BOX), dtype=torch.float64))
+        pop = torch_ref.run3(pop, None, kap, w["alpha"], (w["tau_f"], w["tau_g"], w["tau_k"]), g, False, STEPS3)
+        ref = torch_ref.concentrations(pop).numpy()[:, CORE, CORE, CORE]
+        got = _box(G, c, n)[:, CORE, CORE, CORE]
+        err = np.abs(got - ref).max()
+        _note(f"box at {c}: max |C_gpu - C_oracle| = {err:.2e}")
+        assert err <= 1e-5, (c, err)
+
+
+def test_d3q19_256_mrt_fp32_sampled(env, orc):
+    """The 256^3 spinodal with multiple relaxation times (FP32 storage, default launch) after 3 steps: C_m
+    at the cores of four boxes of the C oracle, at 1e-5."""
+    torch, tlb = env
+    n = 256
+    w = inputs.spinodal_3d(n, STEPS3)
+    C = w["C"]().reshape(3, n, n, n)
+    _note("d3q19 256^3 mrt fp32, 3 steps")
+    s = _sim(tlb, w, tlb.TLB_F32, **MRT)
+    s.init_equilibrium(C.reshape(3, -1))
+    s.step(STEPS3)
+    G = _gpu_fields(s, 3, n)
+    s.close()
+    p = orc.Params(**dict({k: w[k] for k in KEYS}, nx=BOX, ny=BOX, nz=BOX), **MRT)
+    for c in _centres(n, 32):
+        pop = orc.init_equilibrium(p, _box(C, c, n).reshape(3, -1))
+        orc.step(p, pop, STEPS3)
+        F = orc.fields(p, pop)
+        ref = np.stack([F[f"C{m + 1}"].reshape(BOX, BOX, BOX) for m in range(3)])[:, CORE, CORE, CORE]
+        got = _box(G, c, n)[:, CORE, CORE, CORE]
+        err = np.abs(got - ref).max()
+        _note(f"box at {c}: max |C_gpu - C_oracle| = {err:.2e}")
+        assert err <= 1e-5, (c, err)
