@@ -1,5 +1,6 @@
 """Full-size parity of the bench's workloads for more than three components (Sec. II.E) and for multiple
-relaxation times (Sec. IV), in the launch shapes the bench times (the defaults).
+relaxation times (Sec. IV), and a few steps of the 256^3 headline, in the launch shapes the bench times (the
+defaults).
 
 The D2Q9 1024^2 forms are compared node by node with the oracle run on the whole lattice for 20 steps.
 At 256^3 the oracle cannot run the whole lattice, but the populations of a node after k steps depend only
@@ -156,6 +157,33 @@ def test_d3q19_256_mrt_fp32_sampled(env, orc):
     s.close()
     p = orc.Params(**dict({k: w[k] for k in KEYS}, nx=BOX, ny=BOX, nz=BOX), **MRT)
     for c in _centres(n, 32):
+        pop = orc.init_equilibrium(p, _box(C, c, n).reshape(3, -1))
+        orc.step(p, pop, STEPS3)
+        F = orc.fields(p, pop)
+        ref = np.stack([F[f"C{m + 1}"].reshape(BOX, BOX, BOX) for m in range(3)])[:, CORE, CORE, CORE]
+        got = _box(G, c, n)[:, CORE, CORE, CORE]
+        err = np.abs(got - ref).max()
+        _note(f"box at {c}: max |C_gpu - C_oracle| = {err:.2e}")
+        assert err <= 1e-5, (c, err)
+
+
+def test_d3q19_256_headline_fp32_sampled(env, orc):
+    """The 256^3 three-component spinodal of the headline (FP32 storage, default launch) after 3 steps:
+    C_m at the cores of four boxes of the C oracle, at 1e-5 (the 2000-step run is checked on stored
+    samples in test_gpu_full_length.py)."""
+    torch, tlb = env
+    n = 256
+    w = inputs.spinodal_3d(n, STEPS3)
+    C = w["C"]().reshape(3, n, n, n)
+    _note("d3q19 256^3 bgk fp32, 3 steps")
+    s = _sim(tlb, w, tlb.TLB_F32)
+    assert s.launch() == dict(width=64, height=4, chunk=256, variant=2)
+    s.init_equilibrium(C.reshape(3, -1))
+    s.step(STEPS3)
+    G = _gpu_fields(s, 3, n)
+    s.close()
+    p = orc.Params(**dict({k: w[k] for k in KEYS}, nx=BOX, ny=BOX, nz=BOX))
+    for c in _centres(n, 33):
         pop = orc.init_equilibrium(p, _box(C, c, n).reshape(3, -1))
         orc.step(p, pop, STEPS3)
         F = orc.fields(p, pop)
