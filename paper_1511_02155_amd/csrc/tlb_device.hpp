@@ -433,17 +433,21 @@ __device__ __forceinline__ void collide_core(const Phys<T>& P, const Moments<T, 
 #pragma unroll
             for (int l = 0; l < NK; ++l) ki[l] = ld(2 + l, d);
             if constexpr (MRT) {
-                const T di = fi - feq;
-                dq[d] = di;
-                me += T(mrt_energy<L>(d)) * di;
-#pragma unroll
-                for (int q = 0; q < NS; ++q) ms[q] += T(mrt_stress<L>(q, d)) * di;
+                dq[d] = fi - feq;
             } else {
                 st(0, d, fi + wf * (feq - fi));
             }
             st(1, d, gi + wg * (geq - gi));
 #pragma unroll
             for (int l = 0; l < NK; ++l) st(2 + l, d, ki[l] + wk * ((ke[l] + sgn * ko[l]) - ki[l]));
+        }
+        if constexpr (MRT) {
+            // the energy and stress coefficients are even in e: the pair enters its moments as a sum
+            const T ds = dq[i] + dq[j];
+            me += T(mrt_energy<L>(i)) * ds;
+#pragma unroll
+            for (int q = 0; q < NS; ++q)
+                if (mrt_stress<L>(q, i) != 0.0) ms[q] += T(mrt_stress<L>(q, i)) * ds;
         }
     }
     const T f0 = ld(0, 0), g0 = ld(1, 0);
@@ -454,13 +458,18 @@ __device__ __forceinline__ void collide_core(const Phys<T>& P, const Moments<T, 
         me *= P.mrt_db * T(1.0 / mrt_energy_norm<L>());
 #pragma unroll
         for (int q = 0; q < NS; ++q) ms[q] *= P.mrt_dv * T(1.0 / mrt_stress_norm<L>(q));
+        st(0, 0, f0 - P.mrt_sg * dq[0] - T(mrt_energy<L>(0)) * me);
+        // the projections back onto a pair share their even coefficients
 #pragma unroll
-        for (int i = 0; i < L::Q; ++i) {
-            T r = (i == 0 ? f0 : ld(0, i)) - P.mrt_sg * dq[i] - T(mrt_energy<L>(i)) * me;
+        for (int i = 1; i < L::Q; ++i) {
+            const int j = L::opp[i];
+            if (j < i) continue;
+            T c = T(mrt_energy<L>(i)) * me;
 #pragma unroll
             for (int q = 0; q < NS; ++q)
-                if (mrt_stress<L>(q, i) != 0.0) r -= T(mrt_stress<L>(q, i)) * ms[q];
-            st(0, i, r);
+                if (mrt_stress<L>(q, i) != 0.0) c += T(mrt_stress<L>(q, i)) * ms[q];
+            st(0, i, ld(0, i) - P.mrt_sg * dq[i] - c);
+            st(0, j, ld(0, j) - P.mrt_sg * dq[j] - c);
         }
     } else {
         st(0, 0, f0 + wf * ((mo.drho - sf) - f0));
