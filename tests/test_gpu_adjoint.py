@@ -388,3 +388,41 @@ def test_adjoint_512_full_size_vs_finite_differences(env):
         km[m] *= 1 - eps
         fd = (loss(kap=kp) - loss(kap=km)) / (2 * eps * w["kappa"][m])
         assert dk[m] == pytest.approx(fd, rel=1e-6), m
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_single_step_kappa_reduction_equals_the_pass_reduction(env, prec):
+    """A single reverse step (tlb_adjoint_step_dev) and a checkpointed backward over the same one step
+    (tlb_adjoint_backward, with its recompute on the other stream) give the same dL/dh and dL/dkappa bit for
+    bit, also after changes of launch shape on the same simulation, which change the number of work items
+    whose partials are reduced."""
+    torch, tlb = env
+    P = tlb.TLB_F64 if prec == "f64" else tlb.TLB_F32
+    dt = torch.float64 if prec == "f64" else torch.float32
+    w, C, h, target = _wall_case(nx=70, ny=41)
+    stream = torch.cuda.Stream()
+    s = _sim(torch, tlb, w, C, h, P, stream)
+    esize = 8 if prec == "f64" else 4
+    # the default shape, then more work items, then fewer again on the same simulation
+    for launch in (None, dict(width=64, rows=2, chunk=3, variant=2), dict(width=64, rows=4, chunk=9, variant=2)):
+        _note(f"fused kappa reduction {prec} {launch}")
+        if launch:
+            s.set_adjoint_launch(**launch)
+        with torch.cuda.stream(stream):
+            ck = torch.empty(s.state_bytes() // esize, dtype=dt, device="cuda")
+            dLdC = torch.randn((3, w["nx"] * w["ny"]), generator=torch.Generator().manual_seed(4), dtype=torch.float64)
+            dLdC = dLdC.to(dtype=dt, device="cuda")
+            lam, out = torch.empty_like(ck), torch.empty_like(ck)
+            dh1, dk1 = torch.zeros((2, 3, w["nx"]), dtype=torch.float64, device="cuda"), torch.zeros(3, dtype=torch.float64, device="cuda")
+            dh2, dk2 = torch.zeros_like(dh1), torch.zeros_like(dk1)
+        tlb.check(tlb.tlb_forward_checkpointed(s.handle, 1, 1, ck.data_ptr()), "forward")
+        tlb.check(tlb.tlb_adjoint_backward(s.handle, 1, 1, ck.data_ptr(), dLdC.data_ptr(), dh1.data_ptr(),
+                                           dk1.data_ptr()), "backward")
+        tlb.check(tlb.tlb_adjoint_seed_dev(s.handle, dLdC.data_ptr(), lam.data_ptr()), "seed")
+        tlb.check(tlb.tlb_adjoint_step_dev(s.handle, ck.data_ptr(), lam.data_ptr(), out.data_ptr(), dh2.data_ptr(),
+                                           dk2.data_ptr()), "step")
+        s.synchronize()
+        assert dk1.abs().max() > 0 and dh1.abs().max() > 0
+        assert torch.equal(dh1, dh2)
+        assert torch.equal(dk1, dk2), (dk1, dk2)
+    s.close()
