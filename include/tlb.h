@@ -518,8 +518,9 @@ tlb_status tlb_batch_get_launch(const tlb_batch* batch, tlb_launch* out);
 /*
  * Time every launch shape for trial_steps steps from the current state
  * (which is restored) in one stream group, then the fastest of them in 1, 2,
- * 3 and 4 groups for 4 * trial_steps steps each, and keep the fastest of
- * those; writes it to *chosen if not NULL.
+ * 3 and 4 groups, each with its chunk and with twice and four times its
+ * chunk, for 4 * trial_steps steps each, and keep the fastest of those;
+ * writes it to *chosen if not NULL.
  * If the environment variable TLB_TUNE_CACHE names a file, a previous result
  * for the same domain sizes is taken from it, and new results are appended.
  */

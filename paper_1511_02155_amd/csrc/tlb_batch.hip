@@ -1039,6 +1039,7 @@ extern "C" tlb_status tlb_batch_autotune(tlb_batch* b, int32_t trial_steps, tlb_
     const int widths[3] = {64, 128, 256};
     const int chunks[4] = {8, 16, 32, 64};
     tlb_status st = TLB_OK;
+    float margin = 1.0f;  // a later shape replaces the best one if its time is below margin * best
     auto trial = [&](const tlb_launch& l, int steps) {
         st = tlb_batch_set_launch(b, &l);
         // warm-up as long as the trial: a group's first launches on a new stream are slower
@@ -1050,20 +1051,24 @@ extern "C" tlb_status tlb_batch_autotune(tlb_batch* b, int32_t trial_steps, tlb_
         (void)hipEventSynchronize(e1);
         float ms = 0;
         (void)hipEventElapsedTime(&ms, e0, e1);
-        if (!st && ms < best_ms) {
+        if (!st && ms < margin * best_ms) {
             best_ms = ms;
             best = l;
         }
     };
-    // every shape in one stream group; then the fastest of them again and split over 2..4 groups,
-    // with four times the steps (the groups differ by a few percent)
+    // every shape in one stream group; then the fastest of them again in 1..4 groups and with items of
+    // one, two and four times its rows (with several groups the drain of one launch is covered by the
+    // others, so longer items, with fewer halo rows, can pay), with four times the steps (these
+    // differ by a few percent)
     for (int wi = 0; wi < 3 && !st; ++wi)
         for (int ci = 0; ci < 4 && !st; ++ci)
             for (int v = 0; v < 3 && !st; ++v) trial(tlb_launch{widths[wi], 1, chunks[ci], v}, trial_steps);
     const tlb_launch one = best;
     best_ms = 1e30f;
+    margin = 0.995f;  // fewer groups and shorter items first; a later one must be faster by more than 0.5%
     for (int g = 1; g <= std::min(kMaxGroups, b->ndom) && !st; ++g)
-        trial(tlb_launch{one.width, g, one.chunk, one.variant}, 4 * trial_steps);
+        for (int f = 1; f <= 4 && !st; f *= 2)
+            if ((int64_t)one.chunk * f <= 65535) trial(tlb_launch{one.width, g, one.chunk * f, one.variant}, 4 * trial_steps);
     (void)hipMemcpyAsync(b->state[cur0], save, bytes, hipMemcpyDeviceToDevice, b->stream);
     (void)hipStreamSynchronize(b->stream);
     (void)hipFree(save);

@@ -115,7 +115,7 @@ def test_spinodal_256cube_full_2000_steps_fp32(tlb):
 BATCH_VS_STORAGE32 = 1e-6
 
 
-@pytest.mark.parametrize("launch", [None, dict(width=256, chunk=16, variant=2, groups=2)])
+@pytest.mark.parametrize("launch", [None, dict(width=256, chunk=32, variant=2, groups=2)])
 def test_batched_512_domains_full_5000_steps(tlb, launch):
     """The 512-domain batch (h_m ~ U[-0.01, 0.01] unclipped), FP32 storage, 5000 steps, on four
     domains: against the FP64 oracle at 1e-5 wherever FP32 storage itself allows it, and against the
